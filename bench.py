@@ -1,0 +1,212 @@
+"""Benchmark of the coupled two-lattice LB path on one MI355X.
+
+Workload: heterogeneous injection, 2-D 4096 x 4096 on D2Q5, float32
+populations, log-normal permeability (seeded Gaussian random field,
+sigma_lnK = 1, correlation length 16 cells), porosity uniform in [0.15, 0.3],
+quadratic relative permeabilities, viscosity ratio 5, pressure 1 / saturation
+1 imposed at x = 0, pressure 0 and a zero-gradient saturation outlet at
+x = L, no flux on y faces, S0 = 0, P0 linear.  Every coupled step solves the
+pressure lattice to r <= 1e-8 (residual stride m = 64) and advances the
+saturation lattice once.
+
+A "step" is one coupled step.  W warm-up steps (the first one is the cold
+pressure solve from the linear profile) are followed by K timed steps,
+bracketed by torch.cuda.synchronize().  value = MLUPS over both lattices:
+cells x (pressure iterations + saturation steps) / time / 1e6.
+
+Also reported: the f-sweep kernel against the HBM roofline (average
+duration from HIP events around a burst of sweeps on the solver's stream),
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+F_SWEEP_BYTES_PER_CELL = {"D2Q5": 36, "D3Q7": 52}   # pops read + written + 1/tau_f read
+KERNEL_SRC = os.path.join(ROOT, "paper_1808_07554_amd", "csrc", "lbtp_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "f_sweep_traffic_injection2d_4096.txt")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4999)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--m", type=int, default=64)
+    ap.add_argument("--max-iters", type=int, default=20_000_000)
+    ap.add_argument("--burst", type=int, default=200, help="plain sweeps timed for the roofline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def measured_traffic(ncell):
+    """HBM bytes per f-sweep launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source (else None)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m = re.search(r"source_sha256:\s*([0-9a-f]{64})", txt)
+    b = re.search(r"bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b:
+        return None
+    cur = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if cur != m.group(1):
+        return None
+    return float(b.group(1))
+
+
+def cpu_baseline(seconds):
+    """The float64 oracle on a 512 x 512 crop of the same workload recipe:
+    coupled steps with 64 pressure iterations each until ~seconds of CPU work."""
+    import oracle
+    from paper_1808_07554_amd import inputs
+    n = 512
+    params, fl = inputs.injection_problem((n, n), 1.0, 16.0, 2, 3)
+    o = oracle.Solver(params["lattice"], params["shape"], beta=params["beta"], Ds=params["Ds"],
+                      coef=oracle.QuadraticKr(params["mu_w"], params["mu_n"]),
+                      bc_f=params["bc_f"], bc_g=params["bc_g"], m=64)
+    o.set_fields(inputs.f32(fl["K"]).astype(np.float64), inputs.f32(fl["phi"]).astype(np.float64))
+    o.set_state(fl["P0"], fl["S0"])
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        o.step(-1.0, 64)
+        steps += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    updates = n * n * steps * (64 + 1)
+    return {"value": updates / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"float64 NumPy oracle, 512x512 crop of the same recipe, {steps} coupled steps "
+                      f"of 64 pressure iterations + 1 saturation step, {dt:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1808_07554_amd import inputs, lbtp
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    params, fl = inputs.injection_2d(a.n)
+    ncell = a.n * a.n
+    K = torch.from_numpy(inputs.f32(fl["K"]).ravel()).to(dev)
+    phi = torch.from_numpy(inputs.f32(fl["phi"]).ravel()).to(dev)
+    P0 = torch.from_numpy(inputs.f32(fl["P0"]).ravel()).to(dev)
+    S0 = torch.from_numpy(inputs.f32(fl["S0"]).ravel()).to(dev)
+    s = lbtp.from_problem(params, m=a.m)
+    s.set_fields(K, phi)
+    s.set_state(P0, S0)
+    del K, phi, P0, S0
+    torch.cuda.synchronize()
+
+    def coupled_step(progress=False):
+        """One coupled step: coefficients, pressure solve to tol, saturation step.
+        The solve runs in calls of 64k iterations so a long (cold) solve reports
+        progress; each call continues the same iteration (checks stay on
+        multiples of m)."""
+        s.update_coefficients()
+        total, t0 = 0, time.perf_counter()
+        while True:
+            k, r, st = s.pressure_solve(a.tol, min(65536, a.max_iters - total))
+            total += k
+            if progress:
+                print(f"  cold solve: {total} iterations, r = {r:.3e}, {time.perf_counter() - t0:.1f} s",
+                      file=sys.stderr, flush=True)
+            if st == lbtp.OK or total >= a.max_iters:
+                break
+            if st < 0:
+                raise RuntimeError(f"pressure solve failed: {st}")
+        s.saturation_step()
+        return total
+
+    warm_its = []
+    t_cold = None
+    for w in range(a.warmup):
+        t0 = time.perf_counter()
+        warm_its.append(coupled_step(progress=(w == 0)))
+        torch.cuda.synchronize()
+        if w == 0:
+            t_cold = time.perf_counter() - t0
+        print(f"warmup step {w}: {warm_its[-1]} iterations, {time.perf_counter() - t0:.3f} s",
+              file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its_all = []
+    for k in range(a.steps):
+        its_all.append(coupled_step())
+        if (k + 1) % 10 == 0:
+            print(f"timed step {k + 1}: {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_run = time.perf_counter() - t0
+    f_updates = sum(its_all)
+    mlups = ncell * (f_updates + a.steps) / t_run / 1e6
+    print(f"timed: {a.steps} steps in {t_run:.3f} s, iterations {f_updates}", file=sys.stderr, flush=True)
+
+    # f-sweep roofline: a burst of plain sweeps, HIP events on the solver's stream
+    stream = torch.cuda.current_stream()
+    s.update_coefficients()
+    s.pressure_solve(-1.0, 20)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.pressure_solve(-1.0, a.burst)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sweep_s = e0.elapsed_time(e1) / 1e3 / a.burst
+    alg_bytes = F_SWEEP_BYTES_PER_CELL[params["lattice"]] * ncell
+    achieved = alg_bytes / sweep_s / 1e9
+    traffic = measured_traffic(ncell)
+
+    out = {
+        "metric": "MLUPS (both lattices) + s/coupled step vs plain FP32 at residual 1e-8",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(t_run / a.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"heterogeneous injection 2-D {a.n}x{a.n} (log-normal K sigma 1, corr. length 16)",
+                   "lattice": params["lattice"], "storage": "fp32", "tol": a.tol, "residual_stride": a.m,
+                   "cells": ncell},
+        "s_per_coupled_step": t_run / a.steps,
+        "iterations_per_step_mean": f_updates / a.steps,
+        "iterations_per_step_max": max(its_all),
+        "whole_job_s": (t_cold or 0.0) + t_run,
+        "cold_first_step_s": t_cold,
+        "cold_first_step_iterations": warm_its[0] if warm_its else None,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "f_sweep_kernel<2,false,0,false>", "avg_launch_us": round(sweep_s * 1e6, 2),
+                     "bytes_per_launch": alg_bytes},
+    }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * lbtp.h -- C ABI of an MI355X (gfx950) implementation of the
+ * double-distribution lattice Boltzmann model for two-phase flow in porous
+ * media of Chai, Liang, Du and Shi (arXiv:1808.07554).
+ *
+ * Problem solved (Section 2): the global-pressure Poisson equation
+ *     div(D_p grad P) + F_p = 0,                  D_p = K lambda_t   (eq. 2-15, 2-16)
+ * and the saturation equation with convection written as a source
+ *     phi dS/dt = div(D_s grad S) + F_s + div(lambda_w K grad P)   (eq. 2-18)
+ * with lambda_a = k_ra / mu_a (eq. 2-9), k_rw = S^2, k_rn = (1-S)^2
+ * (Section 4.3), on a box of nx x ny (x nz) nodes.
+ *
+ * Method (Section 3): a pressure lattice f_i iterated in pseudo time to a
+ * steady state (eq. 3-1, 3-3) and a saturation lattice g_i advanced in
+ * physical time (eq. 3-2, 3-4b), on D2Q5 or D3Q7 (Remark V).  The pressure
+ * gradient and velocity come from the local first moment of f (eq. 3-10);
+ * the relaxation times follow from D_p and D_s (eq. 3-11).  Dirichlet
+ * boundaries use anti-bounce-back, no-flux boundaries bounce-back
+ * (Section 4).
+ *
+ * Conventions
+ *   - Lattice units of the caller: dx, dt given; c = dx/dt; c_s^2 = c^2/3
+ *     (D2Q5) or c^2/4 (D3Q7).
+ *   - Scalar fields are float32 arrays of nx*ny*nz values, x fastest:
+ *     index = x + nx*(y + ny*z).  Vector fields are component-major:
+ *     component a of cell c at a*ncell + c.
+ *   - Population order: i = 0 rest, then +x, +y, -x, -y (D2Q5), followed by
+ *     +z, -z (D3Q7).  The rest population of the pressure lattice never
+ *     influences any output (P sums i >= 1, eq. 3-9a; c_0 = 0 in eq. 3-10;
+ *     bar-omega_0 = 0; walls act on moving populations only), so it is not
+ *     stored; f arrays hold Q-1 populations, g arrays hold Q.
+ *   - on_device: 1 if a pointer is device memory of the current HIP device
+ *     (e.g. a torch tensor's data_ptr), 0 if it is host memory.
+ *   - Ownership: the context owns all device memory it allocates.  Caller
+ *     pointers are only read or written during the call; none is retained.
+ *   - Streams: every device operation is enqueued on params.stream (a
+ *     hipStream_t; NULL = the null stream).  Calls that return host values
+ *     synchronise that stream.  A context is not thread-safe; use one per
+ *     stream.
+ *   - Return codes: 0 ok; > 0 warning; < 0 error (see lbtp_status).  On an
+ *     error no device state has been changed unless stated.
+ */
+#ifndef LBTP_H
+#define LBTP_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define LBTP_API __attribute__((visibility("default")))
+#else
+#define LBTP_API
+#endif
+
+typedef struct lbtp_ctx lbtp_ctx;
+
+enum lbtp_lattice { LBTP_D2Q5 = 0, LBTP_D3Q7 = 1 };
+
+/* Population storage.  FP32 stores f and g as float.  The *_DEV forms store
+ * each population as a 16-bit deviation from a per-cell base equilibrium
+ * (f_i - w_i P_b, g_i - g_i^eq(S_b)); collision arithmetic stays float32 and
+ * the residual / mass reductions stay float64. */
+enum lbtp_storage { LBTP_FP32 = 0, LBTP_FP16_DEV = 1, LBTP_BF16_DEV = 2 };
+
+/* Boundary condition of one face (faces ordered -x, +x, -y, +y, -z, +z).
+ * DIRICHLET: anti-bounce-back with the face value (Section 4).
+ * NOFLUX:    bounce-back (Section 4).
+ * OUTFLOW:   saturation lattice only: anti-bounce-back with S_wb equal to the
+ *            current saturation of the boundary node (zero-gradient outlet).
+ * PERIODIC must be set on both faces of an axis, for f and for g. */
+enum lbtp_bc { LBTP_BC_PERIODIC = 0, LBTP_BC_DIRICHLET = 1, LBTP_BC_NOFLUX = 2, LBTP_BC_OUTFLOW = 3 };
+
+enum lbtp_status {
+  LBTP_OK = 0,
+  LBTP_NOT_CONVERGED = 1,   /* max_iters reached before the residual met tol */
+  LBTP_EINVAL = -1,         /* invalid argument or parameter; nothing done */
+  LBTP_ENOMEM = -2,         /* device allocation failed */
+  LBTP_EHIP = -3,           /* a HIP runtime call failed */
+  LBTP_EUNSTABLE = -4,      /* non-finite residual or mass */
+  LBTP_ESTATE = -5          /* call out of order (e.g. step before set_state) */
+};
+
+typedef struct lbtp_params {
+  int lattice;                 /* lbtp_lattice */
+  int nx, ny, nz;              /* nodes per axis; nz = 1 for D2Q5 */
+  double dx, dt;               /* lattice spacing and time step */
+  double beta;                 /* equilibrium parameter of eq. 3-4b; 0 <= beta <= min(phi)/(1-w_0) */
+  double Ds;                   /* saturation diffusivity; tau_g = 1/2 + Ds/(beta c_s^2 dt) (eq. 3-11b) */
+  double mu_w, mu_n;           /* phase viscosities (eq. 2-9) */
+  int storage;                 /* lbtp_storage */
+  int residual_stride;         /* m >= 1: the stopping rule compares P^k with P^(k-m) */
+  int bc_f[6];                 /* pressure-lattice face conditions (PERIODIC, DIRICHLET, NOFLUX) */
+  double bc_P[6];              /* Dirichlet pressure per face */
+  int bc_g[6];                 /* saturation-lattice face conditions (any lbtp_bc) */
+  double bc_S[6];              /* Dirichlet saturation per face */
+  int init_neq;                /* 1: lbtp_set_state adds the first-order non-equilibrium parts */
+  void *stream;                /* hipStream_t for all device work; NULL = null stream */
+} lbtp_params;
+
+/* Fill *p with defaults: D2Q5, 1x1x1, dx = dt = 1, beta = 1, Ds = 0, mu = 1,
+ * FP32, m = 64, periodic faces, init_neq = 1, null stream. */
+LBTP_API void lbtp_default_params(lbtp_params *p);
+
+/* Validate *p (tau_g > 1/2, beta >= 0, periodicity consistent, sizes > 0,
+ * storage/lattice known) and allocate all device buffers of a context.
+ * Returns LBTP_EINVAL, LBTP_ENOMEM or LBTP_EHIP on failure (*out = NULL). */
+LBTP_API int lbtp_init(const lbtp_params *p, lbtp_ctx **out);
+
+/* Release every device buffer of ctx; ctx may be NULL. */
+LBTP_API void lbtp_destroy(lbtp_ctx *ctx);
+
+/* Follow another stream from now on (hipStream_t, NULL = null stream). */
+LBTP_API int lbtp_set_stream(lbtp_ctx *ctx, void *stream);
+
+/* The medium and the sources of eq. 2-15/2-18 (Section 2): absolute
+ * permeability K > 0, porosity phi > 0, F_p = q_w/rho_w + q_n/rho_n and
+ * F_s = q_w/rho_w (eq. 2-17).  Fp / Fs may be NULL for zero.  Fails with
+ * LBTP_EINVAL if K or phi is not positive and finite, if beta violates the
+ * non-negativity bound of eq. 3-4b for the smallest phi, or if a fully
+ * periodic pressure problem has sum(F_p) != 0 (no solution). */
+LBTP_API int lbtp_set_fields(lbtp_ctx *ctx, const float *K, const float *phi,
+                    const float *Fp, const float *Fs, int on_device);
+
+/* Replace F_p and F_s only (time-dependent sources); NULL = zero. */
+LBTP_API int lbtp_set_sources(lbtp_ctx *ctx, const float *Fp, const float *Fs, int on_device);
+
+/* Initial populations (initialisation paragraph of Section 4):
+ *   g_i = g_i^eq(S0) + eps g_i^(1) with eps g_i^(1) of eq. (gneq),
+ *   f_i = w_i P0 - tau_f dt w_i c_i . grad P0   (i >= 1, Appendix A order 1).
+ * dP0 / dS0 are component-major gradient fields (dim x ncell) or NULL, in
+ * which case second-order central differences of P0 / S0 are used
+ * (one-sided at walls).  With params.init_neq = 0 both are pure equilibria.
+ * Resets the step counter and the mass ledger. */
+LBTP_API int lbtp_set_state(lbtp_ctx *ctx, const float *P0, const float *S0,
+                   const float *dP0, const float *dS0, int on_device);
+
+/* Coefficients of the current coupled step: S^n (eq. 3-9b), lambda_w,
+ * lambda_t (eq. 2-9), D_p = K lambda_t (eq. 2-16), 1/tau_f (eq. 3-11a), and
+ * the mass M^n = sum phi S^n in float64. */
+LBTP_API int lbtp_update_coefficients(lbtp_ctx *ctx);
+
+/* Iterate the pressure lattice (eq. 3-1) with the current coefficients.
+ * Stopping rule: r_k = ||P^k - P^(k-m)||_2 / (m ||P^k||_2) (float64 sums),
+ * tested when k is a positive multiple of m; stops at the first r_k <= tol
+ * or after max_iters iterations (tol < 0: exactly max_iters iterations).
+ * *iters receives the iteration count, *resid the last tested r (or -1 if
+ * none).  Returns LBTP_OK, LBTP_NOT_CONVERGED or LBTP_EUNSTABLE. */
+LBTP_API int lbtp_pressure_solve(lbtp_ctx *ctx, double tol, long long max_iters,
+                        long long *iters, double *resid);
+
+/* One step of the saturation lattice (eq. 3-2, 3-4b) with S^n, the local
+ * gradient of the current pressure lattice (eq. 3-10a) and the current F_s;
+ * accumulates the net boundary-link flux into the mass ledger and advances
+ * the step counter. */
+LBTP_API int lbtp_saturation_step(lbtp_ctx *ctx);
+
+/* nsteps coupled steps, each = update_coefficients + pressure_solve(tol,
+ * max_iters) + saturation_step.  iters (may be NULL) receives nsteps
+ * iteration counts.  Stops early with the first error or LBTP_EUNSTABLE;
+ * a step that does not converge continues (returns LBTP_NOT_CONVERGED at
+ * the end). */
+LBTP_API int lbtp_step(lbtp_ctx *ctx, long long nsteps, double tol, long long max_iters,
+              long long *iters);
+
+/* Outputs on the current state.  pressure: eq. 3-9a of the pre-collision f.
+ * velocity: u = K lambda_t sum_i c_i f_i / (tau_f dt c_s^2) (eq. 3-10b), dim
+ * components, with the coefficients of the last update_coefficients.
+ * grad_p: eq. 3-10a.  saturation: eq. 3-9b with the current F_s. */
+LBTP_API int lbtp_pressure(lbtp_ctx *ctx, float *P, int on_device);
+LBTP_API int lbtp_velocity(lbtp_ctx *ctx, float *u, int on_device);
+LBTP_API int lbtp_grad_p(lbtp_ctx *ctx, float *gradP, int on_device);
+LBTP_API int lbtp_saturation(lbtp_ctx *ctx, float *S, int on_device);
+
+/* Mass M = sum_x phi S (float64, current g and F_s) and the accumulated net
+ * flux of g through Dirichlet/outflow links since lbtp_set_state.  Exactly,
+ * M^{n+1} = M^n + dt/2 sum(F_s^n + F_s^{n+1}) + flux_n. */
+LBTP_API int lbtp_mass(lbtp_ctx *ctx, double *mass, double *ledger);
+
+/* Checkpoint: pre-collision populations as float32, f as (Q-1) x ncell,
+ * g as Q x ncell (population-major), plus the step counter.  put_state
+ * restores them; a run resumed from a checkpoint is bitwise identical. */
+LBTP_API int lbtp_get_state(lbtp_ctx *ctx, float *f, float *g, long long *step, int on_device);
+LBTP_API int lbtp_put_state(lbtp_ctx *ctx, const float *f, const float *g, long long step, int on_device);
+
+/* Static description of a status code. */
+LBTP_API const char *lbtp_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBTP_H */

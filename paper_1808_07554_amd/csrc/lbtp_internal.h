@@ -1,0 +1,99 @@
+// Internal declarations shared by the kernels and the host side of liblbtp.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lbtp.h"
+
+namespace lbtp {
+
+// Stored moving directions j = 0..2*DIM-1 (population i = j + 1):
+//   0:+x 1:+y 2:-x 3:-y 4:+z 5:-z
+// axis, sign and opposite of each.
+__host__ __device__ constexpr int dir_axis(int j) { return (j == 0 || j == 2) ? 0 : (j == 1 || j == 3) ? 1 : 2; }
+__host__ __device__ constexpr int dir_sign(int j) { return (j == 0 || j == 1 || j == 4) ? 1 : -1; }
+__host__ __device__ constexpr int dir_opp(int j) { return j == 0 ? 2 : j == 1 ? 3 : j == 2 ? 0 : j == 3 ? 1 : j == 4 ? 5 : 4; }
+
+constexpr int kThreads = 256;       // threads per block of every cell kernel
+
+// Lattice constants and boundary data passed by value to every cell kernel.
+struct KC {
+  int nx, ny, nz;
+  int ncell;
+  float c;          // dx / dt
+  float dt;
+  float cs2;        // c_s^2
+  float w0, w1;     // rest and moving weights
+  float inv_1mw0;   // 1 / (1 - w0)
+  float wbar;       // source weight of a moving direction (eq. 3-5a pattern)
+  float beta;
+  float inv_tau_g;  // 1 / tau_g
+  float src_g;      // dt (1 - 1/(2 tau_g)): weight of F_s in eq. 3-2
+  float inv_mu_w, inv_mu_n;
+  float inv_cs2dt;  // 1 / (c_s^2 dt)
+  float geq0_phi;   // (w0 - 1) beta: g_0^eq = (geq0_phi + phi) S
+  float w1beta;     // w1 beta: g_i^eq = w1 beta S
+  float half_dt;    // dt / 2
+  int bc_f[6];
+  float abbP[6];    // 2 w1 P_b of a Dirichlet pressure face
+  int bc_g[6];
+  float abbS[6];    // 2 w1 beta S_b of a Dirichlet saturation face
+};
+
+// Device-side control block of a pressure solve and the float64 reductions.
+struct Ctl {
+  int done;          // set once the solve has stopped (converged or unstable)
+  int status;        // LBTP_OK or LBTP_EUNSTABLE when done
+  long long K;       // iteration at which it stopped
+  long long kmax;    // sweeps with index > kmax do nothing
+  double tol;
+  double resid;      // last evaluated residual
+  long long last_check;
+  double mass;       // last mass reduction
+  double ledger;     // accumulated boundary-link flux of g
+  double last_flux;  // flux of the last saturation step
+};
+
+// ----------------------------------------------------------------- launchers
+// Each returns the hipError_t of the launch.  Pointer arrays hold one base
+// pointer per stored population.
+struct FPtrs { float *p[6]; };
+struct GPtrs { float *p[7]; };
+
+hipError_t launch_f_sweep(int dim, const KC &kc, FPtrs fin, FPtrs fout, const float *itau,
+                          const float *Fp, float *Psnap, double *partials, const Ctl *ctl,
+                          long long k, int local, int snap, hipStream_t s);
+hipError_t launch_finish_residual(const double *partials, int nblk, Ctl *ctl, long long k, int m,
+                                  hipStream_t s);
+hipError_t launch_ctl_reset(Ctl *ctl, long long kmax, double tol, hipStream_t s);
+hipError_t launch_moments(int dim, const KC &kc, GPtrs g, const float *K, const float *phi,
+                          const float *Fs, float *S, float *itau, double *partials, int write_coef,
+                          hipStream_t s);
+hipError_t launch_finish_sum(const double *partials, int nblk, double *dst, int accumulate,
+                             double *copy_to, hipStream_t s);
+hipError_t launch_g_sweep(int dim, const KC &kc, GPtrs gin, GPtrs gout, FPtrs f, int f_local,
+                          const float *itau, const float *K, const float *phi, const float *Fs,
+                          double *partials, hipStream_t s);
+hipError_t launch_init(int dim, const KC &kc, const float *P0, const float *S0, const float *dP0,
+                       const float *dS0, const float *K, const float *phi, const float *Fs,
+                       int neq, FPtrs f, GPtrs g, hipStream_t s);
+hipError_t launch_pressure(int dim, const KC &kc, FPtrs f, int f_local, float *P, hipStream_t s);
+hipError_t launch_grad(int dim, const KC &kc, FPtrs f, int f_local, const float *itau,
+                       const float *K, const float *S, int velocity, float *out, hipStream_t s);
+hipError_t launch_saturation(int dim, const KC &kc, GPtrs g, const float *phi, const float *Fs,
+                             float *S, hipStream_t s);
+hipError_t launch_materialize_f(int dim, const KC &kc, FPtrs fin, int f_local, FPtrs fout,
+                                hipStream_t s);
+
+inline int nblocks(long long n) { return (int)((n + kThreads - 1) / kThreads); }
+
+// Grid of the pressure sweep: a grid-stride loop over at most kSweepBlocks
+// blocks (256 CUs x 16 resident blocks), so that a sweep queued behind a
+// converged solve costs one short dispatch.
+constexpr int kSweepBlocks = 4096;
+inline int sweep_blocks(long long n) {
+  const int b = nblocks(n);
+  return b < kSweepBlocks ? b : kSweepBlocks;
+}
+
+}  // namespace lbtp

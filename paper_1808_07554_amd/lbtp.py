@@ -1,0 +1,266 @@
+"""ctypes binding of liblbtp (include/lbtp.h).
+
+Argument marshalling only: every step of the method runs in the HIP
+library.  Device buffers come from torch (CUDA/HIP tensors); host arrays
+(numpy) are accepted too and copied by the library.  If liblbtp.so is not
+built, or there is no GPU, constructing a Solver raises at once.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbtp.so")
+
+D2Q5, D3Q7 = 0, 1
+FP32, FP16_DEV, BF16_DEV = 0, 1, 2
+BC_PERIODIC, BC_DIRICHLET, BC_NOFLUX, BC_OUTFLOW = 0, 1, 2, 3
+OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, EUNSTABLE, ESTATE = 0, 1, -1, -2, -3, -4, -5
+
+_BC = {"periodic": BC_PERIODIC, "abb": BC_DIRICHLET, "dirichlet": BC_DIRICHLET,
+       "bb": BC_NOFLUX, "noflux": BC_NOFLUX, "outflow": BC_OUTFLOW}
+_STORAGE = {"fp32": FP32, "fp16": FP16_DEV, "bf16": BF16_DEV}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("dx", ctypes.c_double), ("dt", ctypes.c_double),
+        ("beta", ctypes.c_double), ("Ds", ctypes.c_double),
+        ("mu_w", ctypes.c_double), ("mu_n", ctypes.c_double),
+        ("storage", ctypes.c_int),
+        ("residual_stride", ctypes.c_int),
+        ("bc_f", ctypes.c_int * 6), ("bc_P", ctypes.c_double * 6),
+        ("bc_g", ctypes.c_int * 6), ("bc_S", ctypes.c_double * 6),
+        ("init_neq", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+EXPORTS = {
+    "lbtp_default_params": (None, [ctypes.POINTER(Params)]),
+    "lbtp_init": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_void_p)]),
+    "lbtp_destroy": (None, [ctypes.c_void_p]),
+    "lbtp_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "lbtp_set_fields": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4 + [ctypes.c_int]),
+    "lbtp_set_sources": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 2 + [ctypes.c_int]),
+    "lbtp_set_state": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4 + [ctypes.c_int]),
+    "lbtp_update_coefficients": (ctypes.c_int, [ctypes.c_void_p]),
+    "lbtp_pressure_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_longlong,
+                                           ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]),
+    "lbtp_saturation_step": (ctypes.c_int, [ctypes.c_void_p]),
+    "lbtp_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_double, ctypes.c_longlong,
+                                 ctypes.c_void_p]),
+    "lbtp_pressure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "lbtp_velocity": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "lbtp_grad_p": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "lbtp_saturation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "lbtp_mass": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double)]),
+    "lbtp_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
+    "lbtp_put_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_longlong, ctypes.c_int]),
+    "lbtp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+_lib = None
+
+
+def load():
+    """Load liblbtp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_1808_07554_amd.build")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class LbtpError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: {load().lbtp_strerror(code).decode()} ({code})")
+
+
+def _check(code, what):
+    if code < 0:
+        raise LbtpError(code, what)
+    return code
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("liblbtp needs a HIP device; none is visible")
+    return torch
+
+
+class _Arg:
+    """A caller array as (pointer, on_device, keep-alive)."""
+
+    def __init__(self, a, n, torch=None):
+        if a is None:
+            self.ptr, self.dev, self.keep = None, 0, None
+            return
+        if torch is not None and isinstance(a, torch.Tensor):
+            if a.dtype != torch.float32:
+                a = a.float()
+            a = a.contiguous()
+            if a.numel() != n:
+                raise ValueError(f"expected {n} values, got {a.numel()}")
+            self.dev = 1 if a.is_cuda else 0
+            self.ptr, self.keep = a.data_ptr(), a
+        else:
+            h = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+            if h.size != n:
+                raise ValueError(f"expected {n} values, got {h.size}")
+            self.ptr, self.dev, self.keep = h.ctypes.data, 0, h
+
+
+class Solver:
+    """One realisation on the GPU.  Same calls as the C ABI.
+
+    bc_f / bc_g: per face (-x, +x, -y, +y[, -z, +z]) a tuple ("periodic",),
+    ("abb", value), ("bb",) or ("outflow",).
+    """
+
+    def __init__(self, lattice, shape, *, beta, Ds, mu_w, mu_n, bc_f, bc_g, dx=1.0, dt=1.0, m=64,
+                 storage="fp32", init_neq=True, stream=None, **_):
+        self.torch = _torch()
+        lib = load()
+        p = Params()
+        lib.lbtp_default_params(ctypes.byref(p))
+        p.lattice = D2Q5 if lattice == "D2Q5" else D3Q7
+        shape = tuple(shape) + (1,) * (3 - len(shape))
+        p.nx, p.ny, p.nz = shape
+        p.dx, p.dt, p.beta, p.Ds, p.mu_w, p.mu_n = dx, dt, beta, Ds, mu_w, mu_n
+        p.storage = _STORAGE[storage] if isinstance(storage, str) else storage
+        p.residual_stride = m
+        for f, b in enumerate(bc_f):
+            p.bc_f[f] = _BC[b[0]]
+            p.bc_P[f] = float(b[1]) if len(b) > 1 else 0.0
+        for f, b in enumerate(bc_g):
+            p.bc_g[f] = _BC[b[0]]
+            p.bc_S[f] = float(b[1]) if len(b) > 1 else 0.0
+        p.init_neq = 1 if init_neq else 0
+        if stream is None:
+            stream = self.torch.cuda.current_stream()
+        self.stream = stream
+        p.stream = stream.cuda_stream
+        self.params = p
+        self.dim = 2 if p.lattice == D2Q5 else 3
+        self.Q = 2 * self.dim + 1
+        self.shape = shape
+        self.ncell = shape[0] * shape[1] * shape[2]
+        h = ctypes.c_void_p()
+        _check(lib.lbtp_init(ctypes.byref(p), ctypes.byref(h)), "lbtp_init")
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.lbtp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- helpers
+    def _arg(self, a, n=None):
+        return _Arg(a, self.ncell if n is None else n, self.torch)
+
+    def _both(self, *args):
+        dev = {a.dev for a in args if a.ptr is not None}
+        if len(dev) > 1:
+            raise ValueError("mix of host and device arrays in one call")
+        return dev.pop() if dev else 0
+
+    def _empty(self, n):
+        return self.torch.empty(n, dtype=self.torch.float32, device="cuda")
+
+    def _fshape(self):
+        return (self.shape[2], self.shape[1], self.shape[0])
+
+    # ------------------------------------------------------------------ calls
+    def set_fields(self, K, phi, Fp=None, Fs=None):
+        a = [self._arg(x) for x in (K, phi, Fp, Fs)]
+        _check(self._lib.lbtp_set_fields(self._h, *(x.ptr for x in a), self._both(*a)), "lbtp_set_fields")
+
+    def set_sources(self, Fp=None, Fs=None):
+        a = [self._arg(x) for x in (Fp, Fs)]
+        _check(self._lib.lbtp_set_sources(self._h, *(x.ptr for x in a), self._both(*a)), "lbtp_set_sources")
+
+    def set_state(self, P0, S0, dP0=None, dS0=None):
+        a = [self._arg(P0), self._arg(S0), self._arg(dP0, self.dim * self.ncell),
+             self._arg(dS0, self.dim * self.ncell)]
+        _check(self._lib.lbtp_set_state(self._h, *(x.ptr for x in a), self._both(*a)), "lbtp_set_state")
+
+    def update_coefficients(self):
+        _check(self._lib.lbtp_update_coefficients(self._h), "lbtp_update_coefficients")
+
+    def pressure_solve(self, tol, max_iters):
+        it, r = ctypes.c_longlong(), ctypes.c_double()
+        st = _check(self._lib.lbtp_pressure_solve(self._h, tol, int(max_iters), ctypes.byref(it), ctypes.byref(r)),
+                    "lbtp_pressure_solve")
+        return it.value, r.value, st
+
+    def saturation_step(self):
+        _check(self._lib.lbtp_saturation_step(self._h), "lbtp_saturation_step")
+
+    def step(self, nsteps, tol, max_iters):
+        its = (ctypes.c_longlong * max(1, nsteps))()
+        st = _check(self._lib.lbtp_step(self._h, int(nsteps), tol, int(max_iters), ctypes.cast(its, ctypes.c_void_p)),
+                    "lbtp_step")
+        return list(its)[:nsteps], st
+
+    def _out(self, fn, ncomp, what):
+        t = self._empty(ncomp * self.ncell)
+        _check(fn(self._h, ctypes.c_void_p(t.data_ptr()), 1), what)
+        return t
+
+    def pressure(self):
+        return self._out(self._lib.lbtp_pressure, 1, "lbtp_pressure").view(self._fshape())
+
+    def saturation(self):
+        return self._out(self._lib.lbtp_saturation, 1, "lbtp_saturation").view(self._fshape())
+
+    def velocity(self):
+        return self._out(self._lib.lbtp_velocity, self.dim, "lbtp_velocity").view((self.dim,) + self._fshape())
+
+    def grad_p(self):
+        return self._out(self._lib.lbtp_grad_p, self.dim, "lbtp_grad_p").view((self.dim,) + self._fshape())
+
+    def mass(self):
+        m, l = ctypes.c_double(), ctypes.c_double()
+        _check(self._lib.lbtp_mass(self._h, ctypes.byref(m), ctypes.byref(l)), "lbtp_mass")
+        return m.value, l.value
+
+    def get_state(self):
+        f = self._empty((self.Q - 1) * self.ncell)
+        g = self._empty(self.Q * self.ncell)
+        st = ctypes.c_longlong()
+        _check(self._lib.lbtp_get_state(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                                        ctypes.byref(st), 1), "lbtp_get_state")
+        return f.view((self.Q - 1,) + self._fshape()), g.view((self.Q,) + self._fshape()), st.value
+
+    def put_state(self, f, g, step=0):
+        a = [self._arg(f, (self.Q - 1) * self.ncell), self._arg(g, self.Q * self.ncell)]
+        _check(self._lib.lbtp_put_state(self._h, a[0].ptr, a[1].ptr, int(step), self._both(*a)), "lbtp_put_state")
+
+
+def from_problem(params, **kw):
+    """Solver from a plain parameter dict (as produced by paper_1808_07554_amd.inputs)."""
+    d = dict(params)
+    d.update(kw)
+    return Solver(d.pop("lattice"), d.pop("shape"), **d)
