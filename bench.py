@@ -32,7 +32,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-F_SWEEP_BYTES_PER_CELL = {"D2Q5": 36, "D3Q7": 52}   # pops read + written + 1/tau_f read
+# algorithmic bytes of one plain pressure sweep per node: the Q-1 stored
+# deviations read and written, 1/tau_f and the base pressure P_b read
+POP_BYTES = {"fp32": 4, "fp16": 2, "bf16": 2}
+
+
+def f_sweep_bytes(lattice, storage):
+    q1 = 4 if lattice == "D2Q5" else 6
+    return 2 * q1 * POP_BYTES[storage] + 4 + 4
 KERNEL_SRC = os.path.join(ROOT, "paper_1808_07554_amd", "csrc", "lbtp_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "f_sweep_traffic_injection2d_4096.txt")
 
@@ -45,6 +52,7 @@ def parse():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--m", type=int, default=64)
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--max-iters", type=int, default=20_000_000)
     ap.add_argument("--burst", type=int, default=200, help="plain sweeps timed for the roofline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -111,7 +119,7 @@ def main():
     phi = torch.from_numpy(inputs.f32(fl["phi"]).ravel()).to(dev)
     P0 = torch.from_numpy(inputs.f32(fl["P0"]).ravel()).to(dev)
     S0 = torch.from_numpy(inputs.f32(fl["S0"]).ravel()).to(dev)
-    s = lbtp.from_problem(params, m=a.m)
+    s = lbtp.from_problem(params, m=a.m, storage=a.storage)
     s.set_fields(K, phi)
     s.set_state(P0, S0)
     del K, phi, P0, S0
@@ -172,7 +180,7 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     sweep_s = e0.elapsed_time(e1) / 1e3 / a.burst
-    alg_bytes = F_SWEEP_BYTES_PER_CELL[params["lattice"]] * ncell
+    alg_bytes = f_sweep_bytes(params["lattice"], a.storage) * ncell
     achieved = alg_bytes / sweep_s / 1e9
     traffic = measured_traffic(ncell)
 
@@ -187,10 +195,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if a.storage == "fp32" else f"f32 math, {a.storage} storage",
         "data": "synthetic",
         "config": {"workload": f"heterogeneous injection 2-D {a.n}x{a.n} (log-normal K sigma 1, corr. length 16)",
-                   "lattice": params["lattice"], "storage": "fp32", "tol": a.tol, "residual_stride": a.m,
+                   "lattice": params["lattice"], "storage": a.storage, "tol": a.tol, "residual_stride": a.m,
                    "cells": ncell},
         "s_per_coupled_step": t_run / a.steps,
         "iterations_per_step_mean": f_updates / a.steps,
@@ -200,7 +208,7 @@ def main():
         "cold_first_step_iterations": warm_its[0] if warm_its else None,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "f_sweep_kernel<2,false,0,false>", "avg_launch_us": round(sweep_s * 1e6, 2),
+                     "kernel": "f_sweep_kernel (plain sweep)", "avg_launch_us": round(sweep_s * 1e6, 2),
                      "bytes_per_launch": alg_bytes},
     }
     if not a.no_cpu:

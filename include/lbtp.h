@@ -57,10 +57,12 @@ typedef struct lbtp_ctx lbtp_ctx;
 
 enum lbtp_lattice { LBTP_D2Q5 = 0, LBTP_D3Q7 = 1 };
 
-/* Population storage.  FP32 stores f and g as float.  The *_DEV forms store
- * each population as a 16-bit deviation from a per-cell base equilibrium
- * (f_i - w_i P_b, g_i - g_i^eq(S_b)); collision arithmetic stays float32 and
- * the residual / mass reductions stay float64. */
+/* Storage of the pressure-lattice populations.  Every form stores the
+ * deviation of f_i from a per-node base equilibrium, f_i - w_i P_b, where P_b
+ * is the pressure at the start of the solve or at the last residual check;
+ * FP32 stores it as float, FP16_DEV as (power-of-two scaled) fp16, BF16_DEV
+ * as bf16.  Collision arithmetic is float32 in every form, the saturation
+ * lattice is float32, and the residual / mass reductions are float64. */
 enum lbtp_storage { LBTP_FP32 = 0, LBTP_FP16_DEV = 1, LBTP_BF16_DEV = 2 };
 
 /* Boundary condition of one face (faces ordered -x, +x, -y, +y, -z, +z).
@@ -177,11 +179,20 @@ LBTP_API int lbtp_saturation(lbtp_ctx *ctx, float *S, int on_device);
  * M^{n+1} = M^n + dt/2 sum(F_s^n + F_s^{n+1}) + flux_n. */
 LBTP_API int lbtp_mass(lbtp_ctx *ctx, double *mass, double *ledger);
 
-/* Checkpoint: pre-collision populations as float32, f as (Q-1) x ncell,
- * g as Q x ncell (population-major), plus the step counter.  put_state
- * restores them; a run resumed from a checkpoint is bitwise identical. */
-LBTP_API int lbtp_get_state(lbtp_ctx *ctx, float *f, float *g, long long *step, int on_device);
-LBTP_API int lbtp_put_state(lbtp_ctx *ctx, const float *f, const float *g, long long step, int on_device);
+/* Pre-collision populations of the current state as float32, population-
+ * major: f (Q-1) x ncell for i = 1..Q-1 (the rest population of f is not
+ * stored), g Q x ncell.  Either pointer may be NULL. */
+LBTP_API int lbtp_populations(lbtp_ctx *ctx, float *f, float *g, int on_device);
+
+/* Checkpoint of the full device state (raw stored populations in their
+ * storage type, the pressure base, g, step counter, mass ledger) as an opaque
+ * byte image of lbtp_checkpoint_size() bytes.  put_state needs a context with
+ * the same lattice, size and storage (LBTP_EINVAL otherwise) that has had
+ * lbtp_set_fields; a run resumed from a checkpoint is bitwise identical to
+ * the uninterrupted run. */
+LBTP_API long long lbtp_checkpoint_size(lbtp_ctx *ctx);
+LBTP_API int lbtp_get_state(lbtp_ctx *ctx, void *buf, long long nbytes, int on_device);
+LBTP_API int lbtp_put_state(lbtp_ctx *ctx, const void *buf, long long nbytes, int on_device);
 
 /* Static description of a status code. */
 LBTP_API const char *lbtp_strerror(int status);

@@ -22,13 +22,14 @@ struct lbtp_ctx {
   long long ncell = 0;
   hipStream_t stream = nullptr;
   KC kc;
-  float *fbuf[2] = {nullptr, nullptr};   // nf * ncell each
+  void *fbuf[2] = {nullptr, nullptr};    // nf * ncell deviations of the storage type each
   float *gbuf[2] = {nullptr, nullptr};   // Q * ncell each
-  int fs = 0, gs = 0;                    // index of the state buffer
+  float *Pb[2] = {nullptr, nullptr};     // base pressure of the f deviations
+  int fs = 0, gs = 0, pbs = 0;           // index of the state buffers
   int f_local = 1;                       // state buffer holds pre-collision values
   float *K = nullptr, *phi = nullptr, *Fp = nullptr, *Fs = nullptr;
   int has_Fp = 0, has_Fs = 0;
-  float *S = nullptr, *itau = nullptr, *Psnap = nullptr, *scratch = nullptr;
+  float *S = nullptr, *itau = nullptr, *scratch = nullptr;
   double *partials = nullptr;
   int nblk = 0;
   Ctl *ctl = nullptr;       // device
@@ -47,9 +48,10 @@ namespace {
     if (e_ != hipSuccess) return LBTP_EHIP; \
   } while (0)
 
-FPtrs fptrs(const lbtp_ctx *c, float *base) {
+FPtrs fptrs(const lbtp_ctx *c, void *base) {
   FPtrs r{};
-  for (int j = 0; j < c->nf; ++j) r.p[j] = base + (size_t)j * c->ncell;
+  const size_t es = storage_bytes(c->p.storage);
+  for (int j = 0; j < c->nf; ++j) r.p[j] = (char *)base + (size_t)j * c->ncell * es;
   return r;
 }
 GPtrs gptrs(const lbtp_ctx *c, float *base) {
@@ -72,7 +74,7 @@ int validate(const lbtp_params *p) {
   if ((long long)Q * n >= (1LL << 31)) return LBTP_EINVAL;   // 32-bit cell indexing
   if (!(p->dx > 0) || !(p->dt > 0) || !(p->beta > 0) || !(p->Ds > 0)) return LBTP_EINVAL;
   if (!(p->mu_w > 0) || !(p->mu_n > 0)) return LBTP_EINVAL;
-  if (p->storage != LBTP_FP32) return LBTP_EINVAL;
+  if (p->storage != LBTP_FP32 && p->storage != LBTP_FP16_DEV && p->storage != LBTP_BF16_DEV) return LBTP_EINVAL;
   if (p->residual_stride < 1) return LBTP_EINVAL;
   const int dim = p->lattice == LBTP_D2Q5 ? 2 : 3;
   const double c = p->dx / p->dt;
@@ -123,11 +125,13 @@ void fill_kc(lbtp_ctx *c) {
   k.geq0_phi = (float)((w0 - 1.0) * p.beta);
   k.w1beta = (float)(w1 * p.beta);
   k.half_dt = (float)(0.5 * p.dt);
+  k.dev_scale = 1.0f;
+  k.inv_dev_scale = 1.0f;
   for (int f = 0; f < 6; ++f) {
     const bool used = f < 2 * c->dim;
     k.bc_f[f] = used ? p.bc_f[f] : LBTP_BC_PERIODIC;
     k.bc_g[f] = used ? p.bc_g[f] : LBTP_BC_PERIODIC;
-    k.abbP[f] = (float)(2.0 * w1 * p.bc_P[f]);
+    k.Pw[f] = (float)p.bc_P[f];
     k.abbS[f] = (float)(2.0 * w1 * p.beta * p.bc_S[f]);
   }
 }
@@ -234,9 +238,9 @@ const char *lbtp_strerror(int s) {
 
 void lbtp_destroy(lbtp_ctx *c) {
   if (!c) return;
-  float *bufs[] = {c->fbuf[0], c->fbuf[1], c->gbuf[0], c->gbuf[1], c->K, c->phi, c->Fp, c->Fs,
-                   c->S, c->itau, c->Psnap, c->scratch};
-  for (float *b : bufs)
+  void *bufs[] = {c->fbuf[0], c->fbuf[1], c->gbuf[0], c->gbuf[1], c->Pb[0], c->Pb[1], c->K, c->phi,
+                  c->Fp, c->Fs, c->S, c->itau, c->scratch};
+  for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (c->partials) (void)hipFree(c->partials);
   if (c->ctl) (void)hipFree(c->ctl);
@@ -262,15 +266,25 @@ int lbtp_init(const lbtp_params *p, lbtp_ctx **out) {
   c->nblk = nblocks(c->ncell);
   fill_kc(c);
   const size_t n = (size_t)c->ncell;
+  const size_t fbytes = n * c->nf * storage_bytes(p->storage);
   struct {
-    float **ptr;
-    size_t count;
-  } allocs[] = {{&c->fbuf[0], n * c->nf}, {&c->fbuf[1], n * c->nf}, {&c->gbuf[0], n * c->Q},
-                {&c->gbuf[1], n * c->Q},  {&c->K, n},               {&c->phi, n},
-                {&c->Fp, n},              {&c->Fs, n},              {&c->S, n},
-                {&c->itau, n},            {&c->Psnap, n},           {&c->scratch, n * 3}};
+    void **ptr;
+    size_t bytes;
+  } allocs[] = {{&c->fbuf[0], fbytes},
+                {&c->fbuf[1], fbytes},
+                {(void **)&c->gbuf[0], n * c->Q * 4},
+                {(void **)&c->gbuf[1], n * c->Q * 4},
+                {(void **)&c->Pb[0], n * 4},
+                {(void **)&c->Pb[1], n * 4},
+                {(void **)&c->K, n * 4},
+                {(void **)&c->phi, n * 4},
+                {(void **)&c->Fp, n * 4},
+                {(void **)&c->Fs, n * 4},
+                {(void **)&c->S, n * 4},
+                {(void **)&c->itau, n * 4},
+                {(void **)&c->scratch, n * 3 * 4}};
   for (auto &a : allocs) {
-    if (hipMalloc((void **)a.ptr, a.count * sizeof(float)) != hipSuccess) {
+    if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {
       lbtp_destroy(c);
       return LBTP_ENOMEM;
     }
@@ -346,8 +360,25 @@ int lbtp_set_state(lbtp_ctx *c, const float *P0, const float *S0, const float *d
   if (!c || !P0 || !S0) return LBTP_EINVAL;
   if (!c->have_fields) return LBTP_ESTATE;
   const size_t n = (size_t)c->ncell;
-  // stage P0 in Psnap, S0 in S, gradients in scratch (dP0) and the second f buffer (dS0)
-  int rc = upload(c, c->Psnap, P0, n, on_device);
+  if (c->p.storage == LBTP_FP16_DEV) {
+    // fp16 deviations are scaled so that w_1 max|P| maps to about 1024: the
+    // deviations (at most a few w_1 |P|) stay below the fp16 maximum and the
+    // typical ones stay out of the subnormal range
+    std::vector<float> h;
+    int rc = fetch_host(c, P0, on_device, h);
+    if (rc) return rc;
+    double pmax = 0.0;
+    for (float v : h) pmax = fmax(pmax, fabs((double)v));
+    for (int f = 0; f < 2 * c->dim; ++f)
+      if (c->p.bc_f[f] == LBTP_BC_DIRICHLET) pmax = fmax(pmax, fabs(c->p.bc_P[f]));
+    if (!(pmax > 0.0) || !isfinite(pmax)) pmax = 1.0;
+    const int e2 = (int)floor(log2(1024.0 / (weight_move(c->p.lattice) * pmax)));
+    c->kc.dev_scale = (float)ldexp(1.0, e2 < -60 ? -60 : (e2 > 60 ? 60 : e2));
+    c->kc.inv_dev_scale = 1.0f / c->kc.dev_scale;
+  }
+  // stage P0 in the second base buffer, S0 in S, dP0 in scratch and dS0 in
+  // the second f buffer (at least dim floats per node for every storage)
+  int rc = upload(c, c->Pb[1], P0, n, on_device);
   if (rc) return rc;
   rc = upload(c, c->S, S0, n, on_device);
   if (rc) return rc;
@@ -358,14 +389,15 @@ int lbtp_set_state(lbtp_ctx *c, const float *P0, const float *S0, const float *d
     dP = c->scratch;
   }
   if (dS0) {
-    rc = upload(c, c->fbuf[1], dS0, n * c->dim, on_device);
+    rc = upload(c, (float *)c->fbuf[1], dS0, n * c->dim, on_device);
     if (rc) return rc;
-    dS = c->fbuf[1];
+    dS = (const float *)c->fbuf[1];
   }
-  HIP_TRY(launch_init(c->dim, c->kc, c->Psnap, c->S, dP, dS, c->K, c->phi, Fs_or_null(c), c->p.init_neq,
-                      fptrs(c, c->fbuf[0]), gptrs(c, c->gbuf[0]), c->stream));
+  HIP_TRY(launch_init(c->dim, c->p.storage, c->kc, c->Pb[1], c->S, dP, dS, c->K, c->phi, Fs_or_null(c),
+                      c->p.init_neq, fptrs(c, c->fbuf[0]), c->Pb[0], gptrs(c, c->gbuf[0]), c->stream));
   c->fs = 0;
   c->gs = 0;
+  c->pbs = 0;
   c->f_local = 1;
   c->step = 0;
   c->ctl_host->ledger = 0.0;
@@ -397,14 +429,21 @@ int lbtp_pressure_solve(lbtp_ctx *c, double tol, long long max_iters, long long 
   // max_iters handle the snapshot and the stopping rule.
   long long last = max_iters - 1;   // last sweep whose output is needed
   if (checks) last = (max_iters / m) * m > last ? (max_iters / m) * m : last;
+  // Sweep k reads the deviations of buffer (fs + k) & 1 against base pb and
+  // writes the other buffer.  Sweep 0 and every sweep with k % m == 0 reset
+  // the base to the current P (writing the other base buffer); with checks on,
+  // those with k > 0 also evaluate the stopping rule.
+  int pb = c->pbs;
   auto sweep = [&](long long k) -> hipError_t {
     const int parity = (int)((c->fs + k) & 1);
-    const int snap = !checks ? 0 : (k % m != 0 ? 0 : (k == 0 ? 1 : 2));
+    const int mode = (k % m != 0) ? 0 : ((k == 0 || !checks) ? 1 : 2);
     const int local = (k == 0) && c->f_local;
-    hipError_t e = launch_f_sweep(c->dim, c->kc, fptrs(c, c->fbuf[parity]), fptrs(c, c->fbuf[parity ^ 1]),
-                                  c->itau, Fp_or_null(c), c->Psnap, c->partials, c->ctl, k, local, snap, c->stream);
-    if (e == hipSuccess && snap == 2)
-      e = launch_finish_residual(c->partials, sweep_blocks(c->ncell), c->ctl, k, m, c->stream);
+    hipError_t e = launch_f_sweep(c->dim, c->p.storage, c->kc, fptrs(c, c->fbuf[parity]),
+                                  fptrs(c, c->fbuf[parity ^ 1]), c->Pb[pb], c->Pb[pb ^ 1], c->itau,
+                                  Fp_or_null(c), c->partials, c->ctl, k, local, mode, c->stream);
+    if (e == hipSuccess && mode == 2)
+      e = launch_finish_residual(c->partials, sweep_blocks(c->kc, local), c->ctl, k, m, c->stream);
+    if (mode >= 1) pb ^= 1;
     return e;
   };
   // Chunk 0 is sweep 0 (snapshot of P^0); chunk j >= 1 is sweeps
@@ -451,7 +490,11 @@ int lbtp_pressure_solve(lbtp_ctx *c, double tol, long long max_iters, long long 
     status = checks ? LBTP_NOT_CONVERGED : LBTP_OK;
   }
   if (K > 0) {
+    // the state is the buffer sweep K read, against the base sweep K read:
+    // sweeps 0 and k % m == 0 (k < K) reset the base
+    const long long flips = 1 + (K - 1) / m;
     c->fs = (int)((c->fs + K) & 1);
+    c->pbs = (int)((c->pbs + flips) & 1);
     c->f_local = 0;
   }
   if (iters) *iters = K;
@@ -463,9 +506,9 @@ int lbtp_pressure_solve(lbtp_ctx *c, double tol, long long max_iters, long long 
 int lbtp_saturation_step(lbtp_ctx *c) {
   if (!c) return LBTP_EINVAL;
   if (!c->have_coef) return LBTP_ESTATE;
-  HIP_TRY(launch_g_sweep(c->dim, c->kc, gptrs(c, c->gbuf[c->gs]), gptrs(c, c->gbuf[c->gs ^ 1]),
-                         fptrs(c, c->fbuf[c->fs]), c->f_local, c->itau, c->K, c->phi, Fs_or_null(c), c->partials,
-                         c->stream));
+  HIP_TRY(launch_g_sweep(c->dim, c->p.storage, c->kc, gptrs(c, c->gbuf[c->gs]), gptrs(c, c->gbuf[c->gs ^ 1]),
+                         fptrs(c, c->fbuf[c->fs]), c->f_local, c->Pb[c->pbs], c->itau, c->K, c->phi, Fs_or_null(c),
+                         c->partials, c->stream));
   HIP_TRY(launch_finish_sum(c->partials, c->nblk, &c->ctl->ledger, 1, &c->ctl->last_flux, c->stream));
   c->gs ^= 1;
   c->step += 1;
@@ -494,7 +537,8 @@ int lbtp_step(lbtp_ctx *c, long long nsteps, double tol, long long max_iters, lo
 int lbtp_pressure(lbtp_ctx *c, float *P, int on_device) {
   if (!c || !P) return LBTP_EINVAL;
   if (!c->have_state) return LBTP_ESTATE;
-  HIP_TRY(launch_pressure(c->dim, c->kc, fptrs(c, c->fbuf[c->fs]), c->f_local, c->scratch, c->stream));
+  HIP_TRY(launch_pressure(c->dim, c->p.storage, c->kc, fptrs(c, c->fbuf[c->fs]), c->f_local, c->Pb[c->pbs],
+                          c->scratch, c->stream));
   return download(c, P, c->scratch, c->ncell, on_device);
 }
 
@@ -506,8 +550,8 @@ static int grad_common(lbtp_ctx *c, float *out, int on_device, int velocity) {
     int rc = lbtp_update_coefficients(c);
     if (rc) return rc;
   }
-  HIP_TRY(launch_grad(c->dim, c->kc, fptrs(c, c->fbuf[c->fs]), c->f_local, c->itau, c->K, c->S, velocity,
-                      c->scratch, c->stream));
+  HIP_TRY(launch_grad(c->dim, c->p.storage, c->kc, fptrs(c, c->fbuf[c->fs]), c->f_local, c->Pb[c->pbs], c->itau,
+                      c->K, c->S, velocity, c->scratch, c->stream));
   return download(c, out, c->scratch, (size_t)c->ncell * c->dim, on_device);
 }
 
@@ -536,48 +580,127 @@ int lbtp_mass(lbtp_ctx *c, double *mass, double *ledger) {
   return LBTP_OK;
 }
 
-int lbtp_get_state(lbtp_ctx *c, float *f, float *g, long long *step, int on_device) {
+int lbtp_populations(lbtp_ctx *c, float *f, float *g, int on_device) {
   if (!c) return LBTP_EINVAL;
   if (!c->have_state) return LBTP_ESTATE;
   const size_t n = (size_t)c->ncell;
   if (f) {
-    // materialise the pre-collision f into the other buffer's space is not
-    // allowed (it may be needed); use the caller buffer directly when it is
-    // on the device, else a staging copy through scratch one population at a time
-    if (on_device) {
-      HIP_TRY(launch_materialize_f(c->dim, c->kc, fptrs(c, c->fbuf[c->fs]), c->f_local, fptrs(c, f), c->stream));
-      HIP_TRY(hipStreamSynchronize(c->stream));
-    } else {
-      float *tmp = nullptr;
-      if (hipMalloc((void **)&tmp, n * c->nf * sizeof(float)) != hipSuccess) return LBTP_ENOMEM;
-      hipError_t e = launch_materialize_f(c->dim, c->kc, fptrs(c, c->fbuf[c->fs]), c->f_local, fptrs(c, tmp), c->stream);
-      if (e == hipSuccess) e = hipMemcpyAsync(f, tmp, n * c->nf * sizeof(float), hipMemcpyDeviceToHost, c->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-      (void)hipFree(tmp);
-      if (e != hipSuccess) return LBTP_EHIP;
-    }
+    float *dst = f;
+    if (!on_device && hipMalloc((void **)&dst, n * c->nf * sizeof(float)) != hipSuccess) return LBTP_ENOMEM;
+    hipError_t e = launch_populations(c->dim, c->p.storage, c->kc, fptrs(c, c->fbuf[c->fs]), c->f_local,
+                                      c->Pb[c->pbs], dst, c->stream);
+    if (e == hipSuccess && !on_device)
+      e = hipMemcpyAsync(f, dst, n * c->nf * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (!on_device) (void)hipFree(dst);
+    if (e != hipSuccess) return LBTP_EHIP;
   }
   if (g) {
     int rc = download(c, g, c->gbuf[c->gs], n * c->Q, on_device);
     if (rc) return rc;
   }
-  if (step) *step = c->step;
   return LBTP_OK;
 }
 
-int lbtp_put_state(lbtp_ctx *c, const float *f, const float *g, long long step, int on_device) {
-  if (!c || !f || !g) return LBTP_EINVAL;
-  if (!c->have_fields) return LBTP_ESTATE;
+namespace {
+struct CkptHeader {
+  uint32_t magic, version;
+  int32_t lattice, nx, ny, nz, storage, f_local;
+  int64_t step;
+  double ledger;
+  float dev_scale, inv_dev_scale;
+};
+constexpr uint32_t kCkptMagic = 0x5054424Cu;   // "LBTP"
+
+size_t ckpt_parts(const lbtp_ctx *c, size_t *fb, size_t *pb, size_t *gb) {
   const size_t n = (size_t)c->ncell;
-  int rc = upload(c, c->fbuf[0], f, n * c->nf, on_device);
+  *fb = n * c->nf * storage_bytes(c->p.storage);
+  *pb = n * sizeof(float);
+  *gb = n * c->Q * sizeof(float);
+  return sizeof(CkptHeader) + *fb + *pb + *gb;
+}
+
+int copy_bytes(lbtp_ctx *c, void *dst, const void *src, size_t bytes, hipMemcpyKind kind) {
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, kind, c->stream));
+  return LBTP_OK;
+}
+}  // namespace
+
+long long lbtp_checkpoint_size(lbtp_ctx *c) {
+  if (!c) return LBTP_EINVAL;
+  size_t fb, pb, gb;
+  return (long long)ckpt_parts(c, &fb, &pb, &gb);
+}
+
+int lbtp_get_state(lbtp_ctx *c, void *buf, long long nbytes, int on_device) {
+  if (!c || !buf) return LBTP_EINVAL;
+  if (!c->have_state) return LBTP_ESTATE;
+  size_t fb, pb, gb;
+  if (nbytes < (long long)ckpt_parts(c, &fb, &pb, &gb)) return LBTP_EINVAL;
+  int rc = read_ctl(c);
   if (rc) return rc;
-  rc = upload(c, c->gbuf[0], g, n * c->Q, on_device);
-  if (rc) return rc;
+  CkptHeader h{};
+  h.magic = kCkptMagic;
+  h.version = 1;
+  h.lattice = c->p.lattice;
+  h.nx = c->p.nx;
+  h.ny = c->p.ny;
+  h.nz = c->p.nz;
+  h.storage = c->p.storage;
+  h.f_local = c->f_local;
+  h.step = c->step;
+  h.ledger = c->ctl_host->ledger;
+  h.dev_scale = c->kc.dev_scale;
+  h.inv_dev_scale = c->kc.inv_dev_scale;
+  char *out = (char *)buf;
+  const hipMemcpyKind d2x = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (on_device) {
+    rc = copy_bytes(c, out, &h, sizeof(h), hipMemcpyHostToDevice);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  } else {
+    memcpy(out, &h, sizeof(h));
+  }
+  out += sizeof(h);
+  if ((rc = copy_bytes(c, out, c->fbuf[c->fs], fb, d2x))) return rc;
+  if ((rc = copy_bytes(c, out + fb, c->Pb[c->pbs], pb, d2x))) return rc;
+  if ((rc = copy_bytes(c, out + fb + pb, c->gbuf[c->gs], gb, d2x))) return rc;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBTP_OK;
+}
+
+int lbtp_put_state(lbtp_ctx *c, const void *buf, long long nbytes, int on_device) {
+  if (!c || !buf) return LBTP_EINVAL;
+  if (!c->have_fields) return LBTP_ESTATE;
+  size_t fb, pb, gb;
+  if (nbytes < (long long)ckpt_parts(c, &fb, &pb, &gb)) return LBTP_EINVAL;
+  CkptHeader h;
+  const char *in = (const char *)buf;
+  if (on_device) {
+    HIP_TRY(hipMemcpyAsync(&h, in, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  } else {
+    memcpy(&h, in, sizeof(h));
+  }
+  if (h.magic != kCkptMagic || h.version != 1 || h.lattice != c->p.lattice || h.nx != c->p.nx ||
+      h.ny != c->p.ny || h.nz != c->p.nz || h.storage != c->p.storage)
+    return LBTP_EINVAL;
+  in += sizeof(h);
+  const hipMemcpyKind x2d = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  int rc;
+  if ((rc = copy_bytes(c, c->fbuf[0], in, fb, x2d))) return rc;
+  if ((rc = copy_bytes(c, c->Pb[0], in + fb, pb, x2d))) return rc;
+  if ((rc = copy_bytes(c, c->gbuf[0], in + fb + pb, gb, x2d))) return rc;
+  c->ctl_host->ledger = h.ledger;
+  if ((rc = copy_bytes(c, &c->ctl->ledger, &c->ctl_host->ledger, sizeof(double), hipMemcpyHostToDevice))) return rc;
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->fs = 0;
   c->gs = 0;
-  c->f_local = 1;
-  c->step = step;
+  c->pbs = 0;
+  c->f_local = h.f_local;
+  c->step = h.step;
+  c->kc.dev_scale = h.dev_scale;
+  c->kc.inv_dev_scale = h.inv_dev_scale;
   c->have_state = 1;
   c->have_coef = 0;
   return LBTP_OK;

@@ -34,8 +34,10 @@ struct KC {
   float geq0_phi;   // (w0 - 1) beta: g_0^eq = (geq0_phi + phi) S
   float w1beta;     // w1 beta: g_i^eq = w1 beta S
   float half_dt;    // dt / 2
+  float dev_scale;      // storage scale of 16-bit float deviations (a power of two)
+  float inv_dev_scale;  // its inverse
   int bc_f[6];
-  float abbP[6];    // 2 w1 P_b of a Dirichlet pressure face
+  float Pw[6];      // Dirichlet pressure of a face
   int bc_g[6];
   float abbS[6];    // 2 w1 beta S_b of a Dirichlet saturation face
 };
@@ -57,12 +59,12 @@ struct Ctl {
 // ----------------------------------------------------------------- launchers
 // Each returns the hipError_t of the launch.  Pointer arrays hold one base
 // pointer per stored population.
-struct FPtrs { float *p[6]; };
+struct FPtrs { void *p[6]; };
 struct GPtrs { float *p[7]; };
 
-hipError_t launch_f_sweep(int dim, const KC &kc, FPtrs fin, FPtrs fout, const float *itau,
-                          const float *Fp, float *Psnap, double *partials, const Ctl *ctl,
-                          long long k, int local, int snap, hipStream_t s);
+hipError_t launch_f_sweep(int dim, int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb_in,
+                          float *Pb_out, const float *itau, const float *Fp, double *partials, const Ctl *ctl,
+                          long long k, int local, int mode, hipStream_t s);
 hipError_t launch_finish_residual(const double *partials, int nblk, Ctl *ctl, long long k, int m,
                                   hipStream_t s);
 hipError_t launch_ctl_reset(Ctl *ctl, long long kmax, double tol, hipStream_t s);
@@ -71,29 +73,31 @@ hipError_t launch_moments(int dim, const KC &kc, GPtrs g, const float *K, const 
                           hipStream_t s);
 hipError_t launch_finish_sum(const double *partials, int nblk, double *dst, int accumulate,
                              double *copy_to, hipStream_t s);
-hipError_t launch_g_sweep(int dim, const KC &kc, GPtrs gin, GPtrs gout, FPtrs f, int f_local,
-                          const float *itau, const float *K, const float *phi, const float *Fs,
-                          double *partials, hipStream_t s);
-hipError_t launch_init(int dim, const KC &kc, const float *P0, const float *S0, const float *dP0,
-                       const float *dS0, const float *K, const float *phi, const float *Fs,
-                       int neq, FPtrs f, GPtrs g, hipStream_t s);
-hipError_t launch_pressure(int dim, const KC &kc, FPtrs f, int f_local, float *P, hipStream_t s);
-hipError_t launch_grad(int dim, const KC &kc, FPtrs f, int f_local, const float *itau,
-                       const float *K, const float *S, int velocity, float *out, hipStream_t s);
+hipError_t launch_g_sweep(int dim, int storage, const KC &kc, GPtrs gin, GPtrs gout, FPtrs f, int f_local,
+                          const float *Pb, const float *itau, const float *K, const float *phi,
+                          const float *Fs, double *partials, hipStream_t s);
+hipError_t launch_init(int dim, int storage, const KC &kc, const float *P0, const float *S0, const float *dP0,
+                       const float *dS0, const float *K, const float *phi, const float *Fs, int neq, FPtrs f,
+                       float *Pb, GPtrs g, hipStream_t s);
+hipError_t launch_pressure(int dim, int storage, const KC &kc, FPtrs f, int f_local, const float *Pb, float *P,
+                           hipStream_t s);
+hipError_t launch_grad(int dim, int storage, const KC &kc, FPtrs f, int f_local, const float *Pb,
+                       const float *itau, const float *K, const float *S, int velocity, float *out,
+                       hipStream_t s);
 hipError_t launch_saturation(int dim, const KC &kc, GPtrs g, const float *phi, const float *Fs,
                              float *S, hipStream_t s);
-hipError_t launch_materialize_f(int dim, const KC &kc, FPtrs fin, int f_local, FPtrs fout,
-                                hipStream_t s);
+hipError_t launch_populations(int dim, int storage, const KC &kc, FPtrs f, int f_local, const float *Pb,
+                              float *out, hipStream_t s);
+
+inline size_t storage_bytes(int storage) { return storage == LBTP_FP32 ? 4 : 2; }
+
+inline int nblocks(long long n);
+// Blocks of a pull-form pressure sweep (and so its residual partials): rows
+// with nx % 4 == 0 run four nodes per thread.
+inline int sweep_blocks(const KC &kc, int local) {
+  return (!local && kc.nx % 4 == 0) ? nblocks(kc.ncell / 4) : nblocks(kc.ncell);
+}
 
 inline int nblocks(long long n) { return (int)((n + kThreads - 1) / kThreads); }
-
-// Grid of the pressure sweep: a grid-stride loop over at most kSweepBlocks
-// blocks (256 CUs x 16 resident blocks), so that a sweep queued behind a
-// converged solve costs one short dispatch.
-constexpr int kSweepBlocks = 4096;
-inline int sweep_blocks(long long n) {
-  const int b = nblocks(n);
-  return b < kSweepBlocks ? b : kSweepBlocks;
-}
 
 }  // namespace lbtp

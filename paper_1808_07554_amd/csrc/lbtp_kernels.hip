@@ -1,21 +1,40 @@
 // HIP kernels (gfx950) of the double-distribution lattice Boltzmann model
 // (Chai, Liang, Du, Shi, arXiv:1808.07554) on D2Q5 / D3Q7.
 //
-// Data layout: structure of arrays, one float32 array per population and per
-// scalar field, x fastest (index = x + nx*(y + ny*z)).  The pressure lattice
-// is a two-buffer ping-pong in "pull" form: the buffer holds post-collision
-// values f_i^+ of the previous sweep, and a sweep at node x reads
-// f_i^+(x - c_i) (streaming, eq. 3-1) or, where x - c_i lies beyond a wall,
-// the Section 4 rule: -f_opp^+(x) + 2 w P_b (anti-bounce-back) or f_opp^+(x)
-// (bounce-back).  Right after initialisation the buffer instead holds
-// pre-collision values read in place ("local" form).  The saturation lattice
-// keeps pre-collision g and pushes post-collision values to the neighbours.
+// Data layout: structure of arrays, one array per population and per scalar
+// field, x fastest (index = x + nx*(y + ny*z)).
 //
-// Every cell kernel runs one thread per node, kThreads per block; all
-// reductions are float64, first per wavefront (shuffles), then per block
-// (LDS), then over blocks by a single-block finishing kernel in a fixed
-// order, so every result is deterministic.
+// Pressure lattice.  Populations are kept as deviations from a per-node base
+// equilibrium, d_i(x) = f_i(x) - w_i P_b(x), stored as float, fp16 or bf16
+// (type T) in a two-buffer ping-pong in "pull" form: the buffer holds the
+// post-collision deviations of the previous sweep, and a sweep at node y
+// reads d_i(y - c_i) (streaming, eq. 3-1), re-expressed against its own
+// base:  e_i(y) = f_i(y) - w_i P_b(y) = d_i(y - c_i) + w_i (P_b(y - c_i) - P_b(y)).
+// Where y - c_i lies beyond a wall the Section 4 rules apply:
+//   anti-bounce-back f_i = -f_opp^+ + 2 w P_w  ->  e_i = -d_opp(y) + 2 w (P_w - P_b(y)),
+//   bounce-back      f_i =  f_opp^+            ->  e_i =  d_opp(y).
+// With w_0 + sum_{i>=1} w_i = 1 the moment eq. 3-9a becomes
+// P - P_b = sum_i e_i / (1 - w_0), and the BGK collision (eq. 2-1b a) acts on
+// the deviations unchanged: e_i^+ = e_i + (w_i (P - P_b) - e_i) / tau_f.
+// Every quantity the sweep rounds is therefore of the size of the
+// non-equilibrium part, not of P.  The base is reset to the current P at the
+// first sweep of a solve and at every residual check (re-basing shifts the
+// stored deviations by w (P_b,old - P_b,new), an exact difference), so the
+// stopping-rule numerator P^k - P^{k-m} is the deviation itself.
+// Right after initialisation the buffer holds pre-collision deviations read
+// in place ("local" form).  The rest population of f never affects an output
+// and is not stored.
+//
+// Saturation lattice: float pre-collision g, pushed to x + c_i after the
+// collision (eq. 3-2).
+//
+// Cell kernels run one thread per node, kThreads per block; reductions are
+// float64, per wavefront (shuffles), per block (LDS), then over blocks in a
+// fixed order by a single-block kernel, so every result is deterministic.
 #include <math.h>
+#include <stdint.h>
+
+#include <type_traits>
 
 #include "lbtp_internal.h"
 
@@ -40,47 +59,100 @@ __device__ inline int coord(const Cell &q, int a) { return a == 0 ? q.x : (a == 
 __device__ inline int extent(const KC &kc, int a) { return a == 0 ? kc.nx : (a == 1 ? kc.ny : kc.nz); }
 __device__ inline int stride_of(const KC &kc, int a) { return a == 0 ? 1 : (a == 1 ? kc.nx : kc.nx * kc.ny); }
 
-// Pre-collision f_j at node q (moving directions only).
-template <int DIM, bool LOCAL>
-__device__ inline void load_f(const FPtrs &fin, const Cell &q, const KC &kc, float *f) {
+// ------------------------------------------------------------ storage types
+// bf16 is kept as raw 16-bit words (round to nearest even on store).
+struct bf16_t {
+  uint16_t u;
+};
+
+template <typename T>
+struct Storage;
+
+template <>
+struct Storage<float> {
+  static __device__ inline float load(const float *p, int i, float) { return p[i]; }
+  static __device__ inline void store(float *p, int i, float v, float) { p[i] = v; }
+};
+
+// fp16 values are scaled by a power of two (kc.dev_scale) to keep the
+// deviations in the normal range.
+template <>
+struct Storage<_Float16> {
+  static __device__ inline float load(const _Float16 *p, int i, float inv_s) { return (float)p[i] * inv_s; }
+  static __device__ inline void store(_Float16 *p, int i, float v, float s) { p[i] = (_Float16)(v * s); }
+};
+
+template <>
+struct Storage<bf16_t> {
+  static __device__ inline float load(const bf16_t *p, int i, float) {
+    return __uint_as_float((uint32_t)p[i].u << 16);
+  }
+  static __device__ inline void store(bf16_t *p, int i, float v, float) {
+    const uint32_t u = __float_as_uint(v);
+    const uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
+    bf16_t b;
+    b.u = (uint16_t)(r >> 16);
+    p[i] = b;
+  }
+};
+
+template <typename T>
+struct FP {
+  T *p[6];
+};
+
+template <typename T>
+__host__ __device__ inline FP<T> typed(const FPtrs &f) {
+  FP<T> r;
+  for (int j = 0; j < 6; ++j) r.p[j] = (T *)f.p[j];
+  return r;
+}
+
+// Pre-collision deviations e_j at node q (moving directions) against P_b(q).
+template <int DIM, typename T, bool LOCAL>
+__device__ inline void load_e(const FP<T> &fin, const float *__restrict__ Pb, const Cell &q, const KC &kc,
+                              float pb, float *e) {
 #pragma unroll
   for (int j = 0; j < 2 * DIM; ++j) {
     if (LOCAL) {
-      f[j] = fin.p[j][q.c];
+      e[j] = Storage<T>::load(fin.p[j], q.c, kc.inv_dev_scale);
       continue;
     }
     const int a = dir_axis(j), s = dir_sign(j);
     const int x = coord(q, a), n = extent(kc, a), st = stride_of(kc, a);
     const bool out = (s > 0) ? (x == 0) : (x == n - 1);
     if (!out) {
-      f[j] = fin.p[j][q.c - s * st];
+      const int src = q.c - s * st;
+      e[j] = Storage<T>::load(fin.p[j], src, kc.inv_dev_scale) + kc.w1 * (Pb[src] - pb);
     } else {
       const int face = 2 * a + (s > 0 ? 0 : 1);
       const int bc = kc.bc_f[face];
       if (bc == LBTP_BC_PERIODIC) {
-        f[j] = fin.p[j][q.c - s * st + s * n * st];
+        const int src = q.c - s * st + s * n * st;
+        e[j] = Storage<T>::load(fin.p[j], src, kc.inv_dev_scale) + kc.w1 * (Pb[src] - pb);
       } else {
-        const float o = fin.p[dir_opp(j)][q.c];
-        f[j] = (bc == LBTP_BC_DIRICHLET) ? (kc.abbP[face] - o) : o;
+        const float o = Storage<T>::load(fin.p[dir_opp(j)], q.c, kc.inv_dev_scale);
+        e[j] = (bc == LBTP_BC_DIRICHLET) ? (2.0f * kc.w1 * (kc.Pw[face] - pb) - o) : o;
       }
     }
   }
 }
 
+// P - P_b from the deviations (eq. 3-9a).
 template <int DIM>
-__device__ inline float moment_p(const float *f, const KC &kc) {
-  float s = f[0];
+__device__ inline float dpressure(const float *e, const KC &kc) {
+  float s = e[0];
 #pragma unroll
-  for (int j = 1; j < 2 * DIM; ++j) s += f[j];
-  return s * kc.inv_1mw0;   // eq. 3-9a
+  for (int j = 1; j < 2 * DIM; ++j) s += e[j];
+  return s * kc.inv_1mw0;
 }
 
-// First moment sum_i c_i f_i along each axis.
+// First moment sum_i c_i f_i = sum_i c_i e_i along each axis (the base part cancels).
 template <int DIM>
-__device__ inline void moment_c(const float *f, const KC &kc, float *m1) {
-  m1[0] = kc.c * (f[0] - f[2]);
-  m1[1] = kc.c * (f[1] - f[3]);
-  if (DIM == 3) m1[2] = kc.c * (f[4] - f[5]);
+__device__ inline void moment_c(const float *e, const KC &kc, float *m1) {
+  m1[0] = kc.c * (e[0] - e[2]);
+  m1[1] = kc.c * (e[1] - e[3]);
+  if (DIM == 3) m1[2] = kc.c * (e[4] - e[5]);
 }
 
 template <int DIM>
@@ -133,43 +205,273 @@ __device__ inline void block_sum(double *v, double *out) {
 }
 
 // ------------------------------------------------------------- pressure sweep
-// One iteration of eq. 3-1: read (stream) f, P (eq. 3-9a), BGK collision with
-// the local 1/tau_f (eq. 2-1b a), write f^+ in place of node x.
-// SNAP: 0 nothing, 1 store P in the snapshot, 2 also accumulate
-// sum (P - P_snap)^2 and sum P^2 for the stopping rule.
-template <int DIM, bool LOCAL, int SNAP, bool HAS_FP>
-__global__ __launch_bounds__(kThreads) void f_sweep_kernel(KC kc, FPtrs fin, FPtrs fout,
+// One iteration of eq. 3-1: stream, P (eq. 3-9a), BGK collision with the local
+// 1/tau_f (eq. 2-1b a) and the source dt wbar_i F_p, store at node y.
+// MODE 0: plain; 1: also reset the base to P (first sweep of a solve);
+// 2: reset the base and accumulate sum (P - P_b)^2 and sum P^2 (stopping rule).
+template <int DIM, typename T, bool LOCAL, int MODE, bool HAS_FP>
+__global__ __launch_bounds__(kThreads) void f_sweep_kernel(KC kc, FPtrs fin_, FPtrs fout_,
+                                                           const float *__restrict__ Pb_in,
+                                                           float *__restrict__ Pb_out,
                                                            const float *__restrict__ itau,
                                                            const float *__restrict__ Fp,
-                                                           float *__restrict__ Psnap,
                                                            double *__restrict__ partials,
                                                            const Ctl *__restrict__ ctl, long long k) {
   // a converged (or finished) solve turns the remaining queued sweeps into no-ops
   if (ctl->done || k > ctl->kmax) return;
+  const FP<T> fin = typed<T>(fin_), fout = typed<T>(fout_);
+  const int c = blockIdx.x * kThreads + threadIdx.x;
   double acc[2] = {0.0, 0.0};
-  const int stride = gridDim.x * kThreads;
-  for (int c = blockIdx.x * kThreads + threadIdx.x; c < kc.ncell; c += stride) {
+  if (c < kc.ncell) {
     const Cell q = cell_of(c, kc);
-    float f[2 * DIM];
-    load_f<DIM, LOCAL>(fin, q, kc, f);
-    const float P = moment_p<DIM>(f, kc);
-    const float wP = kc.w1 * P;
+    const float pb = Pb_in[c];
+    float e[2 * DIM];
+    load_e<DIM, T, LOCAL>(fin, Pb_in, q, kc, pb, e);
+    const float dP = dpressure<DIM>(e, kc);
+    const float wdP = kc.w1 * dP;
     const float it = itau[c];
-    const float src = HAS_FP ? kc.dt * kc.wbar * Fp[c] : 0.0f;
+    float add = HAS_FP ? kc.dt * kc.wbar * Fp[c] : 0.0f;
+    if (MODE >= 1) {
+      const float P = pb + dP;
+      add += kc.w1 * (pb - P);          // re-base to P_b = P (exact difference)
+      Pb_out[c] = P;
+      if (MODE == 2) {
+        acc[0] = (double)dP * (double)dP;
+        acc[1] = (double)P * (double)P;
+      }
+    }
 #pragma unroll
     for (int j = 0; j < 2 * DIM; ++j) {
-      float o = f[j] + (wP - f[j]) * it;
-      if (HAS_FP) o += src;
-      fout.p[j][c] = o;
+      float o = e[j] + (wdP - e[j]) * it;
+      if (HAS_FP || MODE >= 1) o += add;
+      Storage<T>::store(fout.p[j], c, o, kc.dev_scale);
     }
-    if (SNAP == 2) {
-      const double d = (double)P - (double)Psnap[c];
-      acc[0] += d * d;
-      acc[1] += (double)P * (double)P;
-    }
-    if (SNAP >= 1) Psnap[c] = P;
   }
-  if (SNAP == 2) block_sum<2>(acc, partials);
+  if (MODE == 2) block_sum<2>(acc, partials);
+}
+
+// ------------------------------------------------- pressure sweep, 4 nodes / thread
+// The same sweep with each thread owning four consecutive nodes of a row
+// (nx % 4 == 0), so populations, base and 1/tau_f move as 16-byte (float) or
+// 8-byte (16-bit) vectors.  The x-streamed populations and the x-neighbour
+// bases come from the adjacent lane of the wavefront (a lane shuffle) or, at a
+// wavefront edge, from one scalar load; rows at walls use the Section 4 rules.
+template <typename T>
+struct Vec4;
+
+template <>
+struct Vec4<float> {
+  static __device__ inline float4 load(const float *p, int i, float) { return *(const float4 *)(p + i); }
+  static __device__ inline void store(float *p, int i, float4 v, float) { *(float4 *)(p + i) = v; }
+};
+
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+
+template <>
+struct Vec4<_Float16> {
+  static __device__ inline float4 load(const _Float16 *p, int i, float inv_s) {
+    const half4_t h = *(const half4_t *)(p + i);
+    return make_float4((float)h.x * inv_s, (float)h.y * inv_s, (float)h.z * inv_s, (float)h.w * inv_s);
+  }
+  static __device__ inline void store(_Float16 *p, int i, float4 v, float s) {
+    half4_t h;
+    h.x = (_Float16)(v.x * s);
+    h.y = (_Float16)(v.y * s);
+    h.z = (_Float16)(v.z * s);
+    h.w = (_Float16)(v.w * s);
+    *(half4_t *)(p + i) = h;
+  }
+};
+
+__device__ inline uint32_t bf16_round(float v) {
+  const uint32_t u = __float_as_uint(v);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+template <>
+struct Vec4<bf16_t> {
+  static __device__ inline float4 load(const bf16_t *p, int i, float) {
+    const uint2 w = *(const uint2 *)(p + i);
+    return make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u),
+                       __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xFFFF0000u));
+  }
+  static __device__ inline void store(bf16_t *p, int i, float4 v, float) {
+    uint2 w;
+    w.x = bf16_round(v.x) | (bf16_round(v.y) << 16);
+    w.y = bf16_round(v.z) | (bf16_round(v.w) << 16);
+    *(uint2 *)(p + i) = w;
+  }
+};
+
+__device__ inline float f4get(const float4 &v, int i) { return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w)); }
+__device__ inline void f4set(float4 &v, int i, float x) {
+  if (i == 0) v.x = x;
+  else if (i == 1) v.y = x;
+  else if (i == 2) v.z = x;
+  else v.w = x;
+}
+
+template <int DIM, typename T, int MODE, bool HAS_FP>
+__global__ __launch_bounds__(kThreads) void f_sweep_vec_kernel(KC kc, FPtrs fin_, FPtrs fout_,
+                                                               const float *__restrict__ Pb_in,
+                                                               float *__restrict__ Pb_out,
+                                                               const float *__restrict__ itau,
+                                                               const float *__restrict__ Fp,
+                                                               double *__restrict__ partials,
+                                                               const Ctl *__restrict__ ctl, long long k) {
+  if (ctl->done || k > ctl->kmax) return;
+  const FP<T> fin = typed<T>(fin_), fout = typed<T>(fout_);
+  const int n4 = kc.ncell >> 2;
+  const int qi = blockIdx.x * kThreads + threadIdx.x;
+  const bool active = qi < n4;
+  const int c = (active ? qi : n4 - 1) << 2;     // first of the four nodes
+  const int lane = threadIdx.x & 63;
+  const int row = c / kc.nx;
+  const int x0 = c - row * kc.nx;
+  const int z = row / kc.ny;
+  const int y = row - z * kc.ny;
+  const float is = kc.inv_dev_scale;
+
+  const float4 pb = *(const float4 *)(Pb_in + c);
+  // x-streamed populations: +x (j = 0) pulls from x - 1, -x (j = 2) from x + 1
+  const float4 A = Vec4<T>::load(fin.p[0], c, is);
+  const float4 B = Vec4<T>::load(fin.p[2], c, is);
+  float a_left = __shfl_up(A.w, 1, 64), pb_left = __shfl_up(pb.w, 1, 64);
+  float b_right = __shfl_down(B.x, 1, 64), pb_right = __shfl_down(pb.x, 1, 64);
+
+  float4 e[2 * DIM];
+  // +x for nodes 1..3 from the own vector, node 0 from the left neighbour
+  e[0] = make_float4(0.f, A.x + kc.w1 * (pb.x - pb.y), A.y + kc.w1 * (pb.y - pb.z), A.z + kc.w1 * (pb.z - pb.w));
+  e[2] = make_float4(B.y + kc.w1 * (pb.y - pb.x), B.z + kc.w1 * (pb.z - pb.y), B.w + kc.w1 * (pb.w - pb.z), 0.f);
+  if (x0 == 0) {
+    const int bc = kc.bc_f[0];
+    if (bc == LBTP_BC_PERIODIC) {
+      const int src = c + kc.nx - 1;
+      e[0].x = Storage<T>::load(fin.p[0], src, is) + kc.w1 * (Pb_in[src] - pb.x);
+    } else {
+      e[0].x = (bc == LBTP_BC_DIRICHLET) ? (2.0f * kc.w1 * (kc.Pw[0] - pb.x) - B.x) : B.x;
+    }
+  } else {
+    if (lane == 0) {
+      a_left = Storage<T>::load(fin.p[0], c - 1, is);
+      pb_left = Pb_in[c - 1];
+    }
+    e[0].x = a_left + kc.w1 * (pb_left - pb.x);
+  }
+  if (x0 + 4 == kc.nx) {
+    const int bc = kc.bc_f[1];
+    if (bc == LBTP_BC_PERIODIC) {
+      const int src = c + 3 - (kc.nx - 1);
+      e[2].w = Storage<T>::load(fin.p[2], src, is) + kc.w1 * (Pb_in[src] - pb.w);
+    } else {
+      e[2].w = (bc == LBTP_BC_DIRICHLET) ? (2.0f * kc.w1 * (kc.Pw[1] - pb.w) - A.w) : A.w;
+    }
+  } else {
+    if (lane == 63) {
+      b_right = Storage<T>::load(fin.p[2], c + 4, is);
+      pb_right = Pb_in[c + 4];
+    }
+    e[2].w = b_right + kc.w1 * (pb_right - pb.w);
+  }
+  // y (and z) streamed populations: whole vectors from the neighbouring row
+#pragma unroll
+  for (int a = 1; a < DIM; ++a) {
+    const int jp = (a == 1) ? 1 : 4, jm = (a == 1) ? 3 : 5;   // +a and -a directions
+    const int coordv = (a == 1) ? y : z;
+    const int n = (a == 1) ? kc.ny : kc.nz;
+    const int st = (a == 1) ? kc.nx : kc.nx * kc.ny;
+    // +a pulls from coord - 1
+    if (coordv == 0) {
+      const int bc = kc.bc_f[2 * a];
+      if (bc == LBTP_BC_PERIODIC) {
+        const int src = c + (n - 1) * st;
+        const float4 v = Vec4<T>::load(fin.p[jp], src, is);
+        const float4 q = *(const float4 *)(Pb_in + src);
+        e[jp] = make_float4(v.x + kc.w1 * (q.x - pb.x), v.y + kc.w1 * (q.y - pb.y), v.z + kc.w1 * (q.z - pb.z),
+                            v.w + kc.w1 * (q.w - pb.w));
+      } else {
+        const float4 o = Vec4<T>::load(fin.p[jm], c, is);
+        if (bc == LBTP_BC_DIRICHLET) {
+          const float pw = kc.Pw[2 * a];
+          e[jp] = make_float4(2.0f * kc.w1 * (pw - pb.x) - o.x, 2.0f * kc.w1 * (pw - pb.y) - o.y,
+                              2.0f * kc.w1 * (pw - pb.z) - o.z, 2.0f * kc.w1 * (pw - pb.w) - o.w);
+        } else {
+          e[jp] = o;
+        }
+      }
+    } else {
+      const int src = c - st;
+      const float4 v = Vec4<T>::load(fin.p[jp], src, is);
+      const float4 q = *(const float4 *)(Pb_in + src);
+      e[jp] = make_float4(v.x + kc.w1 * (q.x - pb.x), v.y + kc.w1 * (q.y - pb.y), v.z + kc.w1 * (q.z - pb.z),
+                          v.w + kc.w1 * (q.w - pb.w));
+    }
+    // -a pulls from coord + 1
+    if (coordv == n - 1) {
+      const int bc = kc.bc_f[2 * a + 1];
+      if (bc == LBTP_BC_PERIODIC) {
+        const int src = c - (n - 1) * st;
+        const float4 v = Vec4<T>::load(fin.p[jm], src, is);
+        const float4 q = *(const float4 *)(Pb_in + src);
+        e[jm] = make_float4(v.x + kc.w1 * (q.x - pb.x), v.y + kc.w1 * (q.y - pb.y), v.z + kc.w1 * (q.z - pb.z),
+                            v.w + kc.w1 * (q.w - pb.w));
+      } else {
+        const float4 o = Vec4<T>::load(fin.p[jp], c, is);
+        if (bc == LBTP_BC_DIRICHLET) {
+          const float pw = kc.Pw[2 * a + 1];
+          e[jm] = make_float4(2.0f * kc.w1 * (pw - pb.x) - o.x, 2.0f * kc.w1 * (pw - pb.y) - o.y,
+                              2.0f * kc.w1 * (pw - pb.z) - o.z, 2.0f * kc.w1 * (pw - pb.w) - o.w);
+        } else {
+          e[jm] = o;
+        }
+      }
+    } else {
+      const int src = c + st;
+      const float4 v = Vec4<T>::load(fin.p[jm], src, is);
+      const float4 q = *(const float4 *)(Pb_in + src);
+      e[jm] = make_float4(v.x + kc.w1 * (q.x - pb.x), v.y + kc.w1 * (q.y - pb.y), v.z + kc.w1 * (q.z - pb.z),
+                          v.w + kc.w1 * (q.w - pb.w));
+    }
+  }
+
+  const float4 it = *(const float4 *)(itau + c);
+  float4 fp = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (HAS_FP) fp = *(const float4 *)(Fp + c);
+  float4 o[2 * DIM];
+  float4 pnew;
+  double acc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float ev[2 * DIM];
+#pragma unroll
+    for (int j = 0; j < 2 * DIM; ++j) ev[j] = f4get(e[j], i);
+    const float dP = dpressure<DIM>(ev, kc);
+    const float wdP = kc.w1 * dP;
+    const float t = f4get(it, i);
+    float add = HAS_FP ? kc.dt * kc.wbar * f4get(fp, i) : 0.0f;
+    if (MODE >= 1) {
+      const float pbi = f4get(pb, i);
+      const float P = pbi + dP;
+      add += kc.w1 * (pbi - P);
+      f4set(pnew, i, P);
+      if (MODE == 2 && active) {
+        acc[0] += (double)dP * (double)dP;
+        acc[1] += (double)P * (double)P;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 2 * DIM; ++j) {
+      float v = ev[j] + (wdP - ev[j]) * t;
+      if (HAS_FP || MODE >= 1) v += add;
+      f4set(o[j], i, v);
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int j = 0; j < 2 * DIM; ++j) Vec4<T>::store(fout.p[j], c, o[j], kc.dev_scale);
+    if (MODE >= 1) *(float4 *)(Pb_out + c) = pnew;
+  }
+  if (MODE == 2) block_sum<2>(acc, partials);
 }
 
 // Stopping rule r = ||P^k - P^{k-m}|| / (m ||P^k||) from the block partials.
@@ -274,13 +576,15 @@ __global__ __launch_bounds__(kThreads) void moments_kernel(KC kc, GPtrs g, const
 // gamma = -lambda_w K / (c_s^2 dt) (eq. 3-8); post-collision values are
 // pushed to x + c_i, or reflected at walls (Section 4).  Block partials of
 // the net flux through reflected links.
-template <int DIM, bool FLOCAL, bool HAS_FS>
-__global__ __launch_bounds__(kThreads) void g_sweep_kernel(KC kc, GPtrs gin, GPtrs gout, FPtrs f,
+template <int DIM, typename T, bool FLOCAL, bool HAS_FS>
+__global__ __launch_bounds__(kThreads) void g_sweep_kernel(KC kc, GPtrs gin, GPtrs gout, FPtrs f_,
+                                                           const float *__restrict__ Pb,
                                                            const float *__restrict__ itau,
                                                            const float *__restrict__ K,
                                                            const float *__restrict__ phi,
                                                            const float *__restrict__ Fs,
                                                            double *__restrict__ partials) {
+  const FP<T> f = typed<T>(f_);
   const int c = blockIdx.x * kThreads + threadIdx.x;
   double acc[1] = {0.0};
   if (c < kc.ncell) {
@@ -291,10 +595,10 @@ __global__ __launch_bounds__(kThreads) void g_sweep_kernel(KC kc, GPtrs gin, GPt
     const float fs = HAS_FS ? Fs[c] : 0.0f;
     const float ph = phi[c];
     const float Sv = saturation_of(sum_g<DIM>(gv), fs, ph, kc);
-    float fv[2 * DIM];
-    load_f<DIM, FLOCAL>(f, q, kc, fv);
+    float e[2 * DIM];
+    load_e<DIM, T, FLOCAL>(f, Pb, q, kc, Pb[c], e);
     float m1[3];
-    moment_c<DIM>(fv, kc, m1);
+    moment_c<DIM>(e, kc, m1);
     const float gscale = -itau[c] * kc.inv_cs2dt;      // grad P = gscale * m1
     const float lw = Sv * Sv * kc.inv_mu_w;
     const float gamma = -lw * K[c] * kc.inv_cs2dt;
@@ -341,7 +645,6 @@ __global__ __launch_bounds__(kThreads) void g_sweep_kernel(KC kc, GPtrs gin, GPt
 
 // ------------------------------------------------------------ initialisation
 // Central difference of u along axis a (one-sided second order at walls).
-template <int DIM>
 __device__ inline float cdiff(const float *__restrict__ u, const Cell &q, int a, const KC &kc, float inv2dx) {
   const int x = coord(q, a), n = extent(kc, a), st = stride_of(kc, a);
   const bool periodic = kc.bc_f[2 * a] == LBTP_BC_PERIODIC;
@@ -356,19 +659,22 @@ __device__ inline float cdiff(const float *__restrict__ u, const Cell &q, int a,
   return (u[c + st] - u[c - st]) * inv2dx;
 }
 
-// f_i = w_i P0 - tau_f dt w_i c_i . grad P0 (i >= 1); g_i = g_i^eq(S0) + eps g_i^(1)
-// with eps g_i^(1) = -tau_g dt [(Gamma_i/phi - w_i(1 - 1/(2 tau_g))) F_s
-//                               + Gamma_i c_i . grad S0 - gamma w_i c_i . grad P0 / tau_g]
-// (eq. gini, gneq), Gamma_i = g_i^eq / S.  f is written in local form.
-template <int DIM>
+// f_i = w_i P0 - tau_f dt w_i c_i . grad P0 (i >= 1): base P_b = P0 and local
+// deviations e_i = -tau_f dt w_i c_i . grad P0.
+// g_i = g_i^eq(S0) + eps g_i^(1) with
+// eps g_i^(1) = -tau_g dt [(Gamma_i/phi - w_i(1 - 1/(2 tau_g))) F_s
+//                          + Gamma_i c_i . grad S0 - gamma w_i c_i . grad P0 / tau_g]
+// (eq. gini, gneq), Gamma_i = g_i^eq / S.
+template <int DIM, typename T>
 __global__ __launch_bounds__(kThreads) void init_kernel(KC kc, const float *__restrict__ P0,
                                                         const float *__restrict__ S0,
                                                         const float *__restrict__ dP0,
                                                         const float *__restrict__ dS0,
                                                         const float *__restrict__ K,
                                                         const float *__restrict__ phi,
-                                                        const float *__restrict__ Fs, int neq, FPtrs f,
-                                                        GPtrs g) {
+                                                        const float *__restrict__ Fs, int neq, FPtrs f_,
+                                                        float *__restrict__ Pb, GPtrs g) {
+  const FP<T> f = typed<T>(f_);
   const int c = blockIdx.x * kThreads + threadIdx.x;
   if (c >= kc.ncell) return;
   const Cell q = cell_of(c, kc);
@@ -379,8 +685,8 @@ __global__ __launch_bounds__(kThreads) void init_kernel(KC kc, const float *__re
     const float inv2dx = 0.5f / (kc.c * kc.dt);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-      gp[a] = dP0 ? dP0[a * kc.ncell + c] : cdiff<DIM>(P0, q, a, kc, inv2dx);
-      gs[a] = dS0 ? dS0[a * kc.ncell + c] : cdiff<DIM>(S0, q, a, kc, inv2dx);
+      gp[a] = dP0 ? dP0[a * kc.ncell + c] : cdiff(P0, q, a, kc, inv2dx);
+      gs[a] = dS0 ? dS0[a * kc.ncell + c] : cdiff(S0, q, a, kc, inv2dx);
     }
   }
   const float itf = inv_tau_f_of(S, K[c], kc);
@@ -389,12 +695,12 @@ __global__ __launch_bounds__(kThreads) void init_kernel(KC kc, const float *__re
   const float gamma = -lw * K[c] * kc.inv_cs2dt;
   const float tau_g = 1.0f / kc.inv_tau_g;
   const float wsrc = 1.0f - 0.5f * kc.inv_tau_g;
-  const float wP = kc.w1 * P;
+  Pb[c] = P;
 #pragma unroll
   for (int j = 0; j < 2 * DIM; ++j) {
     const int a = dir_axis(j), s = dir_sign(j);
     const float cdp = (float)s * kc.c * gp[a];
-    f.p[j][c] = neq ? wP - tau_f * kc.dt * kc.w1 * cdp : wP;
+    Storage<T>::store(f.p[j], c, neq ? -tau_f * kc.dt * kc.w1 * cdp : 0.0f, kc.dev_scale);
   }
   // rest population: Gamma_0 = (w0 - 1) beta + phi, c_0 = 0
   {
@@ -418,29 +724,32 @@ __global__ __launch_bounds__(kThreads) void init_kernel(KC kc, const float *__re
 }
 
 // ----------------------------------------------------------------- outputs
-template <int DIM, bool LOCAL>
-__global__ __launch_bounds__(kThreads) void pressure_kernel(KC kc, FPtrs f, float *__restrict__ P) {
+template <int DIM, typename T, bool LOCAL>
+__global__ __launch_bounds__(kThreads) void pressure_kernel(KC kc, FPtrs f_, const float *__restrict__ Pb,
+                                                            float *__restrict__ P) {
   const int c = blockIdx.x * kThreads + threadIdx.x;
   if (c >= kc.ncell) return;
   const Cell q = cell_of(c, kc);
-  float fv[2 * DIM];
-  load_f<DIM, LOCAL>(f, q, kc, fv);
-  P[c] = moment_p<DIM>(fv, kc);
+  const float pb = Pb[c];
+  float e[2 * DIM];
+  load_e<DIM, T, LOCAL>(typed<T>(f_), Pb, q, kc, pb, e);
+  P[c] = pb + dpressure<DIM>(e, kc);
 }
 
 // grad P (eq. 3-10a) or u = -K lambda_t grad P (eq. 3-10b), component-major.
-template <int DIM, bool LOCAL>
-__global__ __launch_bounds__(kThreads) void grad_kernel(KC kc, FPtrs f, const float *__restrict__ itau,
+template <int DIM, typename T, bool LOCAL>
+__global__ __launch_bounds__(kThreads) void grad_kernel(KC kc, FPtrs f_, const float *__restrict__ Pb,
+                                                        const float *__restrict__ itau,
                                                         const float *__restrict__ K,
                                                         const float *__restrict__ S, int velocity,
                                                         float *__restrict__ out) {
   const int c = blockIdx.x * kThreads + threadIdx.x;
   if (c >= kc.ncell) return;
   const Cell q = cell_of(c, kc);
-  float fv[2 * DIM];
-  load_f<DIM, LOCAL>(f, q, kc, fv);
+  float e[2 * DIM];
+  load_e<DIM, T, LOCAL>(typed<T>(f_), Pb, q, kc, Pb[c], e);
   float m1[3];
-  moment_c<DIM>(fv, kc, m1);
+  moment_c<DIM>(e, kc, m1);
   float scale = -itau[c] * kc.inv_cs2dt;
   if (velocity) {
     const float Sv = S[c];
@@ -463,52 +772,80 @@ __global__ __launch_bounds__(kThreads) void saturation_kernel(KC kc, GPtrs g, co
   S[c] = saturation_of(sum_g<DIM>(gv), HAS_FS ? Fs[c] : 0.0f, phi[c], kc);
 }
 
-template <int DIM, bool LOCAL>
-__global__ __launch_bounds__(kThreads) void materialize_kernel(KC kc, FPtrs fin, FPtrs fout) {
+// Pre-collision populations f_i = w_i P_b + e_i (float) for inspection.
+template <int DIM, typename T, bool LOCAL>
+__global__ __launch_bounds__(kThreads) void populations_kernel(KC kc, FPtrs f_, const float *__restrict__ Pb,
+                                                               float *__restrict__ out) {
   const int c = blockIdx.x * kThreads + threadIdx.x;
   if (c >= kc.ncell) return;
   const Cell q = cell_of(c, kc);
-  float fv[2 * DIM];
-  load_f<DIM, LOCAL>(fin, q, kc, fv);
+  const float pb = Pb[c];
+  float e[2 * DIM];
+  load_e<DIM, T, LOCAL>(typed<T>(f_), Pb, q, kc, pb, e);
 #pragma unroll
-  for (int j = 0; j < 2 * DIM; ++j) fout.p[j][c] = fv[j];
+  for (int j = 0; j < 2 * DIM; ++j) out[j * kc.ncell + c] = kc.w1 * pb + e[j];
 }
 
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
 #define LBTP_GRID(kc) dim3(nblocks((kc).ncell)), dim3(kThreads), 0, s
-#define LBTP_SWEEP_GRID(kc) dim3(sweep_blocks((kc).ncell)), dim3(kThreads), 0, s
 
-template <int DIM, bool LOCAL, int SNAP>
-static void f_sweep_fp(const KC &kc, FPtrs fin, FPtrs fout, const float *itau, const float *Fp,
-                       float *Psnap, double *partials, const Ctl *ctl, long long k, hipStream_t s) {
-  if (Fp)
-    hipLaunchKernelGGL((f_sweep_kernel<DIM, LOCAL, SNAP, true>), LBTP_SWEEP_GRID(kc), kc, fin, fout, itau, Fp,
-                       Psnap, partials, ctl, k);
-  else
-    hipLaunchKernelGGL((f_sweep_kernel<DIM, LOCAL, SNAP, false>), LBTP_SWEEP_GRID(kc), kc, fin, fout, itau, Fp,
-                       Psnap, partials, ctl, k);
-}
-
-template <int DIM, bool LOCAL>
-static void f_sweep_snap(const KC &kc, FPtrs fin, FPtrs fout, const float *itau, const float *Fp,
-                         float *Psnap, double *partials, const Ctl *ctl, long long k, int snap, hipStream_t s) {
-  if (snap == 0) f_sweep_fp<DIM, LOCAL, 0>(kc, fin, fout, itau, Fp, Psnap, partials, ctl, k, s);
-  else if (snap == 1) f_sweep_fp<DIM, LOCAL, 1>(kc, fin, fout, itau, Fp, Psnap, partials, ctl, k, s);
-  else f_sweep_fp<DIM, LOCAL, 2>(kc, fin, fout, itau, Fp, Psnap, partials, ctl, k, s);
-}
-
-hipError_t launch_f_sweep(int dim, const KC &kc, FPtrs fin, FPtrs fout, const float *itau, const float *Fp,
-                          float *Psnap, double *partials, const Ctl *ctl, long long k, int local, int snap,
-                          hipStream_t s) {
+// Dispatch on lattice (2-D / 3-D), storage type and the local flag.
+template <template <int, typename, bool> class Fn, typename... A>
+static void dispatch(int dim, int storage, int local, A &&...args) {
+  auto go = [&](auto d, auto t) {
+    constexpr int D = decltype(d)::value;
+    using T = typename decltype(t)::type;
+    if (local) Fn<D, T, true>::run(args...);
+    else Fn<D, T, false>::run(args...);
+  };
+  struct F32 { using type = float; };
+  struct F16 { using type = _Float16; };
+  struct B16 { using type = bf16_t; };
+  using D2 = std::integral_constant<int, 2>;
+  using D3 = std::integral_constant<int, 3>;
   if (dim == 2) {
-    if (local) f_sweep_snap<2, true>(kc, fin, fout, itau, Fp, Psnap, partials, ctl, k, snap, s);
-    else f_sweep_snap<2, false>(kc, fin, fout, itau, Fp, Psnap, partials, ctl, k, snap, s);
+    if (storage == LBTP_FP16_DEV) go(D2{}, F16{});
+    else if (storage == LBTP_BF16_DEV) go(D2{}, B16{});
+    else go(D2{}, F32{});
   } else {
-    if (local) f_sweep_snap<3, true>(kc, fin, fout, itau, Fp, Psnap, partials, ctl, k, snap, s);
-    else f_sweep_snap<3, false>(kc, fin, fout, itau, Fp, Psnap, partials, ctl, k, snap, s);
+    if (storage == LBTP_FP16_DEV) go(D3{}, F16{});
+    else if (storage == LBTP_BF16_DEV) go(D3{}, B16{});
+    else go(D3{}, F32{});
   }
+}
+
+template <int DIM, typename T, bool LOCAL>
+struct SweepLaunch {
+  static void run(const KC &kc, FPtrs fin, FPtrs fout, const float *Pb_in, float *Pb_out, const float *itau,
+                  const float *Fp, double *partials, const Ctl *ctl, long long k, int mode, hipStream_t s) {
+#define LBTP_SWEEP(M, HF)                                                                                     \
+  do {                                                                                                        \
+    if (!LOCAL && kc.nx % 4 == 0)                                                                             \
+      hipLaunchKernelGGL((f_sweep_vec_kernel<DIM, T, M, HF>), dim3(nblocks(kc.ncell / 4)), dim3(kThreads), 0, s, \
+                         kc, fin, fout, Pb_in, Pb_out, itau, Fp, partials, ctl, k);                           \
+    else                                                                                                      \
+      hipLaunchKernelGGL((f_sweep_kernel<DIM, T, LOCAL, M, HF>), LBTP_GRID(kc), kc, fin, fout, Pb_in, Pb_out,  \
+                         itau, Fp, partials, ctl, k);                                                         \
+  } while (0)
+    if (Fp) {
+      if (mode == 0) LBTP_SWEEP(0, true);
+      else if (mode == 1) LBTP_SWEEP(1, true);
+      else LBTP_SWEEP(2, true);
+    } else {
+      if (mode == 0) LBTP_SWEEP(0, false);
+      else if (mode == 1) LBTP_SWEEP(1, false);
+      else LBTP_SWEEP(2, false);
+    }
+#undef LBTP_SWEEP
+  }
+};
+
+hipError_t launch_f_sweep(int dim, int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb_in,
+                          float *Pb_out, const float *itau, const float *Fp, double *partials, const Ctl *ctl,
+                          long long k, int local, int mode, hipStream_t s) {
+  dispatch<SweepLaunch>(dim, storage, local, kc, fin, fout, Pb_in, Pb_out, itau, Fp, partials, ctl, k, mode, s);
   return hipGetLastError();
 }
 
@@ -540,52 +877,66 @@ hipError_t launch_moments(int dim, const KC &kc, GPtrs g, const float *K, const 
   return hipGetLastError();
 }
 
-template <int DIM, bool FLOCAL>
-static void g_sweep_fs(const KC &kc, GPtrs gin, GPtrs gout, FPtrs f, const float *itau, const float *K,
-                       const float *phi, const float *Fs, double *partials, hipStream_t s) {
-  if (Fs) hipLaunchKernelGGL((g_sweep_kernel<DIM, FLOCAL, true>), LBTP_GRID(kc), kc, gin, gout, f, itau, K, phi, Fs, partials);
-  else hipLaunchKernelGGL((g_sweep_kernel<DIM, FLOCAL, false>), LBTP_GRID(kc), kc, gin, gout, f, itau, K, phi, Fs, partials);
-}
-
-hipError_t launch_g_sweep(int dim, const KC &kc, GPtrs gin, GPtrs gout, FPtrs f, int f_local, const float *itau,
-                          const float *K, const float *phi, const float *Fs, double *partials, hipStream_t s) {
-  if (dim == 2) {
-    if (f_local) g_sweep_fs<2, true>(kc, gin, gout, f, itau, K, phi, Fs, partials, s);
-    else g_sweep_fs<2, false>(kc, gin, gout, f, itau, K, phi, Fs, partials, s);
-  } else {
-    if (f_local) g_sweep_fs<3, true>(kc, gin, gout, f, itau, K, phi, Fs, partials, s);
-    else g_sweep_fs<3, false>(kc, gin, gout, f, itau, K, phi, Fs, partials, s);
+template <int DIM, typename T, bool LOCAL>
+struct GSweepLaunch {
+  static void run(const KC &kc, GPtrs gin, GPtrs gout, FPtrs f, const float *Pb, const float *itau, const float *K,
+                  const float *phi, const float *Fs, double *partials, hipStream_t s) {
+    if (Fs)
+      hipLaunchKernelGGL((g_sweep_kernel<DIM, T, LOCAL, true>), LBTP_GRID(kc), kc, gin, gout, f, Pb, itau, K, phi,
+                         Fs, partials);
+    else
+      hipLaunchKernelGGL((g_sweep_kernel<DIM, T, LOCAL, false>), LBTP_GRID(kc), kc, gin, gout, f, Pb, itau, K, phi,
+                         Fs, partials);
   }
+};
+
+hipError_t launch_g_sweep(int dim, int storage, const KC &kc, GPtrs gin, GPtrs gout, FPtrs f, int f_local,
+                          const float *Pb, const float *itau, const float *K, const float *phi, const float *Fs,
+                          double *partials, hipStream_t s) {
+  dispatch<GSweepLaunch>(dim, storage, f_local, kc, gin, gout, f, Pb, itau, K, phi, Fs, partials, s);
   return hipGetLastError();
 }
 
-hipError_t launch_init(int dim, const KC &kc, const float *P0, const float *S0, const float *dP0, const float *dS0,
-                       const float *K, const float *phi, const float *Fs, int neq, FPtrs f, GPtrs g, hipStream_t s) {
-  if (dim == 2) hipLaunchKernelGGL((init_kernel<2>), LBTP_GRID(kc), kc, P0, S0, dP0, dS0, K, phi, Fs, neq, f, g);
-  else hipLaunchKernelGGL((init_kernel<3>), LBTP_GRID(kc), kc, P0, S0, dP0, dS0, K, phi, Fs, neq, f, g);
+template <int DIM, typename T, bool LOCAL_UNUSED>
+struct InitLaunch {
+  static void run(const KC &kc, const float *P0, const float *S0, const float *dP0, const float *dS0,
+                  const float *K, const float *phi, const float *Fs, int neq, FPtrs f, float *Pb, GPtrs g,
+                  hipStream_t s) {
+    hipLaunchKernelGGL((init_kernel<DIM, T>), LBTP_GRID(kc), kc, P0, S0, dP0, dS0, K, phi, Fs, neq, f, Pb, g);
+  }
+};
+
+hipError_t launch_init(int dim, int storage, const KC &kc, const float *P0, const float *S0, const float *dP0,
+                       const float *dS0, const float *K, const float *phi, const float *Fs, int neq, FPtrs f,
+                       float *Pb, GPtrs g, hipStream_t s) {
+  dispatch<InitLaunch>(dim, storage, 0, kc, P0, S0, dP0, dS0, K, phi, Fs, neq, f, Pb, g, s);
   return hipGetLastError();
 }
 
-hipError_t launch_pressure(int dim, const KC &kc, FPtrs f, int f_local, float *P, hipStream_t s) {
-  if (dim == 2) {
-    if (f_local) hipLaunchKernelGGL((pressure_kernel<2, true>), LBTP_GRID(kc), kc, f, P);
-    else hipLaunchKernelGGL((pressure_kernel<2, false>), LBTP_GRID(kc), kc, f, P);
-  } else {
-    if (f_local) hipLaunchKernelGGL((pressure_kernel<3, true>), LBTP_GRID(kc), kc, f, P);
-    else hipLaunchKernelGGL((pressure_kernel<3, false>), LBTP_GRID(kc), kc, f, P);
+template <int DIM, typename T, bool LOCAL>
+struct PressureLaunch {
+  static void run(const KC &kc, FPtrs f, const float *Pb, float *P, hipStream_t s) {
+    hipLaunchKernelGGL((pressure_kernel<DIM, T, LOCAL>), LBTP_GRID(kc), kc, f, Pb, P);
   }
+};
+
+hipError_t launch_pressure(int dim, int storage, const KC &kc, FPtrs f, int f_local, const float *Pb, float *P,
+                           hipStream_t s) {
+  dispatch<PressureLaunch>(dim, storage, f_local, kc, f, Pb, P, s);
   return hipGetLastError();
 }
 
-hipError_t launch_grad(int dim, const KC &kc, FPtrs f, int f_local, const float *itau, const float *K,
-                       const float *S, int velocity, float *out, hipStream_t s) {
-  if (dim == 2) {
-    if (f_local) hipLaunchKernelGGL((grad_kernel<2, true>), LBTP_GRID(kc), kc, f, itau, K, S, velocity, out);
-    else hipLaunchKernelGGL((grad_kernel<2, false>), LBTP_GRID(kc), kc, f, itau, K, S, velocity, out);
-  } else {
-    if (f_local) hipLaunchKernelGGL((grad_kernel<3, true>), LBTP_GRID(kc), kc, f, itau, K, S, velocity, out);
-    else hipLaunchKernelGGL((grad_kernel<3, false>), LBTP_GRID(kc), kc, f, itau, K, S, velocity, out);
+template <int DIM, typename T, bool LOCAL>
+struct GradLaunch {
+  static void run(const KC &kc, FPtrs f, const float *Pb, const float *itau, const float *K, const float *S,
+                  int velocity, float *out, hipStream_t s) {
+    hipLaunchKernelGGL((grad_kernel<DIM, T, LOCAL>), LBTP_GRID(kc), kc, f, Pb, itau, K, S, velocity, out);
   }
+};
+
+hipError_t launch_grad(int dim, int storage, const KC &kc, FPtrs f, int f_local, const float *Pb,
+                       const float *itau, const float *K, const float *S, int velocity, float *out, hipStream_t s) {
+  dispatch<GradLaunch>(dim, storage, f_local, kc, f, Pb, itau, K, S, velocity, out, s);
   return hipGetLastError();
 }
 
@@ -601,14 +952,16 @@ hipError_t launch_saturation(int dim, const KC &kc, GPtrs g, const float *phi, c
   return hipGetLastError();
 }
 
-hipError_t launch_materialize_f(int dim, const KC &kc, FPtrs fin, int f_local, FPtrs fout, hipStream_t s) {
-  if (dim == 2) {
-    if (f_local) hipLaunchKernelGGL((materialize_kernel<2, true>), LBTP_GRID(kc), kc, fin, fout);
-    else hipLaunchKernelGGL((materialize_kernel<2, false>), LBTP_GRID(kc), kc, fin, fout);
-  } else {
-    if (f_local) hipLaunchKernelGGL((materialize_kernel<3, true>), LBTP_GRID(kc), kc, fin, fout);
-    else hipLaunchKernelGGL((materialize_kernel<3, false>), LBTP_GRID(kc), kc, fin, fout);
+template <int DIM, typename T, bool LOCAL>
+struct PopulationsLaunch {
+  static void run(const KC &kc, FPtrs f, const float *Pb, float *out, hipStream_t s) {
+    hipLaunchKernelGGL((populations_kernel<DIM, T, LOCAL>), LBTP_GRID(kc), kc, f, Pb, out);
   }
+};
+
+hipError_t launch_populations(int dim, int storage, const KC &kc, FPtrs f, int f_local, const float *Pb,
+                              float *out, hipStream_t s) {
+  dispatch<PopulationsLaunch>(dim, storage, f_local, kc, f, Pb, out, s);
   return hipGetLastError();
 }
 

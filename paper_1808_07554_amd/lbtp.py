@@ -59,10 +59,10 @@ EXPORTS = {
     "lbtp_saturation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "lbtp_mass": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_double)]),
-    "lbtp_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                      ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
-    "lbtp_put_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                      ctypes.c_longlong, ctypes.c_int]),
+    "lbtp_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "lbtp_checkpoint_size": (ctypes.c_longlong, [ctypes.c_void_p]),
+    "lbtp_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_longlong, ctypes.c_int]),
+    "lbtp_put_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_longlong, ctypes.c_int]),
     "lbtp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
 }
 
@@ -246,17 +246,30 @@ class Solver:
         _check(self._lib.lbtp_mass(self._h, ctypes.byref(m), ctypes.byref(l)), "lbtp_mass")
         return m.value, l.value
 
-    def get_state(self):
+    def populations(self):
+        """Pre-collision populations (float32): f_1..f_{Q-1} and g_0..g_{Q-1}."""
         f = self._empty((self.Q - 1) * self.ncell)
         g = self._empty(self.Q * self.ncell)
-        st = ctypes.c_longlong()
-        _check(self._lib.lbtp_get_state(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(g.data_ptr()),
-                                        ctypes.byref(st), 1), "lbtp_get_state")
-        return f.view((self.Q - 1,) + self._fshape()), g.view((self.Q,) + self._fshape()), st.value
+        _check(self._lib.lbtp_populations(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(g.data_ptr()), 1),
+               "lbtp_populations")
+        return f.view((self.Q - 1,) + self._fshape()), g.view((self.Q,) + self._fshape())
 
-    def put_state(self, f, g, step=0):
-        a = [self._arg(f, (self.Q - 1) * self.ncell), self._arg(g, self.Q * self.ncell)]
-        _check(self._lib.lbtp_put_state(self._h, a[0].ptr, a[1].ptr, int(step), self._both(*a)), "lbtp_put_state")
+    def get_state(self):
+        """Opaque checkpoint image (uint8 device tensor)."""
+        n = self._lib.lbtp_checkpoint_size(self._h)
+        _check(n, "lbtp_checkpoint_size")
+        buf = self.torch.empty(n, dtype=self.torch.uint8, device="cuda")
+        _check(self._lib.lbtp_get_state(self._h, ctypes.c_void_p(buf.data_ptr()), n, 1), "lbtp_get_state")
+        return buf
+
+    def put_state(self, buf):
+        if isinstance(buf, self.torch.Tensor):
+            buf = buf.contiguous()
+            _check(self._lib.lbtp_put_state(self._h, ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                                            1 if buf.is_cuda else 0), "lbtp_put_state")
+        else:
+            h = np.ascontiguousarray(np.frombuffer(bytes(buf), dtype=np.uint8))
+            _check(self._lib.lbtp_put_state(self._h, ctypes.c_void_p(h.ctypes.data), h.size, 0), "lbtp_put_state")
 
 
 def from_problem(params, **kw):
