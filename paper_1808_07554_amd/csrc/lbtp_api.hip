@@ -12,6 +12,7 @@
 
 #include <vector>
 
+#include "../../include/lbtp_probe.h"
 #include "lbtp_internal.h"
 
 using namespace lbtp;
@@ -703,6 +704,13 @@ int lbtp_put_state(lbtp_ctx *c, const void *buf, long long nbytes, int on_device
   c->kc.inv_dev_scale = h.inv_dev_scale;
   c->have_state = 1;
   c->have_coef = 0;
+  return LBTP_OK;
+}
+
+int lbtp_copy_probe(void *dst, const void *src, long long bytes, void *stream) {
+  if (!dst || !src || bytes <= 0 || bytes % 16 != 0) return LBTP_EINVAL;
+  if ((((uintptr_t)dst) | ((uintptr_t)src)) % 16 != 0) return LBTP_EINVAL;
+  HIP_TRY(launch_copy_probe(src, dst, bytes / 16, (hipStream_t)stream));
   return LBTP_OK;
 }
 

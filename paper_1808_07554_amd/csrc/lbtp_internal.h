@@ -89,6 +89,8 @@ hipError_t launch_saturation(int dim, const KC &kc, GPtrs g, const float *phi, c
 hipError_t launch_populations(int dim, int storage, const KC &kc, FPtrs f, int f_local, const float *Pb,
                               float *out, hipStream_t s);
 
+hipError_t launch_copy_probe(const void *src, void *dst, long long n4, hipStream_t s);
+
 inline size_t storage_bytes(int storage) { return storage == LBTP_FP32 ? 4 : 2; }
 
 inline int nblocks(long long n);

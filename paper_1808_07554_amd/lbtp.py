@@ -64,6 +64,7 @@ EXPORTS = {
     "lbtp_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_longlong, ctypes.c_int]),
     "lbtp_put_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_longlong, ctypes.c_int]),
     "lbtp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "lbtp_copy_probe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p]),
 }
 
 _lib = None

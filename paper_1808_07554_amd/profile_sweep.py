@@ -1,0 +1,115 @@
+"""Profiling workload and counter summary for the pressure sweep.
+
+Run under rocprofv3 (one counter per run):
+    rocprofv3 --pmc FETCH_SIZE -d DIR -o run -- python -m paper_1808_07554_amd.profile_sweep
+    rocprofv3 --pmc WRITE_SIZE -d DIR -o run -- python -m paper_1808_07554_amd.profile_sweep
+The workload is a 1 GiB plain copy (lbtp_copy_probe, the known-size
+reference) followed by a burst of plain pressure sweeps on the 4096 x 4096
+injection problem.  Then, on any machine:
+    python -m paper_1808_07554_amd.profile_sweep --summarize FETCH.csv WRITE.csv OUT.txt [--storage S]
+converts the counters of the sweep into HBM bytes per launch with the
+copy's bytes-per-count scale and writes a short text summary.
+"""
+import argparse
+import csv
+import hashlib
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+COPY_BYTES = 1 << 30
+
+
+def run(storage, n, sweeps):
+    import ctypes
+
+    import torch
+
+    from . import inputs, lbtp
+    dev = torch.device("cuda", 0)
+    lib = lbtp.load()
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream().cuda_stream
+    for _ in range(3):
+        rc = lib.lbtp_copy_probe(ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(a.data_ptr()), COPY_BYTES,
+                                 ctypes.c_void_p(stream))
+        assert rc == 0, rc
+    torch.cuda.synchronize()
+    del a, b
+    params, fl = inputs.injection_2d(n)
+    s = lbtp.from_problem(params, m=64, storage=storage)
+    s.set_fields(torch.from_numpy(inputs.f32(fl["K"]).ravel()).to(dev),
+                 torch.from_numpy(inputs.f32(fl["phi"]).ravel()).to(dev))
+    s.set_state(torch.from_numpy(inputs.f32(fl["P0"]).ravel()).to(dev),
+                torch.from_numpy(inputs.f32(fl["S0"]).ravel()).to(dev))
+    s.update_coefficients()
+    s.pressure_solve(-1.0, sweeps)
+    torch.cuda.synchronize()
+    print(f"profile workload done: copy {COPY_BYTES} B x3, {sweeps} sweeps at {n}^2 ({storage})", flush=True)
+
+
+def _counter_rows(path):
+    with open(path) as f:
+        rows = list(csv.DictReader(f))
+    out = []
+    for r in rows:
+        name = r.get("Kernel_Name") or r.get("Kernel-Name") or ""
+        val = r.get("Counter_Value") or r.get("Counter-Value")
+        cname = r.get("Counter_Name") or r.get("Counter-Name")
+        if val is None:
+            continue
+        out.append((name, cname, float(val)))
+    return out
+
+
+def _per_dispatch(rows, pattern, exclude=None):
+    vals = [v for (k, _, v) in rows if pattern in k and (exclude is None or exclude not in k)]
+    return sum(vals) / len(vals) if vals else None, len(vals)
+
+
+def summarize(fetch_csv, write_csv, out_txt, storage, n, command):
+    f_rows = _counter_rows(fetch_csv)
+    w_rows = _counter_rows(write_csv)
+    copy_f, ncf = _per_dispatch(f_rows, "copy_probe")
+    copy_w, ncw = _per_dispatch(w_rows, "copy_probe")
+    # plain sweeps: MODE 0 instantiation of the 4-node kernel
+    sw_f, nsf = _per_dispatch(f_rows, "f_sweep_vec_kernel")
+    sw_w, nsw = _per_dispatch(w_rows, "f_sweep_vec_kernel")
+    scale_f = COPY_BYTES / copy_f
+    scale_w = COPY_BYTES / copy_w
+    fetch_b = sw_f * scale_f
+    write_b = sw_w * scale_w
+    q1, pop = 4, (4 if storage == "fp32" else 2)
+    alg_read = n * n * (q1 * pop + 8)
+    alg_write = n * n * q1 * pop
+    src = os.path.join(HERE, "csrc", "lbtp_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    text = f"""Pressure sweep HBM traffic, heterogeneous injection 2-D {n}x{n}, D2Q5, {storage} storage
+command: {command}
+counters: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each from its own rocprofv3 --pmc run
+calibration: lbtp_copy_probe of {COPY_BYTES} B: FETCH_SIZE {copy_f:.1f} ({ncf} dispatches), WRITE_SIZE {copy_w:.1f} ({ncw}) -> {scale_f:.2f} / {scale_w:.2f} B per count
+f_sweep_vec_kernel ({nsf} dispatches): FETCH_SIZE {sw_f:.1f} -> {fetch_b / 1e6:.1f} MB read (algorithmic {alg_read / 1e6:.1f} MB, ratio {fetch_b / alg_read:.3f})
+f_sweep_vec_kernel ({nsw} dispatches): WRITE_SIZE {sw_w:.1f} -> {write_b / 1e6:.1f} MB written (algorithmic {alg_write / 1e6:.1f} MB, ratio {write_b / alg_write:.3f})
+bytes_per_launch: {fetch_b + write_b:.6e}
+algorithmic_bytes_per_launch: {alg_read + alg_write:.6e}
+source_sha256: {sha}
+"""
+    with open(out_txt, "w") as f:
+        f.write(text)
+    print(text)
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--storage", default="fp32")
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--sweeps", type=int, default=40)
+    ap.add_argument("--summarize", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_TXT"))
+    ap.add_argument("--command", default="rocprofv3 --pmc <COUNTER> -d DIR -o run -- python -m paper_1808_07554_amd.profile_sweep")
+    a = ap.parse_args()
+    if a.summarize:
+        summarize(*a.summarize, a.storage, a.n, a.command)
+    else:
+        run(a.storage, a.n, a.sweeps)
+        sys.exit(0)

@@ -12,8 +12,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared():
-    src = open(os.path.join(ROOT, "include", "lbtp.h")).read()
-    return sorted(set(re.findall(r"LBTP_API[^;(]*?\b(lbtp_\w+)\s*\(", src)))
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            names |= set(re.findall(r"LBTP_API[^;(]*?\b(lbtp_\w+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_the_binding_exports():
@@ -55,6 +59,12 @@ def test_inconsistent_periodicity_rejected():
     p.bc_f[0] = lbtp.BC_DIRICHLET      # -x walled, +x periodic
     h = ctypes.c_void_p()
     assert lib.lbtp_init(ctypes.byref(p), ctypes.byref(h)) == lbtp.EINVAL
+
+
+def test_copy_probe_rejects_bad_arguments_without_device():
+    lib = lbtp.load()
+    assert lib.lbtp_copy_probe(None, None, 16, None) == lbtp.EINVAL
+    assert lib.lbtp_copy_probe(ctypes.c_void_p(64), ctypes.c_void_p(128), 15, None) == lbtp.EINVAL
 
 
 def test_null_handles_rejected():
