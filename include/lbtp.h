@@ -194,6 +194,45 @@ LBTP_API long long lbtp_checkpoint_size(lbtp_ctx *ctx);
 LBTP_API int lbtp_get_state(lbtp_ctx *ctx, void *buf, long long nbytes, int on_device);
 LBTP_API int lbtp_put_state(lbtp_ctx *ctx, const void *buf, long long nbytes, int on_device);
 
+/* ------------------------------------------------------------------------
+ * Ensembles: n independent realisations (their own size, K, phi, boundary
+ * values and sources) advanced together, every coupled step covering all
+ * members with one launch per kernel.  Each member's pressure solve stops on
+ * its own; members that stopped drop out of the remaining sweeps.  The
+ * members' numbers are bit-identical to separate lbtp_ctx runs with the same
+ * parameters.  All members share lattice, storage, stream and the residual
+ * stride m, which must be even; nx % 4 == 0 for every member; max_iters of a
+ * step must be a positive multiple of m.  A NULL stream makes the ensemble
+ * use a stream of its own (HIP graphs cannot be captured on the null
+ * stream).
+ * ------------------------------------------------------------------------ */
+typedef struct lbtp_batch lbtp_batch;
+
+LBTP_API int lbtp_batch_init(const lbtp_params *members, int n, lbtp_batch **out);
+LBTP_API void lbtp_batch_destroy(lbtp_batch *b);
+LBTP_API int lbtp_batch_size(lbtp_batch *b);
+/* Per-member versions of lbtp_set_fields / lbtp_set_state (member in [0, n)). */
+LBTP_API int lbtp_batch_set_fields(lbtp_batch *b, int member, const float *K, const float *phi,
+                                   const float *Fp, const float *Fs, int on_device);
+LBTP_API int lbtp_batch_set_state(lbtp_batch *b, int member, const float *P0, const float *S0,
+                                  const float *dP0, const float *dS0, int on_device);
+/* nsteps coupled steps of every member (as lbtp_step).  iters (may be NULL)
+ * receives nsteps x n iteration counts, step-major. */
+LBTP_API int lbtp_batch_step(lbtp_batch *b, long long nsteps, double tol, long long max_iters,
+                             long long *iters);
+/* Per-member outputs, as lbtp_pressure / lbtp_saturation / lbtp_velocity /
+ * lbtp_mass (the ledger is the ensemble's record of the member's flux). */
+LBTP_API int lbtp_batch_pressure(lbtp_batch *b, int member, float *P, int on_device);
+LBTP_API int lbtp_batch_saturation(lbtp_batch *b, int member, float *S, int on_device);
+LBTP_API int lbtp_batch_velocity(lbtp_batch *b, int member, float *u, int on_device);
+LBTP_API int lbtp_batch_mass(lbtp_batch *b, int member, double *mass, double *ledger);
+/* Block width of the ensemble pressure sweep: 64, 128, 256 (default) or 512
+ * threads of four nodes each.  lbtp_batch_autotune times `sweeps` plain
+ * sweeps of the whole ensemble for each width (leaving the state unchanged)
+ * and keeps the fastest; *threads receives it. */
+LBTP_API int lbtp_batch_set_threads(lbtp_batch *b, int threads);
+LBTP_API int lbtp_batch_autotune(lbtp_batch *b, int sweeps, int *threads);
+
 /* Static description of a status code. */
 LBTP_API const char *lbtp_strerror(int status);
 

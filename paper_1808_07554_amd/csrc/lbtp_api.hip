@@ -715,3 +715,385 @@ int lbtp_copy_probe(void *dst, const void *src, long long bytes, void *stream) {
 }
 
 }  // extern "C"
+
+// ======================================================================
+// Ensembles.  A batch owns one lbtp_ctx per member (so every per-member call
+// reuses the single-realisation code and buffers) plus the tables that let
+// one launch cover all members.
+// ======================================================================
+struct lbtp_batch {
+  int n = 0, dim = 2, storage = 0, m = 64, nt = 256;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<lbtp_ctx *> ctx;
+  Member *d_mem = nullptr;
+  BCtl *d_ctl = nullptr, *h_ctl = nullptr;      // h_ctl pinned
+  int *d_tm_s = nullptr, *d_ti_s = nullptr;     // sweep tiling (4*nt nodes per tile)
+  int *d_tm_c = nullptr, *d_ti_c = nullptr;     // cell tiling (kCellTile nodes per tile)
+  int ntiles_s = 0, ntiles_c = 0, tiles_cap = 0;
+  double *partials = nullptr;
+  int *d_active = nullptr, *h_active = nullptr;  // h_active: pinned, two slots
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipGraphExec_t chunk = nullptr;
+  int gs = 0, f_local = 1;
+  long long step = 0;
+};
+
+namespace {
+
+void batch_free(lbtp_batch *b) {
+  if (!b) return;
+  if (b->chunk) (void)hipGraphExecDestroy(b->chunk);
+  void *bufs[] = {b->d_mem, b->d_ctl, b->d_tm_s, b->d_ti_s, b->d_tm_c, b->d_ti_c, b->partials, b->d_active};
+  for (void *p : bufs)
+    if (p) (void)hipFree(p);
+  if (b->h_ctl) (void)hipHostFree(b->h_ctl);
+  if (b->h_active) (void)hipHostFree(b->h_active);
+  for (int i = 0; i < 2; ++i)
+    if (b->ev[i]) (void)hipEventDestroy(b->ev[i]);
+  for (lbtp_ctx *c : b->ctx) lbtp_destroy(c);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+// (Re)build the member table and both tile tables for sweep width nt.
+int batch_tables(lbtp_batch *b, int nt) {
+  std::vector<Member> mem(b->n);
+  std::vector<int> tm_s, ti_s, tm_c, ti_c;
+  const int tile_s = 4 * nt;
+  for (int i = 0; i < b->n; ++i) {
+    lbtp_ctx *c = b->ctx[i];
+    Member &M = mem[i];
+    memset(&M, 0, sizeof(M));
+    M.kc = c->kc;
+    M.f[0] = fptrs(c, c->fbuf[0]);
+    M.f[1] = fptrs(c, c->fbuf[1]);
+    M.g[0] = gptrs(c, c->gbuf[0]);
+    M.g[1] = gptrs(c, c->gbuf[1]);
+    M.Pb[0] = c->Pb[0];
+    M.Pb[1] = c->Pb[1];
+    M.K = c->K;
+    M.phi = c->phi;
+    M.S = c->S;
+    M.itau = c->itau;
+    M.Fp = c->has_Fp ? c->Fp : nullptr;
+    M.Fs = c->has_Fs ? c->Fs : nullptr;
+    const int ns = (int)((c->ncell + tile_s - 1) / tile_s);
+    const int nc = (int)((c->ncell + kCellTile - 1) / kCellTile);
+    M.tstart_s = (int)tm_s.size();
+    M.ntiles_s = ns;
+    M.tstart_c = (int)tm_c.size();
+    M.ntiles_c = nc;
+    for (int t = 0; t < ns; ++t) {
+      tm_s.push_back(i);
+      ti_s.push_back(t);
+    }
+    for (int t = 0; t < nc; ++t) {
+      tm_c.push_back(i);
+      ti_c.push_back(t);
+    }
+  }
+  const int need = (int)(tm_s.size() > tm_c.size() ? tm_s.size() : tm_c.size());
+  if (need > b->tiles_cap) {
+    for (int **p : {&b->d_tm_s, &b->d_ti_s, &b->d_tm_c, &b->d_ti_c}) {
+      if (*p) (void)hipFree(*p);
+      *p = nullptr;
+      if (hipMalloc((void **)p, need * sizeof(int)) != hipSuccess) return LBTP_ENOMEM;
+    }
+    if (b->partials) (void)hipFree(b->partials);
+    b->partials = nullptr;
+    if (hipMalloc((void **)&b->partials, (size_t)need * 2 * sizeof(double)) != hipSuccess) return LBTP_ENOMEM;
+    b->tiles_cap = need;
+  }
+  b->ntiles_s = (int)tm_s.size();
+  b->ntiles_c = (int)tm_c.size();
+  b->nt = nt;
+  HIP_TRY(hipMemcpyAsync(b->d_mem, mem.data(), b->n * sizeof(Member), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->d_tm_s, tm_s.data(), tm_s.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->d_ti_s, ti_s.data(), ti_s.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->d_tm_c, tm_c.data(), tm_c.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->d_ti_c, ti_c.data(), ti_c.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  if (b->chunk) {
+    (void)hipGraphExecDestroy(b->chunk);
+    b->chunk = nullptr;
+  }
+  return LBTP_OK;
+}
+
+// Enqueue one chunk: sweeps j = 1 .. m (the last one evaluates the stopping
+// rule and re-bases), then the per-member finish.
+int batch_enqueue_chunk(lbtp_batch *b) {
+  for (int j = 1; j <= b->m; ++j) {
+    const int mode = (j == b->m) ? 2 : 0;
+    HIP_TRY(batch_launch_sweep(b->nt, b->dim, b->storage, mode, 0, b->ntiles_s, b->d_mem, b->d_ctl, b->d_tm_s,
+                               b->d_ti_s, b->partials, j, b->stream));
+  }
+  HIP_TRY(batch_launch_finish(b->n, b->d_mem, b->d_ctl, b->partials, b->m, b->d_active, b->stream));
+  return LBTP_OK;
+}
+
+int batch_capture(lbtp_batch *b) {
+  if (b->chunk) return LBTP_OK;
+  HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  int rc = batch_enqueue_chunk(b);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return LBTP_EHIP;
+  e = hipGraphInstantiate(&b->chunk, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    b->chunk = nullptr;
+    return LBTP_EHIP;
+  }
+  return LBTP_OK;
+}
+
+bool batch_ready(const lbtp_batch *b) {
+  for (lbtp_ctx *c : b->ctx)
+    if (!c->have_state) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbtp_batch_init(const lbtp_params *members, int n, lbtp_batch **out) {
+  if (!out || !members || n < 1) return LBTP_EINVAL;
+  *out = nullptr;
+  const lbtp_params &p0 = members[0];
+  if (p0.residual_stride < 2 || p0.residual_stride % 2) return LBTP_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    const lbtp_params &p = members[i];
+    if (p.lattice != p0.lattice || p.storage != p0.storage || p.residual_stride != p0.residual_stride ||
+        p.stream != p0.stream)
+      return LBTP_EINVAL;
+    if (p.nx % 4) return LBTP_EINVAL;   // the ensemble sweep runs four nodes per thread
+    int rc = validate(&p);
+    if (rc) return rc;
+  }
+  lbtp_batch *b = new lbtp_batch();
+  b->n = n;
+  b->dim = p0.lattice == LBTP_D2Q5 ? 2 : 3;
+  b->storage = p0.storage;
+  b->m = p0.residual_stride;
+  if (p0.stream) {
+    b->stream = (hipStream_t)p0.stream;
+  } else {
+    // graph capture needs a stream other than the null stream
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      return LBTP_EHIP;
+    }
+    b->own_stream = true;
+  }
+  for (int i = 0; i < n; ++i) {
+    lbtp_params p = members[i];
+    p.stream = b->stream;
+    lbtp_ctx *c = nullptr;
+    int rc = lbtp_init(&p, &c);
+    if (rc) {
+      batch_free(b);
+      return rc;
+    }
+    b->ctx.push_back(c);
+  }
+  if (hipMalloc((void **)&b->d_mem, n * sizeof(Member)) != hipSuccess ||
+      hipMalloc((void **)&b->d_ctl, n * sizeof(BCtl)) != hipSuccess ||
+      hipMalloc((void **)&b->d_active, sizeof(int)) != hipSuccess ||
+      hipHostMalloc((void **)&b->h_ctl, n * sizeof(BCtl), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&b->h_active, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    batch_free(b);
+    return LBTP_ENOMEM;
+  }
+  memset(b->h_ctl, 0, n * sizeof(BCtl));
+  for (int i = 0; i < 2; ++i) {
+    if (hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming) != hipSuccess) {
+      batch_free(b);
+      return LBTP_EHIP;
+    }
+  }
+  if (hipMemcpyAsync(b->d_ctl, b->h_ctl, n * sizeof(BCtl), hipMemcpyHostToDevice, b->stream) != hipSuccess) {
+    batch_free(b);
+    return LBTP_EHIP;
+  }
+  int rc = batch_tables(b, 256);
+  if (rc) {
+    batch_free(b);
+    return rc;
+  }
+  *out = b;
+  return LBTP_OK;
+}
+
+void lbtp_batch_destroy(lbtp_batch *b) { batch_free(b); }
+
+int lbtp_batch_size(lbtp_batch *b) { return b ? b->n : LBTP_EINVAL; }
+
+int lbtp_batch_set_fields(lbtp_batch *b, int i, const float *K, const float *phi, const float *Fp, const float *Fs,
+                          int on_device) {
+  if (!b || i < 0 || i >= b->n) return LBTP_EINVAL;
+  int rc = lbtp_set_fields(b->ctx[i], K, phi, Fp, Fs, on_device);
+  if (rc) return rc;
+  return batch_tables(b, b->nt);   // source pointers may have appeared or gone
+}
+
+int lbtp_batch_set_state(lbtp_batch *b, int i, const float *P0, const float *S0, const float *dP0,
+                         const float *dS0, int on_device) {
+  if (!b || i < 0 || i >= b->n) return LBTP_EINVAL;
+  int rc = lbtp_set_state(b->ctx[i], P0, S0, dP0, dS0, on_device);
+  if (rc) return rc;
+  // a fresh state: base buffer 0, no ledger, local form (all members are
+  // (re)initialised before the first ensemble step)
+  BCtl h{};
+  h.pb = 0;
+  HIP_TRY(hipMemcpyAsync(&b->d_ctl[i], &h, sizeof(BCtl), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  b->gs = 0;
+  b->f_local = 1;
+  b->step = 0;
+  return batch_tables(b, b->nt);   // dev_scale of fp16 members is set by set_state
+}
+
+int lbtp_batch_set_threads(lbtp_batch *b, int nt) {
+  if (!b || (nt != 64 && nt != 128 && nt != 256 && nt != 512)) return LBTP_EINVAL;
+  return batch_tables(b, nt);
+}
+
+int lbtp_batch_step(lbtp_batch *b, long long nsteps, double tol, long long max_iters, long long *iters) {
+  if (!b || nsteps < 0 || max_iters < b->m || max_iters % b->m) return LBTP_EINVAL;
+  if (!batch_ready(b)) return LBTP_ESTATE;
+  int rc = batch_capture(b);
+  if (rc) return rc;
+  int worst = LBTP_OK;
+  for (long long s = 0; s < nsteps; ++s) {
+    // coefficients of every member
+    HIP_TRY(batch_launch_moments(b->dim, b->ntiles_c, b->d_mem, b->d_tm_c, b->d_ti_c, b->partials, b->gs, 1,
+                                 b->stream));
+    HIP_TRY(batch_launch_sum(b->n, b->d_mem, b->d_ctl, b->partials, 0, b->stream));
+    // pressure solve of every member: first sweep (re-base), then chunks
+    HIP_TRY(batch_launch_reset(b->n, b->d_ctl, max_iters, tol, b->d_active, b->stream));
+    HIP_TRY(batch_launch_sweep(b->nt, b->dim, b->storage, 1, b->f_local, b->ntiles_s, b->d_mem, b->d_ctl, b->d_tm_s,
+                               b->d_ti_s, b->partials, 0, b->stream));
+    HIP_TRY(batch_launch_flip(b->n, b->d_ctl, b->stream));
+    int slot = 0;
+    bool pending[2] = {false, false};
+    for (long long chunk = 1;; ++chunk) {
+      HIP_TRY(hipGraphLaunch(b->chunk, b->stream));
+      HIP_TRY(hipMemcpyAsync(&b->h_active[slot], b->d_active, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+      HIP_TRY(hipEventRecord(b->ev[slot], b->stream));
+      pending[slot] = true;
+      const int prev = slot ^ 1;
+      int wait = chunk == 1 ? slot : (pending[prev] ? prev : -1);
+      bool stop = chunk * b->m >= max_iters;
+      if (wait >= 0) {
+        HIP_TRY(hipEventSynchronize(b->ev[wait]));
+        pending[wait] = false;
+        if (b->h_active[wait] == 0) stop = true;
+      }
+      slot = prev;
+      if (stop) break;
+    }
+    // saturation step of every member, then its flux into the ledger
+    HIP_TRY(batch_launch_gsweep(b->dim, b->storage, 0, b->ntiles_c, b->d_mem, b->d_ctl, b->d_tm_c, b->d_ti_c,
+                                b->partials, b->gs, b->stream));
+    HIP_TRY(batch_launch_sum(b->n, b->d_mem, b->d_ctl, b->partials, 1, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->h_ctl, b->d_ctl, b->n * sizeof(BCtl), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->gs ^= 1;
+    b->f_local = 0;
+    b->step += 1;
+    for (int i = 0; i < b->n; ++i) {
+      const BCtl &h = b->h_ctl[i];
+      if (iters) iters[s * b->n + i] = h.K;
+      if (h.status == LBTP_EUNSTABLE) return LBTP_EUNSTABLE;
+      if (h.status == LBTP_NOT_CONVERGED && tol >= 0.0) worst = LBTP_NOT_CONVERGED;
+      // keep the member contexts consistent with the ensemble state
+      lbtp_ctx *c = b->ctx[i];
+      c->fs = 0;
+      c->pbs = h.pb;
+      c->gs = b->gs;
+      c->f_local = 0;
+      c->step = b->step;
+      c->have_coef = 0;
+    }
+  }
+  return worst;
+}
+
+int lbtp_batch_pressure(lbtp_batch *b, int i, float *P, int on_device) {
+  if (!b || i < 0 || i >= b->n) return LBTP_EINVAL;
+  return lbtp_pressure(b->ctx[i], P, on_device);
+}
+
+int lbtp_batch_saturation(lbtp_batch *b, int i, float *S, int on_device) {
+  if (!b || i < 0 || i >= b->n) return LBTP_EINVAL;
+  return lbtp_saturation(b->ctx[i], S, on_device);
+}
+
+int lbtp_batch_velocity(lbtp_batch *b, int i, float *u, int on_device) {
+  if (!b || i < 0 || i >= b->n) return LBTP_EINVAL;
+  return lbtp_velocity(b->ctx[i], u, on_device);
+}
+
+int lbtp_batch_mass(lbtp_batch *b, int i, double *mass, double *ledger) {
+  if (!b || i < 0 || i >= b->n) return LBTP_EINVAL;
+  double m = 0.0;
+  int rc = lbtp_mass(b->ctx[i], &m, nullptr);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(&b->h_ctl[i], &b->d_ctl[i], sizeof(BCtl), hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  if (mass) *mass = m;
+  if (ledger) *ledger = b->h_ctl[i].ledger;
+  return LBTP_OK;
+}
+
+int lbtp_batch_autotune(lbtp_batch *b, int sweeps, int *threads) {
+  if (!b || sweeps < 1) return LBTP_EINVAL;
+  if (!batch_ready(b)) return LBTP_ESTATE;
+  // time plain sweeps of every member (state untouched: sweeps read buffer 0,
+  // write buffer 1) for each block width and keep the fastest
+  hipEvent_t t0, t1;
+  HIP_TRY(hipEventCreate(&t0));
+  HIP_TRY(hipEventCreate(&t1));
+  const int cand[4] = {64, 128, 256, 512};
+  int best = b->nt;
+  float best_ms = 1e30f;
+  int rc = LBTP_OK;
+  HIP_TRY(batch_launch_reset(b->n, b->d_ctl, 1LL << 60, -1.0, b->d_active, b->stream));
+  for (int ci = 0; ci < 4 && !rc; ++ci) {
+    rc = batch_tables(b, cand[ci]);
+    if (rc) break;
+    for (int w = 0; w < 2 && !rc; ++w)
+      if (batch_launch_sweep(b->nt, b->dim, b->storage, 0, b->f_local, b->ntiles_s, b->d_mem, b->d_ctl, b->d_tm_s,
+                             b->d_ti_s, b->partials, 0, b->stream) != hipSuccess)
+        rc = LBTP_EHIP;
+    if (rc) break;
+    if (hipEventRecord(t0, b->stream) != hipSuccess) rc = LBTP_EHIP;
+    for (int r = 0; r < sweeps && !rc; ++r)
+      if (batch_launch_sweep(b->nt, b->dim, b->storage, 0, b->f_local, b->ntiles_s, b->d_mem, b->d_ctl, b->d_tm_s,
+                             b->d_ti_s, b->partials, 0, b->stream) != hipSuccess)
+        rc = LBTP_EHIP;
+    if (!rc && (hipEventRecord(t1, b->stream) != hipSuccess || hipEventSynchronize(t1) != hipSuccess)) rc = LBTP_EHIP;
+    float ms = 0.f;
+    if (!rc && hipEventElapsedTime(&ms, t0, t1) != hipSuccess) rc = LBTP_EHIP;
+    if (!rc && ms < best_ms) {
+      best_ms = ms;
+      best = cand[ci];
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (rc) return rc;
+  rc = batch_tables(b, best);
+  if (rc) return rc;
+  if (threads) *threads = best;
+  return LBTP_OK;
+}
+
+}  // extern "C"

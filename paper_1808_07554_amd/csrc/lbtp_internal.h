@@ -93,6 +93,48 @@ hipError_t launch_copy_probe(const void *src, void *dst, long long n4, hipStream
 
 inline size_t storage_bytes(int storage) { return storage == LBTP_FP32 ? 4 : 2; }
 
+// ------------------------------------------------------------------ ensembles
+// One member of an ensemble: its lattice constants and device buffers, and
+// its tile ranges in the sweep tiling (4*NT nodes per tile) and the cell
+// tiling (1024 nodes per tile).
+struct Member {
+  KC kc;
+  FPtrs f[2];
+  GPtrs g[2];
+  float *Pb[2];
+  float *K, *phi, *S, *itau, *Fp, *Fs;
+  int tstart_s, ntiles_s, tstart_c, ntiles_c;
+};
+
+// Device control block of one member's pressure solve and reductions.
+struct BCtl {
+  int done;          // the member's current solve has stopped
+  int status;        // LBTP_OK, LBTP_NOT_CONVERGED or LBTP_EUNSTABLE
+  int pb;            // base buffer of the member's pressure state
+  int pad;
+  long long kbase;   // iteration index before the current chunk
+  long long kmax;
+  long long K;       // iterations of the last solve
+  double tol;
+  double resid;
+  double mass;
+  double ledger;
+};
+
+constexpr int kCellTile = 1024;   // nodes per tile of the ensemble cell kernels
+
+hipError_t batch_launch_sweep(int nt, int dim, int storage, int mode, int local, int nblk, const Member *mem,
+                              const BCtl *ctl, const int *tm, const int *ti, double *part, int j, hipStream_t s);
+hipError_t batch_launch_moments(int dim, int nblk, const Member *mem, const int *tm, const int *ti, double *part,
+                                int gs, int write_coef, hipStream_t s);
+hipError_t batch_launch_gsweep(int dim, int storage, int local, int nblk, const Member *mem, const BCtl *ctl,
+                               const int *tm, const int *ti, double *part, int gs, hipStream_t s);
+hipError_t batch_launch_finish(int n, const Member *mem, BCtl *ctl, const double *part, int m, int *active,
+                               hipStream_t s);
+hipError_t batch_launch_reset(int n, BCtl *ctl, long long kmax, double tol, int *active, hipStream_t s);
+hipError_t batch_launch_flip(int n, BCtl *ctl, hipStream_t s);
+hipError_t batch_launch_sum(int n, const Member *mem, BCtl *ctl, const double *part, int ledger, hipStream_t s);
+
 inline int nblocks(long long n);
 // Blocks of a pull-form pressure sweep (and so its residual partials): rows
 // with nx % 4 == 0 run four nodes per thread.

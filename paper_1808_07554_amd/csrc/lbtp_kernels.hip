@@ -36,173 +36,10 @@
 
 #include <type_traits>
 
-#include "lbtp_internal.h"
+#include "lbtp_device.h"
 
 namespace lbtp {
 namespace {
-
-struct Cell {
-  int c, x, y, z;
-};
-
-__device__ inline Cell cell_of(int c, const KC &kc) {
-  Cell r;
-  r.c = c;
-  int row = c / kc.nx;
-  r.x = c - row * kc.nx;
-  r.z = row / kc.ny;
-  r.y = row - r.z * kc.ny;
-  return r;
-}
-
-__device__ inline int coord(const Cell &q, int a) { return a == 0 ? q.x : (a == 1 ? q.y : q.z); }
-__device__ inline int extent(const KC &kc, int a) { return a == 0 ? kc.nx : (a == 1 ? kc.ny : kc.nz); }
-__device__ inline int stride_of(const KC &kc, int a) { return a == 0 ? 1 : (a == 1 ? kc.nx : kc.nx * kc.ny); }
-
-// ------------------------------------------------------------ storage types
-// bf16 is kept as raw 16-bit words (round to nearest even on store).
-struct bf16_t {
-  uint16_t u;
-};
-
-template <typename T>
-struct Storage;
-
-template <>
-struct Storage<float> {
-  static __device__ inline float load(const float *p, int i, float) { return p[i]; }
-  static __device__ inline void store(float *p, int i, float v, float) { p[i] = v; }
-};
-
-// fp16 values are scaled by a power of two (kc.dev_scale) to keep the
-// deviations in the normal range.
-template <>
-struct Storage<_Float16> {
-  static __device__ inline float load(const _Float16 *p, int i, float inv_s) { return (float)p[i] * inv_s; }
-  static __device__ inline void store(_Float16 *p, int i, float v, float s) { p[i] = (_Float16)(v * s); }
-};
-
-template <>
-struct Storage<bf16_t> {
-  static __device__ inline float load(const bf16_t *p, int i, float) {
-    return __uint_as_float((uint32_t)p[i].u << 16);
-  }
-  static __device__ inline void store(bf16_t *p, int i, float v, float) {
-    const uint32_t u = __float_as_uint(v);
-    const uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
-    bf16_t b;
-    b.u = (uint16_t)(r >> 16);
-    p[i] = b;
-  }
-};
-
-template <typename T>
-struct FP {
-  T *p[6];
-};
-
-template <typename T>
-__host__ __device__ inline FP<T> typed(const FPtrs &f) {
-  FP<T> r;
-  for (int j = 0; j < 6; ++j) r.p[j] = (T *)f.p[j];
-  return r;
-}
-
-// Pre-collision deviations e_j at node q (moving directions) against P_b(q).
-template <int DIM, typename T, bool LOCAL>
-__device__ inline void load_e(const FP<T> &fin, const float *__restrict__ Pb, const Cell &q, const KC &kc,
-                              float pb, float *e) {
-#pragma unroll
-  for (int j = 0; j < 2 * DIM; ++j) {
-    if (LOCAL) {
-      e[j] = Storage<T>::load(fin.p[j], q.c, kc.inv_dev_scale);
-      continue;
-    }
-    const int a = dir_axis(j), s = dir_sign(j);
-    const int x = coord(q, a), n = extent(kc, a), st = stride_of(kc, a);
-    const bool out = (s > 0) ? (x == 0) : (x == n - 1);
-    if (!out) {
-      const int src = q.c - s * st;
-      e[j] = Storage<T>::load(fin.p[j], src, kc.inv_dev_scale) + kc.w1 * (Pb[src] - pb);
-    } else {
-      const int face = 2 * a + (s > 0 ? 0 : 1);
-      const int bc = kc.bc_f[face];
-      if (bc == LBTP_BC_PERIODIC) {
-        const int src = q.c - s * st + s * n * st;
-        e[j] = Storage<T>::load(fin.p[j], src, kc.inv_dev_scale) + kc.w1 * (Pb[src] - pb);
-      } else {
-        const float o = Storage<T>::load(fin.p[dir_opp(j)], q.c, kc.inv_dev_scale);
-        e[j] = (bc == LBTP_BC_DIRICHLET) ? (2.0f * kc.w1 * (kc.Pw[face] - pb) - o) : o;
-      }
-    }
-  }
-}
-
-// P - P_b from the deviations (eq. 3-9a).
-template <int DIM>
-__device__ inline float dpressure(const float *e, const KC &kc) {
-  float s = e[0];
-#pragma unroll
-  for (int j = 1; j < 2 * DIM; ++j) s += e[j];
-  return s * kc.inv_1mw0;
-}
-
-// First moment sum_i c_i f_i = sum_i c_i e_i along each axis (the base part cancels).
-template <int DIM>
-__device__ inline void moment_c(const float *e, const KC &kc, float *m1) {
-  m1[0] = kc.c * (e[0] - e[2]);
-  m1[1] = kc.c * (e[1] - e[3]);
-  if (DIM == 3) m1[2] = kc.c * (e[4] - e[5]);
-}
-
-template <int DIM>
-__device__ inline float sum_g(const float *g) {
-  float s = g[0];
-#pragma unroll
-  for (int i = 1; i <= 2 * DIM; ++i) s += g[i];
-  return s;
-}
-
-// eq. 3-9b
-__device__ inline float saturation_of(float gsum, float Fs, float phi, const KC &kc) {
-  return (gsum + kc.half_dt * Fs) / phi;
-}
-
-// 1/tau_f from eq. 3-11a with D_p = K lambda_t (eq. 2-9, 2-16).
-__device__ inline float inv_tau_f_of(float S, float K, const KC &kc) {
-  const float lw = S * S * kc.inv_mu_w;
-  const float ln = (1.0f - S) * (1.0f - S) * kc.inv_mu_n;
-  const float Dp = K * (lw + ln);
-  return 1.0f / (0.5f + Dp * kc.inv_cs2dt);
-}
-
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Block sum of NV doubles, written by thread 0 to out[NV*blockIdx.x + v].
-template <int NV>
-__device__ inline void block_sum(double *v, double *out) {
-  __shared__ double sh[NV][kThreads / 64];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) sh[i][wid] = v[i];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      double t = 0.0;
-      for (int w = 0; w < kThreads / 64; ++w) t += sh[i][w];
-      out[NV * blockIdx.x + i] = t;
-    }
-  }
-}
 
 // ------------------------------------------------------------- pressure sweep
 // One iteration of eq. 3-1: stream, P (eq. 3-9a), BGK collision with the local
@@ -219,105 +56,11 @@ __global__ __launch_bounds__(kThreads) void f_sweep_kernel(KC kc, FPtrs fin_, FP
                                                            const Ctl *__restrict__ ctl, long long k) {
   // a converged (or finished) solve turns the remaining queued sweeps into no-ops
   if (ctl->done || k > ctl->kmax) return;
-  const FP<T> fin = typed<T>(fin_), fout = typed<T>(fout_);
   const int c = blockIdx.x * kThreads + threadIdx.x;
   double acc[2] = {0.0, 0.0};
-  if (c < kc.ncell) {
-    const Cell q = cell_of(c, kc);
-    const float pb = Pb_in[c];
-    float e[2 * DIM];
-    load_e<DIM, T, LOCAL>(fin, Pb_in, q, kc, pb, e);
-    const float dP = dpressure<DIM>(e, kc);
-    const float wdP = kc.w1 * dP;
-    const float it = itau[c];
-    float add = HAS_FP ? kc.dt * kc.wbar * Fp[c] : 0.0f;
-    if (MODE >= 1) {
-      const float P = pb + dP;
-      add += kc.w1 * (pb - P);          // re-base to P_b = P (exact difference)
-      Pb_out[c] = P;
-      if (MODE == 2) {
-        acc[0] = (double)dP * (double)dP;
-        acc[1] = (double)P * (double)P;
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 2 * DIM; ++j) {
-      float o = e[j] + (wdP - e[j]) * it;
-      if (HAS_FP || MODE >= 1) o += add;
-      Storage<T>::store(fout.p[j], c, o, kc.dev_scale);
-    }
-  }
+  if (c < kc.ncell)
+    sweep_cell<DIM, T, LOCAL, MODE, HAS_FP>(kc, typed<T>(fin_), typed<T>(fout_), Pb_in, Pb_out, itau, Fp, c, acc);
   if (MODE == 2) block_sum<2>(acc, partials);
-}
-
-// ------------------------------------------------- pressure sweep, 4 nodes / thread
-// The same sweep with each thread owning four consecutive nodes of a row
-// (nx % 4 == 0), so populations, base and 1/tau_f move as 16-byte (float) or
-// 8-byte (16-bit) vectors.  The x-streamed populations and the x-neighbour
-// bases come from the adjacent lane of the wavefront (a lane shuffle) or, at a
-// wavefront edge, from one scalar load; rows at walls use the Section 4 rules.
-template <typename T>
-struct Vec4;
-
-// Stores are non-temporal: a sweep's output is only read by the next sweep,
-// after the whole grid has passed, so keeping it in the caches only evicts
-// the neighbour rows the current sweep still reads.
-typedef float float4_t __attribute__((ext_vector_type(4)));
-typedef uint32_t uint2_t __attribute__((ext_vector_type(2)));
-
-template <>
-struct Vec4<float> {
-  static __device__ inline float4 load(const float *p, int i, float) { return *(const float4 *)(p + i); }
-  static __device__ inline void store(float *p, int i, float4 v, float) {
-    const float4_t w = {v.x, v.y, v.z, v.w};
-    __builtin_nontemporal_store(w, (float4_t *)(p + i));
-  }
-};
-
-typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
-
-template <>
-struct Vec4<_Float16> {
-  static __device__ inline float4 load(const _Float16 *p, int i, float inv_s) {
-    const half4_t h = *(const half4_t *)(p + i);
-    return make_float4((float)h.x * inv_s, (float)h.y * inv_s, (float)h.z * inv_s, (float)h.w * inv_s);
-  }
-  static __device__ inline void store(_Float16 *p, int i, float4 v, float s) {
-    half4_t h;
-    h.x = (_Float16)(v.x * s);
-    h.y = (_Float16)(v.y * s);
-    h.z = (_Float16)(v.z * s);
-    h.w = (_Float16)(v.w * s);
-    __builtin_nontemporal_store(h, (half4_t *)(p + i));
-  }
-};
-
-__device__ inline uint32_t bf16_round(float v) {
-  const uint32_t u = __float_as_uint(v);
-  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
-}
-
-template <>
-struct Vec4<bf16_t> {
-  static __device__ inline float4 load(const bf16_t *p, int i, float) {
-    const uint2 w = *(const uint2 *)(p + i);
-    return make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u),
-                       __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xFFFF0000u));
-  }
-  static __device__ inline void store(bf16_t *p, int i, float4 v, float) {
-    uint2_t w;
-    w.x = bf16_round(v.x) | (bf16_round(v.y) << 16);
-    w.y = bf16_round(v.z) | (bf16_round(v.w) << 16);
-    __builtin_nontemporal_store(w, (uint2_t *)(p + i));
-  }
-};
-
-__device__ inline float f4get(const float4 &v, int i) { return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w)); }
-__device__ inline void f4set(float4 &v, int i, float x) {
-  if (i == 0) v.x = x;
-  else if (i == 1) v.y = x;
-  else if (i == 2) v.z = x;
-  else v.w = x;
 }
 
 template <int DIM, typename T, int MODE, bool HAS_FP>
@@ -329,157 +72,9 @@ __global__ __launch_bounds__(kThreads) void f_sweep_vec_kernel(KC kc, FPtrs fin_
                                                                double *__restrict__ partials,
                                                                const Ctl *__restrict__ ctl, long long k) {
   if (ctl->done || k > ctl->kmax) return;
-  const FP<T> fin = typed<T>(fin_), fout = typed<T>(fout_);
-  const int n4 = kc.ncell >> 2;
-  const int qi = blockIdx.x * kThreads + threadIdx.x;
-  const bool active = qi < n4;
-  const int c = (active ? qi : n4 - 1) << 2;     // first of the four nodes
-  const int lane = threadIdx.x & 63;
-  const int row = c / kc.nx;
-  const int x0 = c - row * kc.nx;
-  const int z = row / kc.ny;
-  const int y = row - z * kc.ny;
-  const float is = kc.inv_dev_scale;
-
-  const float4 pb = *(const float4 *)(Pb_in + c);
-  // x-streamed populations: +x (j = 0) pulls from x - 1, -x (j = 2) from x + 1
-  const float4 A = Vec4<T>::load(fin.p[0], c, is);
-  const float4 B = Vec4<T>::load(fin.p[2], c, is);
-  float a_left = __shfl_up(A.w, 1, 64), pb_left = __shfl_up(pb.w, 1, 64);
-  float b_right = __shfl_down(B.x, 1, 64), pb_right = __shfl_down(pb.x, 1, 64);
-
-  float4 e[2 * DIM];
-  // +x for nodes 1..3 from the own vector, node 0 from the left neighbour
-  e[0] = make_float4(0.f, A.x + kc.w1 * (pb.x - pb.y), A.y + kc.w1 * (pb.y - pb.z), A.z + kc.w1 * (pb.z - pb.w));
-  e[2] = make_float4(B.y + kc.w1 * (pb.y - pb.x), B.z + kc.w1 * (pb.z - pb.y), B.w + kc.w1 * (pb.w - pb.z), 0.f);
-  if (x0 == 0) {
-    const int bc = kc.bc_f[0];
-    if (bc == LBTP_BC_PERIODIC) {
-      const int src = c + kc.nx - 1;
-      e[0].x = Storage<T>::load(fin.p[0], src, is) + kc.w1 * (Pb_in[src] - pb.x);
-    } else {
-      e[0].x = (bc == LBTP_BC_DIRICHLET) ? (2.0f * kc.w1 * (kc.Pw[0] - pb.x) - B.x) : B.x;
-    }
-  } else {
-    if (lane == 0) {
-      a_left = Storage<T>::load(fin.p[0], c - 1, is);
-      pb_left = Pb_in[c - 1];
-    }
-    e[0].x = a_left + kc.w1 * (pb_left - pb.x);
-  }
-  if (x0 + 4 == kc.nx) {
-    const int bc = kc.bc_f[1];
-    if (bc == LBTP_BC_PERIODIC) {
-      const int src = c + 3 - (kc.nx - 1);
-      e[2].w = Storage<T>::load(fin.p[2], src, is) + kc.w1 * (Pb_in[src] - pb.w);
-    } else {
-      e[2].w = (bc == LBTP_BC_DIRICHLET) ? (2.0f * kc.w1 * (kc.Pw[1] - pb.w) - A.w) : A.w;
-    }
-  } else {
-    if (lane == 63) {
-      b_right = Storage<T>::load(fin.p[2], c + 4, is);
-      pb_right = Pb_in[c + 4];
-    }
-    e[2].w = b_right + kc.w1 * (pb_right - pb.w);
-  }
-  // y (and z) streamed populations: whole vectors from the neighbouring row
-#pragma unroll
-  for (int a = 1; a < DIM; ++a) {
-    const int jp = (a == 1) ? 1 : 4, jm = (a == 1) ? 3 : 5;   // +a and -a directions
-    const int coordv = (a == 1) ? y : z;
-    const int n = (a == 1) ? kc.ny : kc.nz;
-    const int st = (a == 1) ? kc.nx : kc.nx * kc.ny;
-    // +a pulls from coord - 1
-    if (coordv == 0) {
-      const int bc = kc.bc_f[2 * a];
-      if (bc == LBTP_BC_PERIODIC) {
-        const int src = c + (n - 1) * st;
-        const float4 v = Vec4<T>::load(fin.p[jp], src, is);
-        const float4 q = *(const float4 *)(Pb_in + src);
-        e[jp] = make_float4(v.x + kc.w1 * (q.x - pb.x), v.y + kc.w1 * (q.y - pb.y), v.z + kc.w1 * (q.z - pb.z),
-                            v.w + kc.w1 * (q.w - pb.w));
-      } else {
-        const float4 o = Vec4<T>::load(fin.p[jm], c, is);
-        if (bc == LBTP_BC_DIRICHLET) {
-          const float pw = kc.Pw[2 * a];
-          e[jp] = make_float4(2.0f * kc.w1 * (pw - pb.x) - o.x, 2.0f * kc.w1 * (pw - pb.y) - o.y,
-                              2.0f * kc.w1 * (pw - pb.z) - o.z, 2.0f * kc.w1 * (pw - pb.w) - o.w);
-        } else {
-          e[jp] = o;
-        }
-      }
-    } else {
-      const int src = c - st;
-      const float4 v = Vec4<T>::load(fin.p[jp], src, is);
-      const float4 q = *(const float4 *)(Pb_in + src);
-      e[jp] = make_float4(v.x + kc.w1 * (q.x - pb.x), v.y + kc.w1 * (q.y - pb.y), v.z + kc.w1 * (q.z - pb.z),
-                          v.w + kc.w1 * (q.w - pb.w));
-    }
-    // -a pulls from coord + 1
-    if (coordv == n - 1) {
-      const int bc = kc.bc_f[2 * a + 1];
-      if (bc == LBTP_BC_PERIODIC) {
-        const int src = c - (n - 1) * st;
-        const float4 v = Vec4<T>::load(fin.p[jm], src, is);
-        const float4 q = *(const float4 *)(Pb_in + src);
-        e[jm] = make_float4(v.x + kc.w1 * (q.x - pb.x), v.y + kc.w1 * (q.y - pb.y), v.z + kc.w1 * (q.z - pb.z),
-                            v.w + kc.w1 * (q.w - pb.w));
-      } else {
-        const float4 o = Vec4<T>::load(fin.p[jp], c, is);
-        if (bc == LBTP_BC_DIRICHLET) {
-          const float pw = kc.Pw[2 * a + 1];
-          e[jm] = make_float4(2.0f * kc.w1 * (pw - pb.x) - o.x, 2.0f * kc.w1 * (pw - pb.y) - o.y,
-                              2.0f * kc.w1 * (pw - pb.z) - o.z, 2.0f * kc.w1 * (pw - pb.w) - o.w);
-        } else {
-          e[jm] = o;
-        }
-      }
-    } else {
-      const int src = c + st;
-      const float4 v = Vec4<T>::load(fin.p[jm], src, is);
-      const float4 q = *(const float4 *)(Pb_in + src);
-      e[jm] = make_float4(v.x + kc.w1 * (q.x - pb.x), v.y + kc.w1 * (q.y - pb.y), v.z + kc.w1 * (q.z - pb.z),
-                          v.w + kc.w1 * (q.w - pb.w));
-    }
-  }
-
-  const float4 it = *(const float4 *)(itau + c);
-  float4 fp = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (HAS_FP) fp = *(const float4 *)(Fp + c);
-  float4 o[2 * DIM];
-  float4 pnew;
   double acc[2] = {0.0, 0.0};
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    float ev[2 * DIM];
-#pragma unroll
-    for (int j = 0; j < 2 * DIM; ++j) ev[j] = f4get(e[j], i);
-    const float dP = dpressure<DIM>(ev, kc);
-    const float wdP = kc.w1 * dP;
-    const float t = f4get(it, i);
-    float add = HAS_FP ? kc.dt * kc.wbar * f4get(fp, i) : 0.0f;
-    if (MODE >= 1) {
-      const float pbi = f4get(pb, i);
-      const float P = pbi + dP;
-      add += kc.w1 * (pbi - P);
-      f4set(pnew, i, P);
-      if (MODE == 2 && active) {
-        acc[0] += (double)dP * (double)dP;
-        acc[1] += (double)P * (double)P;
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 2 * DIM; ++j) {
-      float v = ev[j] + (wdP - ev[j]) * t;
-      if (HAS_FP || MODE >= 1) v += add;
-      f4set(o[j], i, v);
-    }
-  }
-  if (active) {
-#pragma unroll
-    for (int j = 0; j < 2 * DIM; ++j) Vec4<T>::store(fout.p[j], c, o[j], kc.dev_scale);
-    if (MODE >= 1) *(float4 *)(Pb_out + c) = pnew;
-  }
+  sweep_quad<DIM, T, MODE, HAS_FP>(kc, typed<T>(fin_), typed<T>(fout_), Pb_in, Pb_out, itau, Fp,
+                                   blockIdx.x * kThreads + threadIdx.x, acc);
   if (MODE == 2) block_sum<2>(acc, partials);
 }
 
@@ -559,23 +154,7 @@ __global__ __launch_bounds__(kThreads) void moments_kernel(KC kc, GPtrs g, const
                                                            double *__restrict__ partials, int write_coef) {
   const int c = blockIdx.x * kThreads + threadIdx.x;
   double acc[1] = {0.0};
-  if (c < kc.ncell) {
-    float gv[2 * DIM + 1];
-    double dm = 0.0;
-#pragma unroll
-    for (int i = 0; i <= 2 * DIM; ++i) {
-      gv[i] = g.p[i][c];
-      dm += (double)gv[i];
-    }
-    const float fs = HAS_FS ? Fs[c] : 0.0f;
-    const float Sv = saturation_of(sum_g<DIM>(gv), fs, phi[c], kc);
-    if (write_coef) {
-      S[c] = Sv;
-      itau[c] = inv_tau_f_of(Sv, K[c], kc);
-    }
-    if (HAS_FS) dm += 0.5 * (double)kc.dt * (double)fs;
-    acc[0] = dm;
-  }
+  if (c < kc.ncell) acc[0] = moments_cell<DIM, HAS_FS>(kc, g, K, phi, Fs, S, itau, c, write_coef);
   block_sum<1>(acc, partials);
 }
 
@@ -593,87 +172,13 @@ __global__ __launch_bounds__(kThreads) void g_sweep_kernel(KC kc, GPtrs gin, GPt
                                                            const float *__restrict__ phi,
                                                            const float *__restrict__ Fs,
                                                            double *__restrict__ partials) {
-  const FP<T> f = typed<T>(f_);
   const int c = blockIdx.x * kThreads + threadIdx.x;
   double acc[1] = {0.0};
-  if (c < kc.ncell) {
-    const Cell q = cell_of(c, kc);
-    float gv[2 * DIM + 1];
-#pragma unroll
-    for (int i = 0; i <= 2 * DIM; ++i) gv[i] = gin.p[i][c];
-    const float fs = HAS_FS ? Fs[c] : 0.0f;
-    const float ph = phi[c];
-    const float Sv = saturation_of(sum_g<DIM>(gv), fs, ph, kc);
-    float e[2 * DIM];
-    load_e<DIM, T, FLOCAL>(f, Pb, q, kc, Pb[c], e);
-    float m1[3];
-    moment_c<DIM>(e, kc, m1);
-    const float gscale = -itau[c] * kc.inv_cs2dt;      // grad P = gscale * m1
-    const float lw = Sv * Sv * kc.inv_mu_w;
-    const float gamma = -lw * K[c] * kc.inv_cs2dt;
-    const float conv = gamma * kc.dt * kc.w1 * kc.inv_tau_g * kc.c * gscale;  // times s * m1[a]
-    const float srcw = kc.src_g * fs;
-    // rest population
-    {
-      const float geq = (kc.geq0_phi + ph) * Sv;
-      float o = gv[0] + (geq - gv[0]) * kc.inv_tau_g;
-      if (HAS_FS) o += kc.w0 * srcw;
-      gout.p[0][c] = o;
-    }
-    const float geq = kc.w1beta * Sv;
-    double flux = 0.0;
-#pragma unroll
-    for (int j = 0; j < 2 * DIM; ++j) {
-      const int a = dir_axis(j), s = dir_sign(j);
-      float o = gv[j + 1] + (geq - gv[j + 1]) * kc.inv_tau_g;
-      if (HAS_FS) o += kc.w1 * srcw;
-      o += conv * (float)s * m1[a];
-      const int x = coord(q, a), n = extent(kc, a), st = stride_of(kc, a);
-      const bool out = (s > 0) ? (x == n - 1) : (x == 0);
-      if (!out) {
-        gout.p[j + 1][c + s * st] = o;
-      } else {
-        const int face = 2 * a + (s > 0 ? 1 : 0);
-        const int bc = kc.bc_g[face];
-        if (bc == LBTP_BC_PERIODIC) {
-          gout.p[j + 1][c + s * st - s * n * st] = o;
-        } else {
-          float r;
-          if (bc == LBTP_BC_NOFLUX) r = o;
-          else if (bc == LBTP_BC_DIRICHLET) r = kc.abbS[face] - o;
-          else r = 2.0f * kc.w1beta * Sv - o;    // outflow: S_wb = S of this node
-          gout.p[dir_opp(j) + 1][c] = r;
-          flux += (double)r - (double)o;
-        }
-      }
-    }
-    acc[0] = flux;
-  }
+  if (c < kc.ncell)
+    acc[0] = g_sweep_cell<DIM, T, FLOCAL, HAS_FS>(kc, gin, gout, typed<T>(f_), Pb, itau, K, phi, Fs, c);
   block_sum<1>(acc, partials);
 }
 
-// ------------------------------------------------------------ initialisation
-// Central difference of u along axis a (one-sided second order at walls).
-__device__ inline float cdiff(const float *__restrict__ u, const Cell &q, int a, const KC &kc, float inv2dx) {
-  const int x = coord(q, a), n = extent(kc, a), st = stride_of(kc, a);
-  const bool periodic = kc.bc_f[2 * a] == LBTP_BC_PERIODIC;
-  const int c = q.c;
-  if (periodic) {
-    const int cp = (x == n - 1) ? c - (n - 1) * st : c + st;
-    const int cm = (x == 0) ? c + (n - 1) * st : c - st;
-    return (u[cp] - u[cm]) * inv2dx;
-  }
-  if (x == 0) return (-3.0f * u[c] + 4.0f * u[c + st] - u[c + 2 * st]) * inv2dx;
-  if (x == n - 1) return (3.0f * u[c] - 4.0f * u[c - st] + u[c - 2 * st]) * inv2dx;
-  return (u[c + st] - u[c - st]) * inv2dx;
-}
-
-// f_i = w_i P0 - tau_f dt w_i c_i . grad P0 (i >= 1): base P_b = P0 and local
-// deviations e_i = -tau_f dt w_i c_i . grad P0.
-// g_i = g_i^eq(S0) + eps g_i^(1) with
-// eps g_i^(1) = -tau_g dt [(Gamma_i/phi - w_i(1 - 1/(2 tau_g))) F_s
-//                          + Gamma_i c_i . grad S0 - gamma w_i c_i . grad P0 / tau_g]
-// (eq. gini, gneq), Gamma_i = g_i^eq / S.
 template <int DIM, typename T>
 __global__ __launch_bounds__(kThreads) void init_kernel(KC kc, const float *__restrict__ P0,
                                                         const float *__restrict__ S0,
@@ -683,53 +188,8 @@ __global__ __launch_bounds__(kThreads) void init_kernel(KC kc, const float *__re
                                                         const float *__restrict__ phi,
                                                         const float *__restrict__ Fs, int neq, FPtrs f_,
                                                         float *__restrict__ Pb, GPtrs g) {
-  const FP<T> f = typed<T>(f_);
   const int c = blockIdx.x * kThreads + threadIdx.x;
-  if (c >= kc.ncell) return;
-  const Cell q = cell_of(c, kc);
-  const float P = P0[c], S = S0[c], ph = phi[c];
-  const float fs = Fs ? Fs[c] : 0.0f;
-  float gp[3] = {0.f, 0.f, 0.f}, gs[3] = {0.f, 0.f, 0.f};
-  if (neq) {
-    const float inv2dx = 0.5f / (kc.c * kc.dt);
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-      gp[a] = dP0 ? dP0[a * kc.ncell + c] : cdiff(P0, q, a, kc, inv2dx);
-      gs[a] = dS0 ? dS0[a * kc.ncell + c] : cdiff(S0, q, a, kc, inv2dx);
-    }
-  }
-  const float itf = inv_tau_f_of(S, K[c], kc);
-  const float tau_f = 1.0f / itf;
-  const float lw = S * S * kc.inv_mu_w;
-  const float gamma = -lw * K[c] * kc.inv_cs2dt;
-  const float tau_g = 1.0f / kc.inv_tau_g;
-  const float wsrc = 1.0f - 0.5f * kc.inv_tau_g;
-  Pb[c] = P;
-#pragma unroll
-  for (int j = 0; j < 2 * DIM; ++j) {
-    const int a = dir_axis(j), s = dir_sign(j);
-    const float cdp = (float)s * kc.c * gp[a];
-    Storage<T>::store(f.p[j], c, neq ? -tau_f * kc.dt * kc.w1 * cdp : 0.0f, kc.dev_scale);
-  }
-  // rest population: Gamma_0 = (w0 - 1) beta + phi, c_0 = 0
-  {
-    const float G0 = kc.geq0_phi + ph;
-    float v = G0 * S;
-    if (neq) v -= tau_g * kc.dt * ((G0 / ph - kc.w0 * wsrc) * fs);
-    g.p[0][c] = v;
-  }
-  const float G = kc.w1beta;
-#pragma unroll
-  for (int j = 0; j < 2 * DIM; ++j) {
-    const int a = dir_axis(j), s = dir_sign(j);
-    float v = G * S;
-    if (neq) {
-      const float cdp = (float)s * kc.c * gp[a];
-      const float cds = (float)s * kc.c * gs[a];
-      v -= tau_g * kc.dt * ((G / ph - kc.w1 * wsrc) * fs + G * cds - gamma * kc.w1 * cdp * kc.inv_tau_g);
-    }
-    g.p[j + 1][c] = v;
-  }
+  if (c < kc.ncell) init_cell<DIM, T>(kc, P0, S0, dP0, dS0, K, phi, Fs, neq, typed<T>(f_), Pb, g, c);
 }
 
 // ----------------------------------------------------------------- outputs

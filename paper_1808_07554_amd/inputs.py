@@ -179,3 +179,20 @@ def injection_3d(n=512, sigma=1.5, ell=8.0, seed_k=4, seed_phi=5):
 def f32(a):
     """Round once to float32 (the storage type of the GPU fields)."""
     return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+def ensemble(n_members=256, seed0=5000, sizes=(128, 256, 512, 1024), sigma_range=(0.5, 2.0), ell=16.0):
+    """Ensemble of independent 2-D injection realisations of uneven size.
+
+    Member j: side n_j drawn uniformly from `sizes`, sigma_lnK uniform in
+    sigma_range (both from a PCG64 generator seeded seed0 + j), its own
+    log-normal permeability field (seed 2 * (seed0 + j)) and porosity field
+    (seed 2 * (seed0 + j) + 1).  Returns a list of (params, fields).
+    """
+    out = []
+    for j in range(n_members):
+        rng = np.random.default_rng(seed0 + j)
+        n = int(rng.choice(sizes))
+        sigma = float(rng.uniform(*sigma_range))
+        out.append(injection_problem((n, n), sigma, ell, 2 * (seed0 + j), 2 * (seed0 + j) + 1))
+    return out

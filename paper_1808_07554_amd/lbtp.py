@@ -65,6 +65,20 @@ EXPORTS = {
     "lbtp_put_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_longlong, ctypes.c_int]),
     "lbtp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "lbtp_copy_probe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p]),
+    "lbtp_batch_init": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
+    "lbtp_batch_destroy": (None, [ctypes.c_void_p]),
+    "lbtp_batch_size": (ctypes.c_int, [ctypes.c_void_p]),
+    "lbtp_batch_set_fields": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 4 + [ctypes.c_int]),
+    "lbtp_batch_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 4 + [ctypes.c_int]),
+    "lbtp_batch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_double, ctypes.c_longlong,
+                                       ctypes.c_void_p]),
+    "lbtp_batch_pressure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
+    "lbtp_batch_saturation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
+    "lbtp_batch_velocity": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
+    "lbtp_batch_mass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]),
+    "lbtp_batch_set_threads": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "lbtp_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
 }
 
 _lib = None
@@ -124,6 +138,120 @@ class _Arg:
             if h.size != n:
                 raise ValueError(f"expected {n} values, got {h.size}")
             self.ptr, self.dev, self.keep = h.ctypes.data, 0, h
+
+
+def make_params(lattice, shape, *, beta, Ds, mu_w, mu_n, bc_f, bc_g, dx=1.0, dt=1.0, m=64,
+                storage="fp32", init_neq=True, stream_ptr=None, **_):
+    lib = load()
+    p = Params()
+    lib.lbtp_default_params(ctypes.byref(p))
+    p.lattice = D2Q5 if lattice == "D2Q5" else D3Q7
+    shape = tuple(shape) + (1,) * (3 - len(shape))
+    p.nx, p.ny, p.nz = shape
+    p.dx, p.dt, p.beta, p.Ds, p.mu_w, p.mu_n = dx, dt, beta, Ds, mu_w, mu_n
+    p.storage = _STORAGE[storage] if isinstance(storage, str) else storage
+    p.residual_stride = m
+    for f, b in enumerate(bc_f):
+        p.bc_f[f] = _BC[b[0]]
+        p.bc_P[f] = float(b[1]) if len(b) > 1 else 0.0
+    for f, b in enumerate(bc_g):
+        p.bc_g[f] = _BC[b[0]]
+        p.bc_S[f] = float(b[1]) if len(b) > 1 else 0.0
+    p.init_neq = 1 if init_neq else 0
+    p.stream = stream_ptr
+    return p, shape
+
+
+class Batch:
+    """An ensemble of realisations advanced together (lbtp_batch_*).
+
+    members: list of parameter dicts (as produced by paper_1808_07554_amd.inputs).
+    The ensemble runs on a stream of its own unless `stream` is given.
+    """
+
+    def __init__(self, members, m=64, storage="fp32", stream=None):
+        self.torch = _torch()
+        lib = load()
+        n = len(members)
+        arr = (Params * n)()
+        self.shapes = []
+        sptr = stream.cuda_stream if stream is not None else None
+        for i, d in enumerate(members):
+            d = dict(d)
+            p, shape = make_params(d.pop("lattice"), d.pop("shape"), m=m, storage=storage, stream_ptr=sptr, **d)
+            arr[i] = p
+            self.shapes.append(shape)
+        self.dim = 2 if arr[0].lattice == D2Q5 else 3
+        h = ctypes.c_void_p()
+        _check(lib.lbtp_batch_init(arr, n, ctypes.byref(h)), "lbtp_batch_init")
+        self._h, self._lib, self.n = h, lib, n
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.lbtp_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ncell(self, i):
+        s = self.shapes[i]
+        return s[0] * s[1] * s[2]
+
+    def _fshape(self, i):
+        s = self.shapes[i]
+        return (s[2], s[1], s[0])
+
+    def set_fields(self, i, K, phi, Fp=None, Fs=None):
+        a = [_Arg(x, self._ncell(i), self.torch) for x in (K, phi, Fp, Fs)]
+        dev = {x.dev for x in a if x.ptr is not None}
+        _check(self._lib.lbtp_batch_set_fields(self._h, i, *(x.ptr for x in a), dev.pop() if dev else 0),
+               "lbtp_batch_set_fields")
+
+    def set_state(self, i, P0, S0, dP0=None, dS0=None):
+        n = self._ncell(i)
+        a = [_Arg(P0, n, self.torch), _Arg(S0, n, self.torch), _Arg(dP0, self.dim * n, self.torch),
+             _Arg(dS0, self.dim * n, self.torch)]
+        dev = {x.dev for x in a if x.ptr is not None}
+        _check(self._lib.lbtp_batch_set_state(self._h, i, *(x.ptr for x in a), dev.pop() if dev else 0),
+               "lbtp_batch_set_state")
+
+    def step(self, nsteps, tol, max_iters):
+        its = (ctypes.c_longlong * max(1, nsteps * self.n))()
+        st = _check(self._lib.lbtp_batch_step(self._h, int(nsteps), tol, int(max_iters),
+                                              ctypes.cast(its, ctypes.c_void_p)), "lbtp_batch_step")
+        return np.array(list(its)[: nsteps * self.n], dtype=np.int64).reshape(nsteps, self.n), st
+
+    def _out(self, fn, i, ncomp, what):
+        t = self.torch.empty(ncomp * self._ncell(i), dtype=self.torch.float32, device="cuda")
+        _check(fn(self._h, i, ctypes.c_void_p(t.data_ptr()), 1), what)
+        return t
+
+    def pressure(self, i):
+        return self._out(self._lib.lbtp_batch_pressure, i, 1, "lbtp_batch_pressure").view(self._fshape(i))
+
+    def saturation(self, i):
+        return self._out(self._lib.lbtp_batch_saturation, i, 1, "lbtp_batch_saturation").view(self._fshape(i))
+
+    def velocity(self, i):
+        return self._out(self._lib.lbtp_batch_velocity, i, self.dim, "lbtp_batch_velocity").view(
+            (self.dim,) + self._fshape(i))
+
+    def mass(self, i):
+        m, l = ctypes.c_double(), ctypes.c_double()
+        _check(self._lib.lbtp_batch_mass(self._h, i, ctypes.byref(m), ctypes.byref(l)), "lbtp_batch_mass")
+        return m.value, l.value
+
+    def set_threads(self, nt):
+        _check(self._lib.lbtp_batch_set_threads(self._h, int(nt)), "lbtp_batch_set_threads")
+
+    def autotune(self, sweeps=10):
+        t = ctypes.c_int()
+        _check(self._lib.lbtp_batch_autotune(self._h, int(sweeps), ctypes.byref(t)), "lbtp_batch_autotune")
+        return t.value
 
 
 class Solver:

@@ -1,0 +1,126 @@
+"""Ensembles on the GPU: every member of a batched run equals a separate
+single-realisation run (bit for bit), and the per-member solves stop on their
+own.  (Single-realisation runs are checked against the oracle in
+test_gpu_parity.py.)"""
+import numpy as np
+import pytest
+
+from paper_1808_07554_amd import inputs
+from tests.lbhelp import f32, gpu_solver, oracle_solver, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _members(shapes, seed0=70):
+    ms = []
+    for j, shape in enumerate(shapes):
+        p, fl = inputs.injection_problem(shape, 0.5 + 0.3 * j, 4.0, seed0 + 2 * j, seed0 + 2 * j + 1)
+        fshape = fl["K"].shape
+        S0 = 0.3 + 0.2 * np.tanh(inputs.gaussian_random_field(fshape[1:] if fshape[0] == 1 else fshape, 5.0,
+                                                               seed0 + 100 + j)).reshape(fshape)
+        fl["S0"] = S0
+        ms.append((p, {k: f32(v) for k, v in fl.items()}))
+    return ms
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_batch_members_equal_single_runs(storage):
+    from paper_1808_07554_amd import lbtp
+    shapes = [(32, 32), (64, 40), (128, 24), (36, 60), (100, 8)]
+    ms = _members(shapes)
+    b = lbtp.Batch([p for p, _ in ms], m=16, storage=storage)
+    singles = []
+    for i, (p, fl) in enumerate(ms):
+        b.set_fields(i, fl["K"], fl["phi"])
+        b.set_state(i, fl["P0"], fl["S0"])
+        s = gpu_solver(p, m=16, storage=storage)
+        s.set_fields(fl["K"], fl["phi"])
+        s.set_state(fl["P0"], fl["S0"])
+        singles.append(s)
+    # replay: a fixed number of iterations per step
+    its, st = b.step(3, -1.0, 48)
+    assert (its == 48).all()
+    for s in singles:
+        s.step(3, -1.0, 48)
+    for i, s in enumerate(singles):
+        assert bool((b.pressure(i) == s.pressure()).all()), i
+        assert bool((b.saturation(i) == s.saturation()).all()), i
+        assert bool((b.velocity(i) == s.velocity()).all()), i
+        mb, lb = b.mass(i)
+        ms_, ls = s.mass()
+        assert mb == ms_
+        assert abs(lb - ls) <= 1e-12 * max(1.0, abs(ms_))
+    # converging steps: each member stops on its own, like its single run
+    its_b, _ = b.step(2, 1e-6, 16 * 4000)
+    for i, s in enumerate(singles):
+        its_s, _ = s.step(2, 1e-6, 16 * 4000)
+        assert list(its_b[:, i]) == its_s, (i, its_b[:, i], its_s)
+        assert bool((b.pressure(i) == s.pressure()).all()), i
+        assert bool((b.saturation(i) == s.saturation()).all()), i
+    assert len(set(its_b[0])) > 1          # the members really needed different counts
+
+
+def test_batch_autotune_keeps_results():
+    from paper_1808_07554_amd import lbtp
+    shapes = [(64, 64), (128, 32), (32, 96)]
+    ms = _members(shapes, seed0=90)
+
+    def run(nt):
+        b = lbtp.Batch([p for p, _ in ms], m=16)
+        for i, (p, fl) in enumerate(ms):
+            b.set_fields(i, fl["K"], fl["phi"])
+            b.set_state(i, fl["P0"], fl["S0"])
+        if nt == "auto":
+            chosen = b.autotune(sweeps=4)
+            assert chosen in (64, 128, 256, 512)
+        else:
+            b.set_threads(nt)
+        b.step(2, 1e-7, 16 * 2000)
+        return [_np(b.pressure(i)) for i in range(len(ms))] + [_np(b.saturation(i)) for i in range(len(ms))]
+
+    ref = run(256)
+    for nt in (64, 512, "auto"):
+        got = run(nt)
+        for a, c in zip(ref, got):
+            assert np.array_equal(a, c), nt
+
+
+def test_batch_member_against_oracle():
+    from paper_1808_07554_amd import lbtp
+    ms = _members([(48, 20), (40, 44)], seed0=110)
+    b = lbtp.Batch([p for p, _ in ms], m=16)
+    for i, (p, fl) in enumerate(ms):
+        b.set_fields(i, fl["K"], fl["phi"])
+        b.set_state(i, fl["P0"], fl["S0"])
+    b.step(3, -1.0, 64)
+    for i, (p, fl) in enumerate(ms):
+        o = oracle_solver(p, m=16)
+        o.set_fields(fl["K"].astype(np.float64), fl["phi"].astype(np.float64))
+        o.set_state(fl["P0"].astype(np.float64), fl["S0"].astype(np.float64))
+        for _ in range(3):
+            o.step(-1.0, 64)
+        assert rel_l2(o.pressure(), _np(b.pressure(i))) <= 1e-5
+        assert rel_l2(o.saturation(), _np(b.saturation(i))) <= 1e-5
+        assert rel_l2(o.velocity()[:2], _np(b.velocity(i))) <= 1e-5
+
+
+def test_batch_rejects_bad_arguments():
+    from paper_1808_07554_amd import lbtp
+    ms = _members([(32, 32), (30, 32)])
+    with pytest.raises(lbtp.LbtpError):          # nx % 4 != 0
+        lbtp.Batch([p for p, _ in ms], m=16)
+    ms = _members([(32, 32)])
+    with pytest.raises(lbtp.LbtpError):          # odd residual stride
+        lbtp.Batch([p for p, _ in ms], m=15)
+    b = lbtp.Batch([p for p, _ in ms], m=16)
+    with pytest.raises(lbtp.LbtpError) as e:     # step before set_state
+        b.step(1, -1.0, 16)
+    assert e.value.code == lbtp.ESTATE
+    b.set_fields(0, ms[0][1]["K"], ms[0][1]["phi"])
+    b.set_state(0, ms[0][1]["P0"], ms[0][1]["S0"])
+    with pytest.raises(lbtp.LbtpError):          # max_iters not a multiple of m
+        b.step(1, -1.0, 20)
