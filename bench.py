@@ -53,6 +53,11 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--m", type=int, default=64)
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--workload", default="injection2d", choices=["injection2d", "injection3d", "ensemble"],
+                    help="injection2d (default): 4096^2 D2Q5; injection3d: 512^3 D3Q7; ensemble: 256 uneven 2-D realisations")
+    ap.add_argument("--members", type=int, default=256)
+    ap.add_argument("--iters-per-step", type=int, default=64,
+                    help="ensemble: pressure iterations per coupled step (fixed, equal work for batched and sequential)")
     ap.add_argument("--max-iters", type=int, default=20_000_000)
     ap.add_argument("--burst", type=int, default=200, help="plain sweeps timed for the roofline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -102,6 +107,68 @@ def cpu_baseline(seconds):
                       f"of 64 pressure iterations + 1 saturation step, {dt:.1f} s"}
 
 
+def ensemble_bench(a):
+    """All members advanced together (one launch per kernel per sweep, graph-captured
+    chunks) against the same members run one after another through single
+    contexts, at a fixed number of pressure iterations per coupled step."""
+    import torch
+    from paper_1808_07554_amd import inputs, lbtp
+
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    members = inputs.ensemble(a.members)
+    print(f"ensemble inputs: {len(members)} members, {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    cells = sum(p["shape"][0] * p["shape"][1] for p, _ in members)
+    it = a.iters_per_step
+    b = lbtp.Batch([p for p, _ in members], m=a.m, storage=a.storage)
+    dfields = []
+    for i, (p, fl) in enumerate(members):
+        d = {k: torch.from_numpy(inputs.f32(fl[k]).ravel()).to(dev) for k in ("K", "phi", "P0", "S0")}
+        dfields.append(d)
+        b.set_fields(i, d["K"], d["phi"])
+        b.set_state(i, d["P0"], d["S0"])
+    nt = b.autotune(sweeps=5)
+    print(f"autotuned ensemble sweep: {nt} threads per block", file=sys.stderr, flush=True)
+    b.step(a.warmup, -1.0, it)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(a.steps, -1.0, it)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    mlups_batch = cells * a.steps * (it + 1) / t_batch / 1e6
+    print(f"batched: {a.steps} steps in {t_batch:.3f} s", file=sys.stderr, flush=True)
+    b.close()
+    # the same members, one after another
+    t_seq = 0.0
+    for i, (p, fl) in enumerate(members):
+        s = lbtp.from_problem(p, m=a.m, storage=a.storage)
+        d = dfields[i]
+        s.set_fields(d["K"], d["phi"])
+        s.set_state(d["P0"], d["S0"])
+        s.step(a.warmup, -1.0, it)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(a.steps, -1.0, it)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        s.close()
+        del s
+    mlups_seq = cells * a.steps * (it + 1) / t_seq / 1e6
+    print(f"sequential: {t_seq:.3f} s", file=sys.stderr, flush=True)
+    out = {
+        "metric": "MLUPS (both lattices) + s/coupled step vs plain FP32 at residual 1e-8",
+        "value": round(mlups_batch, 1), "unit": "MLUPS", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(t_batch / a.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if a.storage == "fp32" else f"f32 math, {a.storage} storage",
+        "data": "synthetic",
+        "config": {"workload": f"ensemble of {len(members)} 2-D injection realisations, sides 128-1024, "
+                               f"sigma_lnK in [0.5, 2], {it} pressure iterations per coupled step",
+                   "cells": cells, "storage": a.storage, "threads_per_block": nt},
+        "sequential_mlups": round(mlups_seq, 1), "batched_over_sequential": round(t_seq / t_batch, 3),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -113,8 +180,15 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    params, fl = inputs.injection_2d(a.n)
-    ncell = a.n * a.n
+    if a.workload == "ensemble":
+        ensemble_bench(a)
+        return
+    if a.workload == "injection3d":
+        params, fl = inputs.injection_3d(512 if a.n == 4096 else a.n)
+        ncell = int(np.prod(params["shape"]))
+    else:
+        params, fl = inputs.injection_2d(a.n)
+        ncell = a.n * a.n
     K = torch.from_numpy(inputs.f32(fl["K"]).ravel()).to(dev)
     phi = torch.from_numpy(inputs.f32(fl["phi"]).ravel()).to(dev)
     P0 = torch.from_numpy(inputs.f32(fl["P0"]).ravel()).to(dev)
@@ -182,7 +256,7 @@ def main():
     sweep_s = e0.elapsed_time(e1) / 1e3 / a.burst
     alg_bytes = f_sweep_bytes(params["lattice"], a.storage) * ncell
     achieved = alg_bytes / sweep_s / 1e9
-    traffic = measured_traffic(ncell)
+    traffic = measured_traffic(ncell) if (a.workload == "injection2d" and a.storage == "fp32" and a.n == 4096) else None
 
     out = {
         "metric": "MLUPS (both lattices) + s/coupled step vs plain FP32 at residual 1e-8",
@@ -197,7 +271,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if a.storage == "fp32" else f"f32 math, {a.storage} storage",
         "data": "synthetic",
-        "config": {"workload": f"heterogeneous injection 2-D {a.n}x{a.n} (log-normal K sigma 1, corr. length 16)",
+        "config": {"workload": (f"heterogeneous injection 2-D {a.n}x{a.n} (log-normal K sigma 1, corr. length 16)"
+                                if a.workload == "injection2d" else
+                                "heterogeneous injection 3-D %dx%dx%d (log-normal K sigma 1.5, corr. length 8)"
+                                % tuple(params["shape"])),
                    "lattice": params["lattice"], "storage": a.storage, "tol": a.tol, "residual_stride": a.m,
                    "cells": ncell},
         "s_per_coupled_step": t_run / a.steps,
@@ -211,7 +288,7 @@ def main():
                      "kernel": "f_sweep_kernel (plain sweep)", "avg_launch_us": round(sweep_s * 1e6, 2),
                      "bytes_per_launch": alg_bytes},
     }
-    if not a.no_cpu:
+    if not a.no_cpu and a.workload == "injection2d":
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -1,0 +1,59 @@
+/*
+ * lbtp_nn.h -- learned warm start of the pressure iteration (MI355X, bf16
+ * matrix cores).  Not part of the paper's method: the network only supplies
+ * the initial pressure P0 handed to lbtp_set_state / lbtp_batch_set_state;
+ * the lattice Boltzmann pressure iteration (eq. 3-1) then runs to the same
+ * stopping tolerance as from any other start, so it remains the judge.
+ *
+ * Network: convolutional encoder-decoder on an N x H x W batch of fields.
+ * Inputs per node: lnK (log absolute permeability), S (saturation) and the
+ * proximity exp(-d/16) of the nearer Dirichlet wall (d = min(x + 1/2,
+ * W - x - 1/2) nodes; flow axis x, pressure 1 at x = 0 and 0 at x = W).
+ * Output: P = (1 - (x + 1/2)/W) + (scale / W) * net, so the learned part is
+ * per node and a network trained on one grid size applies to others.  `levels` resolution
+ * levels with base * 2^l channels, two 3x3 convolutions + ReLU per level and
+ * side, 2x2 average pooling, nearest 2x upsampling, concatenated skips, 3x3
+ * head.  Parameters: one flat float32 vector, per convolution the weights
+ * [Co][3][3][Ci] then the bias [Co], convolutions in forward order (encoder
+ * levels 0..levels-1, decoder levels levels-2..0, head).  Activations are
+ * bf16, products accumulate in float32 (MFMA), master weights, gradients and
+ * Adam moments are float32.
+ *
+ * Fields are float32 arrays [N][H][W] (x fastest).  H and W must be
+ * multiples of 2^(levels-1).  on_device as in lbtp.h.  Calls run on the
+ * stream given at creation and return after it has finished.  Errors:
+ * LBTP_EINVAL (bad argument or shape), LBTP_ENOMEM, LBTP_EHIP.
+ */
+#ifndef LBTP_NN_H
+#define LBTP_NN_H
+
+#include "lbtp.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbtp_nn lbtp_nn;
+
+/* New network with all parameters zero (set them with lbtp_nn_set_params). */
+LBTP_API int lbtp_nn_create(int base, int levels, double scale, void *stream, lbtp_nn **out);
+LBTP_API void lbtp_nn_destroy(lbtp_nn *nn);
+LBTP_API long long lbtp_nn_num_params(lbtp_nn *nn);
+/* Replace / read the flat parameter vector; set_params also resets Adam. */
+LBTP_API int lbtp_nn_set_params(lbtp_nn *nn, const float *theta, int on_device);
+LBTP_API int lbtp_nn_get_params(lbtp_nn *nn, float *theta, int on_device);
+/* P [N][H][W] from lnK and S. */
+LBTP_API int lbtp_nn_predict(lbtp_nn *nn, const float *lnK, const float *S, int n, int h, int w, float *P,
+                             int on_device);
+/* Mean squared error against P (target) and its gradient (flat, may be NULL). */
+LBTP_API int lbtp_nn_loss_grad(lbtp_nn *nn, const float *lnK, const float *S, const float *P, int n, int h, int w,
+                               double *loss, float *grad, int on_device);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the mean squared error;
+ * *loss (may be NULL) receives the loss before the step. */
+LBTP_API int lbtp_nn_train_step(lbtp_nn *nn, const float *lnK, const float *S, const float *P, int n, int h,
+                                int w, double lr, double *loss, int on_device);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBTP_NN_H */

@@ -1,0 +1,876 @@
+// Warm-start network for the pressure iteration: a convolutional
+// encoder-decoder mapping (lnK, S, wall proximity) on an H x W grid to a
+// pressure estimate P = (1 - (x + 1/2)/W) + (scale / W) * net(.), where the
+// wall proximity is exp(-d/16) with d the distance (in nodes) to the nearer
+// Dirichlet wall; inputs and output are per node, so a network trained on one
+// grid size applies to others.  P is used as the initial pressure of the
+// lattice Boltzmann solve (the solve itself is unchanged and still runs to its
+// tolerance).  Architecture: `levels` levels, base*2^l channels at level l,
+// two 3x3 convolutions + ReLU per level on each side, 2x2 average pooling
+// down, nearest 2x upsampling up, skip connections by channel concatenation
+// [upsampled, skip], and a 3x3 head without activation.
+//
+// Tensors are [N][H][W][C] with C padded to a multiple of 16, activations in
+// bf16, accumulation in float32.  The 3x3 convolution is an implicit GEMM on
+// the bf16 matrix cores (16x16x16 MFMA): a wavefront computes 16 pixels x 16
+// output channels, with K running over the nine taps and the input channels.
+// The backward-data pass is the same kernel with the weights rotated by 180
+// degrees and input/output channels swapped; the weight gradient is a second
+// MFMA GEMM with the pixels as K, split into chunks whose partial sums are
+// added in a fixed order (deterministic).  Master weights, gradients and the
+// Adam moments are float32.
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <vector>
+
+#include "../../include/lbtp_nn.h"
+#include "lbtp_internal.h"
+
+namespace lbtp {
+namespace {
+
+typedef uint16_t bf16;
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline float bf2f(bf16 h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ inline bf16 f2bf(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (bf16)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+// ------------------------------------------------------------------ convolution
+// out[n,y,x,co] = act(bias[co] + sum_{ky,kx,ci} w[co][ky][kx][ci] in[n, y+ky-1, x+kx-1, ci])
+// grid (ceil(W/64) * H * N, Co/16), block 256: wave v covers pixels x0 + 16v .. + 15.
+template <bool RELU, bool OUT_F32>
+__global__ __launch_bounds__(256) void conv3x3_kernel(const bf16 *__restrict__ in, const bf16 *__restrict__ w,
+                                                      const float *__restrict__ bias, void *__restrict__ out, int N,
+                                                      int H, int W, int Ci, int Co) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ntx = (W + 63) / 64;
+  int b = blockIdx.x;
+  const int xt = b % ntx;
+  b /= ntx;
+  const int y = b % H;
+  const int n = b / H;
+  const int x0 = xt * 64 + wave * 16;
+  const int co0 = blockIdx.y * 16;
+  const int m = lane & 15, kq = lane >> 4;
+  const int x = x0 + m;
+  f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+  const bf16x4_t zero = {0, 0, 0, 0};
+  for (int ky = 0; ky < 3; ++ky) {
+    const int yy = y + ky - 1;
+    for (int kx = 0; kx < 3; ++kx) {
+      const int xx = x + kx - 1;
+      const bool valid = x < W && yy >= 0 && yy < H && xx >= 0 && xx < W;
+      const size_t ioff = valid ? ((size_t)(n * H + yy) * W + xx) * Ci + 4 * kq : 0;
+      const size_t woff = ((size_t)(co0 + m) * 9 + ky * 3 + kx) * Ci + 4 * kq;
+      for (int c0 = 0; c0 < Ci; c0 += 16) {
+        const bf16x4_t a = valid ? *(const bf16x4_t *)(in + ioff + c0) : zero;
+        const bf16x4_t bb = *(const bf16x4_t *)(w + woff + c0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc, 0, 0, 0);
+      }
+    }
+  }
+  // lane holds D[4 kq + i][m]: pixel x0 + 4 kq + i, output channel co0 + m
+  const int co = co0 + m;
+  const float bv = bias ? bias[co] : 0.0f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int px = x0 + 4 * kq + i;
+    if (px < W) {
+      float v = acc[i] + bv;
+      if (RELU) v = fmaxf(v, 0.0f);
+      const size_t o = ((size_t)(n * H + y) * W + px) * Co + co;
+      if (OUT_F32) ((float *)out)[o] = v;
+      else ((bf16 *)out)[o] = f2bf(v);
+    }
+  }
+}
+
+// part[chunk][co][tap][ci] = sum over the chunk's pixels p of dy[p][co] x[p shifted by tap][ci]
+// grid ((Co/16) * (Ci/16) * 9, nchunk), block 64.
+__global__ __launch_bounds__(64) void conv3x3_wgrad_kernel(const bf16 *__restrict__ dy, const bf16 *__restrict__ x,
+                                                           float *__restrict__ part, int N, int H, int W, int Ci,
+                                                           int Co, int chunk) {
+  const int lane = threadIdx.x, m = lane & 15, kq = lane >> 4;
+  int t = blockIdx.x;
+  const int tap = t % 9;
+  t /= 9;
+  const int nci = Ci / 16;
+  const int ci0 = (t % nci) * 16, co0 = (t / nci) * 16;
+  const int ky = tap / 3, kx = tap % 3;
+  const long long total = (long long)N * H * W;
+  const long long pb = (long long)blockIdx.y * chunk;
+  const long long pe = pb + chunk < total ? pb + chunk : total;
+  f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+  for (long long p0 = pb; p0 < pe; p0 += 16) {
+    bf16x4_t a, bv;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const long long p = p0 + 4 * kq + i;
+      bf16 av = 0, xv = 0;
+      if (p < pe) {
+        av = dy[p * Co + co0 + m];
+        const int xq = (int)(p % W);
+        const long long r = p / W;
+        const int yq = (int)(r % H);
+        const long long nq = r / H;
+        const int ys = yq + ky - 1, xs = xq + kx - 1;
+        if (ys >= 0 && ys < H && xs >= 0 && xs < W) xv = x[((nq * H + ys) * W + xs) * Ci + ci0 + m];
+      }
+      a[i] = (short)av;
+      bv[i] = (short)xv;
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc, 0, 0, 0);
+  }
+  // lane holds D[4 kq + i][m]: output channel co0 + 4 kq + i, input channel ci0 + m
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    part[(((size_t)blockIdx.y * Co + co0 + 4 * kq + i) * 9 + tap) * Ci + ci0 + m] = acc[i];
+}
+
+// dw[i] = sum over chunks of part[chunk][i] (fixed order)
+__global__ void sum_chunks_kernel(const float *__restrict__ part, float *__restrict__ dw, long long n, int nchunk) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.0f;
+  for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * n + i];
+  dw[i] = s;
+}
+
+// db[co] = sum_p dy[p][co]; one block per channel, fixed-order tree.
+__global__ __launch_bounds__(256) void bias_grad_kernel(const bf16 *__restrict__ dy, float *__restrict__ db,
+                                                        long long npix, int Co) {
+  __shared__ float sh[256];
+  const int co = blockIdx.x;
+  float s = 0.0f;
+  for (long long p = threadIdx.x; p < npix; p += 256) s += bf2f(dy[p * Co + co]);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) db[co] = sh[0];
+}
+
+// ------------------------------------------------------------ element-wise
+#define GRID1(n) dim3((unsigned)(((n) + 255) / 256)), dim3(256)
+
+__global__ void relu_mask_kernel(bf16 *__restrict__ dy, const bf16 *__restrict__ y, long long n) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n && !(bf2f(y[i]) > 0.0f)) dy[i] = 0;
+}
+
+// [N,H,W,C] -> [N,H/2,W/2,C], mean of 2x2
+__global__ void pool_kernel(const bf16 *__restrict__ in, bf16 *__restrict__ out, int N, int H, int W, int C) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int Ho = H / 2, Wo = W / 2;
+  if (i >= (long long)N * Ho * Wo * C) return;
+  const int c = (int)(i % C);
+  long long r = i / C;
+  const int xo = (int)(r % Wo);
+  r /= Wo;
+  const int yo = (int)(r % Ho);
+  const long long n = r / Ho;
+  const size_t b = (((size_t)n * H + 2 * yo) * W + 2 * xo) * C + c;
+  const float s = bf2f(in[b]) + bf2f(in[b + C]) + bf2f(in[b + (size_t)W * C]) + bf2f(in[b + (size_t)W * C + C]);
+  out[i] = f2bf(0.25f * s);
+}
+
+// adjoint of pool: [N,H/2,W/2,C] -> [N,H,W,C]
+__global__ void pool_bwd_kernel(const bf16 *__restrict__ dout, bf16 *__restrict__ din, int N, int H, int W, int C) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (long long)N * H * W * C) return;
+  const int c = (int)(i % C);
+  long long r = i / C;
+  const int x = (int)(r % W);
+  r /= W;
+  const int y = (int)(r % H);
+  const long long n = r / H;
+  din[i] = f2bf(0.25f * bf2f(dout[(((size_t)n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c]));
+}
+
+// nearest 2x: [N,H,W,C] -> [N,2H,2W,C]
+__global__ void up_kernel(const bf16 *__restrict__ in, bf16 *__restrict__ out, int N, int H, int W, int C) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int Ho = 2 * H, Wo = 2 * W;
+  if (i >= (long long)N * Ho * Wo * C) return;
+  const int c = (int)(i % C);
+  long long r = i / C;
+  const int x = (int)(r % Wo);
+  r /= Wo;
+  const int y = (int)(r % Ho);
+  const long long n = r / Ho;
+  out[i] = in[(((size_t)n * H + y / 2) * W + x / 2) * C + c];
+}
+
+// adjoint of up: [N,2H,2W,C] -> [N,H,W,C], sum of 2x2
+__global__ void up_bwd_kernel(const bf16 *__restrict__ dout, bf16 *__restrict__ din, int N, int H, int W, int C) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (long long)N * H * W * C) return;
+  const int c = (int)(i % C);
+  long long r = i / C;
+  const int x = (int)(r % W);
+  r /= W;
+  const int y = (int)(r % H);
+  const long long n = r / H;
+  const int W2 = 2 * W;
+  const size_t b = (((size_t)n * 2 * H + 2 * y) * W2 + 2 * x) * C + c;
+  const float s = bf2f(dout[b]) + bf2f(dout[b + C]) + bf2f(dout[b + (size_t)W2 * C]) +
+                  bf2f(dout[b + (size_t)W2 * C + C]);
+  din[i] = f2bf(s);
+}
+
+// out[p, 0:Ca] = a[p], out[p, Ca:Ca+Cb] = b[p]
+__global__ void concat_kernel(const bf16 *__restrict__ a, const bf16 *__restrict__ b, bf16 *__restrict__ out,
+                              long long npix, int Ca, int Cb) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int C = Ca + Cb;
+  if (i >= npix * C) return;
+  const int c = (int)(i % C);
+  const long long p = i / C;
+  out[i] = c < Ca ? a[p * Ca + c] : b[p * Cb + (c - Ca)];
+}
+
+__global__ void split_kernel(const bf16 *__restrict__ in, bf16 *__restrict__ a, bf16 *__restrict__ b, long long npix,
+                             int Ca, int Cb) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int C = Ca + Cb;
+  if (i >= npix * C) return;
+  const int c = (int)(i % C);
+  const long long p = i / C;
+  if (c < Ca) a[p * Ca + c] = in[i];
+  else b[p * Cb + (c - Ca)] = in[i];
+}
+
+__global__ void add_kernel(bf16 *__restrict__ a, const bf16 *__restrict__ b, long long n) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) a[i] = f2bf(bf2f(a[i]) + bf2f(b[i]));
+}
+
+// network input [N,H,W,16]: lnK, S, wall proximity exp(-d/16), zeros
+__global__ void pack_input_kernel(const float *__restrict__ lnK, const float *__restrict__ S, bf16 *__restrict__ x,
+                                  long long npix, int W) {
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (p >= npix) return;
+  const float xc = (float)(p % W) + 0.5f;
+  const float d = fminf(xc, (float)W - xc);
+  bf16 *o = x + p * 16;
+  o[0] = f2bf(lnK[p]);
+  o[1] = f2bf(S[p]);
+  o[2] = f2bf(expf(-d / 16.0f));
+  for (int c = 3; c < 16; ++c) o[c] = 0;
+}
+
+// P = (1 - (x + 1/2)/W) + (scale / W) * head[..., 0]
+__global__ void head_out_kernel(const float *__restrict__ head, float *__restrict__ P, long long npix, int W,
+                                float scale) {
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (p >= npix) return;
+  const int xq = (int)(p % W);
+  P[p] = (1.0f - ((float)xq + 0.5f) / (float)W) + (scale / (float)W) * head[p * 16];
+}
+
+// loss partial sums and d(loss)/d(head) for L = mean (P - T)^2
+__global__ __launch_bounds__(256) void mse_kernel(const float *__restrict__ P, const float *__restrict__ T,
+                                                  bf16 *__restrict__ dhead, double *__restrict__ partial,
+                                                  long long npix, float scale) {
+  __shared__ double sh[256];
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  double l = 0.0;
+  if (p < npix) {
+    const float r = P[p] - T[p];
+    l = (double)r * (double)r;
+    bf16 *o = dhead + p * 16;
+    o[0] = f2bf(scale * 2.0f * r / (float)npix);
+    for (int c = 1; c < 16; ++c) o[c] = 0;
+  }
+  sh[threadIdx.x] = l;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void sum_double_kernel(const double *__restrict__ part, int n, double *out, double scale) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0] * scale;
+}
+
+// flat float weights [co][3][3][ci] + bias -> padded bf16 w [cop][9][cip], float bias [cop],
+// and the rotated copy wt [cip][9][cop] (wt[ci][8 - tap][co] = w[co][tap][ci]) for backward-data
+__global__ void pack_layer_kernel(const float *__restrict__ flat, int ci, int co, int cip, int cop,
+                                  bf16 *__restrict__ w, bf16 *__restrict__ wt, float *__restrict__ b) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long n = (long long)cop * 9 * cip;
+  if (i < cop) b[i] = i < co ? flat[(size_t)co * 9 * ci + i] : 0.0f;
+  if (i >= n) return;
+  const int c = (int)(i % cip);
+  const long long r = i / cip;
+  const int tap = (int)(r % 9);
+  const int o = (int)(r / 9);
+  const float v = (c < ci && o < co) ? flat[((size_t)o * 9 + tap) * ci + c] : 0.0f;
+  const bf16 h = f2bf(v);
+  w[i] = h;
+  wt[((size_t)c * 9 + (8 - tap)) * cop + o] = h;
+}
+
+// padded dw [cop][9][cip] and db [cop] -> flat gradient of one layer
+__global__ void unpack_grad_kernel(const float *__restrict__ dw, const float *__restrict__ db, int ci, int co,
+                                   int cip, float *__restrict__ flat) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long nw = (long long)co * 9 * ci;
+  if (i < nw) {
+    const int c = (int)(i % ci);
+    const long long r = i / ci;
+    const int tap = (int)(r % 9);
+    const int o = (int)(r / 9);
+    flat[i] = dw[((size_t)o * 9 + tap) * cip + c];
+  } else if (i < nw + co) {
+    flat[i] = db[i - nw];
+  }
+}
+
+__global__ void adam_kernel(float *__restrict__ th, const float *__restrict__ g, float *__restrict__ m,
+                            float *__restrict__ v, long long n, float lr, float b1, float b2, float eps, float c1,
+                            float c2) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+}  // namespace
+}  // namespace lbtp
+
+// =========================================================== host driver
+using namespace lbtp;
+
+namespace {
+
+struct NNLayer {
+  int ci, co, cip, cop;
+  bool relu;
+  size_t off;          // offset of the layer's weights in the flat parameter vector
+  bf16 *w, *wt;        // padded [cop][9][cip] and rotated [cip][9][cop]
+  float *b;            // [cop]
+  float *dw, *db;      // padded gradients
+};
+
+struct Tensor {
+  bf16 *p = nullptr;
+  size_t cap = 0;
+};
+
+int pad16(int c) { return (c + 15) / 16 * 16; }
+
+}  // namespace
+
+struct lbtp_nn {
+  int base = 32, levels = 4;
+  float scale = 1.0f;
+  hipStream_t stream = nullptr;
+  std::vector<NNLayer> L;
+  size_t np = 0;
+  float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
+  long long adam_t = 0;
+  // activations of the last forward pass (training keeps them for backward)
+  std::vector<Tensor> act;     // pool of tensors, reused across calls
+  float *part = nullptr;       // weight-gradient chunk partials
+  size_t part_cap = 0;
+  float *head = nullptr;
+  size_t head_cap = 0;
+  double *lpart = nullptr, *dloss = nullptr;
+  size_t lpart_cap = 0;
+};
+
+namespace {
+
+#define NN_TRY(x)                          \
+  do {                                     \
+    hipError_t e_ = (x);                   \
+    if (e_ != hipSuccess) return LBTP_EHIP; \
+  } while (0)
+
+int ensure(void **p, size_t *cap, size_t bytes) {
+  if (*cap >= bytes) return LBTP_OK;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  if (hipMalloc(p, bytes) != hipSuccess) return LBTP_ENOMEM;
+  *cap = bytes;
+  return LBTP_OK;
+}
+
+bf16 *tensor(lbtp_nn *nn, int slot, size_t elems, int *rc) {
+  if ((int)nn->act.size() <= slot) nn->act.resize(slot + 1);
+  Tensor &t = nn->act[slot];
+  if (ensure((void **)&t.p, &t.cap, elems * sizeof(bf16))) *rc = LBTP_ENOMEM;
+  return t.p;
+}
+
+int conv_fwd(lbtp_nn *nn, const bf16 *in, const bf16 *w, const float *b, void *out, int N, int H, int W, int Ci,
+             int Co, bool relu, bool f32) {
+  const dim3 g((unsigned)(((W + 63) / 64) * H * N), (unsigned)(Co / 16)), bl(256);
+  if (f32) hipLaunchKernelGGL((conv3x3_kernel<false, true>), g, bl, 0, nn->stream, in, w, b, out, N, H, W, Ci, Co);
+  else if (relu) hipLaunchKernelGGL((conv3x3_kernel<true, false>), g, bl, 0, nn->stream, in, w, b, out, N, H, W, Ci, Co);
+  else hipLaunchKernelGGL((conv3x3_kernel<false, false>), g, bl, 0, nn->stream, in, w, b, out, N, H, W, Ci, Co);
+  NN_TRY(hipGetLastError());
+  return LBTP_OK;
+}
+
+int pack_params(lbtp_nn *nn) {
+  for (NNLayer &l : nn->L) {
+    const long long n = (long long)l.cop * 9 * l.cip;
+    hipLaunchKernelGGL(pack_layer_kernel, GRID1(n > l.cop ? n : l.cop), 0, nn->stream, nn->theta + l.off, l.ci, l.co,
+                       l.cip, l.cop, l.w, l.wt, l.b);
+    NN_TRY(hipGetLastError());
+  }
+  return LBTP_OK;
+}
+
+// Tape of one forward pass: per conv the input and output tensors.
+struct Tape {
+  std::vector<const bf16 *> x, y;
+  std::vector<int> H, W;
+};
+
+// Slots in nn->act: 0 input; per conv i: output slot 1 + i; pooled inputs,
+// upsampled and concatenated tensors after that.
+int forward(lbtp_nn *nn, const float *lnK, const float *S, int N, int H, int W, Tape *tape) {
+  int rc = LBTP_OK;
+  const long long npix = (long long)N * H * W;
+  const int nconv = (int)nn->L.size();
+  int slot = 0;
+  bf16 *x = tensor(nn, slot++, (size_t)npix * 16, &rc);
+  if (rc) return rc;
+  hipLaunchKernelGGL(pack_input_kernel, GRID1(npix), 0, nn->stream, lnK, S, x, npix, W);
+  NN_TRY(hipGetLastError());
+  int li = 0, h = H, wd = W;
+  const bf16 *cur = x;
+  std::vector<const bf16 *> skips(nn->levels);
+  auto conv = [&](const bf16 *in) -> const bf16 * {
+    const NNLayer &l = nn->L[li];
+    bf16 *o = tensor(nn, slot++, (size_t)N * h * wd * l.cop, &rc);
+    if (rc) return nullptr;
+    if ((rc = conv_fwd(nn, in, l.w, l.b, o, N, h, wd, l.cip, l.cop, l.relu, false))) return nullptr;
+    if (tape) {
+      tape->x.push_back(in);
+      tape->y.push_back(o);
+      tape->H.push_back(h);
+      tape->W.push_back(wd);
+    }
+    ++li;
+    return o;
+  };
+  for (int lv = 0; lv < nn->levels; ++lv) {
+    if (lv > 0) {
+      const int C = nn->L[li - 1].cop;
+      bf16 *p = tensor(nn, slot++, (size_t)N * (h / 2) * (wd / 2) * C, &rc);
+      if (rc) return rc;
+      hipLaunchKernelGGL(pool_kernel, GRID1((long long)N * (h / 2) * (wd / 2) * C), 0, nn->stream, cur, p, N, h, wd, C);
+      NN_TRY(hipGetLastError());
+      h /= 2;
+      wd /= 2;
+      cur = p;
+    }
+    cur = conv(cur);
+    if (!cur) return rc;
+    cur = conv(cur);
+    if (!cur) return rc;
+    skips[lv] = cur;
+  }
+  for (int lv = nn->levels - 2; lv >= 0; --lv) {
+    const int Cu = nn->L[li - 1].cop, Cs = nn->L[2 * lv + 1].cop;
+    bf16 *u = tensor(nn, slot++, (size_t)N * (2 * h) * (2 * wd) * Cu, &rc);
+    if (rc) return rc;
+    hipLaunchKernelGGL(up_kernel, GRID1((long long)N * 4 * h * wd * Cu), 0, nn->stream, cur, u, N, h, wd, Cu);
+    NN_TRY(hipGetLastError());
+    h *= 2;
+    wd *= 2;
+    bf16 *k = tensor(nn, slot++, (size_t)N * h * wd * (Cu + Cs), &rc);
+    if (rc) return rc;
+    hipLaunchKernelGGL(concat_kernel, GRID1((long long)N * h * wd * (Cu + Cs)), 0, nn->stream, u, skips[lv], k,
+                       (long long)N * h * wd, Cu, Cs);
+    NN_TRY(hipGetLastError());
+    cur = conv(k);
+    if (!cur) return rc;
+    cur = conv(cur);
+    if (!cur) return rc;
+  }
+  // head (float output)
+  const NNLayer &hl = nn->L[nconv - 1];
+  if ((rc = ensure((void **)&nn->head, &nn->head_cap, (size_t)npix * 16 * sizeof(float)))) return rc;
+  if (tape) {
+    tape->x.push_back(cur);
+    tape->y.push_back(nullptr);
+    tape->H.push_back(h);
+    tape->W.push_back(wd);
+  }
+  if ((rc = conv_fwd(nn, cur, hl.w, hl.b, nn->head, N, h, wd, hl.cip, hl.cop, false, true))) return rc;
+  return LBTP_OK;
+}
+
+// Gradient of one convolution: given d(output) after the activation in dy (may
+// be modified), accumulate dw/db and return d(input) in dx (if non-null).
+int conv_bwd(lbtp_nn *nn, int li, const Tape &tp, bf16 *dy, bf16 *dx, int N) {
+  const NNLayer &l = nn->L[li];
+  const int H = tp.H[li], W = tp.W[li];
+  const long long npix = (long long)N * H * W;
+  if (l.relu) {
+    hipLaunchKernelGGL(relu_mask_kernel, GRID1(npix * l.cop), 0, nn->stream, dy, tp.y[li], npix * l.cop);
+    NN_TRY(hipGetLastError());
+  }
+  // weight gradient, split over pixel chunks
+  const int chunk = 4096;
+  const int nchunk = (int)((npix + chunk - 1) / chunk);
+  const size_t nw = (size_t)l.cop * 9 * l.cip;
+  int rc = ensure((void **)&nn->part, &nn->part_cap, (size_t)nchunk * nw * sizeof(float));
+  if (rc) return rc;
+  hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3((unsigned)((l.cop / 16) * (l.cip / 16) * 9), (unsigned)nchunk),
+                     dim3(64), 0, nn->stream, dy, tp.x[li], nn->part, N, H, W, l.cip, l.cop, chunk);
+  NN_TRY(hipGetLastError());
+  hipLaunchKernelGGL(sum_chunks_kernel, GRID1((long long)nw), 0, nn->stream, nn->part, l.dw, (long long)nw, nchunk);
+  NN_TRY(hipGetLastError());
+  hipLaunchKernelGGL(bias_grad_kernel, dim3(l.cop), dim3(256), 0, nn->stream, dy, l.db, npix, l.cop);
+  NN_TRY(hipGetLastError());
+  if (dx) {
+    if ((rc = conv_fwd(nn, dy, l.wt, nullptr, dx, N, H, W, l.cop, l.cip, false, false))) return rc;
+  }
+  return LBTP_OK;
+}
+
+// Backward pass of the tape; gradients land in nn->grad (flat).
+int backward(lbtp_nn *nn, const Tape &tp, int N, int H, int W, bf16 *dhead) {
+  int rc = LBTP_OK;
+  const int nconv = (int)nn->L.size();
+  int slot = 1000;   // gradient tensors live after the forward slots
+  auto grad_tensor = [&](size_t elems) { return tensor(nn, slot++, elems, &rc); };
+  int li = nconv - 1;
+  // head
+  {
+    const NNLayer &l = nn->L[li];
+    bf16 *dx = grad_tensor((size_t)N * tp.H[li] * tp.W[li] * l.cip);
+    if (rc) return rc;
+    if ((rc = conv_bwd(nn, li, tp, dhead, dx, N))) return rc;
+    dhead = dx;
+    --li;
+  }
+  bf16 *dh = dhead;
+  std::vector<bf16 *> dskip(nn->levels, nullptr);
+  for (int lv = 0; lv <= nn->levels - 2; ++lv) {
+    for (int r = 0; r < 2; ++r) {
+      const NNLayer &l = nn->L[li];
+      bf16 *dx = grad_tensor((size_t)N * tp.H[li] * tp.W[li] * l.cip);
+      if (rc) return rc;
+      if ((rc = conv_bwd(nn, li, tp, dh, dx, N))) return rc;
+      dh = dx;
+      --li;
+    }
+    // dh is d(concat) at this level: split into d(up) and d(skip)
+    const NNLayer &l = nn->L[li + 1];
+    const int h = tp.H[li + 1], w = tp.W[li + 1];
+    const int Cs = nn->L[2 * lv + 1].cop;
+    const int Cu = l.cip - Cs;
+    bf16 *du = grad_tensor((size_t)N * h * w * Cu);
+    bf16 *ds = grad_tensor((size_t)N * h * w * Cs);
+    if (rc) return rc;
+    hipLaunchKernelGGL(split_kernel, GRID1((long long)N * h * w * (Cu + Cs)), 0, nn->stream, dh, du, ds,
+                       (long long)N * h * w, Cu, Cs);
+    NN_TRY(hipGetLastError());
+    dskip[lv] = ds;
+    bf16 *dd = grad_tensor((size_t)N * (h / 2) * (w / 2) * Cu);
+    if (rc) return rc;
+    hipLaunchKernelGGL(up_bwd_kernel, GRID1((long long)N * (h / 2) * (w / 2) * Cu), 0, nn->stream, du, dd, N, h / 2,
+                       w / 2, Cu);
+    NN_TRY(hipGetLastError());
+    dh = dd;
+  }
+  for (int lv = nn->levels - 1; lv >= 0; --lv) {
+    const NNLayer &top = nn->L[2 * lv + 1];
+    const int h = tp.H[2 * lv + 1], w = tp.W[2 * lv + 1];
+    if (dskip[lv]) {
+      hipLaunchKernelGGL(add_kernel, GRID1((long long)N * h * w * top.cop), 0, nn->stream, dh, dskip[lv],
+                         (long long)N * h * w * top.cop);
+      NN_TRY(hipGetLastError());
+    }
+    for (int r = 0; r < 2; ++r) {
+      const int idx = 2 * lv + 1 - r;
+      const NNLayer &l = nn->L[idx];
+      const bool need_dx = !(lv == 0 && r == 1);
+      bf16 *dx = need_dx ? grad_tensor((size_t)N * tp.H[idx] * tp.W[idx] * l.cip) : nullptr;
+      if (rc) return rc;
+      if ((rc = conv_bwd(nn, idx, tp, dh, dx, N))) return rc;
+      dh = dx;
+    }
+    if (lv > 0) {
+      const int C = nn->L[2 * lv].cip;
+      bf16 *dp = grad_tensor((size_t)N * (2 * h) * (2 * w) * C);
+      if (rc) return rc;
+      hipLaunchKernelGGL(pool_bwd_kernel, GRID1((long long)N * 4 * h * w * C), 0, nn->stream, dh, dp, N, 2 * h, 2 * w,
+                         C);
+      NN_TRY(hipGetLastError());
+      dh = dp;
+    }
+  }
+  for (NNLayer &l : nn->L) {
+    const long long n = (long long)l.co * 9 * l.ci + l.co;
+    hipLaunchKernelGGL(unpack_grad_kernel, GRID1(n), 0, nn->stream, l.dw, l.db, l.ci, l.co, l.cip, nn->grad + l.off);
+    NN_TRY(hipGetLastError());
+  }
+  return LBTP_OK;
+}
+
+int loss_grad(lbtp_nn *nn, const float *lnK, const float *S, const float *T, int N, int H, int W, double *loss) {
+  Tape tp;
+  int rc = forward(nn, lnK, S, N, H, W, &tp);
+  if (rc) return rc;
+  const long long npix = (long long)N * H * W;
+  float *P = nullptr;
+  size_t pcap = 0;
+  // predicted pressure in a scratch tensor (float) placed after the head
+  if ((rc = ensure((void **)&P, &pcap, (size_t)npix * sizeof(float)))) return rc;
+  hipLaunchKernelGGL(head_out_kernel, GRID1(npix), 0, nn->stream, nn->head, P, npix, W, nn->scale);
+  int nb = (int)((npix + 255) / 256);
+  if ((rc = ensure((void **)&nn->lpart, &nn->lpart_cap, (size_t)(nb + 1) * sizeof(double)))) {
+    (void)hipFree(P);
+    return rc;
+  }
+  bf16 *dhead = tensor(nn, 999, (size_t)npix * 16, &rc);
+  if (rc) {
+    (void)hipFree(P);
+    return rc;
+  }
+  hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, nn->stream, P, T, dhead, nn->lpart, npix, nn->scale / W);
+  hipLaunchKernelGGL(sum_double_kernel, dim3(1), dim3(256), 0, nn->stream, nn->lpart, nb, nn->lpart + nb,
+                     1.0 / (double)npix);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) rc = backward(nn, tp, N, H, W, dhead);
+  else rc = LBTP_EHIP;
+  if (!rc && loss) {
+    e = hipMemcpyAsync(loss, nn->lpart + nb, sizeof(double), hipMemcpyDeviceToHost, nn->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(nn->stream);
+    if (e != hipSuccess) rc = LBTP_EHIP;
+  }
+  (void)hipStreamSynchronize(nn->stream);
+  (void)hipFree(P);
+  return rc;
+}
+
+int check_shape(const lbtp_nn *nn, int N, int H, int W) {
+  const int f = 1 << (nn->levels - 1);
+  if (N < 1 || H < f || W < f || H % f || W % f) return LBTP_EINVAL;
+  return LBTP_OK;
+}
+
+// Stage a caller field of n floats on the device (returns the device pointer).
+const float *stage(lbtp_nn *nn, const float *p, size_t n, int on_device, std::vector<void *> &tmp, int *rc) {
+  if (on_device || !p) return p;
+  void *d = nullptr;
+  if (hipMalloc(&d, n * sizeof(float)) != hipSuccess) {
+    *rc = LBTP_ENOMEM;
+    return nullptr;
+  }
+  tmp.push_back(d);
+  if (hipMemcpyAsync(d, p, n * sizeof(float), hipMemcpyHostToDevice, nn->stream) != hipSuccess) *rc = LBTP_EHIP;
+  return (const float *)d;
+}
+
+void free_tmp(lbtp_nn *nn, std::vector<void *> &tmp) {
+  (void)hipStreamSynchronize(nn->stream);
+  for (void *p : tmp) (void)hipFree(p);
+  tmp.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbtp_nn_create(int base, int levels, double scale, void *stream, lbtp_nn **out) {
+  if (!out || base < 1 || levels < 1 || levels > 6 || !(scale > 0)) return LBTP_EINVAL;
+  *out = nullptr;
+  lbtp_nn *nn = new lbtp_nn();
+  nn->base = base;
+  nn->levels = levels;
+  nn->scale = (float)scale;
+  nn->stream = (hipStream_t)stream;
+  // layer list (same order as the flat parameter vector)
+  std::vector<int> c(levels);
+  for (int l = 0; l < levels; ++l) c[l] = base << l;
+  std::vector<std::pair<int, int>> io;
+  std::vector<bool> relu;
+  int prev = 3;
+  for (int l = 0; l < levels; ++l) {
+    io.push_back({prev, c[l]});
+    io.push_back({c[l], c[l]});
+    relu.push_back(true);
+    relu.push_back(true);
+    prev = c[l];
+  }
+  for (int l = levels - 2; l >= 0; --l) {
+    io.push_back({c[l + 1] + c[l], c[l]});
+    io.push_back({c[l], c[l]});
+    relu.push_back(true);
+    relu.push_back(true);
+  }
+  io.push_back({c[0], 1});
+  relu.push_back(false);
+  size_t off = 0;
+  for (size_t i = 0; i < io.size(); ++i) {
+    NNLayer l{};
+    l.ci = io[i].first;
+    l.co = io[i].second;
+    l.cip = pad16(l.ci);
+    l.cop = pad16(l.co);
+    l.relu = relu[i];
+    l.off = off;
+    off += (size_t)l.co * 9 * l.ci + l.co;
+    nn->L.push_back(l);
+  }
+  nn->np = off;
+  bool ok = hipMalloc((void **)&nn->theta, off * 4) == hipSuccess && hipMalloc((void **)&nn->grad, off * 4) == hipSuccess &&
+            hipMalloc((void **)&nn->m, off * 4) == hipSuccess && hipMalloc((void **)&nn->v, off * 4) == hipSuccess;
+  for (NNLayer &l : nn->L) {
+    const size_t nw = (size_t)l.cop * 9 * l.cip;
+    ok = ok && hipMalloc((void **)&l.w, nw * 2) == hipSuccess && hipMalloc((void **)&l.wt, nw * 2) == hipSuccess &&
+         hipMalloc((void **)&l.b, l.cop * 4) == hipSuccess && hipMalloc((void **)&l.dw, nw * 4) == hipSuccess &&
+         hipMalloc((void **)&l.db, l.cop * 4) == hipSuccess;
+  }
+  if (!ok || hipMemsetAsync(nn->theta, 0, off * 4, nn->stream) != hipSuccess ||
+      hipMemsetAsync(nn->m, 0, off * 4, nn->stream) != hipSuccess ||
+      hipMemsetAsync(nn->v, 0, off * 4, nn->stream) != hipSuccess || pack_params(nn) != LBTP_OK ||
+      hipStreamSynchronize(nn->stream) != hipSuccess) {
+    lbtp_nn_destroy(nn);
+    return ok ? LBTP_EHIP : LBTP_ENOMEM;
+  }
+  *out = nn;
+  return LBTP_OK;
+}
+
+void lbtp_nn_destroy(lbtp_nn *nn) {
+  if (!nn) return;
+  void *bufs[] = {nn->theta, nn->grad, nn->m, nn->v, nn->part, nn->head, nn->lpart};
+  for (void *p : bufs)
+    if (p) (void)hipFree(p);
+  for (NNLayer &l : nn->L) {
+    void *lb[] = {l.w, l.wt, l.b, l.dw, l.db};
+    for (void *p : lb)
+      if (p) (void)hipFree(p);
+  }
+  for (Tensor &t : nn->act)
+    if (t.p) (void)hipFree(t.p);
+  delete nn;
+}
+
+long long lbtp_nn_num_params(lbtp_nn *nn) { return nn ? (long long)nn->np : LBTP_EINVAL; }
+
+int lbtp_nn_set_params(lbtp_nn *nn, const float *theta, int on_device) {
+  if (!nn || !theta) return LBTP_EINVAL;
+  NN_TRY(hipMemcpyAsync(nn->theta, theta, nn->np * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                        nn->stream));
+  NN_TRY(hipMemsetAsync(nn->m, 0, nn->np * 4, nn->stream));
+  NN_TRY(hipMemsetAsync(nn->v, 0, nn->np * 4, nn->stream));
+  nn->adam_t = 0;
+  int rc = pack_params(nn);
+  if (rc) return rc;
+  NN_TRY(hipStreamSynchronize(nn->stream));
+  return LBTP_OK;
+}
+
+int lbtp_nn_get_params(lbtp_nn *nn, float *theta, int on_device) {
+  if (!nn || !theta) return LBTP_EINVAL;
+  NN_TRY(hipMemcpyAsync(theta, nn->theta, nn->np * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                        nn->stream));
+  NN_TRY(hipStreamSynchronize(nn->stream));
+  return LBTP_OK;
+}
+
+int lbtp_nn_predict(lbtp_nn *nn, const float *lnK, const float *S, int N, int H, int W, float *P, int on_device) {
+  if (!nn || !lnK || !S || !P) return LBTP_EINVAL;
+  int rc = check_shape(nn, N, H, W);
+  if (rc) return rc;
+  const size_t npix = (size_t)N * H * W;
+  std::vector<void *> tmp;
+  const float *dK = stage(nn, lnK, npix, on_device, tmp, &rc);
+  const float *dS = stage(nn, S, npix, on_device, tmp, &rc);
+  float *dP = P;
+  if (!rc && !on_device) {
+    if (hipMalloc((void **)&dP, npix * 4) != hipSuccess) rc = LBTP_ENOMEM;
+    else tmp.push_back(dP);
+  }
+  if (!rc) rc = forward(nn, dK, dS, N, H, W, nullptr);
+  if (!rc) {
+    hipLaunchKernelGGL(head_out_kernel, GRID1((long long)npix), 0, nn->stream, nn->head, dP, (long long)npix, W,
+                       nn->scale);
+    if (hipGetLastError() != hipSuccess) rc = LBTP_EHIP;
+  }
+  if (!rc && !on_device &&
+      hipMemcpyAsync(P, dP, npix * 4, hipMemcpyDeviceToHost, nn->stream) != hipSuccess)
+    rc = LBTP_EHIP;
+  free_tmp(nn, tmp);
+  return rc;
+}
+
+int lbtp_nn_loss_grad(lbtp_nn *nn, const float *lnK, const float *S, const float *P, int N, int H, int W,
+                      double *loss, float *grad, int on_device) {
+  if (!nn || !lnK || !S || !P) return LBTP_EINVAL;
+  int rc = check_shape(nn, N, H, W);
+  if (rc) return rc;
+  const size_t npix = (size_t)N * H * W;
+  std::vector<void *> tmp;
+  const float *dK = stage(nn, lnK, npix, on_device, tmp, &rc);
+  const float *dS = stage(nn, S, npix, on_device, tmp, &rc);
+  const float *dT = stage(nn, P, npix, on_device, tmp, &rc);
+  if (!rc) rc = loss_grad(nn, dK, dS, dT, N, H, W, loss);
+  if (!rc && grad &&
+      hipMemcpyAsync(grad, nn->grad, nn->np * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                     nn->stream) != hipSuccess)
+    rc = LBTP_EHIP;
+  free_tmp(nn, tmp);
+  return rc;
+}
+
+int lbtp_nn_train_step(lbtp_nn *nn, const float *lnK, const float *S, const float *P, int N, int H, int W, double lr,
+                       double *loss, int on_device) {
+  if (!nn || !lnK || !S || !P || !(lr > 0)) return LBTP_EINVAL;
+  int rc = check_shape(nn, N, H, W);
+  if (rc) return rc;
+  const size_t npix = (size_t)N * H * W;
+  std::vector<void *> tmp;
+  const float *dK = stage(nn, lnK, npix, on_device, tmp, &rc);
+  const float *dS = stage(nn, S, npix, on_device, tmp, &rc);
+  const float *dT = stage(nn, P, npix, on_device, tmp, &rc);
+  if (!rc) rc = loss_grad(nn, dK, dS, dT, N, H, W, loss);
+  if (!rc) {
+    nn->adam_t += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 - pow(b1, (double)nn->adam_t)), c2 = (float)(1.0 - pow(b2, (double)nn->adam_t));
+    hipLaunchKernelGGL(adam_kernel, GRID1((long long)nn->np), 0, nn->stream, nn->theta, nn->grad, nn->m, nn->v,
+                       (long long)nn->np, (float)lr, (float)b1, (float)b2, 1e-8f, c1, c2);
+    if (hipGetLastError() != hipSuccess) rc = LBTP_EHIP;
+  }
+  if (!rc) rc = pack_params(nn);
+  free_tmp(nn, tmp);
+  return rc;
+}
+
+}  // extern "C"

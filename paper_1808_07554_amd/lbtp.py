@@ -79,6 +79,20 @@ EXPORTS = {
                                        ctypes.POINTER(ctypes.c_double)]),
     "lbtp_batch_set_threads": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "lbtp_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "lbtp_nn_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_void_p)]),
+    "lbtp_nn_destroy": (None, [ctypes.c_void_p]),
+    "lbtp_nn_num_params": (ctypes.c_longlong, [ctypes.c_void_p]),
+    "lbtp_nn_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "lbtp_nn_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "lbtp_nn_predict": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
+    "lbtp_nn_loss_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.c_void_p, ctypes.c_int]),
+    "lbtp_nn_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
 }
 
 _lib = None
@@ -252,6 +266,76 @@ class Batch:
         t = ctypes.c_int()
         _check(self._lib.lbtp_batch_autotune(self._h, int(sweeps), ctypes.byref(t)), "lbtp_batch_autotune")
         return t.value
+
+
+class WarmStartNet:
+    """The learned warm start (include/lbtp_nn.h).  Fields are [N, H, W]
+    float32 torch tensors on the device (or numpy arrays)."""
+
+    def __init__(self, base=32, levels=4, scale=3.2, stream=None):
+        self.torch = _torch()
+        lib = load()
+        s = stream if stream is not None else self.torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(lib.lbtp_nn_create(int(base), int(levels), float(scale), ctypes.c_void_p(s.cuda_stream),
+                                  ctypes.byref(h)), "lbtp_nn_create")
+        self._h, self._lib = h, lib
+        self.base, self.levels, self.scale = base, levels, scale
+        self.n_params = lib.lbtp_nn_num_params(h)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.lbtp_nn_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, a):
+        t = self.torch
+        if isinstance(a, t.Tensor):
+            return a.to(device="cuda", dtype=t.float32).contiguous()
+        return t.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float32))).cuda()
+
+    def set_params(self, theta):
+        th = self._dev(theta).ravel()
+        assert th.numel() == self.n_params
+        _check(self._lib.lbtp_nn_set_params(self._h, ctypes.c_void_p(th.data_ptr()), 1), "lbtp_nn_set_params")
+
+    def get_params(self):
+        th = self.torch.empty(self.n_params, dtype=self.torch.float32, device="cuda")
+        _check(self._lib.lbtp_nn_get_params(self._h, ctypes.c_void_p(th.data_ptr()), 1), "lbtp_nn_get_params")
+        return th
+
+    def predict(self, lnK, S):
+        lnK, S = self._dev(lnK), self._dev(S)
+        n, h, w = lnK.shape
+        P = self.torch.empty_like(lnK)
+        _check(self._lib.lbtp_nn_predict(self._h, ctypes.c_void_p(lnK.data_ptr()), ctypes.c_void_p(S.data_ptr()),
+                                         n, h, w, ctypes.c_void_p(P.data_ptr()), 1), "lbtp_nn_predict")
+        return P
+
+    def loss_grad(self, lnK, S, P):
+        lnK, S, P = self._dev(lnK), self._dev(S), self._dev(P)
+        n, h, w = lnK.shape
+        g = self.torch.empty(self.n_params, dtype=self.torch.float32, device="cuda")
+        loss = ctypes.c_double()
+        _check(self._lib.lbtp_nn_loss_grad(self._h, ctypes.c_void_p(lnK.data_ptr()), ctypes.c_void_p(S.data_ptr()),
+                                           ctypes.c_void_p(P.data_ptr()), n, h, w, ctypes.byref(loss),
+                                           ctypes.c_void_p(g.data_ptr()), 1), "lbtp_nn_loss_grad")
+        return loss.value, g
+
+    def train_step(self, lnK, S, P, lr):
+        lnK, S, P = self._dev(lnK), self._dev(S), self._dev(P)
+        n, h, w = lnK.shape
+        loss = ctypes.c_double()
+        _check(self._lib.lbtp_nn_train_step(self._h, ctypes.c_void_p(lnK.data_ptr()), ctypes.c_void_p(S.data_ptr()),
+                                            ctypes.c_void_p(P.data_ptr()), n, h, w, float(lr), ctypes.byref(loss), 1),
+               "lbtp_nn_train_step")
+        return loss.value
 
 
 class Solver:
