@@ -19,7 +19,6 @@ duration from HIP events around a burst of sweeps on the solver's stream),
 and the CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
-import hashlib
 import json
 import os
 import re
@@ -40,8 +39,7 @@ POP_BYTES = {"fp32": 4, "fp16": 2, "bf16": 2}
 def f_sweep_bytes(lattice, storage):
     q1 = 4 if lattice == "D2Q5" else 6
     return 2 * q1 * POP_BYTES[storage] + 4 + 4
-KERNEL_SRC = os.path.join(ROOT, "paper_1808_07554_amd", "csrc", "lbtp_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "f_sweep_traffic_injection2d_4096.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "f_sweep_traffic_injection2d_4096_{}.txt")
 
 
 def parse():
@@ -65,18 +63,18 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(ncell):
-    """HBM bytes per f-sweep launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source (else None)."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(storage):
+    """HBM bytes per f-sweep launch from the committed rocprofv3 counter summary
+    for this storage format, if it was taken on the current kernel sources
+    (else None)."""
+    from paper_1808_07554_amd.profile_sweep import source_digest
+    path = TRAFFIC_FILE.format(storage)
+    if not os.path.exists(path):
         return None
-    txt = open(TRAFFIC_FILE).read()
+    txt = open(path).read()
     m = re.search(r"source_sha256:\s*([0-9a-f]{64})", txt)
     b = re.search(r"bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m or not b:
-        return None
-    cur = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    if cur != m.group(1):
+    if not m or not b or source_digest() != m.group(1):
         return None
     return float(b.group(1))
 
@@ -256,7 +254,7 @@ def main():
     sweep_s = e0.elapsed_time(e1) / 1e3 / a.burst
     alg_bytes = f_sweep_bytes(params["lattice"], a.storage) * ncell
     achieved = alg_bytes / sweep_s / 1e9
-    traffic = measured_traffic(ncell) if (a.workload == "injection2d" and a.storage == "fp32" and a.n == 4096) else None
+    traffic = measured_traffic(a.storage) if (a.workload == "injection2d" and a.n == 4096) else None
 
     out = {
         "metric": "MLUPS (both lattices) + s/coupled step vs plain FP32 at residual 1e-8",

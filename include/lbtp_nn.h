@@ -42,16 +42,26 @@ LBTP_API long long lbtp_nn_num_params(lbtp_nn *nn);
 /* Replace / read the flat parameter vector; set_params also resets Adam. */
 LBTP_API int lbtp_nn_set_params(lbtp_nn *nn, const float *theta, int on_device);
 LBTP_API int lbtp_nn_get_params(lbtp_nn *nn, float *theta, int on_device);
-/* P [N][H][W] from lnK and S. */
-LBTP_API int lbtp_nn_predict(lbtp_nn *nn, const float *lnK, const float *S, int n, int h, int w, float *P,
-                             int on_device);
-/* Mean squared error against P (target) and its gradient (flat, may be NULL). */
-LBTP_API int lbtp_nn_loss_grad(lbtp_nn *nn, const float *lnK, const float *S, const float *P, int n, int h, int w,
-                               double *loss, float *grad, int on_device);
-/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the mean squared error;
- * *loss (may be NULL) receives the loss before the step. */
-LBTP_API int lbtp_nn_train_step(lbtp_nn *nn, const float *lnK, const float *S, const float *P, int n, int h,
-                                int w, double lr, double *loss, int on_device);
+/* P [N][H][W] from lnK and S.  With factor > 1 the network runs on the grid
+ * coarsened by `factor` (lnK and S averaged over factor x factor blocks, so
+ * the coarse permeability is the geometric block mean); the coarse deviation
+ * from the linear profile is interpolated bilinearly to the fine node centres
+ * (coarse coordinate (x + 1/2)/factor - 1/2, clamped at the edges) and added
+ * to the fine linear profile.  This gives a network trained on one grid size
+ * the long-wavelength pressure modes of a larger grid, which are the slowest
+ * to converge.  h and w must be multiples of factor, and h/factor and
+ * w/factor multiples of 2^(levels-1). */
+LBTP_API int lbtp_nn_predict(lbtp_nn *nn, const float *lnK, const float *S, int n, int h, int w, int factor,
+                             float *P, int on_device);
+/* Weighted mean squared error L = (1 / (n h w)) sum_k weight[k] sum_nodes
+ * (P_net - P)^2 against the target P, and its gradient (flat, may be NULL).
+ * weight: one float per sample, or NULL for all ones. */
+LBTP_API int lbtp_nn_loss_grad(lbtp_nn *nn, const float *lnK, const float *S, const float *P, const float *weight,
+                               int n, int h, int w, double *loss, float *grad, int on_device);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on that loss; *loss (may
+ * be NULL) receives the loss before the step. */
+LBTP_API int lbtp_nn_train_step(lbtp_nn *nn, const float *lnK, const float *S, const float *P, const float *weight,
+                                int n, int h, int w, double lr, double *loss, int on_device);
 
 #ifdef __cplusplus
 }

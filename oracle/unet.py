@@ -167,13 +167,52 @@ def forward(theta, lnK, S, scale, base=32, levels=4, keep=False):
     return (P, tape) if keep else P
 
 
-def loss_and_grad(theta, lnK, S, P_target, scale, base=32, levels=4):
-    """Mean squared error of the predicted pressure and its gradient (flat)."""
+def coarsen(x, f):
+    """Block mean of [N, H, W] over f x f blocks."""
+    N, H, W = x.shape
+    return x.reshape(N, H // f, f, W // f, f).mean(axis=(2, 4))
+
+
+def interpolate(d, f):
+    """Bilinear interpolation of node-centred values d [N, h, w] to the grid
+    refined by f: fine node x sits at coarse coordinate (x + 1/2)/f - 1/2;
+    coordinates outside [0, w - 1] take the edge value."""
+    def axis(n):
+        u = (np.arange(n * f) + 0.5) / f - 0.5
+        u = np.clip(u, 0.0, n - 1)
+        i0 = np.minimum(np.floor(u).astype(int), n - 1)
+        i1 = np.minimum(i0 + 1, n - 1)
+        return i0, i1, u - i0
+    N, h, w = d.shape
+    y0, y1, ty = axis(h)
+    x0, x1, tx = axis(w)
+    rows = d[:, y0, :] * (1 - ty)[None, :, None] + d[:, y1, :] * ty[None, :, None]
+    return rows[:, :, x0] * (1 - tx) + rows[:, :, x1] * tx
+
+
+def predict(theta, lnK, S, scale, factor=1, base=32, levels=4):
+    """Initial pressure of an H x W grid; for factor > 1 the network sees the
+    fields coarsened by `factor` and its deviation from the coarse linear
+    profile is interpolated to the fine grid and added to the fine profile."""
+    if factor == 1:
+        return forward(theta, lnK, S, scale, base, levels)
+    W = lnK.shape[2]
+    Pc = forward(theta, coarsen(lnK, factor), coarsen(S, factor), scale, base, levels)
+    wc = W // factor
+    dev = Pc - (1.0 - (np.arange(wc) + 0.5) / wc)
+    return (1.0 - (np.arange(W) + 0.5) / W) + interpolate(dev, factor)
+
+
+def loss_and_grad(theta, lnK, S, P_target, scale, base=32, levels=4, weight=None):
+    """Weighted mean squared error of the predicted pressure,
+    L = (1 / (N H W)) sum_n weight[n] sum_nodes (P - P_target)^2 (weight None:
+    all ones), and its gradient (flat)."""
     ws = unpack(theta, base, levels)
     P, tape = forward(theta, lnK, S, scale, base, levels, keep=True)
     r = P - P_target
-    loss = float(np.mean(r * r))
-    dP = 2.0 * r / r.size
+    wn = np.ones(r.shape[0]) if weight is None else np.asarray(weight, float)
+    loss = float(np.sum(wn[:, None, None] * r * r) / r.size)
+    dP = 2.0 * wn[:, None, None] * r / r.size
     grads = [None] * len(ws)
     li = len(ws) - 1
 

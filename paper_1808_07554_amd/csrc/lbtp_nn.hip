@@ -276,18 +276,70 @@ __global__ void head_out_kernel(const float *__restrict__ head, float *__restric
   P[p] = (1.0f - ((float)xq + 0.5f) / (float)W) + (scale / (float)W) * head[p * 16];
 }
 
-// loss partial sums and d(loss)/d(head) for L = mean (P - T)^2
+// Block mean over f x f nodes: out[n][Y][X] = f^-2 sum in[n][fY + j][fX + i]
+// (sum in row-major order of (j, i)), for lnK and S together.
+__global__ void coarsen_kernel(const float *__restrict__ a, const float *__restrict__ b, float *__restrict__ ac,
+                               float *__restrict__ bc, long long ncoarse, int Hc, int Wc, int f) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= ncoarse) return;
+  const int X = (int)(q % Wc);
+  const long long r = q / Wc;
+  const int Y = (int)(r % Hc);
+  const long long n = r / Hc;
+  const long long W = (long long)Wc * f;
+  const long long base = (n * Hc * f + (long long)Y * f) * W + (long long)X * f;
+  float sa = 0.f, sb = 0.f;
+  for (int j = 0; j < f; ++j)
+    for (int i = 0; i < f; ++i) {
+      sa += a[base + j * W + i];
+      sb += b[base + j * W + i];
+    }
+  const float inv = 1.0f / (float)(f * f);
+  ac[q] = sa * inv;
+  bc[q] = sb * inv;
+}
+
+// Fine pressure from the coarse network output: the coarse deviation
+// D = (scale / Wc) * head is interpolated bilinearly to the fine node centres
+// (coarse coordinate u = (x + 1/2)/f - 1/2, indices clamped to the grid) and
+// added to the fine linear profile 1 - (x + 1/2)/W.
+__global__ void upsample_kernel(const float *__restrict__ head, float *__restrict__ P, long long npix, int H, int W,
+                                int f, float dscale) {
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (p >= npix) return;
+  const int x = (int)(p % W);
+  const long long r = p / W;
+  const int y = (int)(r % H);
+  const long long n = r / H;
+  const int Hc = H / f, Wc = W / f;
+  const float inv_f = 1.0f / (float)f;
+  const float u = ((float)x + 0.5f) * inv_f - 0.5f, v = ((float)y + 0.5f) * inv_f - 0.5f;
+  const float fu = floorf(u), fv = floorf(v);
+  const float tu = u - fu, tv = v - fv;
+  const int x0 = min(max((int)fu, 0), Wc - 1), x1 = min(max((int)fu + 1, 0), Wc - 1);
+  const int y0 = min(max((int)fv, 0), Hc - 1), y1 = min(max((int)fv + 1, 0), Hc - 1);
+  const float *h = head + n * Hc * Wc * 16;
+  const float d00 = h[((long long)y0 * Wc + x0) * 16], d01 = h[((long long)y0 * Wc + x1) * 16];
+  const float d10 = h[((long long)y1 * Wc + x0) * 16], d11 = h[((long long)y1 * Wc + x1) * 16];
+  const float d0 = d00 + tu * (d01 - d00), d1 = d10 + tu * (d11 - d10);
+  P[p] = (1.0f - ((float)x + 0.5f) / (float)W) + dscale * (d0 + tv * (d1 - d0));
+}
+
+// loss partial sums and d(loss)/d(head) for L = mean w_n (P - T)^2, with a
+// weight per sample (wts NULL: all 1) and hw nodes per sample
 __global__ __launch_bounds__(256) void mse_kernel(const float *__restrict__ P, const float *__restrict__ T,
-                                                  bf16 *__restrict__ dhead, double *__restrict__ partial,
-                                                  long long npix, float scale) {
+                                                  const float *__restrict__ wts, bf16 *__restrict__ dhead,
+                                                  double *__restrict__ partial, long long npix, long long hw,
+                                                  float scale) {
   __shared__ double sh[256];
   const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
   double l = 0.0;
   if (p < npix) {
     const float r = P[p] - T[p];
-    l = (double)r * (double)r;
+    const float wn = wts ? wts[p / hw] : 1.0f;
+    l = (double)wn * (double)r * (double)r;
     bf16 *o = dhead + p * 16;
-    o[0] = f2bf(scale * 2.0f * r / (float)npix);
+    o[0] = f2bf(scale * 2.0f * wn * r / (float)npix);
     for (int c = 1; c < 16; ++c) o[c] = 0;
   }
   sh[threadIdx.x] = l;
@@ -640,7 +692,8 @@ int backward(lbtp_nn *nn, const Tape &tp, int N, int H, int W, bf16 *dhead) {
   return LBTP_OK;
 }
 
-int loss_grad(lbtp_nn *nn, const float *lnK, const float *S, const float *T, int N, int H, int W, double *loss) {
+int loss_grad(lbtp_nn *nn, const float *lnK, const float *S, const float *T, const float *wts, int N, int H, int W,
+              double *loss) {
   Tape tp;
   int rc = forward(nn, lnK, S, N, H, W, &tp);
   if (rc) return rc;
@@ -660,7 +713,8 @@ int loss_grad(lbtp_nn *nn, const float *lnK, const float *S, const float *T, int
     (void)hipFree(P);
     return rc;
   }
-  hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, nn->stream, P, T, dhead, nn->lpart, npix, nn->scale / W);
+  hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, nn->stream, P, T, wts, dhead, nn->lpart, npix,
+                     (long long)H * W, nn->scale / W);
   hipLaunchKernelGGL(sum_double_kernel, dim3(1), dim3(256), 0, nn->stream, nn->lpart, nb, nn->lpart + nb,
                      1.0 / (double)npix);
   hipError_t e = hipGetLastError();
@@ -804,11 +858,13 @@ int lbtp_nn_get_params(lbtp_nn *nn, float *theta, int on_device) {
   return LBTP_OK;
 }
 
-int lbtp_nn_predict(lbtp_nn *nn, const float *lnK, const float *S, int N, int H, int W, float *P, int on_device) {
-  if (!nn || !lnK || !S || !P) return LBTP_EINVAL;
-  int rc = check_shape(nn, N, H, W);
+int lbtp_nn_predict(lbtp_nn *nn, const float *lnK, const float *S, int N, int H, int W, int factor, float *P,
+                    int on_device) {
+  if (!nn || !lnK || !S || !P || factor < 1 || H % factor || W % factor) return LBTP_EINVAL;
+  const int Hc = H / factor, Wc = W / factor;
+  int rc = check_shape(nn, N, Hc, Wc);
   if (rc) return rc;
-  const size_t npix = (size_t)N * H * W;
+  const size_t npix = (size_t)N * H * W, ncoarse = (size_t)N * Hc * Wc;
   std::vector<void *> tmp;
   const float *dK = stage(nn, lnK, npix, on_device, tmp, &rc);
   const float *dS = stage(nn, S, npix, on_device, tmp, &rc);
@@ -817,10 +873,26 @@ int lbtp_nn_predict(lbtp_nn *nn, const float *lnK, const float *S, int N, int H,
     if (hipMalloc((void **)&dP, npix * 4) != hipSuccess) rc = LBTP_ENOMEM;
     else tmp.push_back(dP);
   }
-  if (!rc) rc = forward(nn, dK, dS, N, H, W, nullptr);
+  const float *cK = dK, *cS = dS;
+  if (!rc && factor > 1) {
+    float *c = nullptr;
+    if (hipMalloc((void **)&c, 2 * ncoarse * 4) != hipSuccess) rc = LBTP_ENOMEM;
+    else {
+      tmp.push_back(c);
+      hipLaunchKernelGGL(coarsen_kernel, GRID1((long long)ncoarse), 0, nn->stream, dK, dS, c, c + ncoarse,
+                         (long long)ncoarse, Hc, Wc, factor);
+      cK = c;
+      cS = c + ncoarse;
+    }
+  }
+  if (!rc) rc = forward(nn, cK, cS, N, Hc, Wc, nullptr);
   if (!rc) {
-    hipLaunchKernelGGL(head_out_kernel, GRID1((long long)npix), 0, nn->stream, nn->head, dP, (long long)npix, W,
-                       nn->scale);
+    if (factor == 1)
+      hipLaunchKernelGGL(head_out_kernel, GRID1((long long)npix), 0, nn->stream, nn->head, dP, (long long)npix, W,
+                         nn->scale);
+    else
+      hipLaunchKernelGGL(upsample_kernel, GRID1((long long)npix), 0, nn->stream, nn->head, dP, (long long)npix, H,
+                         W, factor, nn->scale / (float)Wc);
     if (hipGetLastError() != hipSuccess) rc = LBTP_EHIP;
   }
   if (!rc && !on_device &&
@@ -830,8 +902,8 @@ int lbtp_nn_predict(lbtp_nn *nn, const float *lnK, const float *S, int N, int H,
   return rc;
 }
 
-int lbtp_nn_loss_grad(lbtp_nn *nn, const float *lnK, const float *S, const float *P, int N, int H, int W,
-                      double *loss, float *grad, int on_device) {
+int lbtp_nn_loss_grad(lbtp_nn *nn, const float *lnK, const float *S, const float *P, const float *weight, int N,
+                      int H, int W, double *loss, float *grad, int on_device) {
   if (!nn || !lnK || !S || !P) return LBTP_EINVAL;
   int rc = check_shape(nn, N, H, W);
   if (rc) return rc;
@@ -840,7 +912,8 @@ int lbtp_nn_loss_grad(lbtp_nn *nn, const float *lnK, const float *S, const float
   const float *dK = stage(nn, lnK, npix, on_device, tmp, &rc);
   const float *dS = stage(nn, S, npix, on_device, tmp, &rc);
   const float *dT = stage(nn, P, npix, on_device, tmp, &rc);
-  if (!rc) rc = loss_grad(nn, dK, dS, dT, N, H, W, loss);
+  const float *dW = stage(nn, weight, (size_t)N, on_device, tmp, &rc);
+  if (!rc) rc = loss_grad(nn, dK, dS, dT, dW, N, H, W, loss);
   if (!rc && grad &&
       hipMemcpyAsync(grad, nn->grad, nn->np * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                      nn->stream) != hipSuccess)
@@ -849,8 +922,8 @@ int lbtp_nn_loss_grad(lbtp_nn *nn, const float *lnK, const float *S, const float
   return rc;
 }
 
-int lbtp_nn_train_step(lbtp_nn *nn, const float *lnK, const float *S, const float *P, int N, int H, int W, double lr,
-                       double *loss, int on_device) {
+int lbtp_nn_train_step(lbtp_nn *nn, const float *lnK, const float *S, const float *P, const float *weight, int N,
+                       int H, int W, double lr, double *loss, int on_device) {
   if (!nn || !lnK || !S || !P || !(lr > 0)) return LBTP_EINVAL;
   int rc = check_shape(nn, N, H, W);
   if (rc) return rc;
@@ -859,7 +932,8 @@ int lbtp_nn_train_step(lbtp_nn *nn, const float *lnK, const float *S, const floa
   const float *dK = stage(nn, lnK, npix, on_device, tmp, &rc);
   const float *dS = stage(nn, S, npix, on_device, tmp, &rc);
   const float *dT = stage(nn, P, npix, on_device, tmp, &rc);
-  if (!rc) rc = loss_grad(nn, dK, dS, dT, N, H, W, loss);
+  const float *dW = stage(nn, weight, (size_t)N, on_device, tmp, &rc);
+  if (!rc) rc = loss_grad(nn, dK, dS, dT, dW, N, H, W, loss);
   if (!rc) {
     nn->adam_t += 1;
     const double b1 = 0.9, b2 = 0.999;

@@ -86,12 +86,12 @@ EXPORTS = {
     "lbtp_nn_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "lbtp_nn_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "lbtp_nn_predict": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
-                                       ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
     "lbtp_nn_loss_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
-                                         ctypes.c_void_p, ctypes.c_int]),
+                                         ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_int]),
     "lbtp_nn_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                          ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                          ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
 }
 
@@ -268,6 +268,11 @@ class Batch:
         return t.value
 
 
+def _ptr(t):
+    """Device pointer of a tensor, or NULL for None."""
+    return ctypes.c_void_p(None if t is None else t.data_ptr())
+
+
 class WarmStartNet:
     """The learned warm start (include/lbtp_nn.h).  Fields are [N, H, W]
     float32 torch tensors on the device (or numpy arrays)."""
@@ -310,31 +315,37 @@ class WarmStartNet:
         _check(self._lib.lbtp_nn_get_params(self._h, ctypes.c_void_p(th.data_ptr()), 1), "lbtp_nn_get_params")
         return th
 
-    def predict(self, lnK, S):
+    def predict(self, lnK, S, factor=1):
+        """Initial pressure [n, h, w]; factor > 1 runs the network on the grid
+        coarsened by that factor and interpolates its deviation back."""
         lnK, S = self._dev(lnK), self._dev(S)
         n, h, w = lnK.shape
         P = self.torch.empty_like(lnK)
         _check(self._lib.lbtp_nn_predict(self._h, ctypes.c_void_p(lnK.data_ptr()), ctypes.c_void_p(S.data_ptr()),
-                                         n, h, w, ctypes.c_void_p(P.data_ptr()), 1), "lbtp_nn_predict")
+                                         n, h, w, int(factor), ctypes.c_void_p(P.data_ptr()), 1), "lbtp_nn_predict")
         return P
 
-    def loss_grad(self, lnK, S, P):
-        lnK, S, P = self._dev(lnK), self._dev(S), self._dev(P)
+    def _weights(self, weight):
+        return None if weight is None else self._dev(weight)
+
+    def loss_grad(self, lnK, S, P, weight=None):
+        """Weighted MSE (weight: one per sample or None) and its gradient."""
+        lnK, S, P, wt = self._dev(lnK), self._dev(S), self._dev(P), self._weights(weight)
         n, h, w = lnK.shape
         g = self.torch.empty(self.n_params, dtype=self.torch.float32, device="cuda")
         loss = ctypes.c_double()
         _check(self._lib.lbtp_nn_loss_grad(self._h, ctypes.c_void_p(lnK.data_ptr()), ctypes.c_void_p(S.data_ptr()),
-                                           ctypes.c_void_p(P.data_ptr()), n, h, w, ctypes.byref(loss),
+                                           ctypes.c_void_p(P.data_ptr()), _ptr(wt), n, h, w, ctypes.byref(loss),
                                            ctypes.c_void_p(g.data_ptr()), 1), "lbtp_nn_loss_grad")
         return loss.value, g
 
-    def train_step(self, lnK, S, P, lr):
-        lnK, S, P = self._dev(lnK), self._dev(S), self._dev(P)
+    def train_step(self, lnK, S, P, lr, weight=None):
+        lnK, S, P, wt = self._dev(lnK), self._dev(S), self._dev(P), self._weights(weight)
         n, h, w = lnK.shape
         loss = ctypes.c_double()
         _check(self._lib.lbtp_nn_train_step(self._h, ctypes.c_void_p(lnK.data_ptr()), ctypes.c_void_p(S.data_ptr()),
-                                            ctypes.c_void_p(P.data_ptr()), n, h, w, float(lr), ctypes.byref(loss), 1),
-               "lbtp_nn_train_step")
+                                            ctypes.c_void_p(P.data_ptr()), _ptr(wt), n, h, w, float(lr),
+                                            ctypes.byref(loss), 1), "lbtp_nn_train_step")
         return loss.value
 
 

@@ -18,6 +18,18 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 1 << 30
+# the sources the sweep kernels are compiled from
+SWEEP_SOURCES = ("lbtp_kernels.hip", "lbtp_device.h", "lbtp_internal.h")
+
+
+def source_digest():
+    """sha256 over the sweep kernel sources (in SWEEP_SOURCES order): a counter
+    summary is valid only for the kernels it was taken on."""
+    h = hashlib.sha256()
+    for name in SWEEP_SOURCES:
+        with open(os.path.join(HERE, "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def run(storage, n, sweeps):
@@ -83,8 +95,7 @@ def summarize(fetch_csv, write_csv, out_txt, storage, n, command):
     q1, pop = 4, (4 if storage == "fp32" else 2)
     alg_read = n * n * (q1 * pop + 8)
     alg_write = n * n * q1 * pop
-    src = os.path.join(HERE, "csrc", "lbtp_kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = source_digest()
     text = f"""Pressure sweep HBM traffic, heterogeneous injection 2-D {n}x{n}, D2Q5, {storage} storage
 command: {command}
 counters: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each from its own rocprofv3 --pmc run
@@ -93,7 +104,7 @@ f_sweep_vec_kernel ({nsf} dispatches): FETCH_SIZE {sw_f:.1f} -> {fetch_b / 1e6:.
 f_sweep_vec_kernel ({nsw} dispatches): WRITE_SIZE {sw_w:.1f} -> {write_b / 1e6:.1f} MB written (algorithmic {alg_write / 1e6:.1f} MB, ratio {write_b / alg_write:.3f})
 bytes_per_launch: {fetch_b + write_b:.6e}
 algorithmic_bytes_per_launch: {alg_read + alg_write:.6e}
-source_sha256: {sha}
+source_sha256: {sha}  (csrc/{", csrc/".join(SWEEP_SOURCES)})
 """
     with open(out_txt, "w") as f:
         f.write(text)

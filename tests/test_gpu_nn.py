@@ -49,15 +49,31 @@ def test_forward_matches_reference(shape):
     assert err < 3e-2
 
 
-def test_gradients_match_reference():
+@pytest.mark.parametrize("shape,factor", [((2, 64, 64), 2), ((1, 128, 64), 4), ((1, 256, 256), 16)])
+def test_coarse_grid_predict_matches_reference(shape, factor):
+    N, H, W = shape
+    lnK, S, _ = _data(N, H, W, 11)
+    th = _theta(3)
+    net = _net(th)
+    got = net.predict(lnK, S, factor).cpu().numpy().astype(np.float64)
+    ref = unet.predict(th, lnK.astype(np.float64), S.astype(np.float64), SCALE, factor, BASE, LEVELS)
+    ramp = 1.0 - (np.arange(W) + 0.5) / W
+    err = rel_l2(ref - ramp, got - ramp)
+    print("coarse predict rel err", factor, err)
+    assert err < 3e-2
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_gradients_match_reference(weighted):
     N, H, W = 2, 32, 32
     lnK, S, P = _data(N, H, W, 5)
     th = _theta(2)
     net = _net(th)
-    loss_g, g = net.loss_grad(lnK, S, P)
+    wts = np.array([0.25, 3.0], np.float32) if weighted else None
+    loss_g, g = net.loss_grad(lnK, S, P, wts)
     g = g.cpu().numpy().astype(np.float64)
     loss_r, gr = unet.loss_and_grad(th, lnK.astype(np.float64), S.astype(np.float64), P.astype(np.float64), SCALE,
-                                    BASE, LEVELS)
+                                    BASE, LEVELS, weight=wts)
     assert abs(loss_g - loss_r) <= 2e-2 * loss_r
     off = 0
     worst = 0.0
@@ -92,3 +108,7 @@ def test_bad_shapes_rejected():
     net = _net(_theta())
     with pytest.raises(lbtp.LbtpError):
         net.predict(np.zeros((1, 12, 16), np.float32), np.zeros((1, 12, 16), np.float32))   # 12 % 8 != 0
+    with pytest.raises(lbtp.LbtpError):
+        net.predict(np.zeros((1, 64, 64), np.float32), np.zeros((1, 64, 64), np.float32), 3)   # 64 % 3 != 0
+    with pytest.raises(lbtp.LbtpError):
+        net.predict(np.zeros((1, 64, 64), np.float32), np.zeros((1, 64, 64), np.float32), 16)  # coarse 4 % 8 != 0
