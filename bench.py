@@ -30,6 +30,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_1808_07554_amd.profile_sweep import source_digest, sweep_kernel_name  # noqa: E402
+
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes of one plain pressure sweep per node: the Q-1 stored
 # deviations read and written, 1/tau_f and the base pressure P_b read
@@ -67,7 +69,6 @@ def measured_traffic(storage):
     """HBM bytes per f-sweep launch from the committed rocprofv3 counter summary
     for this storage format, if it was taken on the current kernel sources
     (else None)."""
-    from paper_1808_07554_amd.profile_sweep import source_digest
     path = TRAFFIC_FILE.format(storage)
     if not os.path.exists(path):
         return None
@@ -252,6 +253,23 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     sweep_s = e0.elapsed_time(e1) / 1e3 / a.burst
+    # saturation side (after the timed region; advances the state further)
+    nsat = 10
+    e0.record(stream)
+    for _ in range(nsat):
+        s.update_coefficients()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    moments_s = e0.elapsed_time(e1) / 1e3 / nsat
+    gstep_s = 0.0
+    for _ in range(nsat):      # a saturation step needs a pressure solve after the coefficients
+        s.update_coefficients()
+        s.pressure_solve(-1.0, 1)
+        e0.record(stream)
+        s.saturation_step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        gstep_s += e0.elapsed_time(e1) / 1e3 / nsat
     alg_bytes = f_sweep_bytes(params["lattice"], a.storage) * ncell
     achieved = alg_bytes / sweep_s / 1e9
     traffic = measured_traffic(a.storage) if (a.workload == "injection2d" and a.n == 4096) else None
@@ -278,12 +296,17 @@ def main():
         "s_per_coupled_step": t_run / a.steps,
         "iterations_per_step_mean": f_updates / a.steps,
         "iterations_per_step_max": max(its_all),
+        "iterations_per_step_percentiles": {q: int(np.percentile(its_all, q)) for q in (50, 90, 99)},
+        "f_sweep_mlups": round(ncell / sweep_s / 1e6, 1),
+        "g_step_mlups": round(ncell / gstep_s / 1e6, 1),
+        "moments_us": round(moments_s * 1e6, 2),
+        "g_step_us": round(gstep_s * 1e6, 2),
         "whole_job_s": (t_cold or 0.0) + t_run,
         "cold_first_step_s": t_cold,
         "cold_first_step_iterations": warm_its[0] if warm_its else None,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "f_sweep_kernel (plain sweep)", "avg_launch_us": round(sweep_s * 1e6, 2),
+                     "kernel": sweep_kernel_name(a.storage, 3 if a.workload == "injection3d" else 2) + " (plain pressure sweep)", "avg_launch_us": round(sweep_s * 1e6, 2),
                      "bytes_per_launch": alg_bytes},
     }
     if not a.no_cpu and a.workload == "injection2d":

@@ -443,7 +443,7 @@ int lbtp_pressure_solve(lbtp_ctx *c, double tol, long long max_iters, long long 
                                   fptrs(c, c->fbuf[parity ^ 1]), c->Pb[pb], c->Pb[pb ^ 1], c->itau,
                                   Fp_or_null(c), c->partials, c->ctl, k, local, mode, c->stream);
     if (e == hipSuccess && mode == 2)
-      e = launch_finish_residual(c->partials, sweep_blocks(c->kc, local), c->ctl, k, m, c->stream);
+      e = launch_finish_residual(c->partials, sweep_blocks(c->kc, local, c->dim, c->p.storage), c->ctl, k, m, c->stream);
     if (mode >= 1) pb ^= 1;
     return e;
   };

@@ -276,128 +276,122 @@ __device__ inline void f4set(float4 &v, int i, float x) {
   else v.w = x;
 }
 
-// Four nodes starting at quad qi of one realisation; adds the stopping-rule
-// terms of the active quad to acc.  Shared by the single-realisation kernel
-// and the batched (ensemble) kernel, so both compute bit-identical results.
-template <int DIM, typename T, int MODE, bool HAS_FP>
-__device__ inline void sweep_quad(const KC &kc, const FP<T> &fin, const FP<T> &fout, const float *__restrict__ Pb_in,
-                                  float *__restrict__ Pb_out, const float *__restrict__ itau,
-                                  const float *__restrict__ Fp, int qi, double *acc) {
-  const int n4 = kc.ncell >> 2;
-  const bool active = qi < n4;
-  const int c = (active ? qi : n4 - 1) << 2;     // first of the four nodes
+// +x (e0) and -x (e2) deviations of the quad at node c (first node x0):
+// from the thread's own vectors, the adjacent lanes (shuffles), one scalar
+// load at a wavefront edge, or the x-face rules.  Every lane of the
+// wavefront must call it (the shuffles).
+template <typename T>
+__device__ inline void pull_x_quad(const KC &kc, const FP<T> &fin, const float *__restrict__ Pb_in, int c, int x0,
+                                   const float4 &pb, float4 &e0, float4 &e2) {
   const int lane = threadIdx.x & 63;
-  const int row = c / kc.nx;
-  const int x0 = c - row * kc.nx;
-  const int z = row / kc.ny;
-  const int y = row - z * kc.ny;
   const float is = kc.inv_dev_scale;
-
-  const float4 pb = *(const float4 *)(Pb_in + c);
-  // x-streamed populations: +x (j = 0) pulls from x - 1, -x (j = 2) from x + 1
+  // +x (j = 0) pulls from x - 1, -x (j = 2) from x + 1
   const float4 A = Vec4<T>::load(fin.p[0], c, is);
   const float4 B = Vec4<T>::load(fin.p[2], c, is);
   float a_left = __shfl_up(A.w, 1, 64), pb_left = __shfl_up(pb.w, 1, 64);
   float b_right = __shfl_down(B.x, 1, 64), pb_right = __shfl_down(pb.x, 1, 64);
-
-  float4 e[2 * DIM];
   // +x for nodes 1..3 from the own vector, node 0 from the left neighbour
-  e[0] = make_float4(0.f, A.x + kc.w1 * (pb.x - pb.y), A.y + kc.w1 * (pb.y - pb.z), A.z + kc.w1 * (pb.z - pb.w));
-  e[2] = make_float4(B.y + kc.w1 * (pb.y - pb.x), B.z + kc.w1 * (pb.z - pb.y), B.w + kc.w1 * (pb.w - pb.z), 0.f);
+  e0 = make_float4(0.f, A.x + kc.w1 * (pb.x - pb.y), A.y + kc.w1 * (pb.y - pb.z), A.z + kc.w1 * (pb.z - pb.w));
+  e2 = make_float4(B.y + kc.w1 * (pb.y - pb.x), B.z + kc.w1 * (pb.z - pb.y), B.w + kc.w1 * (pb.w - pb.z), 0.f);
   if (x0 == 0) {
     const int bc = kc.bc_f[0];
     if (bc == LBTP_BC_PERIODIC) {
       const int src = c + kc.nx - 1;
-      e[0].x = Storage<T>::load(fin.p[0], src, is) + kc.w1 * (Pb_in[src] - pb.x);
+      e0.x = Storage<T>::load(fin.p[0], src, is) + kc.w1 * (Pb_in[src] - pb.x);
     } else {
-      e[0].x = (bc == LBTP_BC_DIRICHLET) ? (2.0f * kc.w1 * (kc.Pw[0] - pb.x) - B.x) : B.x;
+      e0.x = (bc == LBTP_BC_DIRICHLET) ? (2.0f * kc.w1 * (kc.Pw[0] - pb.x) - B.x) : B.x;
     }
   } else {
     if (lane == 0) {
       a_left = Storage<T>::load(fin.p[0], c - 1, is);
       pb_left = Pb_in[c - 1];
     }
-    e[0].x = a_left + kc.w1 * (pb_left - pb.x);
+    e0.x = a_left + kc.w1 * (pb_left - pb.x);
   }
   if (x0 + 4 == kc.nx) {
     const int bc = kc.bc_f[1];
     if (bc == LBTP_BC_PERIODIC) {
       const int src = c + 3 - (kc.nx - 1);
-      e[2].w = Storage<T>::load(fin.p[2], src, is) + kc.w1 * (Pb_in[src] - pb.w);
+      e2.w = Storage<T>::load(fin.p[2], src, is) + kc.w1 * (Pb_in[src] - pb.w);
     } else {
-      e[2].w = (bc == LBTP_BC_DIRICHLET) ? (2.0f * kc.w1 * (kc.Pw[1] - pb.w) - A.w) : A.w;
+      e2.w = (bc == LBTP_BC_DIRICHLET) ? (2.0f * kc.w1 * (kc.Pw[1] - pb.w) - A.w) : A.w;
     }
   } else {
     if (lane == 63) {
       b_right = Storage<T>::load(fin.p[2], c + 4, is);
       pb_right = Pb_in[c + 4];
     }
-    e[2].w = b_right + kc.w1 * (pb_right - pb.w);
+    e2.w = b_right + kc.w1 * (pb_right - pb.w);
   }
-  // y (and z) streamed populations: whole vectors from the neighbouring row
-#pragma unroll
-  for (int a = 1; a < DIM; ++a) {
-    const int jp = (a == 1) ? 1 : 4, jm = (a == 1) ? 3 : 5;   // +a and -a directions
-    const int coordv = (a == 1) ? y : z;
-    const int n = (a == 1) ? kc.ny : kc.nz;
-    const int st = (a == 1) ? kc.nx : kc.nx * kc.ny;
-    // +a pulls from coord - 1
-    if (coordv == 0) {
-      const int bc = kc.bc_f[2 * a];
-      if (bc == LBTP_BC_PERIODIC) {
-        const int src = c + (n - 1) * st;
-        const float4 v = Vec4<T>::load(fin.p[jp], src, is);
-        const float4 q = *(const float4 *)(Pb_in + src);
-        e[jp] = make_float4(v.x + kc.w1 * (q.x - pb.x), v.y + kc.w1 * (q.y - pb.y), v.z + kc.w1 * (q.z - pb.z),
-                            v.w + kc.w1 * (q.w - pb.w));
-      } else {
-        const float4 o = Vec4<T>::load(fin.p[jm], c, is);
-        if (bc == LBTP_BC_DIRICHLET) {
-          const float pw = kc.Pw[2 * a];
-          e[jp] = make_float4(2.0f * kc.w1 * (pw - pb.x) - o.x, 2.0f * kc.w1 * (pw - pb.y) - o.y,
-                              2.0f * kc.w1 * (pw - pb.z) - o.z, 2.0f * kc.w1 * (pw - pb.w) - o.w);
-        } else {
-          e[jp] = o;
-        }
-      }
-    } else {
-      const int src = c - st;
-      const float4 v = Vec4<T>::load(fin.p[jp], src, is);
-      const float4 q = *(const float4 *)(Pb_in + src);
-      e[jp] = make_float4(v.x + kc.w1 * (q.x - pb.x), v.y + kc.w1 * (q.y - pb.y), v.z + kc.w1 * (q.z - pb.z),
-                          v.w + kc.w1 * (q.w - pb.w));
-    }
-    // -a pulls from coord + 1
-    if (coordv == n - 1) {
-      const int bc = kc.bc_f[2 * a + 1];
-      if (bc == LBTP_BC_PERIODIC) {
-        const int src = c - (n - 1) * st;
-        const float4 v = Vec4<T>::load(fin.p[jm], src, is);
-        const float4 q = *(const float4 *)(Pb_in + src);
-        e[jm] = make_float4(v.x + kc.w1 * (q.x - pb.x), v.y + kc.w1 * (q.y - pb.y), v.z + kc.w1 * (q.z - pb.z),
-                            v.w + kc.w1 * (q.w - pb.w));
-      } else {
-        const float4 o = Vec4<T>::load(fin.p[jp], c, is);
-        if (bc == LBTP_BC_DIRICHLET) {
-          const float pw = kc.Pw[2 * a + 1];
-          e[jm] = make_float4(2.0f * kc.w1 * (pw - pb.x) - o.x, 2.0f * kc.w1 * (pw - pb.y) - o.y,
-                              2.0f * kc.w1 * (pw - pb.z) - o.z, 2.0f * kc.w1 * (pw - pb.w) - o.w);
-        } else {
-          e[jm] = o;
-        }
-      }
-    } else {
-      const int src = c + st;
-      const float4 v = Vec4<T>::load(fin.p[jm], src, is);
-      const float4 q = *(const float4 *)(Pb_in + src);
-      e[jm] = make_float4(v.x + kc.w1 * (q.x - pb.x), v.y + kc.w1 * (q.y - pb.y), v.z + kc.w1 * (q.z - pb.z),
-                          v.w + kc.w1 * (q.w - pb.w));
-    }
-  }
+}
 
-  const float4 it = *(const float4 *)(itau + c);
-  float4 fp = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (HAS_FP) fp = *(const float4 *)(Fp + c);
+// Whether the +a pull at coordinate coordv reads a node (inside, or across a
+// periodic face), and likewise the -a pull; otherwise a wall rule applies.
+__device__ inline bool reads_lo(const KC &kc, int a, int coordv) {
+  return coordv != 0 || kc.bc_f[2 * a] == LBTP_BC_PERIODIC;
+}
+__device__ inline bool reads_hi(const KC &kc, int a, int coordv, int n) {
+  return coordv != n - 1 || kc.bc_f[2 * a + 1] == LBTP_BC_PERIODIC;
+}
+
+// Deviations streamed along axis a >= 1 (+a into ep, -a into em) for the quad
+// at node c with coordinate coordv along a (extent n, stride st): whole
+// vectors from the neighbouring row or plane, or the face rules.  pbm and pbp
+// are the bases of the rows the +a and -a pulls read (used only when they
+// read one).
+template <typename T>
+__device__ inline void pull_axis_quad(const KC &kc, const FP<T> &fin, int c, int a, int coordv, int n, int st,
+                                      const float4 &pb, const float4 &pbm, const float4 &pbp, float4 &ep,
+                                      float4 &em) {
+  const float is = kc.inv_dev_scale;
+  const int jp = (a == 1) ? 1 : 4, jm = (a == 1) ? 3 : 5;   // +a and -a directions
+  // +a pulls from coord - 1
+  if (reads_lo(kc, a, coordv)) {
+    const int src = coordv == 0 ? c + (n - 1) * st : c - st;
+    const float4 v = Vec4<T>::load(fin.p[jp], src, is);
+    ep = make_float4(v.x + kc.w1 * (pbm.x - pb.x), v.y + kc.w1 * (pbm.y - pb.y), v.z + kc.w1 * (pbm.z - pb.z),
+                     v.w + kc.w1 * (pbm.w - pb.w));
+  } else {
+    const float4 o = Vec4<T>::load(fin.p[jm], c, is);
+    if (kc.bc_f[2 * a] == LBTP_BC_DIRICHLET) {
+      const float pw = kc.Pw[2 * a];
+      ep = make_float4(2.0f * kc.w1 * (pw - pb.x) - o.x, 2.0f * kc.w1 * (pw - pb.y) - o.y,
+                       2.0f * kc.w1 * (pw - pb.z) - o.z, 2.0f * kc.w1 * (pw - pb.w) - o.w);
+    } else {
+      ep = o;
+    }
+  }
+  // -a pulls from coord + 1
+  if (reads_hi(kc, a, coordv, n)) {
+    const int src = coordv == n - 1 ? c - (n - 1) * st : c + st;
+    const float4 v = Vec4<T>::load(fin.p[jm], src, is);
+    em = make_float4(v.x + kc.w1 * (pbp.x - pb.x), v.y + kc.w1 * (pbp.y - pb.y), v.z + kc.w1 * (pbp.z - pb.z),
+                     v.w + kc.w1 * (pbp.w - pb.w));
+  } else {
+    const float4 o = Vec4<T>::load(fin.p[jp], c, is);
+    if (kc.bc_f[2 * a + 1] == LBTP_BC_DIRICHLET) {
+      const float pw = kc.Pw[2 * a + 1];
+      em = make_float4(2.0f * kc.w1 * (pw - pb.x) - o.x, 2.0f * kc.w1 * (pw - pb.y) - o.y,
+                       2.0f * kc.w1 * (pw - pb.z) - o.z, 2.0f * kc.w1 * (pw - pb.w) - o.w);
+    } else {
+      em = o;
+    }
+  }
+}
+
+// Bases of the rows the +a / -a pulls read, from memory (only those read).
+__device__ inline void load_pb_axis(const KC &kc, const float *__restrict__ Pb_in, int c, int a, int coordv, int n,
+                                    int st, float4 &pbm, float4 &pbp) {
+  if (reads_lo(kc, a, coordv)) pbm = *(const float4 *)(Pb_in + (coordv == 0 ? c + (n - 1) * st : c - st));
+  if (reads_hi(kc, a, coordv, n)) pbp = *(const float4 *)(Pb_in + (coordv == n - 1 ? c - (n - 1) * st : c + st));
+}
+
+// P (eq. 3-9a), collision (eq. 2-1b a), source, re-basing and stopping-rule
+// terms of the four nodes of a quad, then the stores (active quads only).
+template <int DIM, typename T, int MODE, bool HAS_FP>
+__device__ inline void collide_quad(const KC &kc, const float4 *e, const float4 &pb, const float4 &it,
+                                    const float4 &fp, const FP<T> &fout, float *__restrict__ Pb_out, int c,
+                                    bool active, double *acc) {
   float4 o[2 * DIM];
   float4 pnew;
 #pragma unroll
@@ -430,6 +424,91 @@ __device__ inline void sweep_quad(const KC &kc, const FP<T> &fin, const FP<T> &f
 #pragma unroll
     for (int j = 0; j < 2 * DIM; ++j) Vec4<T>::store(fout.p[j], c, o[j], kc.dev_scale);
     if (MODE >= 1) *(float4 *)(Pb_out + c) = pnew;
+  }
+}
+
+// Four nodes starting at quad qi of one realisation; adds the stopping-rule
+// terms of the active quad to acc.  Shared by the single-realisation kernel
+// and the batched (ensemble) kernel, so both compute bit-identical results.
+template <int DIM, typename T, int MODE, bool HAS_FP>
+__device__ inline void sweep_quad(const KC &kc, const FP<T> &fin, const FP<T> &fout, const float *__restrict__ Pb_in,
+                                  float *__restrict__ Pb_out, const float *__restrict__ itau,
+                                  const float *__restrict__ Fp, int qi, double *acc) {
+  const int n4 = kc.ncell >> 2;
+  const bool active = qi < n4;
+  const int c = (active ? qi : n4 - 1) << 2;     // first of the four nodes
+  const int row = c / kc.nx;
+  const int x0 = c - row * kc.nx;
+  const int z = row / kc.ny;
+  const int y = row - z * kc.ny;
+
+  const float4 pb = *(const float4 *)(Pb_in + c);
+  float4 e[2 * DIM];
+  pull_x_quad<T>(kc, fin, Pb_in, c, x0, pb, e[0], e[2]);
+#pragma unroll
+  for (int a = 1; a < DIM; ++a) {
+    const int coordv = (a == 1) ? y : z;
+    const int n = (a == 1) ? kc.ny : kc.nz;
+    const int st = (a == 1) ? kc.nx : kc.nx * kc.ny;
+    float4 pbm = pb, pbp = pb;
+    load_pb_axis(kc, Pb_in, c, a, coordv, n, st, pbm, pbp);
+    pull_axis_quad<T>(kc, fin, c, a, coordv, n, st, pb, pbm, pbp, e[a == 1 ? 1 : 4], e[a == 1 ? 3 : 5]);
+  }
+  const float4 it = *(const float4 *)(itau + c);
+  float4 fp = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (HAS_FP) fp = *(const float4 *)(Fp + c);
+  collide_quad<DIM, T, MODE, HAS_FP>(kc, e, pb, it, fp, fout, Pb_out, c, active, acc);
+}
+
+// The same sweep with each thread walking kWalk consecutive rows (2-D: along
+// y) or planes (3-D: along z) at one quad position t of the cross-section.
+// The bases of the rows on either side of the walked row stay in registers,
+// so each base value is fetched once per sweep instead of up to three times.
+// Walk positions beyond the grid are computed on clamped indices and not
+// stored; every lane runs the same number of steps (the shuffles).
+template <int DIM, typename T, int MODE, bool HAS_FP>
+__device__ inline void sweep_quad_walk(const KC &kc, const FP<T> &fin, const FP<T> &fout,
+                                       const float *__restrict__ Pb_in, float *__restrict__ Pb_out,
+                                       const float *__restrict__ itau, const float *__restrict__ Fp, int t,
+                                       double *acc) {
+  constexpr int W = DIM - 1;                        // walked axis: y (2-D) or z (3-D)
+  const int nw = W == 1 ? kc.ny : kc.nz;
+  const int sw = W == 1 ? kc.nx : kc.nx * kc.ny;   // its stride
+  const int nline = sw >> 2;                        // quads per cross-section
+  const int ngroup = (nw + kWalk - 1) / kWalk;
+  const bool tvalid = t < nline * ngroup;
+  const int tt = tvalid ? t : nline * ngroup - 1;
+  const int p = tt % nline, g = tt / nline;
+  const int c0 = p << 2;                            // offset within the cross-section
+  const int x0 = c0 % kc.nx;
+  const int y3 = c0 / kc.nx;                        // y of the quad (3-D)
+  const int w0 = g * kWalk;
+  // rolling bases of rows w - 1, w, w + 1 (a wrapped row across a periodic face)
+  float4 pb_cur = *(const float4 *)(Pb_in + w0 * sw + c0);
+  float4 pb_prev = pb_cur, pb_next = pb_cur;
+  if (reads_lo(kc, W, w0)) pb_prev = *(const float4 *)(Pb_in + (w0 == 0 ? nw - 1 : w0 - 1) * sw + c0);
+  for (int r = 0; r < kWalk; ++r) {
+    const int w = w0 + r;
+    const bool active = tvalid && w < nw;
+    const int wl = w < nw ? w : nw - 1;
+    const int c = wl * sw + c0;
+    if (reads_hi(kc, W, wl, nw)) pb_next = *(const float4 *)(Pb_in + (wl == nw - 1 ? 0 : wl + 1) * sw + c0);
+    float4 e[2 * DIM];
+    pull_x_quad<T>(kc, fin, Pb_in, c, x0, pb_cur, e[0], e[2]);
+    if (DIM == 3) {
+      float4 pbm = pb_cur, pbp = pb_cur;
+      load_pb_axis(kc, Pb_in, c, 1, y3, kc.ny, kc.nx, pbm, pbp);
+      pull_axis_quad<T>(kc, fin, c, 1, y3, kc.ny, kc.nx, pb_cur, pbm, pbp, e[1], e[3]);
+    }
+    pull_axis_quad<T>(kc, fin, c, W, wl, nw, sw, pb_cur, pb_prev, pb_next, e[W == 1 ? 1 : 4], e[W == 1 ? 3 : 5]);
+    const float4 it = *(const float4 *)(itau + c);
+    float4 fp = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (HAS_FP) fp = *(const float4 *)(Fp + c);
+    collide_quad<DIM, T, MODE, HAS_FP>(kc, e, pb_cur, it, fp, fout, Pb_out, c, active, acc);
+    if (w < nw - 1) {
+      pb_prev = pb_cur;
+      pb_cur = pb_next;
+    }
   }
 }
 

@@ -32,6 +32,11 @@ def source_digest():
     return h.hexdigest()
 
 
+def sweep_kernel_name(storage, dim=2):
+    """The kernel of a plain pull-form pressure sweep with nx % 4 == 0."""
+    return "f_sweep_walk_kernel" if (dim == 2 and storage != "fp32") else "f_sweep_vec_kernel"
+
+
 def run(storage, n, sweeps):
     import ctypes
 
@@ -85,9 +90,10 @@ def summarize(fetch_csv, write_csv, out_txt, storage, n, command):
     w_rows = _counter_rows(write_csv)
     copy_f, ncf = _per_dispatch(f_rows, "copy_probe")
     copy_w, ncw = _per_dispatch(w_rows, "copy_probe")
-    # plain sweeps: MODE 0 instantiation of the 4-node kernel
-    sw_f, nsf = _per_dispatch(f_rows, "f_sweep_vec_kernel")
-    sw_w, nsw = _per_dispatch(w_rows, "f_sweep_vec_kernel")
+    # plain sweeps of the 4-node kernel (rows walked for 16-bit storage in 2-D)
+    kname = sweep_kernel_name(storage)
+    sw_f, nsf = _per_dispatch(f_rows, kname)
+    sw_w, nsw = _per_dispatch(w_rows, kname)
     scale_f = COPY_BYTES / copy_f
     scale_w = COPY_BYTES / copy_w
     fetch_b = sw_f * scale_f
@@ -100,8 +106,8 @@ def summarize(fetch_csv, write_csv, out_txt, storage, n, command):
 command: {command}
 counters: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each from its own rocprofv3 --pmc run
 calibration: lbtp_copy_probe of {COPY_BYTES} B: FETCH_SIZE {copy_f:.1f} ({ncf} dispatches), WRITE_SIZE {copy_w:.1f} ({ncw}) -> {scale_f:.2f} / {scale_w:.2f} B per count
-f_sweep_vec_kernel ({nsf} dispatches): FETCH_SIZE {sw_f:.1f} -> {fetch_b / 1e6:.1f} MB read (algorithmic {alg_read / 1e6:.1f} MB, ratio {fetch_b / alg_read:.3f})
-f_sweep_vec_kernel ({nsw} dispatches): WRITE_SIZE {sw_w:.1f} -> {write_b / 1e6:.1f} MB written (algorithmic {alg_write / 1e6:.1f} MB, ratio {write_b / alg_write:.3f})
+{kname} ({nsf} dispatches): FETCH_SIZE {sw_f:.1f} -> {fetch_b / 1e6:.1f} MB read (algorithmic {alg_read / 1e6:.1f} MB, ratio {fetch_b / alg_read:.3f})
+{kname} ({nsw} dispatches): WRITE_SIZE {sw_w:.1f} -> {write_b / 1e6:.1f} MB written (algorithmic {alg_write / 1e6:.1f} MB, ratio {write_b / alg_write:.3f})
 bytes_per_launch: {fetch_b + write_b:.6e}
 algorithmic_bytes_per_launch: {alg_read + alg_write:.6e}
 source_sha256: {sha}  (csrc/{", csrc/".join(SWEEP_SOURCES)})
