@@ -12,7 +12,8 @@
  *
  * Method (Section 3): a pressure lattice f_i iterated in pseudo time to a
  * steady state (eq. 3-1, 3-3) and a saturation lattice g_i advanced in
- * physical time (eq. 3-2, 3-4b), on D2Q5 or D3Q7 (Remark V).  The pressure
+ * physical time (eq. 3-2), on D2Q5 or D3Q7 (equilibrium eq. 3-4b, Remark V)
+ * or on the paper's D2Q9 (eq. 3-4, 3-5, 3-6).  The pressure
  * gradient and velocity come from the local first moment of f (eq. 3-10);
  * the relaxation times follow from D_p and D_s (eq. 3-11).  Dirichlet
  * boundaries use anti-bounce-back, no-flux boundaries bounce-back
@@ -20,12 +21,15 @@
  *
  * Conventions
  *   - Lattice units of the caller: dx, dt given; c = dx/dt; c_s^2 = c^2/3
- *     (D2Q5) or c^2/4 (D3Q7).
+ *     (D2Q5, D2Q9) or c^2/4 (D3Q7).  Weights: D2Q5 1/3, 1/6; D3Q7 1/4, 1/8;
+ *     D2Q9 4/9, 1/9 (axes), 1/36 (diagonals) (eq. 3-5).
  *   - Scalar fields are float32 arrays of nx*ny*nz values, x fastest:
  *     index = x + nx*(y + ny*z).  Vector fields are component-major:
  *     component a of cell c at a*ncell + c.
  *   - Population order: i = 0 rest, then +x, +y, -x, -y (D2Q5), followed by
- *     +z, -z (D3Q7).  The rest population of the pressure lattice never
+ *     +z, -z (D3Q7) or by the diagonals (1,1), (-1,1), (-1,-1), (1,-1)
+ *     (D2Q9, eq. 3-6).  On D2Q9 a diagonal link that crosses an x and a y face
+ *     at a corner takes the y face's rule.  The rest population of the pressure lattice never
  *     influences any output (P sums i >= 1, eq. 3-9a; c_0 = 0 in eq. 3-10;
  *     bar-omega_0 = 0; walls act on moving populations only), so it is not
  *     stored; f arrays hold Q-1 populations, g arrays hold Q.
@@ -55,7 +59,8 @@ extern "C" {
 
 typedef struct lbtp_ctx lbtp_ctx;
 
-enum lbtp_lattice { LBTP_D2Q5 = 0, LBTP_D3Q7 = 1 };
+/* D2Q9 runs one node per thread and is not available to ensembles. */
+enum lbtp_lattice { LBTP_D2Q5 = 0, LBTP_D3Q7 = 1, LBTP_D2Q9 = 2 };
 
 /* Storage of the pressure-lattice populations.  Every form stores the
  * deviation of f_i from a per-node base equilibrium, f_i - w_i P_b, where P_b
@@ -85,9 +90,10 @@ enum lbtp_status {
 
 typedef struct lbtp_params {
   int lattice;                 /* lbtp_lattice */
-  int nx, ny, nz;              /* nodes per axis; nz = 1 for D2Q5 */
+  int nx, ny, nz;              /* nodes per axis; nz = 1 for D2Q5 and D2Q9 */
   double dx, dt;               /* lattice spacing and time step */
-  double beta;                 /* equilibrium parameter of eq. 3-4b; 0 <= beta <= min(phi)/(1-w_0) */
+  double beta;                 /* equilibrium parameter: 0 <= beta <= min(phi)/(1-w_0) (eq. 3-4b), or
+                                  max(phi)/2 <= beta <= 2 min(phi) on D2Q9 (eq. 3-4) */
   double Ds;                   /* saturation diffusivity; tau_g = 1/2 + Ds/(beta c_s^2 dt) (eq. 3-11b) */
   double mu_w, mu_n;           /* phase viscosities (eq. 2-9) */
   int storage;                 /* lbtp_storage */

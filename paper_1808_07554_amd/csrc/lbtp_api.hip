@@ -20,6 +20,7 @@ using namespace lbtp;
 struct lbtp_ctx {
   lbtp_params p;
   int dim = 2, Q = 5, nf = 4;
+  int lk = 2;   // lattice kind of the launchers: 2 (D2Q5), 3 (D3Q7), kD2Q9
   long long ncell = 0;
   hipStream_t stream = nullptr;
   KC kc;
@@ -61,23 +62,31 @@ GPtrs gptrs(const lbtp_ctx *c, float *base) {
   return r;
 }
 
-double weight_rest(int lattice) { return lattice == LBTP_D2Q5 ? 1.0 / 3.0 : 1.0 / 4.0; }
-double weight_move(int lattice) { return lattice == LBTP_D2Q5 ? 1.0 / 6.0 : 1.0 / 8.0; }
-double cs2_over_c2(int lattice) { return lattice == LBTP_D2Q5 ? 1.0 / 3.0 : 1.0 / 4.0; }
+// Lattice constants: D2Q9 of eq. 3-5 / 3-6a; D2Q5 and D3Q7 with c_s^2 = 2 w_1 c^2
+// (the moment conditions eq. 3-7 on an axis-aligned lattice).
+double weight_rest(int lattice) {
+  return lattice == LBTP_D2Q5 ? 1.0 / 3.0 : (lattice == LBTP_D3Q7 ? 1.0 / 4.0 : 4.0 / 9.0);
+}
+double weight_move(int lattice) {   // axis directions
+  return lattice == LBTP_D2Q5 ? 1.0 / 6.0 : (lattice == LBTP_D3Q7 ? 1.0 / 8.0 : 1.0 / 9.0);
+}
+double cs2_over_c2(int lattice) { return lattice == LBTP_D3Q7 ? 1.0 / 4.0 : 1.0 / 3.0; }
+int lattice_dim(int lattice) { return lattice == LBTP_D3Q7 ? 3 : 2; }
+int lattice_q(int lattice) { return lattice == LBTP_D2Q5 ? 5 : (lattice == LBTP_D3Q7 ? 7 : 9); }
 
 int validate(const lbtp_params *p) {
   if (!p) return LBTP_EINVAL;
-  if (p->lattice != LBTP_D2Q5 && p->lattice != LBTP_D3Q7) return LBTP_EINVAL;
+  if (p->lattice != LBTP_D2Q5 && p->lattice != LBTP_D3Q7 && p->lattice != LBTP_D2Q9) return LBTP_EINVAL;
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return LBTP_EINVAL;
-  if (p->lattice == LBTP_D2Q5 && p->nz != 1) return LBTP_EINVAL;
+  if (p->lattice != LBTP_D3Q7 && p->nz != 1) return LBTP_EINVAL;
   const long long n = (long long)p->nx * p->ny * p->nz;
-  const int Q = p->lattice == LBTP_D2Q5 ? 5 : 7;
+  const int Q = lattice_q(p->lattice);
   if ((long long)Q * n >= (1LL << 31)) return LBTP_EINVAL;   // 32-bit cell indexing
   if (!(p->dx > 0) || !(p->dt > 0) || !(p->beta > 0) || !(p->Ds > 0)) return LBTP_EINVAL;
   if (!(p->mu_w > 0) || !(p->mu_n > 0)) return LBTP_EINVAL;
   if (p->storage != LBTP_FP32 && p->storage != LBTP_FP16_DEV && p->storage != LBTP_BF16_DEV) return LBTP_EINVAL;
   if (p->residual_stride < 1) return LBTP_EINVAL;
-  const int dim = p->lattice == LBTP_D2Q5 ? 2 : 3;
+  const int dim = lattice_dim(p->lattice);
   const double c = p->dx / p->dt;
   const double cs2 = cs2_over_c2(p->lattice) * c * c;
   const double tau_g = 0.5 + p->Ds / (p->beta * cs2 * p->dt);   // eq. 3-11b
@@ -115,8 +124,9 @@ void fill_kc(lbtp_ctx *c) {
   k.cs2 = (float)cs2;
   k.w0 = (float)w0;
   k.w1 = (float)w1;
+  k.w2 = (float)(1.0 / 36.0);
   k.inv_1mw0 = (float)(1.0 / (1.0 - w0));
-  k.wbar = (float)(1.0 / (2 * c->dim));
+  k.wbar = (float)(1.0 / c->nf);      // bar-omega_i = 1/(Q-1) for every moving direction
   k.beta = (float)p.beta;
   k.inv_tau_g = (float)(1.0 / tau_g);
   k.src_g = (float)(p.dt * (1.0 - 0.5 / tau_g));
@@ -134,6 +144,7 @@ void fill_kc(lbtp_ctx *c) {
     k.bc_g[f] = used ? p.bc_g[f] : LBTP_BC_PERIODIC;
     k.Pw[f] = (float)p.bc_P[f];
     k.abbS[f] = (float)(2.0 * w1 * p.beta * p.bc_S[f]);
+    k.Sw[f] = (float)p.bc_S[f];
   }
 }
 
@@ -259,9 +270,10 @@ int lbtp_init(const lbtp_params *p, lbtp_ctx **out) {
   if (rc) return rc;
   lbtp_ctx *c = new lbtp_ctx();
   c->p = *p;
-  c->dim = p->lattice == LBTP_D2Q5 ? 2 : 3;
-  c->Q = 2 * c->dim + 1;
-  c->nf = 2 * c->dim;
+  c->dim = lattice_dim(p->lattice);
+  c->Q = lattice_q(p->lattice);
+  c->nf = c->Q - 1;
+  c->lk = p->lattice == LBTP_D2Q9 ? kD2Q9 : c->dim;
   c->ncell = (long long)p->nx * p->ny * p->nz;
   c->stream = (hipStream_t)p->stream;
   c->nblk = nblocks(c->ncell);
@@ -332,14 +344,20 @@ int lbtp_set_fields(lbtp_ctx *c, const float *K, const float *phi, const float *
   if (rc) return rc;
   rc = fetch_host(c, phi, on_device, hphi);
   if (rc) return rc;
-  double phimin = INFINITY;
+  double phimin = INFINITY, phimax = 0.0;
   for (long long i = 0; i < c->ncell; ++i) {
     if (!(hK[i] > 0.0f) || !isfinite(hK[i])) return LBTP_EINVAL;
     if (!(hphi[i] > 0.0f) || !isfinite(hphi[i])) return LBTP_EINVAL;
     phimin = fmin(phimin, (double)hphi[i]);
+    phimax = fmax(phimax, (double)hphi[i]);
   }
-  // eq. 3-4b: 0 <= beta <= phi / (1 - w0) keeps every g^eq non-negative
-  if (c->p.beta > phimin / (1.0 - weight_rest(c->p.lattice)) * (1.0 + 1e-12)) return LBTP_EINVAL;
+  if (c->p.lattice == LBTP_D2Q9) {
+    // eq. 3-4: phi/2 <= beta <= 2 phi keeps every g^eq non-negative
+    if (c->p.beta < 0.5 * phimax * (1.0 - 1e-12) || c->p.beta > 2.0 * phimin * (1.0 + 1e-12)) return LBTP_EINVAL;
+  } else {
+    // eq. 3-4b: 0 <= beta <= phi / (1 - w0) keeps every g^eq non-negative
+    if (c->p.beta > phimin / (1.0 - weight_rest(c->p.lattice)) * (1.0 + 1e-12)) return LBTP_EINVAL;
+  }
   rc = upload(c, c->K, K, c->ncell, on_device);
   if (rc) return rc;
   rc = upload(c, c->phi, phi, c->ncell, on_device);
@@ -394,7 +412,7 @@ int lbtp_set_state(lbtp_ctx *c, const float *P0, const float *S0, const float *d
     if (rc) return rc;
     dS = (const float *)c->fbuf[1];
   }
-  HIP_TRY(launch_init(c->dim, c->p.storage, c->kc, c->Pb[1], c->S, dP, dS, c->K, c->phi, Fs_or_null(c),
+  HIP_TRY(launch_init(c->lk, c->p.storage, c->kc, c->Pb[1], c->S, dP, dS, c->K, c->phi, Fs_or_null(c),
                       c->p.init_neq, fptrs(c, c->fbuf[0]), c->Pb[0], gptrs(c, c->gbuf[0]), c->stream));
   c->fs = 0;
   c->gs = 0;
@@ -412,7 +430,7 @@ int lbtp_set_state(lbtp_ctx *c, const float *P0, const float *S0, const float *d
 int lbtp_update_coefficients(lbtp_ctx *c) {
   if (!c) return LBTP_EINVAL;
   if (!c->have_state) return LBTP_ESTATE;
-  HIP_TRY(launch_moments(c->dim, c->kc, gptrs(c, c->gbuf[c->gs]), c->K, c->phi, Fs_or_null(c), c->S, c->itau,
+  HIP_TRY(launch_moments(c->lk, c->kc, gptrs(c, c->gbuf[c->gs]), c->K, c->phi, Fs_or_null(c), c->S, c->itau,
                          c->partials, 1, c->stream));
   HIP_TRY(launch_finish_sum(c->partials, c->nblk, &c->ctl->mass, 0, nullptr, c->stream));
   c->have_coef = 1;
@@ -439,11 +457,11 @@ int lbtp_pressure_solve(lbtp_ctx *c, double tol, long long max_iters, long long 
     const int parity = (int)((c->fs + k) & 1);
     const int mode = (k % m != 0) ? 0 : ((k == 0 || !checks) ? 1 : 2);
     const int local = (k == 0) && c->f_local;
-    hipError_t e = launch_f_sweep(c->dim, c->p.storage, c->kc, fptrs(c, c->fbuf[parity]),
+    hipError_t e = launch_f_sweep(c->lk, c->p.storage, c->kc, fptrs(c, c->fbuf[parity]),
                                   fptrs(c, c->fbuf[parity ^ 1]), c->Pb[pb], c->Pb[pb ^ 1], c->itau,
                                   Fp_or_null(c), c->partials, c->ctl, k, local, mode, c->stream);
     if (e == hipSuccess && mode == 2)
-      e = launch_finish_residual(c->partials, sweep_blocks(c->kc, local, c->dim, c->p.storage), c->ctl, k, m, c->stream);
+      e = launch_finish_residual(c->partials, sweep_blocks(c->kc, local, c->lk, c->p.storage), c->ctl, k, m, c->stream);
     if (mode >= 1) pb ^= 1;
     return e;
   };
@@ -507,7 +525,7 @@ int lbtp_pressure_solve(lbtp_ctx *c, double tol, long long max_iters, long long 
 int lbtp_saturation_step(lbtp_ctx *c) {
   if (!c) return LBTP_EINVAL;
   if (!c->have_coef) return LBTP_ESTATE;
-  HIP_TRY(launch_g_sweep(c->dim, c->p.storage, c->kc, gptrs(c, c->gbuf[c->gs]), gptrs(c, c->gbuf[c->gs ^ 1]),
+  HIP_TRY(launch_g_sweep(c->lk, c->p.storage, c->kc, gptrs(c, c->gbuf[c->gs]), gptrs(c, c->gbuf[c->gs ^ 1]),
                          fptrs(c, c->fbuf[c->fs]), c->f_local, c->Pb[c->pbs], c->itau, c->K, c->phi, Fs_or_null(c),
                          c->partials, c->stream));
   HIP_TRY(launch_finish_sum(c->partials, c->nblk, &c->ctl->ledger, 1, &c->ctl->last_flux, c->stream));
@@ -538,7 +556,7 @@ int lbtp_step(lbtp_ctx *c, long long nsteps, double tol, long long max_iters, lo
 int lbtp_pressure(lbtp_ctx *c, float *P, int on_device) {
   if (!c || !P) return LBTP_EINVAL;
   if (!c->have_state) return LBTP_ESTATE;
-  HIP_TRY(launch_pressure(c->dim, c->p.storage, c->kc, fptrs(c, c->fbuf[c->fs]), c->f_local, c->Pb[c->pbs],
+  HIP_TRY(launch_pressure(c->lk, c->p.storage, c->kc, fptrs(c, c->fbuf[c->fs]), c->f_local, c->Pb[c->pbs],
                           c->scratch, c->stream));
   return download(c, P, c->scratch, c->ncell, on_device);
 }
@@ -551,7 +569,7 @@ static int grad_common(lbtp_ctx *c, float *out, int on_device, int velocity) {
     int rc = lbtp_update_coefficients(c);
     if (rc) return rc;
   }
-  HIP_TRY(launch_grad(c->dim, c->p.storage, c->kc, fptrs(c, c->fbuf[c->fs]), c->f_local, c->Pb[c->pbs], c->itau,
+  HIP_TRY(launch_grad(c->lk, c->p.storage, c->kc, fptrs(c, c->fbuf[c->fs]), c->f_local, c->Pb[c->pbs], c->itau,
                       c->K, c->S, velocity, c->scratch, c->stream));
   return download(c, out, c->scratch, (size_t)c->ncell * c->dim, on_device);
 }
@@ -562,7 +580,7 @@ int lbtp_grad_p(lbtp_ctx *c, float *g, int on_device) { return grad_common(c, g,
 int lbtp_saturation(lbtp_ctx *c, float *S, int on_device) {
   if (!c || !S) return LBTP_EINVAL;
   if (!c->have_state) return LBTP_ESTATE;
-  HIP_TRY(launch_saturation(c->dim, c->kc, gptrs(c, c->gbuf[c->gs]), c->phi, Fs_or_null(c), c->scratch,
+  HIP_TRY(launch_saturation(c->lk, c->kc, gptrs(c, c->gbuf[c->gs]), c->phi, Fs_or_null(c), c->scratch,
                             c->stream));
   return download(c, S, c->scratch, c->ncell, on_device);
 }
@@ -570,7 +588,7 @@ int lbtp_saturation(lbtp_ctx *c, float *S, int on_device) {
 int lbtp_mass(lbtp_ctx *c, double *mass, double *ledger) {
   if (!c) return LBTP_EINVAL;
   if (!c->have_state) return LBTP_ESTATE;
-  HIP_TRY(launch_moments(c->dim, c->kc, gptrs(c, c->gbuf[c->gs]), c->K, c->phi, Fs_or_null(c), nullptr, nullptr,
+  HIP_TRY(launch_moments(c->lk, c->kc, gptrs(c, c->gbuf[c->gs]), c->K, c->phi, Fs_or_null(c), nullptr, nullptr,
                          c->partials, 0, c->stream));
   HIP_TRY(launch_finish_sum(c->partials, c->nblk, &c->ctl->mass, 0, nullptr, c->stream));
   int rc = read_ctl(c);
@@ -588,7 +606,7 @@ int lbtp_populations(lbtp_ctx *c, float *f, float *g, int on_device) {
   if (f) {
     float *dst = f;
     if (!on_device && hipMalloc((void **)&dst, n * c->nf * sizeof(float)) != hipSuccess) return LBTP_ENOMEM;
-    hipError_t e = launch_populations(c->dim, c->p.storage, c->kc, fptrs(c, c->fbuf[c->fs]), c->f_local,
+    hipError_t e = launch_populations(c->lk, c->p.storage, c->kc, fptrs(c, c->fbuf[c->fs]), c->f_local,
                                       c->Pb[c->pbs], dst, c->stream);
     if (e == hipSuccess && !on_device)
       e = hipMemcpyAsync(f, dst, n * c->nf * sizeof(float), hipMemcpyDeviceToHost, c->stream);
@@ -868,6 +886,7 @@ int lbtp_batch_init(const lbtp_params *members, int n, lbtp_batch **out) {
   *out = nullptr;
   const lbtp_params &p0 = members[0];
   if (p0.residual_stride < 2 || p0.residual_stride % 2) return LBTP_EINVAL;
+  if (p0.lattice == LBTP_D2Q9) return LBTP_EINVAL;   // ensembles run D2Q5 / D3Q7
   for (int i = 0; i < n; ++i) {
     const lbtp_params &p = members[i];
     if (p.lattice != p0.lattice || p.storage != p0.storage || p.residual_stride != p0.residual_stride ||

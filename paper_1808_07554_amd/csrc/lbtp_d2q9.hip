@@ -1,0 +1,467 @@
+// D2Q9 kernels (gfx950): the paper's own lattice (Section 3, eq. 3-5, 3-6)
+// for both distributions, one node per thread.
+//
+// Layout and forms are those of the D2Q5 / D3Q7 kernels (lbtp_kernels.hip):
+// the pressure lattice stores the deviations d_i = f_i - w_i P_b of its eight
+// moving populations in a pull-form ping-pong (local form right after
+// initialisation), the saturation lattice stores g_0..g_8 as float and
+// pushes after the collision.  What changes with D2Q9:
+//   - directions j = 0..7 (population i = j + 1, the order of eq. 3-6):
+//     +x, +y, -x, -y, then (1,1), (-1,1), (-1,-1), (1,-1); weights 1/9 on
+//     the axes and 1/36 on the diagonals (eq. 3-5), c_s^2 = c^2/3 (eq. 3-6a),
+//     source weights bar-omega_i = 1/8 (eq. 3-5a);
+//   - g^eq is eq. 3-4 with C = (beta - phi) I, so every g_i^eq depends on the
+//     local porosity:  Gamma_i = g_i^eq / S = w_i (phi + (beta - phi)
+//     (|c_i|^2 - 2 c_s^2) / (2 c_s^2)), i.e. w_0 (2 phi - beta) at rest,
+//     w_1 (phi + beta) / 2 on the axes, w_2 (2 beta - phi) on the diagonals;
+//   - a diagonal link can cross an x face and a y face at once (corner
+//     nodes); the rule of the y face then applies, and a link that crosses
+//     one periodic and one wall face is reflected by the wall.
+#include <math.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "lbtp_device.h"
+
+namespace lbtp {
+namespace {
+
+__device__ constexpr int q9x(int j) { return (j == 0 || j == 4 || j == 7) ? 1 : ((j == 2 || j == 5 || j == 6) ? -1 : 0); }
+__device__ constexpr int q9y(int j) { return (j == 1 || j == 4 || j == 5) ? 1 : ((j == 3 || j == 6 || j == 7) ? -1 : 0); }
+__device__ constexpr int q9opp(int j) { return j < 4 ? (j + 2) & 3 : 4 + ((j - 2) & 3); }
+__device__ inline float q9w(const KC &kc, int j) { return j < 4 ? kc.w1 : kc.w2; }
+
+// Gamma_j = g^eq / S of moving direction j (eq. 3-4 with C = (beta - phi) I).
+__device__ inline float q9_gamma(const KC &kc, int j, float phi) {
+  return j < 4 ? kc.w1 * (phi + 0.5f * (kc.beta - phi)) : kc.w2 * (phi + 2.0f * (kc.beta - phi));
+}
+__device__ inline float q9_gamma0(const KC &kc, float phi) { return kc.w0 * (phi - (kc.beta - phi)); }
+
+// Face a link leaving node (x, y) along (ex, ey) crosses (push view, faces
+// -x, +x, -y, +y = 0..3), or -1 if it stays inside or wraps across periodic
+// faces.  Where it leaves through both an x and a y face the y face counts.
+__device__ inline int q9_exit_face(const KC &kc, const int *bc, int x, int y, int ex, int ey) {
+  const bool outy = ey > 0 ? y == kc.ny - 1 : (ey < 0 ? y == 0 : false);
+  const bool outx = ex > 0 ? x == kc.nx - 1 : (ex < 0 ? x == 0 : false);
+  const int fy = ey > 0 ? 3 : 2, fx = ex > 0 ? 1 : 0;
+  if (outy && bc[fy] != LBTP_BC_PERIODIC) return fy;
+  if (outx && bc[fx] != LBTP_BC_PERIODIC) return fx;
+  return -1;
+}
+
+__device__ inline int q9_wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Pre-collision deviations e_j at node c = (x, y) against P_b(c) = pb:
+// streamed from (x - e_x, y - e_y) (eq. 3-1) and re-expressed against the
+// node's base, or the Section 4 rule of the wall the link comes through:
+// anti-bounce-back e_j = 2 w_j (P_w - pb) - d_opp(c), bounce-back d_opp(c).
+template <typename T, bool LOCAL>
+__device__ inline void q9_load_e(const FP<T> &fin, const float *__restrict__ Pb, int c, int x, int y, const KC &kc,
+                                 float pb, float *e) {
+  const float is = kc.inv_dev_scale;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    if (LOCAL) {
+      e[j] = Storage<T>::load(fin.p[j], c, is);
+      continue;
+    }
+    const int ex = q9x(j), ey = q9y(j);
+    // the pull source lies beyond the face the opposite link leaves through
+    const int face = q9_exit_face(kc, kc.bc_f, x, y, -ex, -ey);
+    const float w = q9w(kc, j);
+    if (face < 0) {
+      const int src = q9_wrap(y - ey, kc.ny) * kc.nx + q9_wrap(x - ex, kc.nx);
+      e[j] = Storage<T>::load(fin.p[j], src, is) + w * (Pb[src] - pb);
+    } else {
+      const float o = Storage<T>::load(fin.p[q9opp(j)], c, is);
+      e[j] = (kc.bc_f[face] == LBTP_BC_DIRICHLET) ? (2.0f * w * (kc.Pw[face] - pb) - o) : o;
+    }
+  }
+}
+
+__device__ inline float q9_dpressure(const float *e, const KC &kc) {
+  float s = e[0];
+#pragma unroll
+  for (int j = 1; j < 8; ++j) s += e[j];
+  return s * kc.inv_1mw0;
+}
+
+// sum_j c_j e_j (the base part cancels: sum_j w_j c_j = 0)
+__device__ inline void q9_moment(const float *e, const KC &kc, float *m1) {
+  float mx = 0.f, my = 0.f;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    if (q9x(j)) mx += (float)q9x(j) * e[j];
+    if (q9y(j)) my += (float)q9y(j) * e[j];
+  }
+  m1[0] = kc.c * mx;
+  m1[1] = kc.c * my;
+}
+
+__device__ inline float q9_sum_g(const float *g) {
+  float s = g[0];
+#pragma unroll
+  for (int i = 1; i < 9; ++i) s += g[i];
+  return s;
+}
+
+// ------------------------------------------------------------ pressure sweep
+// One iteration of eq. 3-1 at one node; MODE as in the D2Q5 sweeps (0 plain,
+// 1 re-base, 2 re-base and stopping-rule terms).
+template <typename T, bool LOCAL, int MODE, bool HAS_FP>
+__global__ __launch_bounds__(kThreads) void q9_f_sweep_kernel(KC kc, FPtrs fin_, FPtrs fout_,
+                                                              const float *__restrict__ Pb_in,
+                                                              float *__restrict__ Pb_out,
+                                                              const float *__restrict__ itau,
+                                                              const float *__restrict__ Fp,
+                                                              double *__restrict__ partials,
+                                                              const Ctl *__restrict__ ctl, long long k) {
+  if (ctl->done || k > ctl->kmax) return;
+  const int c = blockIdx.x * kThreads + threadIdx.x;
+  double acc[2] = {0.0, 0.0};
+  if (c < kc.ncell) {
+    const FP<T> fin = typed<T>(fin_), fout = typed<T>(fout_);
+    const int y = c / kc.nx, x = c - y * kc.nx;
+    const float pb = Pb_in[c];
+    float e[8];
+    q9_load_e<T, LOCAL>(fin, Pb_in, c, x, y, kc, pb, e);
+    const float dP = q9_dpressure(e, kc);
+    const float it = itau[c];
+    const float add = HAS_FP ? kc.dt * kc.wbar * Fp[c] : 0.0f;
+    float rb = 0.0f;
+    if (MODE >= 1) {
+      const float P = pb + dP;
+      rb = pb - P;                      // re-base to P_b = P (exact difference)
+      Pb_out[c] = P;
+      if (MODE == 2) {
+        acc[0] = (double)dP * (double)dP;
+        acc[1] = (double)P * (double)P;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float w = q9w(kc, j);
+      float o = e[j] + (w * dP - e[j]) * it;
+      if (HAS_FP) o += add;
+      if (MODE >= 1) o += w * rb;
+      Storage<T>::store(fout.p[j], c, o, kc.dev_scale);
+    }
+  }
+  if (MODE == 2) block_sum<2>(acc, partials);
+}
+
+// ------------------------------------------------------------------ moments
+template <bool HAS_FS>
+__global__ __launch_bounds__(kThreads) void q9_moments_kernel(KC kc, GPtrs g, const float *__restrict__ K,
+                                                              const float *__restrict__ phi,
+                                                              const float *__restrict__ Fs,
+                                                              float *__restrict__ S, float *__restrict__ itau,
+                                                              double *__restrict__ partials, int write_coef) {
+  const int c = blockIdx.x * kThreads + threadIdx.x;
+  double acc[1] = {0.0};
+  if (c < kc.ncell) {
+    float gv[9];
+    double dm = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      gv[i] = g.p[i][c];
+      dm += (double)gv[i];
+    }
+    const float fs = HAS_FS ? Fs[c] : 0.0f;
+    const float Sv = saturation_of(q9_sum_g(gv), fs, phi[c], kc);
+    if (write_coef) {
+      S[c] = Sv;
+      itau[c] = inv_tau_f_of(Sv, K[c], kc);
+    }
+    if (HAS_FS) dm += 0.5 * (double)kc.dt * (double)fs;
+    acc[0] = dm;
+  }
+  block_sum<1>(acc, partials);
+}
+
+// ---------------------------------------------------------- saturation sweep
+// eq. 3-2 with g^eq of eq. 3-4, the local grad P of eq. 3-10a and
+// gamma = -lambda_w K / (c_s^2 dt); push to x + c_i or reflect at walls
+// (anti-bounce-back with g^eq(S_b, phi(x)), S_b the face value or, for an
+// outflow face, S of the node; bounce-back for no-flux faces).
+template <typename T, bool FLOCAL, bool HAS_FS>
+__global__ __launch_bounds__(kThreads) void q9_g_sweep_kernel(KC kc, GPtrs gin, GPtrs gout, FPtrs f_,
+                                                              const float *__restrict__ Pb,
+                                                              const float *__restrict__ itau,
+                                                              const float *__restrict__ K,
+                                                              const float *__restrict__ phi,
+                                                              const float *__restrict__ Fs,
+                                                              double *__restrict__ partials) {
+  const int c = blockIdx.x * kThreads + threadIdx.x;
+  double acc[1] = {0.0};
+  if (c < kc.ncell) {
+    const int y = c / kc.nx, x = c - y * kc.nx;
+    float gv[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) gv[i] = gin.p[i][c];
+    const float fs = HAS_FS ? Fs[c] : 0.0f;
+    const float ph = phi[c];
+    const float Sv = saturation_of(q9_sum_g(gv), fs, ph, kc);
+    float e[8];
+    q9_load_e<T, FLOCAL>(typed<T>(f_), Pb, c, x, y, kc, Pb[c], e);
+    float m1[2];
+    q9_moment(e, kc, m1);
+    const float gscale = -itau[c] * kc.inv_cs2dt;       // grad P = gscale * m1
+    const float gx = gscale * m1[0], gy = gscale * m1[1];
+    const float lw = Sv * Sv * kc.inv_mu_w;
+    const float gamma = -lw * K[c] * kc.inv_cs2dt;
+    const float conv = gamma * kc.dt * kc.inv_tau_g;     // times w_i c_i . grad P
+    const float srcw = kc.src_g * fs;
+    {
+      const float geq = q9_gamma0(kc, ph) * Sv;
+      float o = gv[0] + (geq - gv[0]) * kc.inv_tau_g;
+      if (HAS_FS) o += kc.w0 * srcw;
+      gout.p[0][c] = o;
+    }
+    double flux = 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int ex = q9x(j), ey = q9y(j);
+      const float w = q9w(kc, j);
+      const float G = q9_gamma(kc, j, ph);
+      float o = gv[j + 1] + (G * Sv - gv[j + 1]) * kc.inv_tau_g;
+      if (HAS_FS) o += w * srcw;
+      o += conv * w * (kc.c * ((float)ex * gx + (float)ey * gy));
+      const int face = q9_exit_face(kc, kc.bc_g, x, y, ex, ey);
+      if (face < 0) {
+        gout.p[j + 1][q9_wrap(y + ey, kc.ny) * kc.nx + q9_wrap(x + ex, kc.nx)] = o;
+      } else {
+        const int bc = kc.bc_g[face];
+        float r;
+        if (bc == LBTP_BC_NOFLUX) r = o;
+        else r = 2.0f * G * (bc == LBTP_BC_DIRICHLET ? kc.Sw[face] : Sv) - o;
+        gout.p[q9opp(j) + 1][c] = r;
+        flux += (double)r - (double)o;
+      }
+    }
+    acc[0] = flux;
+  }
+  block_sum<1>(acc, partials);
+}
+
+// ------------------------------------------------------------ initialisation
+// f_i = w_i P0 - tau_f dt w_i c_i . grad P0 (deviations against P_b = P0) and
+// g_i = g_i^eq(S0) - tau_g dt [(Gamma_i/phi - w_i(1 - 1/(2 tau_g))) F_s
+//       + Gamma_i c_i . grad S0 - gamma w_i c_i . grad P0 / tau_g]  (eq. gini, gneq).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void q9_init_kernel(KC kc, const float *__restrict__ P0,
+                                                           const float *__restrict__ S0,
+                                                           const float *__restrict__ dP0,
+                                                           const float *__restrict__ dS0,
+                                                           const float *__restrict__ K,
+                                                           const float *__restrict__ phi,
+                                                           const float *__restrict__ Fs, int neq, FPtrs f_,
+                                                           float *__restrict__ Pb, GPtrs g) {
+  const int c = blockIdx.x * kThreads + threadIdx.x;
+  if (c >= kc.ncell) return;
+  const FP<T> f = typed<T>(f_);
+  const Cell q = cell_of(c, kc);
+  const float P = P0[c], S = S0[c], ph = phi[c];
+  const float fs = Fs ? Fs[c] : 0.0f;
+  float gp[2] = {0.f, 0.f}, gs[2] = {0.f, 0.f};
+  if (neq) {
+    const float inv2dx = 0.5f / (kc.c * kc.dt);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      gp[a] = dP0 ? dP0[a * kc.ncell + c] : cdiff(P0, q, a, kc, inv2dx);
+      gs[a] = dS0 ? dS0[a * kc.ncell + c] : cdiff(S0, q, a, kc, inv2dx);
+    }
+  }
+  const float tau_f = 1.0f / inv_tau_f_of(S, K[c], kc);
+  const float lw = S * S * kc.inv_mu_w;
+  const float gamma = -lw * K[c] * kc.inv_cs2dt;
+  const float tau_g = 1.0f / kc.inv_tau_g;
+  const float wsrc = 1.0f - 0.5f * kc.inv_tau_g;
+  Pb[c] = P;
+  {
+    const float G0 = q9_gamma0(kc, ph);
+    float v = G0 * S;
+    if (neq) v -= tau_g * kc.dt * ((G0 / ph - kc.w0 * wsrc) * fs);
+    g.p[0][c] = v;
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const float w = q9w(kc, j);
+    const float cdp = kc.c * ((float)q9x(j) * gp[0] + (float)q9y(j) * gp[1]);
+    const float cds = kc.c * ((float)q9x(j) * gs[0] + (float)q9y(j) * gs[1]);
+    Storage<T>::store(f.p[j], c, neq ? -tau_f * kc.dt * w * cdp : 0.0f, kc.dev_scale);
+    const float G = q9_gamma(kc, j, ph);
+    float v = G * S;
+    if (neq) v -= tau_g * kc.dt * ((G / ph - w * wsrc) * fs + G * cds - gamma * w * cdp * kc.inv_tau_g);
+    g.p[j + 1][c] = v;
+  }
+}
+
+// ----------------------------------------------------------------- outputs
+template <typename T, bool LOCAL>
+__global__ __launch_bounds__(kThreads) void q9_pressure_kernel(KC kc, FPtrs f_, const float *__restrict__ Pb,
+                                                               float *__restrict__ P) {
+  const int c = blockIdx.x * kThreads + threadIdx.x;
+  if (c >= kc.ncell) return;
+  const int y = c / kc.nx, x = c - y * kc.nx;
+  const float pb = Pb[c];
+  float e[8];
+  q9_load_e<T, LOCAL>(typed<T>(f_), Pb, c, x, y, kc, pb, e);
+  P[c] = pb + q9_dpressure(e, kc);
+}
+
+template <typename T, bool LOCAL>
+__global__ __launch_bounds__(kThreads) void q9_grad_kernel(KC kc, FPtrs f_, const float *__restrict__ Pb,
+                                                           const float *__restrict__ itau,
+                                                           const float *__restrict__ K,
+                                                           const float *__restrict__ S, int velocity,
+                                                           float *__restrict__ out) {
+  const int c = blockIdx.x * kThreads + threadIdx.x;
+  if (c >= kc.ncell) return;
+  const int y = c / kc.nx, x = c - y * kc.nx;
+  float e[8];
+  q9_load_e<T, LOCAL>(typed<T>(f_), Pb, c, x, y, kc, Pb[c], e);
+  float m1[2];
+  q9_moment(e, kc, m1);
+  float scale = -itau[c] * kc.inv_cs2dt;
+  if (velocity) {
+    const float Sv = S[c];
+    const float lt = Sv * Sv * kc.inv_mu_w + (1.0f - Sv) * (1.0f - Sv) * kc.inv_mu_n;
+    scale = -K[c] * lt * scale;
+  }
+  out[c] = scale * m1[0];
+  out[kc.ncell + c] = scale * m1[1];
+}
+
+template <bool HAS_FS>
+__global__ __launch_bounds__(kThreads) void q9_saturation_kernel(KC kc, GPtrs g, const float *__restrict__ phi,
+                                                                 const float *__restrict__ Fs,
+                                                                 float *__restrict__ S) {
+  const int c = blockIdx.x * kThreads + threadIdx.x;
+  if (c >= kc.ncell) return;
+  float gv[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) gv[i] = g.p[i][c];
+  S[c] = saturation_of(q9_sum_g(gv), HAS_FS ? Fs[c] : 0.0f, phi[c], kc);
+}
+
+template <typename T, bool LOCAL>
+__global__ __launch_bounds__(kThreads) void q9_populations_kernel(KC kc, FPtrs f_, const float *__restrict__ Pb,
+                                                                  float *__restrict__ out) {
+  const int c = blockIdx.x * kThreads + threadIdx.x;
+  if (c >= kc.ncell) return;
+  const int y = c / kc.nx, x = c - y * kc.nx;
+  const float pb = Pb[c];
+  float e[8];
+  q9_load_e<T, LOCAL>(typed<T>(f_), Pb, c, x, y, kc, pb, e);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) out[j * kc.ncell + c] = q9w(kc, j) * pb + e[j];
+}
+
+// Calls fn with the storage type (as a null pointer of that type) and the
+// local flag as compile-time values.
+template <typename Fn>
+void q9_dispatch(int storage, int local, Fn &&fn) {
+  auto by_local = [&](auto t) {
+    if (local) fn(t, std::true_type{});
+    else fn(t, std::false_type{});
+  };
+  if (storage == LBTP_FP16_DEV) by_local((_Float16 *)nullptr);
+  else if (storage == LBTP_BF16_DEV) by_local((bf16_t *)nullptr);
+  else by_local((float *)nullptr);
+}
+
+#define Q9_GRID(kc) dim3(nblocks((kc).ncell)), dim3(kThreads), 0, s
+
+}  // namespace
+
+hipError_t launch_f_sweep_q9(int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb_in, float *Pb_out,
+                             const float *itau, const float *Fp, double *partials, const Ctl *ctl, long long k,
+                             int local, int mode, hipStream_t s) {
+  q9_dispatch(storage, local, [&](auto t, auto l) {
+    using T = std::remove_pointer_t<decltype(t)>;
+    constexpr bool L = decltype(l)::value;
+#define Q9_SWEEP(M, HF) \
+  hipLaunchKernelGGL((q9_f_sweep_kernel<T, L, M, HF>), Q9_GRID(kc), kc, fin, fout, Pb_in, Pb_out, itau, Fp, partials, ctl, k)
+    if (Fp) {
+      if (mode == 0) Q9_SWEEP(0, true);
+      else if (mode == 1) Q9_SWEEP(1, true);
+      else Q9_SWEEP(2, true);
+    } else {
+      if (mode == 0) Q9_SWEEP(0, false);
+      else if (mode == 1) Q9_SWEEP(1, false);
+      else Q9_SWEEP(2, false);
+    }
+#undef Q9_SWEEP
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_moments_q9(const KC &kc, GPtrs g, const float *K, const float *phi, const float *Fs, float *S,
+                             float *itau, double *partials, int write_coef, hipStream_t s) {
+  if (Fs) hipLaunchKernelGGL((q9_moments_kernel<true>), Q9_GRID(kc), kc, g, K, phi, Fs, S, itau, partials, write_coef);
+  else hipLaunchKernelGGL((q9_moments_kernel<false>), Q9_GRID(kc), kc, g, K, phi, Fs, S, itau, partials, write_coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_g_sweep_q9(int storage, const KC &kc, GPtrs gin, GPtrs gout, FPtrs f, int f_local,
+                             const float *Pb, const float *itau, const float *K, const float *phi, const float *Fs,
+                             double *partials, hipStream_t s) {
+  q9_dispatch(storage, f_local, [&](auto t, auto l) {
+    using T = std::remove_pointer_t<decltype(t)>;
+    constexpr bool L = decltype(l)::value;
+    if (Fs)
+      hipLaunchKernelGGL((q9_g_sweep_kernel<T, L, true>), Q9_GRID(kc), kc, gin, gout, f, Pb, itau, K, phi, Fs,
+                         partials);
+    else
+      hipLaunchKernelGGL((q9_g_sweep_kernel<T, L, false>), Q9_GRID(kc), kc, gin, gout, f, Pb, itau, K, phi, Fs,
+                         partials);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_init_q9(int storage, const KC &kc, const float *P0, const float *S0, const float *dP0,
+                          const float *dS0, const float *K, const float *phi, const float *Fs, int neq, FPtrs f,
+                          float *Pb, GPtrs g, hipStream_t s) {
+  q9_dispatch(storage, 0, [&](auto t, auto) {
+    using T = std::remove_pointer_t<decltype(t)>;
+    hipLaunchKernelGGL((q9_init_kernel<T>), Q9_GRID(kc), kc, P0, S0, dP0, dS0, K, phi, Fs, neq, f, Pb, g);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_pressure_q9(int storage, const KC &kc, FPtrs f, int f_local, const float *Pb, float *P,
+                              hipStream_t s) {
+  q9_dispatch(storage, f_local, [&](auto t, auto l) {
+    using T = std::remove_pointer_t<decltype(t)>;
+    hipLaunchKernelGGL((q9_pressure_kernel<T, decltype(l)::value>), Q9_GRID(kc), kc, f, Pb, P);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_q9(int storage, const KC &kc, FPtrs f, int f_local, const float *Pb, const float *itau,
+                          const float *K, const float *S, int velocity, float *out, hipStream_t s) {
+  q9_dispatch(storage, f_local, [&](auto t, auto l) {
+    using T = std::remove_pointer_t<decltype(t)>;
+    hipLaunchKernelGGL((q9_grad_kernel<T, decltype(l)::value>), Q9_GRID(kc), kc, f, Pb, itau, K, S, velocity, out);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_saturation_q9(const KC &kc, GPtrs g, const float *phi, const float *Fs, float *S, hipStream_t s) {
+  if (Fs) hipLaunchKernelGGL((q9_saturation_kernel<true>), Q9_GRID(kc), kc, g, phi, Fs, S);
+  else hipLaunchKernelGGL((q9_saturation_kernel<false>), Q9_GRID(kc), kc, g, phi, Fs, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_populations_q9(int storage, const KC &kc, FPtrs f, int f_local, const float *Pb, float *out,
+                                 hipStream_t s) {
+  q9_dispatch(storage, f_local, [&](auto t, auto l) {
+    using T = std::remove_pointer_t<decltype(t)>;
+    hipLaunchKernelGGL((q9_populations_kernel<T, decltype(l)::value>), Q9_GRID(kc), kc, f, Pb, out);
+  });
+  return hipGetLastError();
+}
+
+}  // namespace lbtp

@@ -67,13 +67,13 @@ struct Storage<bf16_t> {
 
 template <typename T>
 struct FP {
-  T *p[6];
+  T *p[8];
 };
 
 template <typename T>
 __host__ __device__ inline FP<T> typed(const FPtrs &f) {
   FP<T> r;
-  for (int j = 0; j < 6; ++j) r.p[j] = (T *)f.p[j];
+  for (int j = 0; j < 8; ++j) r.p[j] = (T *)f.p[j];
   return r;
 }
 

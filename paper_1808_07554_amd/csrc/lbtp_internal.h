@@ -23,7 +23,8 @@ struct KC {
   float c;          // dx / dt
   float dt;
   float cs2;        // c_s^2
-  float w0, w1;     // rest and moving weights
+  float w0, w1;     // rest and moving weights (D2Q9: w1 of the axis directions)
+  float w2;         // D2Q9: weight of the diagonal directions
   float inv_1mw0;   // 1 / (1 - w0)
   float wbar;       // source weight of a moving direction (eq. 3-5a pattern)
   float beta;
@@ -40,6 +41,7 @@ struct KC {
   float Pw[6];      // Dirichlet pressure of a face
   int bc_g[6];
   float abbS[6];    // 2 w1 beta S_b of a Dirichlet saturation face
+  float Sw[6];      // Dirichlet saturation of a face
 };
 
 // Device-side control block of a pressure solve and the float64 reductions.
@@ -59,8 +61,12 @@ struct Ctl {
 // ----------------------------------------------------------------- launchers
 // Each returns the hipError_t of the launch.  Pointer arrays hold one base
 // pointer per stored population.
-struct FPtrs { void *p[6]; };
-struct GPtrs { float *p[7]; };
+struct FPtrs { void *p[8]; };
+struct GPtrs { float *p[9]; };
+
+// Lattice kind passed to the launchers: 2 = D2Q5, 3 = D3Q7 (the spatial
+// dimension of those), kD2Q9 = D2Q9.
+constexpr int kD2Q9 = 9;
 
 hipError_t launch_f_sweep(int dim, int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb_in,
                           float *Pb_out, const float *itau, const float *Fp, double *partials, const Ctl *ctl,
@@ -90,6 +96,26 @@ hipError_t launch_populations(int dim, int storage, const KC &kc, FPtrs f, int f
                               float *out, hipStream_t s);
 
 hipError_t launch_copy_probe(const void *src, void *dst, long long n4, hipStream_t s);
+
+// D2Q9 (lbtp_d2q9.hip): the same operations, one node per thread.
+hipError_t launch_f_sweep_q9(int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb_in, float *Pb_out,
+                             const float *itau, const float *Fp, double *partials, const Ctl *ctl, long long k,
+                             int local, int mode, hipStream_t s);
+hipError_t launch_moments_q9(const KC &kc, GPtrs g, const float *K, const float *phi, const float *Fs, float *S,
+                             float *itau, double *partials, int write_coef, hipStream_t s);
+hipError_t launch_g_sweep_q9(int storage, const KC &kc, GPtrs gin, GPtrs gout, FPtrs f, int f_local,
+                             const float *Pb, const float *itau, const float *K, const float *phi, const float *Fs,
+                             double *partials, hipStream_t s);
+hipError_t launch_init_q9(int storage, const KC &kc, const float *P0, const float *S0, const float *dP0,
+                          const float *dS0, const float *K, const float *phi, const float *Fs, int neq, FPtrs f,
+                          float *Pb, GPtrs g, hipStream_t s);
+hipError_t launch_pressure_q9(int storage, const KC &kc, FPtrs f, int f_local, const float *Pb, float *P,
+                              hipStream_t s);
+hipError_t launch_grad_q9(int storage, const KC &kc, FPtrs f, int f_local, const float *Pb, const float *itau,
+                          const float *K, const float *S, int velocity, float *out, hipStream_t s);
+hipError_t launch_saturation_q9(const KC &kc, GPtrs g, const float *phi, const float *Fs, float *S, hipStream_t s);
+hipError_t launch_populations_q9(int storage, const KC &kc, FPtrs f, int f_local, const float *Pb, float *out,
+                                 hipStream_t s);
 
 inline size_t storage_bytes(int storage) { return storage == LBTP_FP32 ? 4 : 2; }
 
@@ -157,7 +183,7 @@ constexpr bool walk_form(int dim, int storage) { return dim == 2 && storage != L
 // Blocks of a pull-form pressure sweep (and so its residual partials): rows
 // with nx % 4 == 0 run four nodes per thread.
 inline int sweep_blocks(const KC &kc, int local, int dim, int storage) {
-  if (local || kc.nx % 4 != 0) return nblocks(kc.ncell);
+  if (local || kc.nx % 4 != 0 || dim == kD2Q9) return nblocks(kc.ncell);
   return walk_form(dim, storage) ? nblocks(walk_threads(kc, dim)) : nblocks(kc.ncell / 4);
 }
 

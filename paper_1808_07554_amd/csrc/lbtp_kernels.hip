@@ -346,6 +346,8 @@ struct SweepLaunch {
 hipError_t launch_f_sweep(int dim, int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb_in,
                           float *Pb_out, const float *itau, const float *Fp, double *partials, const Ctl *ctl,
                           long long k, int local, int mode, hipStream_t s) {
+  if (dim == kD2Q9)
+    return launch_f_sweep_q9(storage, kc, fin, fout, Pb_in, Pb_out, itau, Fp, partials, ctl, k, local, mode, s);
   dispatch<SweepLaunch>(dim, storage, local, kc, fin, fout, Pb_in, Pb_out, itau, Fp, partials, ctl, k, mode, s);
   return hipGetLastError();
 }
@@ -368,6 +370,7 @@ hipError_t launch_finish_sum(const double *partials, int nblk, double *dst, int 
 
 hipError_t launch_moments(int dim, const KC &kc, GPtrs g, const float *K, const float *phi, const float *Fs,
                           float *S, float *itau, double *partials, int write_coef, hipStream_t s) {
+  if (dim == kD2Q9) return launch_moments_q9(kc, g, K, phi, Fs, S, itau, partials, write_coef, s);
   if (dim == 2) {
     if (Fs) hipLaunchKernelGGL((moments_kernel<2, true>), LBTP_GRID(kc), kc, g, K, phi, Fs, S, itau, partials, write_coef);
     else hipLaunchKernelGGL((moments_kernel<2, false>), LBTP_GRID(kc), kc, g, K, phi, Fs, S, itau, partials, write_coef);
@@ -394,6 +397,8 @@ struct GSweepLaunch {
 hipError_t launch_g_sweep(int dim, int storage, const KC &kc, GPtrs gin, GPtrs gout, FPtrs f, int f_local,
                           const float *Pb, const float *itau, const float *K, const float *phi, const float *Fs,
                           double *partials, hipStream_t s) {
+  if (dim == kD2Q9)
+    return launch_g_sweep_q9(storage, kc, gin, gout, f, f_local, Pb, itau, K, phi, Fs, partials, s);
   dispatch<GSweepLaunch>(dim, storage, f_local, kc, gin, gout, f, Pb, itau, K, phi, Fs, partials, s);
   return hipGetLastError();
 }
@@ -410,6 +415,7 @@ struct InitLaunch {
 hipError_t launch_init(int dim, int storage, const KC &kc, const float *P0, const float *S0, const float *dP0,
                        const float *dS0, const float *K, const float *phi, const float *Fs, int neq, FPtrs f,
                        float *Pb, GPtrs g, hipStream_t s) {
+  if (dim == kD2Q9) return launch_init_q9(storage, kc, P0, S0, dP0, dS0, K, phi, Fs, neq, f, Pb, g, s);
   dispatch<InitLaunch>(dim, storage, 0, kc, P0, S0, dP0, dS0, K, phi, Fs, neq, f, Pb, g, s);
   return hipGetLastError();
 }
@@ -423,6 +429,7 @@ struct PressureLaunch {
 
 hipError_t launch_pressure(int dim, int storage, const KC &kc, FPtrs f, int f_local, const float *Pb, float *P,
                            hipStream_t s) {
+  if (dim == kD2Q9) return launch_pressure_q9(storage, kc, f, f_local, Pb, P, s);
   dispatch<PressureLaunch>(dim, storage, f_local, kc, f, Pb, P, s);
   return hipGetLastError();
 }
@@ -437,12 +444,14 @@ struct GradLaunch {
 
 hipError_t launch_grad(int dim, int storage, const KC &kc, FPtrs f, int f_local, const float *Pb,
                        const float *itau, const float *K, const float *S, int velocity, float *out, hipStream_t s) {
+  if (dim == kD2Q9) return launch_grad_q9(storage, kc, f, f_local, Pb, itau, K, S, velocity, out, s);
   dispatch<GradLaunch>(dim, storage, f_local, kc, f, Pb, itau, K, S, velocity, out, s);
   return hipGetLastError();
 }
 
 hipError_t launch_saturation(int dim, const KC &kc, GPtrs g, const float *phi, const float *Fs, float *S,
                              hipStream_t s) {
+  if (dim == kD2Q9) return launch_saturation_q9(kc, g, phi, Fs, S, s);
   if (dim == 2) {
     if (Fs) hipLaunchKernelGGL((saturation_kernel<2, true>), LBTP_GRID(kc), kc, g, phi, Fs, S);
     else hipLaunchKernelGGL((saturation_kernel<2, false>), LBTP_GRID(kc), kc, g, phi, Fs, S);
@@ -462,6 +471,7 @@ struct PopulationsLaunch {
 
 hipError_t launch_populations(int dim, int storage, const KC &kc, FPtrs f, int f_local, const float *Pb,
                               float *out, hipStream_t s) {
+  if (dim == kD2Q9) return launch_populations_q9(storage, kc, f, f_local, Pb, out, s);
   dispatch<PopulationsLaunch>(dim, storage, f_local, kc, f, Pb, out, s);
   return hipGetLastError();
 }

@@ -13,7 +13,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbtp.so")
 
-D2Q5, D3Q7 = 0, 1
+D2Q5, D3Q7, D2Q9 = 0, 1, 2
+_LATTICE = {"D2Q5": D2Q5, "D3Q7": D3Q7, "D2Q9": D2Q9}
+_Q = {D2Q5: 5, D3Q7: 7, D2Q9: 9}
 FP32, FP16_DEV, BF16_DEV = 0, 1, 2
 BC_PERIODIC, BC_DIRICHLET, BC_NOFLUX, BC_OUTFLOW = 0, 1, 2, 3
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, EUNSTABLE, ESTATE = 0, 1, -1, -2, -3, -4, -5
@@ -159,7 +161,7 @@ def make_params(lattice, shape, *, beta, Ds, mu_w, mu_n, bc_f, bc_g, dx=1.0, dt=
     lib = load()
     p = Params()
     lib.lbtp_default_params(ctypes.byref(p))
-    p.lattice = D2Q5 if lattice == "D2Q5" else D3Q7
+    p.lattice = _LATTICE[lattice]
     shape = tuple(shape) + (1,) * (3 - len(shape))
     p.nx, p.ny, p.nz = shape
     p.dx, p.dt, p.beta, p.Ds, p.mu_w, p.mu_n = dx, dt, beta, Ds, mu_w, mu_n
@@ -195,7 +197,7 @@ class Batch:
             p, shape = make_params(d.pop("lattice"), d.pop("shape"), m=m, storage=storage, stream_ptr=sptr, **d)
             arr[i] = p
             self.shapes.append(shape)
-        self.dim = 2 if arr[0].lattice == D2Q5 else 3
+        self.dim = 3 if arr[0].lattice == D3Q7 else 2
         h = ctypes.c_void_p()
         _check(lib.lbtp_batch_init(arr, n, ctypes.byref(h)), "lbtp_batch_init")
         self._h, self._lib, self.n = h, lib, n
@@ -362,7 +364,7 @@ class Solver:
         lib = load()
         p = Params()
         lib.lbtp_default_params(ctypes.byref(p))
-        p.lattice = D2Q5 if lattice == "D2Q5" else D3Q7
+        p.lattice = _LATTICE[lattice]
         shape = tuple(shape) + (1,) * (3 - len(shape))
         p.nx, p.ny, p.nz = shape
         p.dx, p.dt, p.beta, p.Ds, p.mu_w, p.mu_n = dx, dt, beta, Ds, mu_w, mu_n
@@ -380,8 +382,8 @@ class Solver:
         self.stream = stream
         p.stream = stream.cuda_stream
         self.params = p
-        self.dim = 2 if p.lattice == D2Q5 else 3
-        self.Q = 2 * self.dim + 1
+        self.dim = 3 if p.lattice == D3Q7 else 2
+        self.Q = _Q[p.lattice]
         self.shape = shape
         self.ncell = shape[0] * shape[1] * shape[2]
         h = ctypes.c_void_p()

@@ -44,12 +44,23 @@ def _params(**kw):
 @pytest.mark.parametrize("kw", [
     dict(lattice=7), dict(nx=0), dict(nz=2), dict(dx=0.0), dict(dt=-1.0), dict(beta=0.0),
     dict(Ds=0.0), dict(mu_w=0.0), dict(storage=9), dict(residual_stride=0),
+    dict(lattice=lbtp.D2Q9, nz=2),
 ])
 def test_invalid_params_rejected_without_device(kw):
     lib = lbtp.load()
     p = _params(**kw)
     h = ctypes.c_void_p()
     assert lib.lbtp_init(ctypes.byref(p), ctypes.byref(h)) == lbtp.EINVAL
+    assert not h.value
+
+
+def test_d2q9_ensemble_rejected_without_device():
+    lib = lbtp.load()
+    arr = (lbtp.Params * 2)()
+    arr[0] = _params(lattice=lbtp.D2Q9, nx=16)
+    arr[1] = _params(lattice=lbtp.D2Q9, nx=16)
+    h = ctypes.c_void_p()
+    assert lib.lbtp_batch_init(arr, 2, ctypes.byref(h)) == lbtp.EINVAL
     assert not h.value
 
 
