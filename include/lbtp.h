@@ -78,6 +78,16 @@ enum lbtp_storage { LBTP_FP32 = 0, LBTP_FP16_DEV = 1, LBTP_BF16_DEV = 2 };
  * PERIODIC must be set on both faces of an axis, for f and for g. */
 enum lbtp_bc { LBTP_BC_PERIODIC = 0, LBTP_BC_DIRICHLET = 1, LBTP_BC_NOFLUX = 2, LBTP_BC_OUTFLOW = 3 };
 
+/* Coefficient model.  QUADRATIC_KR: lambda_a = k_ra/mu_a with k_rw = S^2,
+ * k_rn = (1-S)^2 (eq. 2-9, Section 4.3), D_p = K lambda_t (eq. 2-16),
+ * lambda_w K.  RATIONAL: D_p and lambda_w K given directly, as Sections 4.1
+ * and 4.2 do:  D_p = K (a0 + a1 S) / (b0 + b1 S),
+ * lambda_w K = K (c0 + c1 S) / (b0 + b1 S), coef = {a0, a1, c0, c1, b0, b1}
+ * (Section 4.1: a0 = c0 = 1e-3, b0 = 1, others 0, K = 1; Section 4.2:
+ * a0 = 1, c1 = 1, b0 = 0.5, b1 = -0.2, others 0, K = 1).  The velocity is
+ * u = -D_p grad P in both. */
+enum lbtp_coef_model { LBTP_COEF_QUADRATIC_KR = 0, LBTP_COEF_RATIONAL = 1 };
+
 enum lbtp_status {
   LBTP_OK = 0,
   LBTP_NOT_CONVERGED = 1,   /* max_iters reached before the residual met tol */
@@ -104,10 +114,12 @@ typedef struct lbtp_params {
   double bc_S[6];              /* Dirichlet saturation per face */
   int init_neq;                /* 1: lbtp_set_state adds the first-order non-equilibrium parts */
   void *stream;                /* hipStream_t for all device work; NULL = null stream */
+  int coef_model;              /* lbtp_coef_model */
+  double coef[6];              /* RATIONAL: a0, a1, c0, c1, b0, b1 (unused otherwise) */
 } lbtp_params;
 
 /* Fill *p with defaults: D2Q5, 1x1x1, dx = dt = 1, beta = 1, Ds = 0, mu = 1,
- * FP32, m = 64, periodic faces, init_neq = 1, null stream. */
+ * FP32, m = 64, periodic faces, init_neq = 1, null stream, QUADRATIC_KR. */
 LBTP_API void lbtp_default_params(lbtp_params *p);
 
 /* Validate *p (tau_g > 1/2, beta >= 0, periodicity consistent, sizes > 0,
@@ -133,6 +145,21 @@ LBTP_API int lbtp_set_fields(lbtp_ctx *ctx, const float *K, const float *phi,
 /* Replace F_p and F_s only (time-dependent sources); NULL = zero. */
 LBTP_API int lbtp_set_sources(lbtp_ctx *ctx, const float *Fp, const float *Fs, int on_device);
 
+/* Dirichlet data that vary along a face (and in time: call again before the
+ * solve or step they apply to), for the anti-bounce-back rules of Section 4:
+ * P (pressure lattice) and / or S (saturation lattice) at the midpoint of
+ * every link that crosses the face, x_node - c_i dt / 2 for the population
+ * i arriving at the boundary node.  Layout: face nodes in the order
+ * y + ny z (faces -x, +x), x + nx z (-y, +y), x + nx y (-z, +z), and per
+ * node L values, L = 1 on D2Q5 / D3Q7 (the normal link) and L = 3 on D2Q9:
+ * the normal link, then the diagonal links whose arriving population has
+ * tangential velocity -1 and +1 (at a corner the diagonal link crossing
+ * both faces takes the value of the y face).  NULL keeps the current data
+ * of that lattice; the face constants of params apply until data are set.
+ * The face's condition must be DIRICHLET for the lattice whose data are
+ * given (LBTP_EINVAL otherwise). */
+LBTP_API int lbtp_set_wall_values(lbtp_ctx *ctx, int face, const float *P, const float *S, int on_device);
+
 /* Initial populations (initialisation paragraph of Section 4):
  *   g_i = g_i^eq(S0) + eps g_i^(1) with eps g_i^(1) of eq. (gneq),
  *   f_i = w_i P0 - tau_f dt w_i c_i . grad P0   (i >= 1, Appendix A order 1).
@@ -143,9 +170,9 @@ LBTP_API int lbtp_set_sources(lbtp_ctx *ctx, const float *Fp, const float *Fs, i
 LBTP_API int lbtp_set_state(lbtp_ctx *ctx, const float *P0, const float *S0,
                    const float *dP0, const float *dS0, int on_device);
 
-/* Coefficients of the current coupled step: S^n (eq. 3-9b), lambda_w,
- * lambda_t (eq. 2-9), D_p = K lambda_t (eq. 2-16), 1/tau_f (eq. 3-11a), and
- * the mass M^n = sum phi S^n in float64. */
+/* Coefficients of the current coupled step: S^n (eq. 3-9b), D_p and
+ * lambda_w K of the coefficient model, 1/tau_f (eq. 3-11a), and the mass
+ * M^n = sum phi S^n in float64. */
 LBTP_API int lbtp_update_coefficients(lbtp_ctx *ctx);
 
 /* Iterate the pressure lattice (eq. 3-1) with the current coefficients.
@@ -172,7 +199,7 @@ LBTP_API int lbtp_step(lbtp_ctx *ctx, long long nsteps, double tol, long long ma
               long long *iters);
 
 /* Outputs on the current state.  pressure: eq. 3-9a of the pre-collision f.
- * velocity: u = K lambda_t sum_i c_i f_i / (tau_f dt c_s^2) (eq. 3-10b), dim
+ * velocity: u = D_p sum_i c_i f_i / (tau_f dt c_s^2) (eq. 3-10b), dim
  * components, with the coefficients of the last update_coefficients.
  * grad_p: eq. 3-10a.  saturation: eq. 3-9b with the current F_s. */
 LBTP_API int lbtp_pressure(lbtp_ctx *ctx, float *P, int on_device);

@@ -32,6 +32,7 @@ struct lbtp_ctx {
   float *K = nullptr, *phi = nullptr, *Fp = nullptr, *Fs = nullptr;
   int has_Fp = 0, has_Fs = 0;
   float *S = nullptr, *itau = nullptr, *scratch = nullptr;
+  float *wallP[6] = {}, *wallS[6] = {};   // per-link Dirichlet data (lbtp_set_wall_values)
   double *partials = nullptr;
   int nblk = 0;
   Ctl *ctl = nullptr;       // device
@@ -83,7 +84,13 @@ int validate(const lbtp_params *p) {
   const int Q = lattice_q(p->lattice);
   if ((long long)Q * n >= (1LL << 31)) return LBTP_EINVAL;   // 32-bit cell indexing
   if (!(p->dx > 0) || !(p->dt > 0) || !(p->beta > 0) || !(p->Ds > 0)) return LBTP_EINVAL;
-  if (!(p->mu_w > 0) || !(p->mu_n > 0)) return LBTP_EINVAL;
+  if (p->coef_model != LBTP_COEF_QUADRATIC_KR && p->coef_model != LBTP_COEF_RATIONAL) return LBTP_EINVAL;
+  if (p->coef_model == LBTP_COEF_QUADRATIC_KR && (!(p->mu_w > 0) || !(p->mu_n > 0))) return LBTP_EINVAL;
+  if (p->coef_model == LBTP_COEF_RATIONAL) {
+    for (int i = 0; i < 6; ++i)
+      if (!isfinite(p->coef[i])) return LBTP_EINVAL;
+    if (p->coef[4] == 0.0 && p->coef[5] == 0.0) return LBTP_EINVAL;
+  }
   if (p->storage != LBTP_FP32 && p->storage != LBTP_FP16_DEV && p->storage != LBTP_BF16_DEV) return LBTP_EINVAL;
   if (p->residual_stride < 1) return LBTP_EINVAL;
   const int dim = lattice_dim(p->lattice);
@@ -130,8 +137,10 @@ void fill_kc(lbtp_ctx *c) {
   k.beta = (float)p.beta;
   k.inv_tau_g = (float)(1.0 / tau_g);
   k.src_g = (float)(p.dt * (1.0 - 0.5 / tau_g));
-  k.inv_mu_w = (float)(1.0 / p.mu_w);
-  k.inv_mu_n = (float)(1.0 / p.mu_n);
+  k.inv_mu_w = p.mu_w > 0 ? (float)(1.0 / p.mu_w) : 0.0f;
+  k.inv_mu_n = p.mu_n > 0 ? (float)(1.0 / p.mu_n) : 0.0f;
+  k.coef = p.coef_model;
+  for (int i = 0; i < 6; ++i) k.cf[i] = (float)p.coef[i];
   k.inv_cs2dt = (float)(1.0 / (cs2 * p.dt));
   k.geq0_phi = (float)((w0 - 1.0) * p.beta);
   k.w1beta = (float)(w1 * p.beta);
@@ -254,6 +263,10 @@ void lbtp_destroy(lbtp_ctx *c) {
                   c->Fp, c->Fs, c->S, c->itau, c->scratch};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
+  for (int f = 0; f < 6; ++f) {
+    if (c->wallP[f]) (void)hipFree(c->wallP[f]);
+    if (c->wallS[f]) (void)hipFree(c->wallS[f]);
+  }
   if (c->partials) (void)hipFree(c->partials);
   if (c->ctl) (void)hipFree(c->ctl);
   if (c->ctl_host) (void)hipHostFree(c->ctl_host);
@@ -372,6 +385,26 @@ int lbtp_set_sources(lbtp_ctx *c, const float *Fp, const float *Fs, int on_devic
   if (!c) return LBTP_EINVAL;
   if (!c->have_fields) return LBTP_ESTATE;
   return set_sources_impl(c, Fp, Fs, on_device);
+}
+
+int lbtp_set_wall_values(lbtp_ctx *c, int face, const float *P, const float *S, int on_device) {
+  if (!c || face < 0 || face >= 2 * c->dim) return LBTP_EINVAL;
+  if (P && c->p.bc_f[face] != LBTP_BC_DIRICHLET) return LBTP_EINVAL;
+  if (S && c->p.bc_g[face] != LBTP_BC_DIRICHLET) return LBTP_EINVAL;
+  const int a = face / 2;
+  const long long nface = c->ncell / (a == 0 ? c->p.nx : (a == 1 ? c->p.ny : c->p.nz));
+  const size_t n = (size_t)nface * (c->p.lattice == LBTP_D2Q9 ? 3 : 1);
+  float **dst[2] = {&c->wallP[face], &c->wallS[face]};
+  const float *src[2] = {P, S};
+  for (int i = 0; i < 2; ++i) {
+    if (!src[i]) continue;
+    if (!*dst[i] && hipMalloc((void **)dst[i], n * sizeof(float)) != hipSuccess) return LBTP_ENOMEM;
+    int rc = upload(c, *dst[i], src[i], n, on_device);
+    if (rc) return rc;
+  }
+  c->kc.wP[face] = c->wallP[face];
+  c->kc.wS[face] = c->wallS[face];
+  return LBTP_OK;
 }
 
 int lbtp_set_state(lbtp_ctx *c, const float *P0, const float *S0, const float *dP0, const float *dS0,

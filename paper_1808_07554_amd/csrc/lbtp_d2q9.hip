@@ -52,6 +52,14 @@ __device__ inline int q9_exit_face(const KC &kc, const int *bc, int x, int y, in
 
 __device__ inline int q9_wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Slot of a link in the per-link wall data of a face (three per node): 0 for
+// the normal link, 1 / 2 for the diagonal whose arriving population has
+// tangential velocity -1 / +1.
+__device__ inline int q9_wall_slot(int face, int ax, int ay) {
+  const int t = face < 2 ? ay : ax;
+  return t == 0 ? 0 : (t < 0 ? 1 : 2);
+}
+
 // Pre-collision deviations e_j at node c = (x, y) against P_b(c) = pb:
 // streamed from (x - e_x, y - e_y) (eq. 3-1) and re-expressed against the
 // node's base, or the Section 4 rule of the wall the link comes through:
@@ -75,7 +83,9 @@ __device__ inline void q9_load_e(const FP<T> &fin, const float *__restrict__ Pb,
       e[j] = Storage<T>::load(fin.p[j], src, is) + w * (Pb[src] - pb);
     } else {
       const float o = Storage<T>::load(fin.p[q9opp(j)], c, is);
-      e[j] = (kc.bc_f[face] == LBTP_BC_DIRICHLET) ? (2.0f * w * (kc.Pw[face] - pb) - o) : o;
+      e[j] = (kc.bc_f[face] == LBTP_BC_DIRICHLET)
+                 ? (2.0f * w * (wall_P(kc, face, x, y, 0, 3, q9_wall_slot(face, ex, ey)) - pb) - o)
+                 : o;
     }
   }
 }
@@ -209,8 +219,7 @@ __global__ __launch_bounds__(kThreads) void q9_g_sweep_kernel(KC kc, GPtrs gin, 
     q9_moment(e, kc, m1);
     const float gscale = -itau[c] * kc.inv_cs2dt;       // grad P = gscale * m1
     const float gx = gscale * m1[0], gy = gscale * m1[1];
-    const float lw = Sv * Sv * kc.inv_mu_w;
-    const float gamma = -lw * K[c] * kc.inv_cs2dt;
+    const float gamma = -lwk_of(Sv, K[c], kc) * kc.inv_cs2dt;
     const float conv = gamma * kc.dt * kc.inv_tau_g;     // times w_i c_i . grad P
     const float srcw = kc.src_g * fs;
     {
@@ -235,7 +244,8 @@ __global__ __launch_bounds__(kThreads) void q9_g_sweep_kernel(KC kc, GPtrs gin, 
         const int bc = kc.bc_g[face];
         float r;
         if (bc == LBTP_BC_NOFLUX) r = o;
-        else r = 2.0f * G * (bc == LBTP_BC_DIRICHLET ? kc.Sw[face] : Sv) - o;
+        else if (bc == LBTP_BC_DIRICHLET) r = 2.0f * G * wall_S(kc, face, x, y, 0, 3, q9_wall_slot(face, -ex, -ey)) - o;
+        else r = 2.0f * G * Sv - o;      // outflow: S_b = S of this node
         gout.p[q9opp(j) + 1][c] = r;
         flux += (double)r - (double)o;
       }
@@ -274,8 +284,7 @@ __global__ __launch_bounds__(kThreads) void q9_init_kernel(KC kc, const float *_
     }
   }
   const float tau_f = 1.0f / inv_tau_f_of(S, K[c], kc);
-  const float lw = S * S * kc.inv_mu_w;
-  const float gamma = -lw * K[c] * kc.inv_cs2dt;
+  const float gamma = -lwk_of(S, K[c], kc) * kc.inv_cs2dt;
   const float tau_g = 1.0f / kc.inv_tau_g;
   const float wsrc = 1.0f - 0.5f * kc.inv_tau_g;
   Pb[c] = P;
@@ -325,11 +334,7 @@ __global__ __launch_bounds__(kThreads) void q9_grad_kernel(KC kc, FPtrs f_, cons
   float m1[2];
   q9_moment(e, kc, m1);
   float scale = -itau[c] * kc.inv_cs2dt;
-  if (velocity) {
-    const float Sv = S[c];
-    const float lt = Sv * Sv * kc.inv_mu_w + (1.0f - Sv) * (1.0f - Sv) * kc.inv_mu_n;
-    scale = -K[c] * lt * scale;
-  }
+  if (velocity) scale = -dp_of(S[c], K[c], kc) * scale;   // u = -D_p grad P
   out[c] = scale * m1[0];
   out[kc.ncell + c] = scale * m1[1];
 }

@@ -77,6 +77,23 @@ __host__ __device__ inline FP<T> typed(const FPtrs &f) {
   return r;
 }
 
+// Node index within the wall-value arrays of a face: y + ny z (x faces),
+// x + nx z (y faces), x + nx y (z faces).
+__device__ inline int face_index(const KC &kc, int face, int x, int y, int z) {
+  return face < 2 ? y + kc.ny * z : (face < 4 ? x + kc.nx * z : x + kc.nx * y);
+}
+
+// Dirichlet pressure / saturation of the link k (L per node) arriving at node
+// (x, y, z) through face: the per-link data if set, else the face constant.
+__device__ inline float wall_P(const KC &kc, int face, int x, int y, int z, int L, int k) {
+  const float *a = kc.wP[face];
+  return a ? a[face_index(kc, face, x, y, z) * L + k] : kc.Pw[face];
+}
+__device__ inline float wall_S(const KC &kc, int face, int x, int y, int z, int L, int k) {
+  const float *a = kc.wS[face];
+  return a ? a[face_index(kc, face, x, y, z) * L + k] : kc.Sw[face];
+}
+
 // Pre-collision deviations e_j at node q (moving directions) against P_b(q).
 template <int DIM, typename T, bool LOCAL>
 __device__ inline void load_e(const FP<T> &fin, const float *__restrict__ Pb, const Cell &q, const KC &kc,
@@ -101,7 +118,7 @@ __device__ inline void load_e(const FP<T> &fin, const float *__restrict__ Pb, co
         e[j] = Storage<T>::load(fin.p[j], src, kc.inv_dev_scale) + kc.w1 * (Pb[src] - pb);
       } else {
         const float o = Storage<T>::load(fin.p[dir_opp(j)], q.c, kc.inv_dev_scale);
-        e[j] = (bc == LBTP_BC_DIRICHLET) ? (2.0f * kc.w1 * (kc.Pw[face] - pb) - o) : o;
+        e[j] = (bc == LBTP_BC_DIRICHLET) ? (2.0f * kc.w1 * (wall_P(kc, face, q.x, q.y, q.z, 1, 0) - pb) - o) : o;
       }
     }
   }
@@ -137,13 +154,25 @@ __device__ inline float saturation_of(float gsum, float Fs, float phi, const KC 
   return (gsum + kc.half_dt * Fs) / phi;
 }
 
-// 1/tau_f from eq. 3-11a with D_p = K lambda_t (eq. 2-9, 2-16).
-__device__ inline float inv_tau_f_of(float S, float K, const KC &kc) {
+// D_p and lambda_w K of the coefficient model: K lambda_t and K k_rw/mu_w with
+// k_rw = S^2, k_rn = (1-S)^2 (eq. 2-9, 2-16), or given as rational functions
+// of S (the form Sections 4.1 and 4.2 use).
+__device__ inline float dp_of(float S, float K, const KC &kc) {
+  if (kc.coef == LBTP_COEF_RATIONAL) return K * (kc.cf[0] + kc.cf[1] * S) / (kc.cf[4] + kc.cf[5] * S);
   const float lw = S * S * kc.inv_mu_w;
   const float ln = (1.0f - S) * (1.0f - S) * kc.inv_mu_n;
-  const float Dp = K * (lw + ln);
-  return 1.0f / (0.5f + Dp * kc.inv_cs2dt);
+  return K * (lw + ln);
 }
+__device__ inline float lwk_of(float S, float K, const KC &kc) {
+  if (kc.coef == LBTP_COEF_RATIONAL) return K * (kc.cf[2] + kc.cf[3] * S) / (kc.cf[4] + kc.cf[5] * S);
+  return S * S * kc.inv_mu_w * K;
+}
+
+// 1/tau_f from eq. 3-11a.
+__device__ inline float inv_tau_f_of(float S, float K, const KC &kc) {
+  return 1.0f / (0.5f + dp_of(S, K, kc) * kc.inv_cs2dt);
+}
+
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -282,7 +311,7 @@ __device__ inline void f4set(float4 &v, int i, float x) {
 // wavefront must call it (the shuffles).
 template <typename T>
 __device__ inline void pull_x_quad(const KC &kc, const FP<T> &fin, const float *__restrict__ Pb_in, int c, int x0,
-                                   const float4 &pb, float4 &e0, float4 &e2) {
+                                   int y, int z, const float4 &pb, float4 &e0, float4 &e2) {
   const int lane = threadIdx.x & 63;
   const float is = kc.inv_dev_scale;
   // +x (j = 0) pulls from x - 1, -x (j = 2) from x + 1
@@ -299,7 +328,7 @@ __device__ inline void pull_x_quad(const KC &kc, const FP<T> &fin, const float *
       const int src = c + kc.nx - 1;
       e0.x = Storage<T>::load(fin.p[0], src, is) + kc.w1 * (Pb_in[src] - pb.x);
     } else {
-      e0.x = (bc == LBTP_BC_DIRICHLET) ? (2.0f * kc.w1 * (kc.Pw[0] - pb.x) - B.x) : B.x;
+      e0.x = (bc == LBTP_BC_DIRICHLET) ? (2.0f * kc.w1 * (wall_P(kc, 0, 0, y, z, 1, 0) - pb.x) - B.x) : B.x;
     }
   } else {
     if (lane == 0) {
@@ -314,7 +343,7 @@ __device__ inline void pull_x_quad(const KC &kc, const FP<T> &fin, const float *
       const int src = c + 3 - (kc.nx - 1);
       e2.w = Storage<T>::load(fin.p[2], src, is) + kc.w1 * (Pb_in[src] - pb.w);
     } else {
-      e2.w = (bc == LBTP_BC_DIRICHLET) ? (2.0f * kc.w1 * (kc.Pw[1] - pb.w) - A.w) : A.w;
+      e2.w = (bc == LBTP_BC_DIRICHLET) ? (2.0f * kc.w1 * (wall_P(kc, 1, x0 + 3, y, z, 1, 0) - pb.w) - A.w) : A.w;
     }
   } else {
     if (lane == 63) {
@@ -339,10 +368,19 @@ __device__ inline bool reads_hi(const KC &kc, int a, int coordv, int n) {
 // vectors from the neighbouring row or plane, or the face rules.  pbm and pbp
 // are the bases of the rows the +a and -a pulls read (used only when they
 // read one).
+// Per-link Dirichlet data of the four nodes at face (x0.., other) (other = z
+// for a y face, y for a z face), or the face constant.
+__device__ inline float4 wall_P4(const KC &kc, int face, int x0, int other) {
+  const float *a = kc.wP[face];
+  if (a) return *(const float4 *)(a + x0 + kc.nx * other);
+  const float pw = kc.Pw[face];
+  return make_float4(pw, pw, pw, pw);
+}
+
 template <typename T>
 __device__ inline void pull_axis_quad(const KC &kc, const FP<T> &fin, int c, int a, int coordv, int n, int st,
-                                      const float4 &pb, const float4 &pbm, const float4 &pbp, float4 &ep,
-                                      float4 &em) {
+                                      int x0, int other, const float4 &pb, const float4 &pbm, const float4 &pbp,
+                                      float4 &ep, float4 &em) {
   const float is = kc.inv_dev_scale;
   const int jp = (a == 1) ? 1 : 4, jm = (a == 1) ? 3 : 5;   // +a and -a directions
   // +a pulls from coord - 1
@@ -354,9 +392,9 @@ __device__ inline void pull_axis_quad(const KC &kc, const FP<T> &fin, int c, int
   } else {
     const float4 o = Vec4<T>::load(fin.p[jm], c, is);
     if (kc.bc_f[2 * a] == LBTP_BC_DIRICHLET) {
-      const float pw = kc.Pw[2 * a];
-      ep = make_float4(2.0f * kc.w1 * (pw - pb.x) - o.x, 2.0f * kc.w1 * (pw - pb.y) - o.y,
-                       2.0f * kc.w1 * (pw - pb.z) - o.z, 2.0f * kc.w1 * (pw - pb.w) - o.w);
+      const float4 pw = wall_P4(kc, 2 * a, x0, other);
+      ep = make_float4(2.0f * kc.w1 * (pw.x - pb.x) - o.x, 2.0f * kc.w1 * (pw.y - pb.y) - o.y,
+                       2.0f * kc.w1 * (pw.z - pb.z) - o.z, 2.0f * kc.w1 * (pw.w - pb.w) - o.w);
     } else {
       ep = o;
     }
@@ -370,9 +408,9 @@ __device__ inline void pull_axis_quad(const KC &kc, const FP<T> &fin, int c, int
   } else {
     const float4 o = Vec4<T>::load(fin.p[jp], c, is);
     if (kc.bc_f[2 * a + 1] == LBTP_BC_DIRICHLET) {
-      const float pw = kc.Pw[2 * a + 1];
-      em = make_float4(2.0f * kc.w1 * (pw - pb.x) - o.x, 2.0f * kc.w1 * (pw - pb.y) - o.y,
-                       2.0f * kc.w1 * (pw - pb.z) - o.z, 2.0f * kc.w1 * (pw - pb.w) - o.w);
+      const float4 pw = wall_P4(kc, 2 * a + 1, x0, other);
+      em = make_float4(2.0f * kc.w1 * (pw.x - pb.x) - o.x, 2.0f * kc.w1 * (pw.y - pb.y) - o.y,
+                       2.0f * kc.w1 * (pw.z - pb.z) - o.z, 2.0f * kc.w1 * (pw.w - pb.w) - o.w);
     } else {
       em = o;
     }
@@ -444,7 +482,7 @@ __device__ inline void sweep_quad(const KC &kc, const FP<T> &fin, const FP<T> &f
 
   const float4 pb = *(const float4 *)(Pb_in + c);
   float4 e[2 * DIM];
-  pull_x_quad<T>(kc, fin, Pb_in, c, x0, pb, e[0], e[2]);
+  pull_x_quad<T>(kc, fin, Pb_in, c, x0, y, z, pb, e[0], e[2]);
 #pragma unroll
   for (int a = 1; a < DIM; ++a) {
     const int coordv = (a == 1) ? y : z;
@@ -452,7 +490,8 @@ __device__ inline void sweep_quad(const KC &kc, const FP<T> &fin, const FP<T> &f
     const int st = (a == 1) ? kc.nx : kc.nx * kc.ny;
     float4 pbm = pb, pbp = pb;
     load_pb_axis(kc, Pb_in, c, a, coordv, n, st, pbm, pbp);
-    pull_axis_quad<T>(kc, fin, c, a, coordv, n, st, pb, pbm, pbp, e[a == 1 ? 1 : 4], e[a == 1 ? 3 : 5]);
+    pull_axis_quad<T>(kc, fin, c, a, coordv, n, st, x0, (a == 1) ? z : y, pb, pbm, pbp, e[a == 1 ? 1 : 4],
+                      e[a == 1 ? 3 : 5]);
   }
   const float4 it = *(const float4 *)(itau + c);
   float4 fp = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -494,13 +533,15 @@ __device__ inline void sweep_quad_walk(const KC &kc, const FP<T> &fin, const FP<
     const int c = wl * sw + c0;
     if (reads_hi(kc, W, wl, nw)) pb_next = *(const float4 *)(Pb_in + (wl == nw - 1 ? 0 : wl + 1) * sw + c0);
     float4 e[2 * DIM];
-    pull_x_quad<T>(kc, fin, Pb_in, c, x0, pb_cur, e[0], e[2]);
+    const int yq = W == 1 ? wl : y3, zq = W == 1 ? 0 : wl;
+    pull_x_quad<T>(kc, fin, Pb_in, c, x0, yq, zq, pb_cur, e[0], e[2]);
     if (DIM == 3) {
       float4 pbm = pb_cur, pbp = pb_cur;
       load_pb_axis(kc, Pb_in, c, 1, y3, kc.ny, kc.nx, pbm, pbp);
-      pull_axis_quad<T>(kc, fin, c, 1, y3, kc.ny, kc.nx, pb_cur, pbm, pbp, e[1], e[3]);
+      pull_axis_quad<T>(kc, fin, c, 1, y3, kc.ny, kc.nx, x0, zq, pb_cur, pbm, pbp, e[1], e[3]);
     }
-    pull_axis_quad<T>(kc, fin, c, W, wl, nw, sw, pb_cur, pb_prev, pb_next, e[W == 1 ? 1 : 4], e[W == 1 ? 3 : 5]);
+    pull_axis_quad<T>(kc, fin, c, W, wl, nw, sw, x0, W == 1 ? zq : yq, pb_cur, pb_prev, pb_next,
+                      e[W == 1 ? 1 : 4], e[W == 1 ? 3 : 5]);
     const float4 it = *(const float4 *)(itau + c);
     float4 fp = make_float4(0.f, 0.f, 0.f, 0.f);
     if (HAS_FP) fp = *(const float4 *)(Fp + c);
@@ -556,8 +597,7 @@ __device__ inline double g_sweep_cell(const KC &kc, const GPtrs &gin, const GPtr
   float m1[3];
   moment_c<DIM>(e, kc, m1);
   const float gscale = -itau[c] * kc.inv_cs2dt;      // grad P = gscale * m1
-  const float lw = Sv * Sv * kc.inv_mu_w;
-  const float gamma = -lw * K[c] * kc.inv_cs2dt;
+  const float gamma = -lwk_of(Sv, K[c], kc) * kc.inv_cs2dt;
   const float conv = gamma * kc.dt * kc.w1 * kc.inv_tau_g * kc.c * gscale;  // times s * m1[a]
   const float srcw = kc.src_g * fs;
   // rest population
@@ -587,7 +627,8 @@ __device__ inline double g_sweep_cell(const KC &kc, const GPtrs &gin, const GPtr
       } else {
         float r;
         if (bc == LBTP_BC_NOFLUX) r = o;
-        else if (bc == LBTP_BC_DIRICHLET) r = kc.abbS[face] - o;
+        else if (bc == LBTP_BC_DIRICHLET)
+          r = (kc.wS[face] ? 2.0f * kc.w1beta * wall_S(kc, face, q.x, q.y, q.z, 1, 0) : kc.abbS[face]) - o;
         else r = 2.0f * kc.w1beta * Sv - o;    // outflow: S_wb = S of this node
         gout.p[dir_opp(j) + 1][c] = r;
         flux += (double)r - (double)o;
@@ -638,8 +679,7 @@ __device__ inline void init_cell(const KC &kc, const float *__restrict__ P0, con
   }
   const float itf = inv_tau_f_of(S, K[c], kc);
   const float tau_f = 1.0f / itf;
-  const float lw = S * S * kc.inv_mu_w;
-  const float gamma = -lw * K[c] * kc.inv_cs2dt;
+  const float gamma = -lwk_of(S, K[c], kc) * kc.inv_cs2dt;
   const float tau_g = 1.0f / kc.inv_tau_g;
   const float wsrc = 1.0f - 0.5f * kc.inv_tau_g;
   Pb[c] = P;

@@ -42,6 +42,12 @@ struct KC {
   int bc_g[6];
   float abbS[6];    // 2 w1 beta S_b of a Dirichlet saturation face
   float Sw[6];      // Dirichlet saturation of a face
+  int coef;         // lbtp_coef_model
+  float cf[6];      // RATIONAL: a0, a1, c0, c1, b0, b1
+  // Dirichlet data per link of a face (lbtp_set_wall_values), or null for
+  // the face constants above
+  const float *wP[6];
+  const float *wS[6];
 };
 
 // Device-side control block of a pressure solve and the float64 reductions.

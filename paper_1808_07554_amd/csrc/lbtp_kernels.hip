@@ -236,11 +236,7 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(KC kc, FPtrs f_, const f
   float m1[3];
   moment_c<DIM>(e, kc, m1);
   float scale = -itau[c] * kc.inv_cs2dt;
-  if (velocity) {
-    const float Sv = S[c];
-    const float lt = Sv * Sv * kc.inv_mu_w + (1.0f - Sv) * (1.0f - Sv) * kc.inv_mu_n;
-    scale = -K[c] * lt * scale;
-  }
+  if (velocity) scale = -dp_of(S[c], K[c], kc) * scale;   // u = -D_p grad P
 #pragma unroll
   for (int a = 0; a < DIM; ++a) out[a * kc.ncell + c] = scale * m1[a];
 }

@@ -14,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbtp.so")
 
 D2Q5, D3Q7, D2Q9 = 0, 1, 2
+COEF_QUADRATIC_KR, COEF_RATIONAL = 0, 1
 _LATTICE = {"D2Q5": D2Q5, "D3Q7": D3Q7, "D2Q9": D2Q9}
 _Q = {D2Q5: 5, D3Q7: 7, D2Q9: 9}
 FP32, FP16_DEV, BF16_DEV = 0, 1, 2
@@ -38,6 +39,8 @@ class Params(ctypes.Structure):
         ("bc_g", ctypes.c_int * 6), ("bc_S", ctypes.c_double * 6),
         ("init_neq", ctypes.c_int),
         ("stream", ctypes.c_void_p),
+        ("coef_model", ctypes.c_int),
+        ("coef", ctypes.c_double * 6),
     ]
 
 
@@ -48,6 +51,8 @@ EXPORTS = {
     "lbtp_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "lbtp_set_fields": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4 + [ctypes.c_int]),
     "lbtp_set_sources": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 2 + [ctypes.c_int]),
+    "lbtp_set_wall_values": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_int]),
     "lbtp_set_state": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4 + [ctypes.c_int]),
     "lbtp_update_coefficients": (ctypes.c_int, [ctypes.c_void_p]),
     "lbtp_pressure_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_longlong,
@@ -156,8 +161,11 @@ class _Arg:
             self.ptr, self.dev, self.keep = h.ctypes.data, 0, h
 
 
-def make_params(lattice, shape, *, beta, Ds, mu_w, mu_n, bc_f, bc_g, dx=1.0, dt=1.0, m=64,
-                storage="fp32", init_neq=True, stream_ptr=None, **_):
+def make_params(lattice, shape, *, beta, Ds, mu_w=1.0, mu_n=1.0, bc_f, bc_g, dx=1.0, dt=1.0, m=64,
+                storage="fp32", init_neq=True, stream_ptr=None, coef=None, **_):
+    """lbtp_params from keyword values.  coef: None for the quadratic relative
+    permeabilities with mu_w, mu_n, or ("rational", a0, a1, c0, c1, b0, b1)
+    for D_p = K (a0 + a1 S)/(b0 + b1 S), lambda_w K = K (c0 + c1 S)/(b0 + b1 S)."""
     lib = load()
     p = Params()
     lib.lbtp_default_params(ctypes.byref(p))
@@ -175,6 +183,12 @@ def make_params(lattice, shape, *, beta, Ds, mu_w, mu_n, bc_f, bc_g, dx=1.0, dt=
         p.bc_S[f] = float(b[1]) if len(b) > 1 else 0.0
     p.init_neq = 1 if init_neq else 0
     p.stream = stream_ptr
+    if coef is not None:
+        if coef[0] != "rational" or len(coef) != 7:
+            raise ValueError(f"unknown coefficient model {coef!r}")
+        p.coef_model = COEF_RATIONAL
+        for i, v in enumerate(coef[1:]):
+            p.coef[i] = float(v)
     return p, shape
 
 
@@ -358,29 +372,16 @@ class Solver:
     ("abb", value), ("bb",) or ("outflow",).
     """
 
-    def __init__(self, lattice, shape, *, beta, Ds, mu_w, mu_n, bc_f, bc_g, dx=1.0, dt=1.0, m=64,
-                 storage="fp32", init_neq=True, stream=None, **_):
+    def __init__(self, lattice, shape, *, beta, Ds, mu_w=1.0, mu_n=1.0, bc_f, bc_g, dx=1.0, dt=1.0, m=64,
+                 storage="fp32", init_neq=True, stream=None, coef=None, **_):
         self.torch = _torch()
         lib = load()
-        p = Params()
-        lib.lbtp_default_params(ctypes.byref(p))
-        p.lattice = _LATTICE[lattice]
-        shape = tuple(shape) + (1,) * (3 - len(shape))
-        p.nx, p.ny, p.nz = shape
-        p.dx, p.dt, p.beta, p.Ds, p.mu_w, p.mu_n = dx, dt, beta, Ds, mu_w, mu_n
-        p.storage = _STORAGE[storage] if isinstance(storage, str) else storage
-        p.residual_stride = m
-        for f, b in enumerate(bc_f):
-            p.bc_f[f] = _BC[b[0]]
-            p.bc_P[f] = float(b[1]) if len(b) > 1 else 0.0
-        for f, b in enumerate(bc_g):
-            p.bc_g[f] = _BC[b[0]]
-            p.bc_S[f] = float(b[1]) if len(b) > 1 else 0.0
-        p.init_neq = 1 if init_neq else 0
         if stream is None:
             stream = self.torch.cuda.current_stream()
         self.stream = stream
-        p.stream = stream.cuda_stream
+        p, shape = make_params(lattice, shape, beta=beta, Ds=Ds, mu_w=mu_w, mu_n=mu_n, bc_f=bc_f, bc_g=bc_g,
+                               dx=dx, dt=dt, m=m, storage=storage, init_neq=init_neq,
+                               stream_ptr=stream.cuda_stream, coef=coef)
         self.params = p
         self.dim = 3 if p.lattice == D3Q7 else 2
         self.Q = _Q[p.lattice]
@@ -426,6 +427,15 @@ class Solver:
     def set_sources(self, Fp=None, Fs=None):
         a = [self._arg(x) for x in (Fp, Fs)]
         _check(self._lib.lbtp_set_sources(self._h, *(x.ptr for x in a), self._both(*a)), "lbtp_set_sources")
+
+    def set_wall_values(self, face, P=None, S=None):
+        """Per-link Dirichlet data of one face (lbtp_set_wall_values): P and / or
+        S at the midpoints of the links crossing the face (L per face node)."""
+        n = self.ncell // self.shape[face // 2]
+        n *= 3 if self.params.lattice == D2Q9 else 1
+        a, b = self._arg(P, n), self._arg(S, n)
+        _check(self._lib.lbtp_set_wall_values(self._h, int(face), a.ptr, b.ptr, self._both(a, b)),
+               "lbtp_set_wall_values")
 
     def set_state(self, P0, S0, dP0=None, dS0=None):
         a = [self._arg(P0), self._arg(S0), self._arg(dP0, self.dim * self.ncell),

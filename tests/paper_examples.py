@@ -3,7 +3,9 @@
 Both use the D2Q9 lattice of Section 3, anti-bounce-back Dirichlet data from
 the exact solutions on all four walls, initial data from the exact
 solutions (with exact gradients for the non-equilibrium parts), and the
-global relative L1 error E of Section 4.
+global relative L1 error E of Section 4.  With out={} the pressure iteration
+counts of every coupled step (and of the final solve) and the solver are
+returned in it, so the GPU can replay the run.
 """
 import numpy as np
 
@@ -14,7 +16,7 @@ def rel_l1(exact, num):
     return float(np.abs(exact - num).sum() / np.abs(exact).sum())
 
 
-def example1(N, c=1.0, T=1.0, tol=1e-12, max_iters=500000):
+def example1(N, c=1.0, T=1.0, tol=1e-12, max_iters=500000, out=None):
     """Example 1: decoupled problem on [0,2]^2, phi = 1, D_p = D_s = 0.001, beta = 1
     (eq. 4-1, 4-2).  Decoupling sets lambda_t = lambda_w, so lambda_w K = D_p and
     F_s = Q + F_p."""
@@ -36,18 +38,19 @@ def example1(N, c=1.0, T=1.0, tol=1e-12, max_iters=500000):
     s.set_fields(1.0, phi, *sources(0.0))
     dP = np.stack([np.pi * np.cos(np.pi * X) * np.sin(np.pi * Y), np.pi * np.sin(np.pi * X) * np.cos(np.pi * Y), 0 * X])
     s.set_state(1.0 + ss, 0 * ss, dP0=dP, dS0=np.zeros_like(dP))
-    for _ in range(int(round(T / dt))):
-        s.step(tol, max_iters, sources=sources)
+    iters = [s.step(tol, max_iters, sources=sources) for _ in range(int(round(T / dt)))]
     s.set_sources(*sources(s.t))
     s.update_coefficients()
-    s.pressure_solve(tol, max_iters)
+    iters.append(s.pressure_solve(tol, max_iters)[0])
     u = s.velocity()
+    if out is not None:
+        out.update(iters=iters, solver=s)
     ua = -Dp * dP
     return dict(EP=rel_l1(1.0 + ss, s.pressure()), Eux=rel_l1(ua[0], u[0]), Euy=rel_l1(ua[1], u[1]),
                 ES=rel_l1(s.t * ss, s.saturation()))
 
 
-def example2(N, c=10.0, T=0.2, phi=1.0, beta=1.0, tol=1e-12, max_iters=2000000):
+def example2(N, c=10.0, T=0.2, phi=1.0, beta=1.0, tol=1e-12, max_iters=2000000, out=None):
     """Example 2: coupled problem on [0,1]^2 with D_p = 1/(0.5 - 0.2 S), D_s = 0.01,
     f_w = S, lambda_w K = f_w D_p, F_p = 0 (eq. 4-4, 4-5)."""
     L, Ds = 1.0, 0.01
@@ -69,12 +72,13 @@ def example2(N, c=10.0, T=0.2, phi=1.0, beta=1.0, tol=1e-12, max_iters=2000000):
     gp = S0 / 5 - 0.5
     gs = np.pi * np.cos(th(X, Y, 0.0))
     s.set_state(Pex(X, Y, 0, 0.0), S0, dP0=np.stack([gp, gp, 0 * X]), dS0=np.stack([gs, gs, 0 * X]))
-    for _ in range(int(round(T / dt))):
-        s.step(tol, max_iters, sources=sources)
+    iters = [s.step(tol, max_iters, sources=sources) for _ in range(int(round(T / dt)))]
     s.set_sources(*sources(s.t))
     s.update_coefficients()
-    s.pressure_solve(tol, max_iters)
+    iters.append(s.pressure_solve(tol, max_iters)[0])
     u = s.velocity()
+    if out is not None:
+        out.update(iters=iters, solver=s)
     one = np.ones_like(X)
     return dict(EP=rel_l1(Pex(X, Y, 0, s.t), s.pressure()), Eux=rel_l1(one, u[0]), Euy=rel_l1(one, u[1]),
                 ES=rel_l1(Sex(X, Y, 0, s.t), s.saturation()))
