@@ -39,7 +39,7 @@ POP_BYTES = {"fp32": 4, "fp16": 2, "bf16": 2}
 
 
 def f_sweep_bytes(lattice, storage):
-    q1 = 4 if lattice == "D2Q5" else 6
+    q1 = {"D2Q5": 4, "D3Q7": 6, "D2Q9": 8}[lattice]
     return 2 * q1 * POP_BYTES[storage] + 4 + 4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "f_sweep_traffic_injection2d_4096_{}.txt")
 
@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--workload", default="injection2d", choices=["injection2d", "injection3d", "ensemble"],
                     help="injection2d (default): 4096^2 D2Q5; injection3d: 512^3 D3Q7; ensemble: 256 uneven 2-D realisations")
+    ap.add_argument("--lattice", default="D2Q5", choices=["D2Q5", "D2Q9"],
+                    help="lattice of the 2-D injection workload (D2Q9: the paper's own, beta = 0.2)")
     ap.add_argument("--members", type=int, default=256)
     ap.add_argument("--iters-per-step", type=int, default=64,
                     help="ensemble: pressure iterations per coupled step (fixed, equal work for batched and sequential)")
@@ -187,6 +189,9 @@ def main():
         ncell = int(np.prod(params["shape"]))
     else:
         params, fl = inputs.injection_2d(a.n)
+        if a.lattice == "D2Q9":
+            # eq. 3-4 needs max(phi)/2 <= beta <= 2 min(phi): phi in [0.15, 0.3] -> beta 0.2
+            params = dict(params, lattice="D2Q9", beta=0.2)
         ncell = a.n * a.n
     K = torch.from_numpy(inputs.f32(fl["K"]).ravel()).to(dev)
     phi = torch.from_numpy(inputs.f32(fl["phi"]).ravel()).to(dev)
@@ -272,7 +277,8 @@ def main():
         gstep_s += e0.elapsed_time(e1) / 1e3 / nsat
     alg_bytes = f_sweep_bytes(params["lattice"], a.storage) * ncell
     achieved = alg_bytes / sweep_s / 1e9
-    traffic = measured_traffic(a.storage) if (a.workload == "injection2d" and a.n == 4096) else None
+    traffic = (measured_traffic(a.storage)
+               if (a.workload == "injection2d" and a.n == 4096 and a.lattice == "D2Q5") else None)
 
     out = {
         "metric": "MLUPS (both lattices) + s/coupled step vs plain FP32 at residual 1e-8",
@@ -306,7 +312,9 @@ def main():
         "cold_first_step_iterations": warm_its[0] if warm_its else None,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": sweep_kernel_name(a.storage, 3 if a.workload == "injection3d" else 2) + " (plain pressure sweep)", "avg_launch_us": round(sweep_s * 1e6, 2),
+                     "kernel": ("q9_f_sweep_kernel" if params["lattice"] == "D2Q9" else
+                                sweep_kernel_name(a.storage, 3 if a.workload == "injection3d" else 2))
+                     + " (plain pressure sweep)", "avg_launch_us": round(sweep_s * 1e6, 2),
                      "bytes_per_launch": alg_bytes},
     }
     if not a.no_cpu and a.workload == "injection2d":
