@@ -312,7 +312,8 @@ def main():
         "cold_first_step_iterations": warm_its[0] if warm_its else None,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": ("q9_f_sweep_kernel" if params["lattice"] == "D2Q9" else
+                     "kernel": (("q9_f_sweep_vec_kernel" if a.n % 4 == 0 else "q9_f_sweep_kernel")
+                                if params["lattice"] == "D2Q9" else
                                 sweep_kernel_name(a.storage, 3 if a.workload == "injection3d" else 2))
                      + " (plain pressure sweep)", "avg_launch_us": round(sweep_s * 1e6, 2),
                      "bytes_per_launch": alg_bytes},

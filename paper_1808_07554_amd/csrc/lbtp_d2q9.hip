@@ -161,6 +161,177 @@ __global__ __launch_bounds__(kThreads) void q9_f_sweep_kernel(KC kc, FPtrs fin_,
   if (MODE == 2) block_sum<2>(acc, partials);
 }
 
+// ------------------------------------------- pressure sweep, 4 nodes / thread
+// The same sweep with each thread owning four consecutive nodes of a row
+// (nx % 4 == 0): every population and base row moves as one vector; values
+// from x - 1 / x + 1 come from the adjacent lane (shuffles) or, at a
+// wavefront edge, from one scalar load.  Every lane runs every shuffle.
+
+// 4-vector of the node-wise Dirichlet pressures of a y face for slot k.
+__device__ inline float4 q9_wall_P4(const KC &kc, int face, int x0, int k) {
+  const float *a = kc.wP[face];
+  if (!a) {
+    const float pw = kc.Pw[face];
+    return make_float4(pw, pw, pw, pw);
+  }
+  return make_float4(a[(x0 + 0) * 3 + k], a[(x0 + 1) * 3 + k], a[(x0 + 2) * 3 + k], a[(x0 + 3) * 3 + k]);
+}
+
+template <typename T, int MODE, bool HAS_FP>
+__device__ inline void q9_sweep_quad(const KC &kc, const FP<T> &fin, const FP<T> &fout,
+                                     const float *__restrict__ Pb_in, float *__restrict__ Pb_out,
+                                     const float *__restrict__ itau, const float *__restrict__ Fp, int qi,
+                                     double *acc) {
+  const int n4 = kc.ncell >> 2;
+  const bool active = qi < n4;
+  const int c = (active ? qi : n4 - 1) << 2;
+  const int lane = threadIdx.x & 63;
+  const int y = c / kc.nx;
+  const int x0 = c - y * kc.nx;
+  const float is = kc.inv_dev_scale;
+  const float4 pb = *(const float4 *)(Pb_in + c);
+  // source rows of the y-moving populations: ey = +1 pulls from row y - 1,
+  // ey = -1 from row y + 1 (wrapped across a periodic face); r_has = false
+  // means the row lies beyond a wall and the y-face rule applies
+  const bool lo_in = y > 0, hi_in = y < kc.ny - 1;
+  const bool lo_has = lo_in || kc.bc_f[2] == LBTP_BC_PERIODIC;
+  const bool hi_has = hi_in || kc.bc_f[3] == LBTP_BC_PERIODIC;
+  const int c_lo = (lo_in ? y - 1 : kc.ny - 1) * kc.nx + x0;   // first node of the quad's source row
+  const int c_hi = (hi_in ? y + 1 : 0) * kc.nx + x0;
+  const float4 pb_lo = lo_has ? *(const float4 *)(Pb_in + c_lo) : pb;
+  const float4 pb_hi = hi_has ? *(const float4 *)(Pb_in + c_hi) : pb;
+  float4 e[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int ex = q9x(j), ey = q9y(j);
+    const float w = q9w(kc, j);
+    const bool has = ey == 0 ? true : (ey > 0 ? lo_has : hi_has);
+    const int cs = ey == 0 ? c : (ey > 0 ? c_lo : c_hi);
+    const float4 P = ey == 0 ? pb : (ey > 0 ? pb_lo : pb_hi);
+    // the source row as loaded by this lane (a valid address for every lane)
+    const float4 V = Vec4<T>::load(fin.p[j], has ? cs : c, is);
+    // elements at x - 1 (ex = +1) or x + 1 (ex = -1) of the neighbouring lanes
+    float vn = 0.f, pn = 0.f;
+    if (ex > 0) {
+      vn = __shfl_up(V.w, 1, 64);
+      pn = __shfl_up(P.w, 1, 64);
+      if (lane == 0 && x0 > 0 && has) {
+        vn = Storage<T>::load(fin.p[j], cs - 1, is);
+        pn = Pb_in[cs - 1];
+      }
+    } else if (ex < 0) {
+      vn = __shfl_down(V.x, 1, 64);
+      pn = __shfl_down(P.x, 1, 64);
+      if (lane == 63 && x0 + 4 < kc.nx && has) {
+        vn = Storage<T>::load(fin.p[j], cs + 4, is);
+        pn = Pb_in[cs + 4];
+      }
+    }
+    if (!has) {
+      // the whole quad takes the y-face rule (it also wins at the corners)
+      const int face = ey > 0 ? 2 : 3;
+      const float4 o = Vec4<T>::load(fin.p[q9opp(j)], c, is);
+      if (kc.bc_f[face] == LBTP_BC_DIRICHLET) {
+        const float4 pw = q9_wall_P4(kc, face, x0, q9_wall_slot(face, ex, ey));
+        e[j] = make_float4(2.0f * w * (pw.x - pb.x) - o.x, 2.0f * w * (pw.y - pb.y) - o.y,
+                           2.0f * w * (pw.z - pb.z) - o.z, 2.0f * w * (pw.w - pb.w) - o.w);
+      } else {
+        e[j] = o;
+      }
+      continue;
+    }
+    float4 src, psrc;
+    if (ex == 0) {
+      src = V;
+      psrc = P;
+    } else if (ex > 0) {
+      src = make_float4(vn, V.x, V.y, V.z);
+      psrc = make_float4(pn, P.x, P.y, P.z);
+    } else {
+      src = make_float4(V.y, V.z, V.w, vn);
+      psrc = make_float4(P.y, P.z, P.w, pn);
+    }
+    e[j] = make_float4(src.x + w * (psrc.x - pb.x), src.y + w * (psrc.y - pb.y), src.z + w * (psrc.z - pb.z),
+                       src.w + w * (psrc.w - pb.w));
+    // x faces: node 0 (ex = +1, x0 == 0) or node 3 (ex = -1, x0 + 4 == nx)
+    if (ex > 0 && x0 == 0) {
+      if (kc.bc_f[0] == LBTP_BC_PERIODIC) {
+        const int s0 = cs + kc.nx - 1;
+        e[j].x = Storage<T>::load(fin.p[j], s0, is) + w * (Pb_in[s0] - pb.x);
+      } else {
+        const float o = Storage<T>::load(fin.p[q9opp(j)], c, is);
+        e[j].x = kc.bc_f[0] == LBTP_BC_DIRICHLET
+                     ? 2.0f * w * (wall_P(kc, 0, 0, y, 0, 3, q9_wall_slot(0, ex, ey)) - pb.x) - o
+                     : o;
+      }
+    } else if (ex < 0 && x0 + 4 == kc.nx) {
+      if (kc.bc_f[1] == LBTP_BC_PERIODIC) {
+        const int s3 = cs + 3 - (kc.nx - 1);
+        e[j].w = Storage<T>::load(fin.p[j], s3, is) + w * (Pb_in[s3] - pb.w);
+      } else {
+        const float o = Storage<T>::load(fin.p[q9opp(j)], c + 3, is);
+        e[j].w = kc.bc_f[1] == LBTP_BC_DIRICHLET
+                     ? 2.0f * w * (wall_P(kc, 1, kc.nx - 1, y, 0, 3, q9_wall_slot(1, ex, ey)) - pb.w) - o
+                     : o;
+      }
+    }
+  }
+  // collision, re-basing and stopping-rule terms, as in the one-node kernel
+  const float4 it = *(const float4 *)(itau + c);
+  float4 fp = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (HAS_FP) fp = *(const float4 *)(Fp + c);
+  float4 o[8];
+  float4 pnew;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float ev[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ev[j] = f4get(e[j], i);
+    const float dP = q9_dpressure(ev, kc);
+    const float t = f4get(it, i);
+    const float add = HAS_FP ? kc.dt * kc.wbar * f4get(fp, i) : 0.0f;
+    float rb = 0.0f;
+    if (MODE >= 1) {
+      const float pbi = f4get(pb, i);
+      const float P = pbi + dP;
+      rb = pbi - P;
+      f4set(pnew, i, P);
+      if (MODE == 2 && active) {
+        acc[0] += (double)dP * (double)dP;
+        acc[1] += (double)P * (double)P;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float w = q9w(kc, j);
+      float v = ev[j] + (w * dP - ev[j]) * t;
+      if (HAS_FP) v += add;
+      if (MODE >= 1) v += w * rb;
+      f4set(o[j], i, v);
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) Vec4<T>::store(fout.p[j], c, o[j], kc.dev_scale);
+    if (MODE >= 1) *(float4 *)(Pb_out + c) = pnew;
+  }
+}
+
+template <typename T, int MODE, bool HAS_FP>
+__global__ __launch_bounds__(kThreads) void q9_f_sweep_vec_kernel(KC kc, FPtrs fin_, FPtrs fout_,
+                                                                  const float *__restrict__ Pb_in,
+                                                                  float *__restrict__ Pb_out,
+                                                                  const float *__restrict__ itau,
+                                                                  const float *__restrict__ Fp,
+                                                                  double *__restrict__ partials,
+                                                                  const Ctl *__restrict__ ctl, long long k) {
+  if (ctl->done || k > ctl->kmax) return;
+  double acc[2] = {0.0, 0.0};
+  q9_sweep_quad<T, MODE, HAS_FP>(kc, typed<T>(fin_), typed<T>(fout_), Pb_in, Pb_out, itau, Fp,
+                                 blockIdx.x * kThreads + threadIdx.x, acc);
+  if (MODE == 2) block_sum<2>(acc, partials);
+}
+
 // ------------------------------------------------------------------ moments
 template <bool HAS_FS>
 __global__ __launch_bounds__(kThreads) void q9_moments_kernel(KC kc, GPtrs g, const float *__restrict__ K,
@@ -387,8 +558,15 @@ hipError_t launch_f_sweep_q9(int storage, const KC &kc, FPtrs fin, FPtrs fout, c
   q9_dispatch(storage, local, [&](auto t, auto l) {
     using T = std::remove_pointer_t<decltype(t)>;
     constexpr bool L = decltype(l)::value;
-#define Q9_SWEEP(M, HF) \
-  hipLaunchKernelGGL((q9_f_sweep_kernel<T, L, M, HF>), Q9_GRID(kc), kc, fin, fout, Pb_in, Pb_out, itau, Fp, partials, ctl, k)
+#define Q9_SWEEP(M, HF)                                                                                   \
+  do {                                                                                                    \
+    if (!L && kc.nx % 4 == 0)                                                                             \
+      hipLaunchKernelGGL((q9_f_sweep_vec_kernel<T, M, HF>), dim3(nblocks(kc.ncell / 4)), dim3(kThreads), 0, s, \
+                         kc, fin, fout, Pb_in, Pb_out, itau, Fp, partials, ctl, k);                        \
+    else                                                                                                  \
+      hipLaunchKernelGGL((q9_f_sweep_kernel<T, L, M, HF>), Q9_GRID(kc), kc, fin, fout, Pb_in, Pb_out, itau, \
+                         Fp, partials, ctl, k);                                                           \
+  } while (0)
     if (Fp) {
       if (mode == 0) Q9_SWEEP(0, true);
       else if (mode == 1) Q9_SWEEP(1, true);

@@ -189,7 +189,8 @@ constexpr bool walk_form(int dim, int storage) { return dim == 2 && storage != L
 // Blocks of a pull-form pressure sweep (and so its residual partials): rows
 // with nx % 4 == 0 run four nodes per thread.
 inline int sweep_blocks(const KC &kc, int local, int dim, int storage) {
-  if (local || kc.nx % 4 != 0 || dim == kD2Q9) return nblocks(kc.ncell);
+  if (local || kc.nx % 4 != 0) return nblocks(kc.ncell);
+  if (dim == kD2Q9) return nblocks(kc.ncell / 4);
   return walk_form(dim, storage) ? nblocks(walk_threads(kc, dim)) : nblocks(kc.ncell / 4);
 }
 
