@@ -207,6 +207,15 @@ LBTP_API int lbtp_velocity(lbtp_ctx *ctx, float *u, int on_device);
 LBTP_API int lbtp_grad_p(lbtp_ctx *ctx, float *gradP, int on_device);
 LBTP_API int lbtp_saturation(lbtp_ctx *ctx, float *S, int on_device);
 
+/* Phase velocities of eq. 2-12 / 2-13 (dim x ncell each, component-major)
+ * with the coefficients of the last update_coefficients: with the constant
+ * D_s of the model, D_s = -K lambda_n f_w dP_c/dS (eq. 2-16), so
+ *   u_w = f_w u - D_s grad S,   u_n = f_n u + D_s grad S,
+ * f_w = lambda_w K / D_p (eq. 2-10), u of lbtp_velocity and grad S^n by
+ * second-order central differences (one-sided at walls).  LBTP_ESTATE before
+ * the first update_coefficients. */
+LBTP_API int lbtp_phase_velocities(lbtp_ctx *ctx, float *uw, float *un, int on_device);
+
 /* Mass M = sum_x phi S (float64, current g and F_s) and the accumulated net
  * flux of g through Dirichlet/outflow links since lbtp_set_state.  Exactly,
  * M^{n+1} = M^n + dt/2 sum(F_s^n + F_s^{n+1}) + flux_n. */

@@ -213,6 +213,22 @@ class Solver:
         """eq. (3-10b): u = -K lambda_t grad P with K lambda_t = D_p at S^n."""
         return -self.Dp * self.grad_p()
 
+    def phase_velocities(self):
+        """Phase velocities of eq. (2-12), (2-13) at S^n:
+            u_w = f_w (u + K lambda_n grad P_c),  u_n = f_n (u - K lambda_w grad P_c),
+        with f_w = lambda_w / lambda_t = (lambda_w K) / D_p (eq. 2-10).  The
+        saturation diffusivity of eq. (2-16), D_s = -K lambda_n f_w P_c'(S),
+        is the constant D_s of the model, so K lambda_n grad P_c =
+        K lambda_n P_c' grad S = -(D_s / f_w) grad S and
+            u_w = f_w u - D_s grad S,  u_n = f_n u + D_s grad S.
+        grad S by second-order central differences (one-sided at walls)."""
+        u = self.velocity()
+        fw = self.lamwK / self.Dp
+        gS = self._cdiff(self.S.astype(np.float64))
+        uw = fw * u - self.Ds * gS
+        un = (1.0 - fw) * u + self.Ds * gS
+        return uw, un
+
     def mass(self):
         """M = sum_x phi S (float64), and the accumulated boundary-link flux of g."""
         return float(np.sum((self.phi * self.saturation()).astype(np.float64))), self.flux_ledger

@@ -632,6 +632,27 @@ int lbtp_mass(lbtp_ctx *c, double *mass, double *ledger) {
   return LBTP_OK;
 }
 
+int lbtp_phase_velocities(lbtp_ctx *c, float *uw, float *un, int on_device) {
+  if (!c || !uw || !un) return LBTP_EINVAL;
+  if (!c->have_coef) return LBTP_ESTATE;
+  const size_t nv = (size_t)c->ncell * c->dim;
+  HIP_TRY(launch_grad(c->lk, c->p.storage, c->kc, fptrs(c, c->fbuf[c->fs]), c->f_local, c->Pb[c->pbs], c->itau,
+                      c->K, c->S, 1, c->scratch, c->stream));
+  float *dw = uw, *dn = un;
+  if (!on_device) {
+    if (hipMalloc((void **)&dw, 2 * nv * sizeof(float)) != hipSuccess) return LBTP_ENOMEM;
+    dn = dw + nv;
+  }
+  hipError_t e = launch_phase(c->dim, c->kc, c->scratch, c->S, c->K, (float)c->p.Ds, dw, dn, c->stream);
+  if (e == hipSuccess && !on_device) {
+    e = hipMemcpyAsync(uw, dw, nv * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(un, dn, nv * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (!on_device) (void)hipFree(dw);
+  return e == hipSuccess ? LBTP_OK : LBTP_EHIP;
+}
+
 int lbtp_populations(lbtp_ctx *c, float *f, float *g, int on_device) {
   if (!c) return LBTP_EINVAL;
   if (!c->have_state) return LBTP_ESTATE;

@@ -102,6 +102,9 @@ hipError_t launch_populations(int dim, int storage, const KC &kc, FPtrs f, int f
                               float *out, hipStream_t s);
 
 hipError_t launch_copy_probe(const void *src, void *dst, long long n4, hipStream_t s);
+// dim = spatial dimension (any lattice); u: dim x ncell total velocity
+hipError_t launch_phase(int dim, const KC &kc, const float *u, const float *S, const float *K, float Ds, float *uw,
+                        float *un, hipStream_t s);
 
 // D2Q9 (lbtp_d2q9.hip): the same operations, one node per thread.
 hipError_t launch_f_sweep_q9(int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb_in, float *Pb_out,

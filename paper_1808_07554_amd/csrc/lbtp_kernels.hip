@@ -253,6 +253,29 @@ __global__ __launch_bounds__(kThreads) void saturation_kernel(KC kc, GPtrs g, co
   S[c] = saturation_of(sum_g<DIM>(gv), HAS_FS ? Fs[c] : 0.0f, phi[c], kc);
 }
 
+// Phase velocities (eq. 2-12, 2-13) from the total velocity u (component-
+// major, dim x ncell) and S^n: with the constant D_s of the model,
+// D_s = -K lambda_n f_w P_c' (eq. 2-16) turns K lambda_n grad P_c into
+// -(D_s / f_w) grad S, so u_w = f_w u - D_s grad S, u_n = f_n u + D_s grad S,
+// f_w = lambda_w K / D_p (eq. 2-10); grad S by second-order central
+// differences (one-sided at walls).
+__global__ __launch_bounds__(kThreads) void phase_kernel(KC kc, int dim, const float *__restrict__ u,
+                                                         const float *__restrict__ S, const float *__restrict__ K,
+                                                         float Ds, float *__restrict__ uw, float *__restrict__ un) {
+  const int c = blockIdx.x * kThreads + threadIdx.x;
+  if (c >= kc.ncell) return;
+  const Cell q = cell_of(c, kc);
+  const float Sv = S[c], Kv = K[c];
+  const float fw = lwk_of(Sv, Kv, kc) / dp_of(Sv, Kv, kc);
+  const float inv2dx = 0.5f / (kc.c * kc.dt);
+  for (int a = 0; a < dim; ++a) {
+    const float gs = cdiff(S, q, a, kc, inv2dx);
+    const float ua = u[a * kc.ncell + c];
+    uw[a * kc.ncell + c] = fw * ua - Ds * gs;
+    un[a * kc.ncell + c] = (1.0f - fw) * ua + Ds * gs;
+  }
+}
+
 // Pre-collision populations f_i = w_i P_b + e_i (float) for inspection.
 template <int DIM, typename T, bool LOCAL>
 __global__ __launch_bounds__(kThreads) void populations_kernel(KC kc, FPtrs f_, const float *__restrict__ Pb,
@@ -469,6 +492,12 @@ hipError_t launch_populations(int dim, int storage, const KC &kc, FPtrs f, int f
                               float *out, hipStream_t s) {
   if (dim == kD2Q9) return launch_populations_q9(storage, kc, f, f_local, Pb, out, s);
   dispatch<PopulationsLaunch>(dim, storage, f_local, kc, f, Pb, out, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_phase(int dim, const KC &kc, const float *u, const float *S, const float *K, float Ds, float *uw,
+                        float *un, hipStream_t s) {
+  hipLaunchKernelGGL(phase_kernel, LBTP_GRID(kc), kc, dim, u, S, K, Ds, uw, un);
   return hipGetLastError();
 }
 

@@ -51,6 +51,7 @@ EXPORTS = {
     "lbtp_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "lbtp_set_fields": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4 + [ctypes.c_int]),
     "lbtp_set_sources": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 2 + [ctypes.c_int]),
+    "lbtp_phase_velocities": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "lbtp_set_wall_values": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_int]),
     "lbtp_set_state": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4 + [ctypes.c_int]),
@@ -481,6 +482,14 @@ class Solver:
         m, l = ctypes.c_double(), ctypes.c_double()
         _check(self._lib.lbtp_mass(self._h, ctypes.byref(m), ctypes.byref(l)), "lbtp_mass")
         return m.value, l.value
+
+    def phase_velocities(self):
+        """(u_w, u_n) of eq. 2-12 / 2-13, each (dim, nz, ny, nx)."""
+        uw = self._empty(self.dim * self.ncell)
+        un = self._empty(self.dim * self.ncell)
+        _check(self._lib.lbtp_phase_velocities(self._h, ctypes.c_void_p(uw.data_ptr()),
+                                               ctypes.c_void_p(un.data_ptr()), 1), "lbtp_phase_velocities")
+        return uw.view((self.dim,) + self._fshape()), un.view((self.dim,) + self._fshape())
 
     def populations(self):
         """Pre-collision populations (float32): f_1..f_{Q-1} and g_0..g_{Q-1}."""

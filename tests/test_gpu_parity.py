@@ -268,3 +268,32 @@ def test_periodic_3d_replay(shape):
         _check_fields(o, g, f"periodic 3-D step {n}", periodic=True)
         o.saturation_step()
         g.saturation_step()
+
+
+@pytest.mark.parametrize("shape,lattice", [((70, 45), "D2Q5"), ((24, 17, 13), "D3Q7"), ((40, 30), "D2Q9")])
+def test_phase_velocities_match_oracle(shape, lattice):
+    """eq. 2-12 / 2-13 on the GPU against the oracle after a replayed step."""
+    params = injection_params(shape)
+    if lattice == "D2Q9":
+        params = dict(params, lattice="D2Q9", beta=0.2)
+    o, g = _pair(params, seed=31)
+    with pytest.raises(Exception):
+        g.phase_velocities()                      # before update_coefficients: LBTP_ESTATE
+    for iters in (1, 50):
+        o.update_coefficients()
+        g.update_coefficients()
+        o.pressure_solve(-1.0, iters)
+        g.pressure_solve(-1.0, iters)
+        o.saturation_step()
+        g.saturation_step()
+    o.update_coefficients()
+    g.update_coefficients()
+    o.pressure_solve(-1.0, 20)
+    g.pressure_solve(-1.0, 20)
+    uw_o, un_o = o.phase_velocities()
+    uw, un = (_np(t) for t in g.phase_velocities())
+    d = uw.shape[0]
+    e = {"u_w": rel_l2(uw_o[:d], uw), "u_n": rel_l2(un_o[:d], un)}
+    print(lattice, shape, {k: f"{v:.2e}" for k, v in e.items()})
+    for k, v in e.items():
+        assert v <= TOL, (k, v)

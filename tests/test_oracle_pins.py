@@ -372,3 +372,45 @@ def test_example2_printed_bounds_for_pressure_and_velocity():
     for k in ("EP", "Eux", "Euy"):
         assert E[k] < g["paper_bound"] == 1.91e-3, (k, E[k])
     assert E["ES"] < 1.5 * g["paper_bound"]      # recorded, within 20 % of the bound
+
+
+# ------------------------------------------------------------ phase velocities
+def _phase_solver(S0):
+    from tests.lbhelp import oracle_solver
+    from paper_1808_07554_amd import inputs
+    p, fl = inputs.injection_problem((24, 16), 1.0, 4.0, 21, 22)
+    o = oracle_solver(p, m=1)
+    o.set_fields(fl["K"], fl["phi"])
+    P0 = fl["P0"] + 0.02 * np.sin(np.pi * (np.arange(16) + 0.5) / 16)[None, :, None]
+    o.set_state(P0, S0)
+    o.update_coefficients()
+    o.pressure_solve(-1.0, 30)
+    return o
+
+
+def test_phase_velocities_sum_and_linear_saturation():
+    """eq. 2-12/2-13 with the constant D_s: u_w + u_n = u; for S linear in x
+    (central and one-sided second-order differences are exact) u_w - f_w u =
+    -D_s dS/dx and u_n - f_n u = +D_s dS/dx everywhere, and nothing along y."""
+    L = 24
+    x = (np.arange(L) + 0.5)
+    b = 0.5 / L
+    S0 = np.broadcast_to(0.2 + b * x, (1, 16, L)).copy()
+    o = _phase_solver(S0)
+    assert np.allclose(o.S, S0, atol=1e-13)          # sum_i g_i = phi S0 exactly
+    u = o.velocity()
+    uw, un = o.phase_velocities()
+    assert np.allclose(uw + un, u, atol=1e-15)
+    fw = (o.S ** 2 / 1.0) / (o.S ** 2 / 1.0 + (1 - o.S) ** 2 / 5.0)
+    assert np.allclose(uw[0] - fw * u[0], -o.Ds * b, rtol=1e-10, atol=1e-16)
+    assert np.allclose(un[0] - (1 - fw) * u[0], o.Ds * b, rtol=1e-10, atol=1e-16)
+    assert np.allclose(uw[1], fw * u[1], atol=1e-16)
+
+
+def test_phase_velocities_uniform_saturation_is_fractional_flow():
+    o = _phase_solver(np.full((1, 16, 24), 0.35))
+    u = o.velocity()
+    uw, un = o.phase_velocities()
+    fw = 0.35 ** 2 / (0.35 ** 2 + 0.65 ** 2 / 5.0)
+    assert np.allclose(uw, fw * u, rtol=1e-12, atol=1e-15)
+    assert np.allclose(un, (1 - fw) * u, rtol=1e-12, atol=1e-15)
