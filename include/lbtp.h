@@ -116,6 +116,10 @@ typedef struct lbtp_params {
   void *stream;                /* hipStream_t for all device work; NULL = null stream */
   int coef_model;              /* lbtp_coef_model */
   double coef[6];              /* RATIONAL: a0, a1, c0, c1, b0, b1 (unused otherwise) */
+  double cap_B;                /* >= 0: capillary curve P_c = cap_B (1 - S), which adds
+                                  cap_B K lambda_n f_w to Ds (eq. 2-16), so D_s and tau_g
+                                  vary with S and K from node to node; 0 = constant Ds.
+                                  Single contexts only (ensembles: LBTP_EINVAL). */
 } lbtp_params;
 
 /* Fill *p with defaults: D2Q5, 1x1x1, dx = dt = 1, beta = 1, Ds = 0, mu = 1,

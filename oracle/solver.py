@@ -10,7 +10,9 @@ float64).  The algorithm follows the paper's order:
   coupled step n (physical time t_n = n dt)
     1. S^n from the g moments, eq. (3-9b); mobilities and D_p = K lambda_t,
        eq. (2-9), (2-16); tau_f(x) from eq. (3-11a); gamma(x) from eq. (3-8);
-       tau_g from eq. (3-11b) (a scalar: D_s and beta are uniform).
+       tau_g from eq. (3-11b): a scalar for a constant D_s; with a capillary
+       coefficient B > 0, D_s(x) = D_s + B K lambda_n f_w (eq. 2-16 with the
+       linear capillary curve P_c = B (1 - S)) and tau_g(x) is a field.
     2. Pressure iteration in pseudo time, eq. (3-1) with eq. (3-3): moment
        P = sum_{i>=1} f_i / (1 - w_0) (eq. 3-9a), BGK collision (eq. 2-1b a),
        streaming, then the boundary rules of Section 4: anti-bounce-back for
@@ -89,7 +91,7 @@ class Solver:
     """
 
     def __init__(self, lattice, shape, *, beta, Ds, coef, bc_f, bc_g,
-                 dx=1.0, dt=1.0, m=1, dtype=np.float64):
+                 dx=1.0, dt=1.0, m=1, dtype=np.float64, cap_B=0.0):
         self.lat = _lat.get(lattice) if isinstance(lattice, str) else lattice
         shape = tuple(int(s) for s in shape)
         if len(shape) == 2:
@@ -103,6 +105,9 @@ class Solver:
         self.c = self.dx / self.dt
         self.cs2 = self.lat.cs2_c2 * self.c * self.c
         self.beta, self.Ds = float(beta), float(Ds)
+        self.cap_B = float(cap_B)
+        if self.cap_B < 0:
+            raise ValueError("capillary coefficient must be non-negative")
         self.coef = coef
         self.m = int(m)
         self.bc_f = [tuple(b) for b in bc_f]
@@ -115,7 +120,7 @@ class Solver:
             if any(per) and not all(per):
                 raise ValueError("periodicity must hold on both faces of an axis for f and g")
         # tau_g from eq. (3-11b); validity: tau > 1/2 and non-negative g^eq
-        self.tau_g = 0.5 + self.Ds / (self.beta * self.cs2 * self.dt)
+        self.tau_g = self._tau_g(self.Ds)
         if not self.tau_g > 0.5:
             raise ValueError("tau_g must exceed 1/2")
         self.t = 0.0
@@ -234,10 +239,26 @@ class Solver:
         return float(np.sum((self.phi * self.saturation()).astype(np.float64))), self.flux_ledger
 
     # ---------------------------------------------------------- coefficients
+    def _tau_g(self, Ds):
+        """eq. (3-11b)."""
+        return 0.5 + Ds / (self.beta * self.cs2 * self.dt)
+
+    def saturation_diffusivity(self, S, Dp, lamwK):
+        """D_s of eq. (2-16), D_s = -K lambda_n f_w dP_c/dS, for the capillary
+        curve P_c = B (1 - S) on top of the constant D_s of the model:
+        D_s + B K lambda_n f_w with K lambda_n = D_p - lambda_w K and
+        f_w = lambda_w K / D_p (eq. 2-10)."""
+        if self.cap_B == 0.0:
+            return self.Ds
+        return self.Ds + self.cap_B * (Dp - lamwK) * (lamwK / Dp)
+
     def update_coefficients(self):
-        """S^n, D_p, tau_f(x), gamma(x) for the current coupled step."""
+        """S^n, D_p, tau_f(x), gamma(x) and tau_g (field with a capillary
+        term) for the current coupled step."""
         self.S = self.saturation()
         self.Dp, self.lamwK = self.coef(self.S, self.K)
+        if self.cap_B != 0.0:
+            self.tau_g = self._tau_g(self.saturation_diffusivity(self.S, *self.coef(self.S, self.K)))
         self.Dp = np.asarray(self.Dp, dtype=self.dtype) * np.ones(self.fshape, self.dtype)
         self.lamwK = np.asarray(self.lamwK, dtype=self.dtype) * np.ones(self.fshape, self.dtype)
         self.tau_f = 0.5 + self.Dp / (self.cs2 * self.dt)          # eq. (3-11a)
@@ -414,7 +435,7 @@ class Solver:
         Dp, lamwK = self.coef(S0, self.K)
         tau_f = 0.5 + Dp / (self.cs2 * self.dt)
         gamma = -lamwK / (self.cs2 * self.dt)
-        tg = self.tau_g
+        tg = self._tau_g(self.saturation_diffusivity(S0, Dp, lamwK))
         f = self.feq(P0)
         g = self.geq(S0)
         if neq:

@@ -33,6 +33,7 @@ struct lbtp_ctx {
   int has_Fp = 0, has_Fs = 0;
   float *S = nullptr, *itau = nullptr, *scratch = nullptr;
   float *wallP[6] = {}, *wallS[6] = {};   // per-link Dirichlet data (lbtp_set_wall_values)
+  float *itg = nullptr;                    // 1/tau_g per node (cap_B > 0)
   double *partials = nullptr;
   int nblk = 0;
   Ctl *ctl = nullptr;       // device
@@ -85,6 +86,7 @@ int validate(const lbtp_params *p) {
   if ((long long)Q * n >= (1LL << 31)) return LBTP_EINVAL;   // 32-bit cell indexing
   if (!(p->dx > 0) || !(p->dt > 0) || !(p->beta > 0) || !(p->Ds > 0)) return LBTP_EINVAL;
   if (p->coef_model != LBTP_COEF_QUADRATIC_KR && p->coef_model != LBTP_COEF_RATIONAL) return LBTP_EINVAL;
+  if (!(p->cap_B >= 0.0) || !isfinite(p->cap_B)) return LBTP_EINVAL;
   if (p->coef_model == LBTP_COEF_QUADRATIC_KR && (!(p->mu_w > 0) || !(p->mu_n > 0))) return LBTP_EINVAL;
   if (p->coef_model == LBTP_COEF_RATIONAL) {
     for (int i = 0; i < 6; ++i)
@@ -141,6 +143,10 @@ void fill_kc(lbtp_ctx *c) {
   k.inv_mu_n = p.mu_n > 0 ? (float)(1.0 / p.mu_n) : 0.0f;
   k.coef = p.coef_model;
   for (int i = 0; i < 6; ++i) k.cf[i] = (float)p.coef[i];
+  k.Ds = (float)p.Ds;
+  k.cap_B = (float)p.cap_B;
+  k.inv_bcs2dt = (float)(1.0 / (p.beta * cs2 * p.dt));
+  k.itg = c->itg;
   k.inv_cs2dt = (float)(1.0 / (cs2 * p.dt));
   k.geq0_phi = (float)((w0 - 1.0) * p.beta);
   k.w1beta = (float)(w1 * p.beta);
@@ -260,7 +266,7 @@ const char *lbtp_strerror(int s) {
 void lbtp_destroy(lbtp_ctx *c) {
   if (!c) return;
   void *bufs[] = {c->fbuf[0], c->fbuf[1], c->gbuf[0], c->gbuf[1], c->Pb[0], c->Pb[1], c->K, c->phi,
-                  c->Fp, c->Fs, c->S, c->itau, c->scratch};
+                  c->Fp, c->Fs, c->S, c->itau, c->scratch, c->itg};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   for (int f = 0; f < 6; ++f) {
@@ -308,13 +314,15 @@ int lbtp_init(const lbtp_params *p, lbtp_ctx **out) {
                 {(void **)&c->Fs, n * 4},
                 {(void **)&c->S, n * 4},
                 {(void **)&c->itau, n * 4},
-                {(void **)&c->scratch, n * 3 * 4}};
+                {(void **)&c->scratch, n * 3 * 4},
+                {(void **)&c->itg, p->cap_B > 0.0 ? n * 4 : 0}};
   for (auto &a : allocs) {
-    if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {
+    if (a.bytes && hipMalloc(a.ptr, a.bytes) != hipSuccess) {
       lbtp_destroy(c);
       return LBTP_ENOMEM;
     }
   }
+  c->kc.itg = c->itg;
   if (hipMalloc((void **)&c->partials, (size_t)c->nblk * 2 * sizeof(double)) != hipSuccess ||
       hipMalloc((void **)&c->ctl, sizeof(Ctl)) != hipSuccess) {
     lbtp_destroy(c);
@@ -941,6 +949,8 @@ int lbtp_batch_init(const lbtp_params *members, int n, lbtp_batch **out) {
   const lbtp_params &p0 = members[0];
   if (p0.residual_stride < 2 || p0.residual_stride % 2) return LBTP_EINVAL;
   if (p0.lattice == LBTP_D2Q9) return LBTP_EINVAL;   // ensembles run D2Q5 / D3Q7
+  for (int i = 0; i < n; ++i)
+    if (members[i].cap_B != 0.0) return LBTP_EINVAL;  // and a uniform tau_g
   for (int i = 0; i < n; ++i) {
     const lbtp_params &p = members[i];
     if (p.lattice != p0.lattice || p.storage != p0.storage || p.residual_stride != p0.residual_stride ||

@@ -354,6 +354,7 @@ __global__ __launch_bounds__(kThreads) void q9_moments_kernel(KC kc, GPtrs g, co
     if (write_coef) {
       S[c] = Sv;
       itau[c] = inv_tau_f_of(Sv, K[c], kc);
+      if (kc.itg) kc.itg[c] = inv_tau_g_of(Sv, K[c], kc);
     }
     if (HAS_FS) dm += 0.5 * (double)kc.dt * (double)fs;
     acc[0] = dm;
@@ -391,11 +392,13 @@ __global__ __launch_bounds__(kThreads) void q9_g_sweep_kernel(KC kc, GPtrs gin, 
     const float gscale = -itau[c] * kc.inv_cs2dt;       // grad P = gscale * m1
     const float gx = gscale * m1[0], gy = gscale * m1[1];
     const float gamma = -lwk_of(Sv, K[c], kc) * kc.inv_cs2dt;
-    const float conv = gamma * kc.dt * kc.inv_tau_g;     // times w_i c_i . grad P
-    const float srcw = kc.src_g * fs;
+    const float itg = kc.itg ? kc.itg[c] : kc.inv_tau_g;
+    const float srcg = kc.itg ? kc.dt * (1.0f - 0.5f * itg) : kc.src_g;
+    const float conv = gamma * kc.dt * itg;     // times w_i c_i . grad P
+    const float srcw = srcg * fs;
     {
       const float geq = q9_gamma0(kc, ph) * Sv;
-      float o = gv[0] + (geq - gv[0]) * kc.inv_tau_g;
+      float o = gv[0] + (geq - gv[0]) * itg;
       if (HAS_FS) o += kc.w0 * srcw;
       gout.p[0][c] = o;
     }
@@ -405,7 +408,7 @@ __global__ __launch_bounds__(kThreads) void q9_g_sweep_kernel(KC kc, GPtrs gin, 
       const int ex = q9x(j), ey = q9y(j);
       const float w = q9w(kc, j);
       const float G = q9_gamma(kc, j, ph);
-      float o = gv[j + 1] + (G * Sv - gv[j + 1]) * kc.inv_tau_g;
+      float o = gv[j + 1] + (G * Sv - gv[j + 1]) * itg;
       if (HAS_FS) o += w * srcw;
       o += conv * w * (kc.c * ((float)ex * gx + (float)ey * gy));
       const int face = q9_exit_face(kc, kc.bc_g, x, y, ex, ey);
@@ -456,8 +459,9 @@ __global__ __launch_bounds__(kThreads) void q9_init_kernel(KC kc, const float *_
   }
   const float tau_f = 1.0f / inv_tau_f_of(S, K[c], kc);
   const float gamma = -lwk_of(S, K[c], kc) * kc.inv_cs2dt;
-  const float tau_g = 1.0f / kc.inv_tau_g;
-  const float wsrc = 1.0f - 0.5f * kc.inv_tau_g;
+  const float itg = kc.cap_B > 0.0f ? inv_tau_g_of(S, K[c], kc) : kc.inv_tau_g;
+  const float tau_g = 1.0f / itg;
+  const float wsrc = 1.0f - 0.5f * itg;
   Pb[c] = P;
   {
     const float G0 = q9_gamma0(kc, ph);
@@ -473,7 +477,7 @@ __global__ __launch_bounds__(kThreads) void q9_init_kernel(KC kc, const float *_
     Storage<T>::store(f.p[j], c, neq ? -tau_f * kc.dt * w * cdp : 0.0f, kc.dev_scale);
     const float G = q9_gamma(kc, j, ph);
     float v = G * S;
-    if (neq) v -= tau_g * kc.dt * ((G / ph - w * wsrc) * fs + G * cds - gamma * w * cdp * kc.inv_tau_g);
+    if (neq) v -= tau_g * kc.dt * ((G / ph - w * wsrc) * fs + G * cds - gamma * w * cdp * itg);
     g.p[j + 1][c] = v;
   }
 }

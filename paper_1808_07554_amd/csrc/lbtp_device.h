@@ -173,6 +173,14 @@ __device__ inline float inv_tau_f_of(float S, float K, const KC &kc) {
   return 1.0f / (0.5f + dp_of(S, K, kc) * kc.inv_cs2dt);
 }
 
+// 1/tau_g (eq. 3-11b) with D_s = Ds + cap_B K lambda_n f_w, K lambda_n =
+// D_p - lambda_w K and f_w = lambda_w K / D_p (eq. 2-10, 2-16).
+__device__ inline float inv_tau_g_of(float S, float K, const KC &kc) {
+  const float dp = dp_of(S, K, kc), lwk = lwk_of(S, K, kc);
+  const float Ds = kc.Ds + kc.cap_B * (dp - lwk) * (lwk / dp);
+  return 1.0f / (0.5f + Ds * kc.inv_bcs2dt);
+}
+
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -571,6 +579,7 @@ __device__ inline double moments_cell(const KC &kc, const GPtrs &g, const float 
   if (write_coef) {
     S[c] = Sv;
     itau[c] = inv_tau_f_of(Sv, K[c], kc);
+    if (kc.itg) kc.itg[c] = inv_tau_g_of(Sv, K[c], kc);
   }
   if (HAS_FS) dm += 0.5 * (double)kc.dt * (double)fs;
   return dm;
@@ -598,12 +607,15 @@ __device__ inline double g_sweep_cell(const KC &kc, const GPtrs &gin, const GPtr
   moment_c<DIM>(e, kc, m1);
   const float gscale = -itau[c] * kc.inv_cs2dt;      // grad P = gscale * m1
   const float gamma = -lwk_of(Sv, K[c], kc) * kc.inv_cs2dt;
-  const float conv = gamma * kc.dt * kc.w1 * kc.inv_tau_g * kc.c * gscale;  // times s * m1[a]
-  const float srcw = kc.src_g * fs;
+  // 1/tau_g and the source weight dt (1 - 1/(2 tau_g)): uniform, or per node
+  const float itg = kc.itg ? kc.itg[c] : kc.inv_tau_g;
+  const float srcg = kc.itg ? kc.dt * (1.0f - 0.5f * itg) : kc.src_g;
+  const float conv = gamma * kc.dt * kc.w1 * itg * kc.c * gscale;  // times s * m1[a]
+  const float srcw = srcg * fs;
   // rest population
   {
     const float geq = (kc.geq0_phi + ph) * Sv;
-    float o = gv[0] + (geq - gv[0]) * kc.inv_tau_g;
+    float o = gv[0] + (geq - gv[0]) * itg;
     if (HAS_FS) o += kc.w0 * srcw;
     gout.p[0][c] = o;
   }
@@ -612,7 +624,7 @@ __device__ inline double g_sweep_cell(const KC &kc, const GPtrs &gin, const GPtr
 #pragma unroll
   for (int j = 0; j < 2 * DIM; ++j) {
     const int a = dir_axis(j), s = dir_sign(j);
-    float o = gv[j + 1] + (geq - gv[j + 1]) * kc.inv_tau_g;
+    float o = gv[j + 1] + (geq - gv[j + 1]) * itg;
     if (HAS_FS) o += kc.w1 * srcw;
     o += conv * (float)s * m1[a];
     const int x = coord(q, a), n = extent(kc, a), st = stride_of(kc, a);
@@ -680,8 +692,9 @@ __device__ inline void init_cell(const KC &kc, const float *__restrict__ P0, con
   const float itf = inv_tau_f_of(S, K[c], kc);
   const float tau_f = 1.0f / itf;
   const float gamma = -lwk_of(S, K[c], kc) * kc.inv_cs2dt;
-  const float tau_g = 1.0f / kc.inv_tau_g;
-  const float wsrc = 1.0f - 0.5f * kc.inv_tau_g;
+  const float itg = kc.cap_B > 0.0f ? inv_tau_g_of(S, K[c], kc) : kc.inv_tau_g;
+  const float tau_g = 1.0f / itg;
+  const float wsrc = 1.0f - 0.5f * itg;
   Pb[c] = P;
 #pragma unroll
   for (int j = 0; j < 2 * DIM; ++j) {
@@ -704,7 +717,7 @@ __device__ inline void init_cell(const KC &kc, const float *__restrict__ P0, con
     if (neq) {
       const float cdp = (float)s * kc.c * gp[a];
       const float cds = (float)s * kc.c * gs[a];
-      v -= tau_g * kc.dt * ((G / ph - kc.w1 * wsrc) * fs + G * cds - gamma * kc.w1 * cdp * kc.inv_tau_g);
+      v -= tau_g * kc.dt * ((G / ph - kc.w1 * wsrc) * fs + G * cds - gamma * kc.w1 * cdp * itg);
     }
     g.p[j + 1][c] = v;
   }

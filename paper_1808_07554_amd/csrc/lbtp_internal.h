@@ -48,6 +48,11 @@ struct KC {
   // the face constants above
   const float *wP[6];
   const float *wS[6];
+  // saturation diffusivity D_s(x) = Ds + cap_B K lambda_n f_w (eq. 2-16 with
+  // the capillary curve P_c = cap_B (1 - S)); itg holds 1/tau_g per node
+  // when cap_B > 0 (written with the coefficients), else null
+  float Ds, cap_B, inv_bcs2dt;   // inv_bcs2dt = 1 / (beta c_s^2 dt)
+  float *itg;
 };
 
 // Device-side control block of a pressure solve and the float64 reductions.

@@ -41,6 +41,7 @@ class Params(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("coef_model", ctypes.c_int),
         ("coef", ctypes.c_double * 6),
+        ("cap_B", ctypes.c_double),
     ]
 
 
@@ -163,7 +164,7 @@ class _Arg:
 
 
 def make_params(lattice, shape, *, beta, Ds, mu_w=1.0, mu_n=1.0, bc_f, bc_g, dx=1.0, dt=1.0, m=64,
-                storage="fp32", init_neq=True, stream_ptr=None, coef=None, **_):
+                storage="fp32", init_neq=True, stream_ptr=None, coef=None, cap_B=0.0, **_):
     """lbtp_params from keyword values.  coef: None for the quadratic relative
     permeabilities with mu_w, mu_n, or ("rational", a0, a1, c0, c1, b0, b1)
     for D_p = K (a0 + a1 S)/(b0 + b1 S), lambda_w K = K (c0 + c1 S)/(b0 + b1 S)."""
@@ -184,6 +185,7 @@ def make_params(lattice, shape, *, beta, Ds, mu_w=1.0, mu_n=1.0, bc_f, bc_g, dx=
         p.bc_S[f] = float(b[1]) if len(b) > 1 else 0.0
     p.init_neq = 1 if init_neq else 0
     p.stream = stream_ptr
+    p.cap_B = float(cap_B)
     if coef is not None:
         if coef[0] != "rational" or len(coef) != 7:
             raise ValueError(f"unknown coefficient model {coef!r}")
@@ -374,7 +376,7 @@ class Solver:
     """
 
     def __init__(self, lattice, shape, *, beta, Ds, mu_w=1.0, mu_n=1.0, bc_f, bc_g, dx=1.0, dt=1.0, m=64,
-                 storage="fp32", init_neq=True, stream=None, coef=None, **_):
+                 storage="fp32", init_neq=True, stream=None, coef=None, cap_B=0.0, **_):
         self.torch = _torch()
         lib = load()
         if stream is None:
@@ -382,7 +384,7 @@ class Solver:
         self.stream = stream
         p, shape = make_params(lattice, shape, beta=beta, Ds=Ds, mu_w=mu_w, mu_n=mu_n, bc_f=bc_f, bc_g=bc_g,
                                dx=dx, dt=dt, m=m, storage=storage, init_neq=init_neq,
-                               stream_ptr=stream.cuda_stream, coef=coef)
+                               stream_ptr=stream.cuda_stream, coef=coef, cap_B=cap_B)
         self.params = p
         self.dim = 3 if p.lattice == D3Q7 else 2
         self.Q = _Q[p.lattice]

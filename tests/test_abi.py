@@ -44,7 +44,7 @@ def _params(**kw):
 @pytest.mark.parametrize("kw", [
     dict(lattice=7), dict(nx=0), dict(nz=2), dict(dx=0.0), dict(dt=-1.0), dict(beta=0.0),
     dict(Ds=0.0), dict(mu_w=0.0), dict(storage=9), dict(residual_stride=0),
-    dict(lattice=lbtp.D2Q9, nz=2),
+    dict(lattice=lbtp.D2Q9, nz=2), dict(cap_B=-1.0), dict(coef_model=5),
 ])
 def test_invalid_params_rejected_without_device(kw):
     lib = lbtp.load()
@@ -62,6 +62,14 @@ def test_d2q9_ensemble_rejected_without_device():
     h = ctypes.c_void_p()
     assert lib.lbtp_batch_init(arr, 2, ctypes.byref(h)) == lbtp.EINVAL
     assert not h.value
+
+
+def test_capillary_ensemble_rejected_without_device():
+    lib = lbtp.load()
+    arr = (lbtp.Params * 1)()
+    arr[0] = _params(cap_B=0.5)
+    h = ctypes.c_void_p()
+    assert lib.lbtp_batch_init(arr, 1, ctypes.byref(h)) == lbtp.EINVAL
 
 
 def test_inconsistent_periodicity_rejected():

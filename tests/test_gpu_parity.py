@@ -297,3 +297,30 @@ def test_phase_velocities_match_oracle(shape, lattice):
     print(lattice, shape, {k: f"{v:.2e}" for k, v in e.items()})
     for k, v in e.items():
         assert v <= TOL, (k, v)
+
+
+@pytest.mark.parametrize("shape,lattice,storage", [((72, 45), "D2Q5", "fp32"), ((70, 45), "D2Q5", "fp32"),
+                                                   ((24, 17, 13), "D3Q7", "fp32"), ((40, 30), "D2Q9", "fp32"),
+                                                   ((72, 45), "D2Q5", "fp16")])
+def test_capillary_diffusivity_replay(shape, lattice, storage):
+    """D_s(x) = Ds + B K lambda_n f_w (a tau_g field recomputed with the
+    coefficients) against the oracle, replayed."""
+    params = dict(injection_params(shape), cap_B=0.5)
+    if lattice == "D2Q9":
+        params = dict(params, lattice="D2Q9", beta=0.2)
+    o, g = _pair(params, seed=41, storage=storage)
+    s_change = 0.0
+    for n, iters in enumerate([1, 30, 100]):
+        o.update_coefficients()
+        g.update_coefficients()
+        o.pressure_solve(-1.0, iters)
+        g.pressure_solve(-1.0, iters)
+        tol = None if storage == "fp32" else reduced_tolerance(o, storage, s_change)
+        _check_fields(o, g, f"capillary {lattice} {storage} step {n}", tol=tol)
+        S_before = o.saturation()
+        o.saturation_step()
+        g.saturation_step()
+        s_change += rel_l2(S_before, o.saturation())
+    assert np.ptp(o.tau_g) > 0.05        # the field does vary
+    _check_fields(o, g, f"capillary {lattice} {storage} end",
+                  tol=None if storage == "fp32" else reduced_tolerance(o, storage, s_change))
