@@ -177,29 +177,35 @@ __device__ inline float4 q9_wall_P4(const KC &kc, int face, int x0, int k) {
   return make_float4(a[(x0 + 0) * 3 + k], a[(x0 + 1) * 3 + k], a[(x0 + 2) * 3 + k], a[(x0 + 3) * 3 + k]);
 }
 
-template <typename T, int MODE, bool HAS_FP>
-__device__ inline void q9_sweep_quad(const KC &kc, const FP<T> &fin, const FP<T> &fout,
-                                     const float *__restrict__ Pb_in, float *__restrict__ Pb_out,
-                                     const float *__restrict__ itau, const float *__restrict__ Fp, int qi,
-                                     double *acc) {
-  const int n4 = kc.ncell >> 2;
-  const bool active = qi < n4;
-  const int c = (active ? qi : n4 - 1) << 2;
-  const int lane = threadIdx.x & 63;
-  const int y = c / kc.nx;
-  const int x0 = c - y * kc.nx;
-  const float is = kc.inv_dev_scale;
-  const float4 pb = *(const float4 *)(Pb_in + c);
-  // source rows of the y-moving populations: ey = +1 pulls from row y - 1,
-  // ey = -1 from row y + 1 (wrapped across a periodic face); r_has = false
-  // means the row lies beyond a wall and the y-face rule applies
+// Source rows of the y-moving populations of the quad at (x0, y): ey = +1
+// pulls from row y - 1, ey = -1 from row y + 1 (wrapped across a periodic
+// face); *_has = false means the row lies beyond a wall (the y-face rule).
+struct Q9Rows {
+  bool lo_has, hi_has;
+  int c_lo, c_hi;   // first node of the quad in the source rows
+};
+
+__device__ inline Q9Rows q9_rows(const KC &kc, int x0, int y) {
+  Q9Rows r;
   const bool lo_in = y > 0, hi_in = y < kc.ny - 1;
-  const bool lo_has = lo_in || kc.bc_f[2] == LBTP_BC_PERIODIC;
-  const bool hi_has = hi_in || kc.bc_f[3] == LBTP_BC_PERIODIC;
-  const int c_lo = (lo_in ? y - 1 : kc.ny - 1) * kc.nx + x0;   // first node of the quad's source row
-  const int c_hi = (hi_in ? y + 1 : 0) * kc.nx + x0;
-  const float4 pb_lo = lo_has ? *(const float4 *)(Pb_in + c_lo) : pb;
-  const float4 pb_hi = hi_has ? *(const float4 *)(Pb_in + c_hi) : pb;
+  r.lo_has = lo_in || kc.bc_f[2] == LBTP_BC_PERIODIC;
+  r.hi_has = hi_in || kc.bc_f[3] == LBTP_BC_PERIODIC;
+  r.c_lo = (lo_in ? y - 1 : kc.ny - 1) * kc.nx + x0;
+  r.c_hi = (hi_in ? y + 1 : 0) * kc.nx + x0;
+  return r;
+}
+
+// The quad's update given its base pb and the bases of its source rows.
+template <typename T, int MODE, bool HAS_FP>
+__device__ inline void q9_quad_core(const KC &kc, const FP<T> &fin, const FP<T> &fout,
+                                    const float *__restrict__ Pb_in, float *__restrict__ Pb_out,
+                                    const float *__restrict__ itau, const float *__restrict__ Fp, int c, int x0,
+                                    int y, bool active, const Q9Rows &R, const float4 &pb, const float4 &pb_lo,
+                                    const float4 &pb_hi, double *acc) {
+  const int lane = threadIdx.x & 63;
+  const float is = kc.inv_dev_scale;
+  const bool lo_has = R.lo_has, hi_has = R.hi_has;
+  const int c_lo = R.c_lo, c_hi = R.c_hi;
   float4 e[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
@@ -315,6 +321,24 @@ __device__ inline void q9_sweep_quad(const KC &kc, const FP<T> &fin, const FP<T>
     for (int j = 0; j < 8; ++j) Vec4<T>::store(fout.p[j], c, o[j], kc.dev_scale);
     if (MODE >= 1) *(float4 *)(Pb_out + c) = pnew;
   }
+}
+
+template <typename T, int MODE, bool HAS_FP>
+__device__ inline void q9_sweep_quad(const KC &kc, const FP<T> &fin, const FP<T> &fout,
+                                     const float *__restrict__ Pb_in, float *__restrict__ Pb_out,
+                                     const float *__restrict__ itau, const float *__restrict__ Fp, int qi,
+                                     double *acc) {
+  const int n4 = kc.ncell >> 2;
+  const bool active = qi < n4;
+  const int c = (active ? qi : n4 - 1) << 2;
+  const int y = c / kc.nx;
+  const int x0 = c - y * kc.nx;
+  const Q9Rows R = q9_rows(kc, x0, y);
+  const float4 pb = *(const float4 *)(Pb_in + c);
+  const float4 pb_lo = R.lo_has ? *(const float4 *)(Pb_in + R.c_lo) : pb;
+  const float4 pb_hi = R.hi_has ? *(const float4 *)(Pb_in + R.c_hi) : pb;
+  q9_quad_core<T, MODE, HAS_FP>(kc, fin, fout, Pb_in, Pb_out, itau, Fp, c, x0, y, active, R, pb, pb_lo, pb_hi,
+                                acc);
 }
 
 template <typename T, int MODE, bool HAS_FP>
