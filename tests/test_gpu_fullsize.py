@@ -116,3 +116,55 @@ def test_injection_3d_512_sampled_parity():
     worst = _check_samples(params, fl, _samples((512, 512, 512), rng, 2), "fp32")
     for k, v in worst.items():
         assert v <= 1e-5, (k, v)
+
+
+def test_ensemble_256_sampled_parity():
+    """The 256-member ensemble of the ensemble benchmark (sides 128..1024), one
+    autotuned, graph-captured coupled step of 64 iterations (ensemble solves
+    run whole chunks of m = 64): sampled nodes of members of every size
+    against the oracle on crops."""
+    import torch
+    from paper_1808_07554_amd import lbtp
+    members = inputs.ensemble(256)
+    dev = torch.device("cuda", 0)
+    b = lbtp.Batch([p for p, _ in members], m=64)
+    for i, (p, fl) in enumerate(members):
+        d = {k: torch.from_numpy(inputs.f32(fl[k]).ravel()).to(dev) for k in ("K", "phi", "P0", "S0")}
+        b.set_fields(i, d["K"], d["phi"])
+        b.set_state(i, d["P0"], d["S0"])
+    b.autotune(sweeps=3)
+    kb = 64
+    its, _ = b.step(1, -1.0, kb)
+    assert (its[0] == kb).all()
+    reach = 1 + kb + 2 + 1 + 2
+    rng = np.random.default_rng(23)
+    by_size = {}
+    for i, (p, _) in enumerate(members):
+        by_size.setdefault(p["shape"][0], []).append(i)
+    worst = {"P": 0.0, "u": 0.0, "S": 0.0}
+    for n, idx in sorted(by_size.items()):
+        for i in (idx[0], idx[-1]):
+            params, fl = members[i]
+            P = b.pressure(i).cpu().numpy()
+            u = b.velocity(i).cpu().numpy()
+            S = b.saturation(i).cpu().numpy()
+            uscale = float(np.abs(u).max())
+            for pt in [(0, 0), (n - 1, n - 1), (int(rng.integers(0, n)), int(rng.integers(0, n)))]:
+                lo = [max(0, pt[a] - reach) for a in range(2)]
+                hi = [min(n, pt[a] + reach + 1) for a in range(2)]
+                sl = (slice(0, 1), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+                o = oracle_solver(_crop_params(params, lo, hi, (n, n)), m=64)
+                K, phi, P0, S0 = (inputs.f32(fl[k]) for k in ("K", "phi", "P0", "S0"))
+                o.set_fields(f32(K[sl]), f32(phi[sl]))
+                o.set_state(f32(P0[sl]), f32(S0[sl]))
+                o.step(-1.0, kb)
+                loc = (0, pt[1] - lo[1], pt[0] - lo[0])
+                gidx = (0, pt[1], pt[0])
+                worst["P"] = max(worst["P"], abs(P[gidx] - o.pressure()[loc]))
+                worst["u"] = max(worst["u"], float(np.max(np.abs(u[(slice(None),) + gidx] -
+                                                                 o.velocity()[(slice(0, 2),) + loc]))) / uscale)
+                worst["S"] = max(worst["S"], abs(S[gidx] - o.saturation()[loc]))
+    b.close()
+    print("ensemble 256", sorted(by_size), {k: f"{v:.2e}" for k, v in worst.items()})
+    for k, v in worst.items():
+        assert v <= 1e-5, (k, v)
