@@ -49,7 +49,8 @@ def test_forward_matches_reference(shape):
     assert err < 3e-2
 
 
-@pytest.mark.parametrize("shape,factor", [((2, 64, 64), 2), ((1, 128, 64), 4), ((1, 256, 256), 16)])
+@pytest.mark.parametrize("shape,factor", [((2, 64, 64), 2), ((1, 128, 64), 4), ((1, 256, 256), 16),
+                                          ((2, 1024, 1024), 16)])
 def test_coarse_grid_predict_matches_reference(shape, factor):
     N, H, W = shape
     lnK, S, _ = _data(N, H, W, 11)

@@ -324,3 +324,35 @@ def test_capillary_diffusivity_replay(shape, lattice, storage):
     assert np.ptp(o.tau_g) > 0.05        # the field does vary
     _check_fields(o, g, f"capillary {lattice} {storage} end",
                   tol=None if storage == "fp32" else reduced_tolerance(o, storage, s_change))
+
+
+def test_manufactured_1000_steps_replay():
+    """The small configuration in full: 64^2 periodic manufactured problem,
+    1000 coupled steps, the oracle solving each pressure step to r <= 1e-10
+    (m = 1) and the GPU replaying its iteration counts; fields compared every
+    250 steps."""
+    params, mp = inputs.manufactured_problem(64)
+    o = oracle_solver(params, m=1)
+    g = gpu_solver(params)
+    src0 = [f32(a) for a in mp.sources(0.0)]
+    o.set_fields(mp.K, mp.phi, *src0)
+    g.set_fields(np.full(64 * 64, mp.K), np.full(64 * 64, mp.phi), *src0)
+    P0, S0 = f32(mp.P()), f32(mp.S(0.0))
+    dP, dS = f32(mp.gradP()), f32(mp.gradS(0.0))
+    o.set_state(P0, S0, dP0=dP, dS0=dS)
+    g.set_state(P0, S0, dP0=dP[:2], dS0=dS[:2])
+    total = 0
+    for n in range(1000):
+        srcs = [f32(a) for a in mp.sources(float(n))]
+        o.set_sources(*srcs)
+        g.set_sources(*srcs)
+        o.update_coefficients()
+        g.update_coefficients()
+        k, _, _ = o.pressure_solve(1e-10, 100000)
+        kg, _, _ = g.pressure_solve(-1.0, k)
+        assert kg == k
+        total += k
+        if n % 250 == 0 or n == 999:
+            _check_fields(o, g, f"manufactured step {n} ({total} iterations so far)", periodic=True)
+        o.saturation_step()
+        g.saturation_step()
