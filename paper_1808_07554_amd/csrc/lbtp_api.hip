@@ -42,6 +42,12 @@ struct lbtp_ctx {
   hipEvent_t ev[2] = {nullptr, nullptr};
   long long step = 0;
   int have_fields = 0, have_state = 0, have_coef = 0;
+  // captured chunks of m sweeps (+ the check), by (buffer parity, base
+  // buffer, checks, F_p); kc_ver counts changes of the launch constants
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t chunk[16] = {};
+  int chunk_ver[16] = {};
+  int kc_ver = 1;
 };
 
 namespace {
@@ -279,6 +285,9 @@ void lbtp_destroy(lbtp_ctx *c) {
   if (c->ctl_ring) (void)hipHostFree(c->ctl_ring);
   for (int i = 0; i < 2; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  for (hipGraphExec_t g : c->chunk)
+    if (g) (void)hipGraphExecDestroy(g);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
 
@@ -412,6 +421,7 @@ int lbtp_set_wall_values(lbtp_ctx *c, int face, const float *P, const float *S, 
   }
   c->kc.wP[face] = c->wallP[face];
   c->kc.wS[face] = c->wallS[face];
+  c->kc_ver += 1;
   return LBTP_OK;
 }
 
@@ -435,6 +445,7 @@ int lbtp_set_state(lbtp_ctx *c, const float *P0, const float *S0, const float *d
     const int e2 = (int)floor(log2(1024.0 / (weight_move(c->p.lattice) * pmax)));
     c->kc.dev_scale = (float)ldexp(1.0, e2 < -60 ? -60 : (e2 > 60 ? 60 : e2));
     c->kc.inv_dev_scale = 1.0f / c->kc.dev_scale;
+    c->kc_ver += 1;
   }
   // stage P0 in the second base buffer, S0 in S, dP0 in scratch and dS0 in
   // the second f buffer (at least dim floats per node for every storage)
@@ -478,6 +489,68 @@ int lbtp_update_coefficients(lbtp_ctx *c) {
   return LBTP_OK;
 }
 
+namespace {
+// Launches of one full chunk: sweeps k0+1 .. k0+m of a solve (pull form), the
+// last one re-basing (and, with checks, evaluating the stopping rule).  With
+// m even the buffer parities of a chunk depend only on fs; the base buffer
+// alternates from chunk to chunk.
+hipError_t enqueue_chunk(lbtp_ctx *c, long long k0, int pb, bool checks, hipStream_t s) {
+  const int m = c->p.residual_stride;
+  for (int i = 1; i <= m; ++i) {
+    const long long k = k0 + i;
+    const int parity = (int)((c->fs + k) & 1);
+    const int mode = i < m ? 0 : (checks ? 2 : 1);
+    hipError_t e = launch_f_sweep(c->lk, c->p.storage, c->kc, fptrs(c, c->fbuf[parity]),
+                                  fptrs(c, c->fbuf[parity ^ 1]), c->Pb[pb], c->Pb[pb ^ 1], c->itau, Fp_or_null(c),
+                                  c->partials, c->ctl, k, 0, mode, s);
+    if (e == hipSuccess && mode == 2)
+      e = launch_finish_residual(c->partials, sweep_blocks(c->kc, 0, c->lk, c->p.storage), c->ctl, m, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// The executable graph of a full chunk in the current configuration,
+// captured on first use (on a private stream: the caller's may be the null
+// stream) and again after the launch constants change.  The sweeps' own
+// iteration arguments are those of the first chunk; they only guard against
+// sweeps beyond the iteration limit, which a full chunk never reaches, and
+// the check counts iterations on the device.
+hipError_t chunk_graph(lbtp_ctx *c, int pb, bool checks, hipGraphExec_t *out) {
+  const int key = (c->fs & 1) | (pb << 1) | ((checks ? 1 : 0) << 2) | ((c->has_Fp ? 1 : 0) << 3);
+  if (c->chunk[key] && c->chunk_ver[key] == c->kc_ver) {
+    *out = c->chunk[key];
+    return hipSuccess;
+  }
+  if (c->chunk[key]) {
+    (void)hipGraphExecDestroy(c->chunk[key]);
+    c->chunk[key] = nullptr;
+  }
+  hipError_t e = hipSuccess;
+  if (!c->cap_stream) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  // the fs of the first chunk of a solve: sweeps 1..m read (fs + k) & 1
+  const hipError_t el = enqueue_chunk(c, 0, pb, checks, c->cap_stream);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(c->cap_stream, &g);
+  if (el != hipSuccess || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return el != hipSuccess ? el : e;
+  }
+  e = hipGraphInstantiate(&c->chunk[key], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->chunk[key] = nullptr;
+    return e;
+  }
+  c->chunk_ver[key] = c->kc_ver;
+  *out = c->chunk[key];
+  return hipSuccess;
+}
+}  // namespace
+
 int lbtp_pressure_solve(lbtp_ctx *c, double tol, long long max_iters, long long *iters, double *resid) {
   if (!c || max_iters < 0) return LBTP_EINVAL;
   if (!c->have_coef) return LBTP_ESTATE;
@@ -502,10 +575,12 @@ int lbtp_pressure_solve(lbtp_ctx *c, double tol, long long max_iters, long long 
                                   fptrs(c, c->fbuf[parity ^ 1]), c->Pb[pb], c->Pb[pb ^ 1], c->itau,
                                   Fp_or_null(c), c->partials, c->ctl, k, local, mode, c->stream);
     if (e == hipSuccess && mode == 2)
-      e = launch_finish_residual(c->partials, sweep_blocks(c->kc, local, c->lk, c->p.storage), c->ctl, k, m, c->stream);
+      e = launch_finish_residual(c->partials, sweep_blocks(c->kc, local, c->lk, c->p.storage), c->ctl, m, c->stream);
     if (mode >= 1) pb ^= 1;
     return e;
   };
+  // full chunks run as captured graphs (m even: the parities repeat)
+  const bool graphs = m % 2 == 0 && m > 1;
   // Chunk 0 is sweep 0 (snapshot of P^0); chunk j >= 1 is sweeps
   // (j-1)m+1 .. jm and ends with the check at jm.  The first check is waited
   // for at once (warm steps usually stop there); later ones are read one
@@ -519,7 +594,15 @@ int lbtp_pressure_solve(lbtp_ctx *c, double tol, long long max_iters, long long 
   bool pending[2] = {false, false};
   for (long long j = 1; k <= last; ++j) {
     const long long kend = (j * m < last) ? j * m : last;
-    for (; k <= kend; ++k) HIP_TRY(sweep(k));
+    if (graphs && kend == j * m && k == (j - 1) * m + 1) {
+      hipGraphExec_t g = nullptr;
+      HIP_TRY(chunk_graph(c, pb, checks, &g));
+      HIP_TRY(hipGraphLaunch(g, c->stream));
+      pb ^= 1;
+      k = kend + 1;
+    } else {
+      for (; k <= kend; ++k) HIP_TRY(sweep(k));
+    }
     if (!checks || k > last) continue;
     HIP_TRY(hipMemcpyAsync(&c->ctl_ring[slot], c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipEventRecord(c->ev[slot], c->stream));
@@ -782,6 +865,7 @@ int lbtp_put_state(lbtp_ctx *c, const void *buf, long long nbytes, int on_device
   c->step = h.step;
   c->kc.dev_scale = h.dev_scale;
   c->kc.inv_dev_scale = h.inv_dev_scale;
+  c->kc_ver += 1;
   c->have_state = 1;
   c->have_coef = 0;
   return LBTP_OK;

@@ -67,6 +67,7 @@ struct Ctl {
   double mass;       // last mass reduction
   double ledger;     // accumulated boundary-link flux of g
   double last_flux;  // flux of the last saturation step
+  long long kcheck;  // iteration of the last stopping-rule check (advanced by m per check)
 };
 
 // ----------------------------------------------------------------- launchers
@@ -82,8 +83,9 @@ constexpr int kD2Q9 = 9;
 hipError_t launch_f_sweep(int dim, int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb_in,
                           float *Pb_out, const float *itau, const float *Fp, double *partials, const Ctl *ctl,
                           long long k, int local, int mode, hipStream_t s);
-hipError_t launch_finish_residual(const double *partials, int nblk, Ctl *ctl, long long k, int m,
-                                  hipStream_t s);
+// Check of the stopping rule at iteration ctl->kcheck + m (device-side
+// count, so a captured chunk serves every position in the solve).
+hipError_t launch_finish_residual(const double *partials, int nblk, Ctl *ctl, int m, hipStream_t s);
 hipError_t launch_ctl_reset(Ctl *ctl, long long kmax, double tol, hipStream_t s);
 hipError_t launch_moments(int dim, const KC &kc, GPtrs g, const float *K, const float *phi,
                           const float *Fs, float *S, float *itau, double *partials, int write_coef,

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kThreads) void f_sweep_vec_kernel(KC kc, FPtrs fin_
 
 // Stopping rule r = ||P^k - P^{k-m}|| / (m ||P^k||) from the block partials.
 __global__ __launch_bounds__(1024) void finish_residual_kernel(const double *__restrict__ partials,
-                                                               int nblk, Ctl *ctl, long long k, int m) {
+                                                               int nblk, Ctl *ctl, int m) {
   __shared__ double sa[1024], sb[1024];
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < nblk; i += 1024) {
@@ -114,7 +114,10 @@ __global__ __launch_bounds__(1024) void finish_residual_kernel(const double *__r
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    if (ctl->done || k > ctl->kmax) return;
+    if (ctl->done) return;
+    const long long k = ctl->kcheck + m;     // the iteration this check follows
+    ctl->kcheck = k;
+    if (k > ctl->kmax) return;
     const double num = sqrt(sa[0]), den = sqrt(sb[0]);
     const double r = den > 0.0 ? num / ((double)m * den) : num / (double)m;
     ctl->resid = r;
@@ -132,6 +135,7 @@ __global__ __launch_bounds__(1024) void finish_residual_kernel(const double *__r
 }
 
 __global__ void ctl_reset_kernel(Ctl *ctl, long long kmax, double tol) {
+  ctl->kcheck = 0;
   ctl->done = 0;
   ctl->status = LBTP_OK;
   ctl->K = -1;
@@ -371,8 +375,8 @@ hipError_t launch_f_sweep(int dim, int storage, const KC &kc, FPtrs fin, FPtrs f
   return hipGetLastError();
 }
 
-hipError_t launch_finish_residual(const double *partials, int nblk, Ctl *ctl, long long k, int m, hipStream_t s) {
-  hipLaunchKernelGGL(finish_residual_kernel, dim3(1), dim3(1024), 0, s, partials, nblk, ctl, k, m);
+hipError_t launch_finish_residual(const double *partials, int nblk, Ctl *ctl, int m, hipStream_t s) {
+  hipLaunchKernelGGL(finish_residual_kernel, dim3(1), dim3(1024), 0, s, partials, nblk, ctl, m);
   return hipGetLastError();
 }
 
