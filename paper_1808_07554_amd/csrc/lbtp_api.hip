@@ -504,7 +504,7 @@ hipError_t enqueue_chunk(lbtp_ctx *c, long long k0, int pb, bool checks, hipStre
                                   fptrs(c, c->fbuf[parity ^ 1]), c->Pb[pb], c->Pb[pb ^ 1], c->itau, Fp_or_null(c),
                                   c->partials, c->ctl, k, 0, mode, s);
     if (e == hipSuccess && mode == 2)
-      e = launch_finish_residual(c->partials, sweep_blocks(c->kc, 0, c->lk, c->p.storage), c->ctl, m, s);
+      e = launch_finish_residual(c->partials, sweep_blocks(c->kc, 0), c->ctl, m, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -575,7 +575,7 @@ int lbtp_pressure_solve(lbtp_ctx *c, double tol, long long max_iters, long long 
                                   fptrs(c, c->fbuf[parity ^ 1]), c->Pb[pb], c->Pb[pb ^ 1], c->itau,
                                   Fp_or_null(c), c->partials, c->ctl, k, local, mode, c->stream);
     if (e == hipSuccess && mode == 2)
-      e = launch_finish_residual(c->partials, sweep_blocks(c->kc, local, c->lk, c->p.storage), c->ctl, m, c->stream);
+      e = launch_finish_residual(c->partials, sweep_blocks(c->kc, local), c->ctl, m, c->stream);
     if (mode >= 1) pb ^= 1;
     return e;
   };

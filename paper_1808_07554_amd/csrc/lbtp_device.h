@@ -507,60 +507,6 @@ __device__ inline void sweep_quad(const KC &kc, const FP<T> &fin, const FP<T> &f
   collide_quad<DIM, T, MODE, HAS_FP>(kc, e, pb, it, fp, fout, Pb_out, c, active, acc);
 }
 
-// The same sweep with each thread walking kWalk consecutive rows (2-D: along
-// y) or planes (3-D: along z) at one quad position t of the cross-section.
-// The bases of the rows on either side of the walked row stay in registers,
-// so each base value is fetched once per sweep instead of up to three times.
-// Walk positions beyond the grid are computed on clamped indices and not
-// stored; every lane runs the same number of steps (the shuffles).
-template <int DIM, typename T, int MODE, bool HAS_FP>
-__device__ inline void sweep_quad_walk(const KC &kc, const FP<T> &fin, const FP<T> &fout,
-                                       const float *__restrict__ Pb_in, float *__restrict__ Pb_out,
-                                       const float *__restrict__ itau, const float *__restrict__ Fp, int t,
-                                       double *acc) {
-  constexpr int W = DIM - 1;                        // walked axis: y (2-D) or z (3-D)
-  const int nw = W == 1 ? kc.ny : kc.nz;
-  const int sw = W == 1 ? kc.nx : kc.nx * kc.ny;   // its stride
-  const int nline = sw >> 2;                        // quads per cross-section
-  const int ngroup = (nw + kWalk - 1) / kWalk;
-  const bool tvalid = t < nline * ngroup;
-  const int tt = tvalid ? t : nline * ngroup - 1;
-  const int p = tt % nline, g = tt / nline;
-  const int c0 = p << 2;                            // offset within the cross-section
-  const int x0 = c0 % kc.nx;
-  const int y3 = c0 / kc.nx;                        // y of the quad (3-D)
-  const int w0 = g * kWalk;
-  // rolling bases of rows w - 1, w, w + 1 (a wrapped row across a periodic face)
-  float4 pb_cur = *(const float4 *)(Pb_in + w0 * sw + c0);
-  float4 pb_prev = pb_cur, pb_next = pb_cur;
-  if (reads_lo(kc, W, w0)) pb_prev = *(const float4 *)(Pb_in + (w0 == 0 ? nw - 1 : w0 - 1) * sw + c0);
-  for (int r = 0; r < kWalk; ++r) {
-    const int w = w0 + r;
-    const bool active = tvalid && w < nw;
-    const int wl = w < nw ? w : nw - 1;
-    const int c = wl * sw + c0;
-    if (reads_hi(kc, W, wl, nw)) pb_next = *(const float4 *)(Pb_in + (wl == nw - 1 ? 0 : wl + 1) * sw + c0);
-    float4 e[2 * DIM];
-    const int yq = W == 1 ? wl : y3, zq = W == 1 ? 0 : wl;
-    pull_x_quad<T>(kc, fin, Pb_in, c, x0, yq, zq, pb_cur, e[0], e[2]);
-    if (DIM == 3) {
-      float4 pbm = pb_cur, pbp = pb_cur;
-      load_pb_axis(kc, Pb_in, c, 1, y3, kc.ny, kc.nx, pbm, pbp);
-      pull_axis_quad<T>(kc, fin, c, 1, y3, kc.ny, kc.nx, x0, zq, pb_cur, pbm, pbp, e[1], e[3]);
-    }
-    pull_axis_quad<T>(kc, fin, c, W, wl, nw, sw, x0, W == 1 ? zq : yq, pb_cur, pb_prev, pb_next,
-                      e[W == 1 ? 1 : 4], e[W == 1 ? 3 : 5]);
-    const float4 it = *(const float4 *)(itau + c);
-    float4 fp = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (HAS_FP) fp = *(const float4 *)(Fp + c);
-    collide_quad<DIM, T, MODE, HAS_FP>(kc, e, pb_cur, it, fp, fout, Pb_out, c, active, acc);
-    if (w < nw - 1) {
-      pb_prev = pb_cur;
-      pb_cur = pb_next;
-    }
-  }
-}
-
 // S^n (eq. 3-9b) and 1/tau_f (eq. 3-11a, 2-9, 2-16) at node c; returns the
 // node's mass sum_i g_i + dt F_s / 2 (= phi S) in float64.
 template <int DIM, bool HAS_FS>

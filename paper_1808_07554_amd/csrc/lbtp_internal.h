@@ -179,29 +179,10 @@ hipError_t batch_launch_sum(int n, const Member *mem, BCtl *ctl, const double *p
 
 inline int nblocks(long long n);
 
-// Rows (2-D) or planes (3-D) one thread walks in the pull-form pressure sweep
-// with four nodes per thread.
-constexpr int kWalk = 8;
-
-// Threads of that sweep: quads per cross-section times groups of kWalk rows.
-__host__ __device__ inline int walk_threads(const KC &kc, int dim) {
-  const int nw = dim == 2 ? kc.ny : kc.nz;
-  const int nline = (kc.ncell >> 2) / nw;
-  return nline * ((nw + kWalk - 1) / kWalk);
-}
-
-// Whether the pull-form sweep with four nodes per thread also walks kWalk
-// rows: measured on MI355X, it pays for 16-bit storage in 2-D (4096^2: fp16
-// 74.0 -> 69.0 us, bf16 76.1 -> 68.6 us) and costs for float storage (122 ->
-// 136 us) and in 3-D (512^3 fp32 1372 -> 1506 us, fp16 788 -> 880 us).
-// (D2Q9 does not walk: 16-bit 4096^2 went from 143 to 183 us.)
-constexpr bool walk_form(int dim, int storage) { return dim == 2 && storage != LBTP_FP32; }
-
 // Blocks of a pull-form pressure sweep (and so its residual partials): rows
 // with nx % 4 == 0 run four nodes per thread.
-inline int sweep_blocks(const KC &kc, int local, int dim, int storage) {
-  if (local || kc.nx % 4 != 0) return nblocks(kc.ncell);
-  return walk_form(dim, storage) ? nblocks(walk_threads(kc, dim)) : nblocks(kc.ncell / 4);
+inline int sweep_blocks(const KC &kc, int local) {
+  return (!local && kc.nx % 4 == 0) ? nblocks(kc.ncell / 4) : nblocks(kc.ncell);
 }
 
 inline int nblocks(long long n) { return (int)((n + kThreads - 1) / kThreads); }

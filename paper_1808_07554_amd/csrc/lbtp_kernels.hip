@@ -63,22 +63,6 @@ __global__ __launch_bounds__(kThreads) void f_sweep_kernel(KC kc, FPtrs fin_, FP
   if (MODE == 2) block_sum<2>(acc, partials);
 }
 
-// Four nodes per thread, kWalk rows (2-D) or planes (3-D) per thread.
-template <int DIM, typename T, int MODE, bool HAS_FP>
-__global__ __launch_bounds__(kThreads) void f_sweep_walk_kernel(KC kc, FPtrs fin_, FPtrs fout_,
-                                                                const float *__restrict__ Pb_in,
-                                                                float *__restrict__ Pb_out,
-                                                                const float *__restrict__ itau,
-                                                                const float *__restrict__ Fp,
-                                                                double *__restrict__ partials,
-                                                                const Ctl *__restrict__ ctl, long long k) {
-  if (ctl->done || k > ctl->kmax) return;
-  double acc[2] = {0.0, 0.0};
-  sweep_quad_walk<DIM, T, MODE, HAS_FP>(kc, typed<T>(fin_), typed<T>(fout_), Pb_in, Pb_out, itau, Fp,
-                                        blockIdx.x * kThreads + threadIdx.x, acc);
-  if (MODE == 2) block_sum<2>(acc, partials);
-}
-
 template <int DIM, typename T, int MODE, bool HAS_FP>
 __global__ __launch_bounds__(kThreads) void f_sweep_vec_kernel(KC kc, FPtrs fin_, FPtrs fout_,
                                                                const float *__restrict__ Pb_in,
@@ -332,21 +316,13 @@ static void dispatch(int dim, int storage, int local, A &&...args) {
   }
 }
 
-template <typename T>
-constexpr int storage_of() {
-  return std::is_same<T, float>::value ? LBTP_FP32 : (std::is_same<T, _Float16>::value ? LBTP_FP16_DEV : LBTP_BF16_DEV);
-}
-
 template <int DIM, typename T, bool LOCAL>
 struct SweepLaunch {
   static void run(const KC &kc, FPtrs fin, FPtrs fout, const float *Pb_in, float *Pb_out, const float *itau,
                   const float *Fp, double *partials, const Ctl *ctl, long long k, int mode, hipStream_t s) {
 #define LBTP_SWEEP(M, HF)                                                                                     \
   do {                                                                                                        \
-    if (!LOCAL && kc.nx % 4 == 0 && walk_form(DIM, storage_of<T>()))                                         \
-      hipLaunchKernelGGL((f_sweep_walk_kernel<DIM, T, M, HF>), dim3(nblocks(walk_threads(kc, DIM))),         \
-                         dim3(kThreads), 0, s, kc, fin, fout, Pb_in, Pb_out, itau, Fp, partials, ctl, k);     \
-    else if (!LOCAL && kc.nx % 4 == 0)                                                                        \
+    if (!LOCAL && kc.nx % 4 == 0)                                                                             \
       hipLaunchKernelGGL((f_sweep_vec_kernel<DIM, T, M, HF>), dim3(nblocks(kc.ncell / 4)), dim3(kThreads), 0, \
                          s, kc, fin, fout, Pb_in, Pb_out, itau, Fp, partials, ctl, k);                        \
     else                                                                                                      \

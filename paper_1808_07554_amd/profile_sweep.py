@@ -33,8 +33,9 @@ def source_digest():
 
 
 def sweep_kernel_name(storage, dim=2):
-    """The kernel of a plain pull-form pressure sweep with nx % 4 == 0."""
-    return "f_sweep_walk_kernel" if (dim == 2 and storage != "fp32") else "f_sweep_vec_kernel"
+    """The kernel of a plain pull-form pressure sweep with nx % 4 == 0 (the
+    same for every storage and dimension)."""
+    return "f_sweep_vec_kernel"
 
 
 def run(storage, n, sweeps):
@@ -90,7 +91,7 @@ def summarize(fetch_csv, write_csv, out_txt, storage, n, command):
     w_rows = _counter_rows(write_csv)
     copy_f, ncf = _per_dispatch(f_rows, "copy_probe")
     copy_w, ncw = _per_dispatch(w_rows, "copy_probe")
-    # plain sweeps of the 4-node kernel (rows walked for 16-bit storage in 2-D)
+    # plain sweeps of the 4-node kernel
     kname = sweep_kernel_name(storage)
     sw_f, nsf = _per_dispatch(f_rows, kname)
     sw_w, nsw = _per_dispatch(w_rows, kname)
