@@ -161,8 +161,24 @@ LBTP_API int lbtp_set_sources(lbtp_ctx *ctx, const float *Fp, const float *Fs, i
  * both faces takes the value of the y face).  NULL keeps the current data
  * of that lattice; the face constants of params apply until data are set.
  * The face's condition must be DIRICHLET for the lattice whose data are
- * given (LBTP_EINVAL otherwise). */
+ * given, or the face must carry per-link conditions in that lattice
+ * (lbtp_set_wall_types); LBTP_EINVAL otherwise. */
 LBTP_API int lbtp_set_wall_values(lbtp_ctx *ctx, int face, const float *P, const float *S, int on_device);
+
+/* D2Q9 only: a condition per link of a face, so that one wall can hold
+ * Dirichlet segments (wells) between no-flux stretches, as the five-spot
+ * problem of Section 4.3 needs.  f_types (pressure lattice: DIRICHLET or
+ * NOFLUX) and g_types (saturation lattice: DIRICHLET, NOFLUX or OUTFLOW)
+ * hold one lbtp_bc value per link in the layout of lbtp_set_wall_values
+ * (three per face node: normal link, then the diagonals with tangential
+ * velocity -1 and +1; at a corner the y face decides a link that crosses
+ * both faces).  A DIRICHLET link takes the per-link data of
+ * lbtp_set_wall_values if set, else the face constant of params.  NULL
+ * keeps that lattice's current list; until a list is set the face condition
+ * holds for every link.  The face must not be periodic in that lattice.
+ * LBTP_EINVAL for another lattice, a bad face or an unknown value (nothing
+ * is changed then).  Device lists are read back to the host for checking. */
+LBTP_API int lbtp_set_wall_types(lbtp_ctx *ctx, int face, const int *f_types, const int *g_types, int on_device);
 
 /* Initial populations (initialisation paragraph of Section 4):
  *   g_i = g_i^eq(S0) + eps g_i^(1) with eps g_i^(1) of eq. (gneq),

@@ -42,6 +42,9 @@ Readings where the paper is silent (each is also listed in the design notes):
     S_wb = S^n at the boundary node (a zero-gradient outlet; the paper has
     only Dirichlet and no-flux walls).
   * the D2Q9 anti-bounce-back equilibrium uses phi at the boundary node.
+  * a face may mix rules link by link (wells on a no-flux wall, the
+    five-spot problem of Section 4.3): a predicate of the cut link's
+    midpoint picks one of two rules for that link.
   * gradients of the initial fields, when not given, are second-order central
     differences (one-sided second order next to walls).
 """
@@ -88,6 +91,9 @@ class Solver:
     bc_f[face] is ("periodic",), ("abb", P_b) or ("bb",);
     bc_g[face] is ("periodic",), ("abb", S_b), ("bb",) or ("outflow",).
     A boundary value may be a number or a function of (x, y, z, t).
+    Either face rule may also be ("links", pick, rule_a, rule_b): each cut
+    link takes rule_a where pick(x, y, z, t) is true at its midpoint and
+    rule_b elsewhere (neither of them periodic).
     """
 
     def __init__(self, lattice, shape, *, beta, Ds, coef, bc_f, bc_g,
@@ -303,18 +309,26 @@ class Solver:
                 sl = [slice(None)] * 3
                 sl[axes[a]] = 0 if ei[a] > 0 else -1
                 sl = tuple(sl)
-                src = post[lat.opp[i]][sl]
-                if b[0] == "bb":
-                    v[sl] = src
-                elif b[0] in ("abb", "outflow"):
-                    v[sl] = -src + wall_value(i, b, sl, t)
-                else:
-                    raise ValueError(b)
+                v[sl] = self._wall_rule(b, i, sl, post[lat.opp[i]][sl], wall_value, t)
                 mask[sl] = True
             if mask.any():
                 flux += float(np.sum(v[mask].astype(np.float64) - post[lat.opp[i]][mask].astype(np.float64)))
             new[i] = v
         return new, flux
+
+    def _wall_rule(self, b, i, sl, src, wall_value, t):
+        """Population i arriving through a wall at cells sl (Section 4):
+        bounce-back gives the reflected post-collision population src,
+        anti-bounce-back -src plus the equilibrium term of the face value."""
+        if b[0] == "bb":
+            return src
+        if b[0] in ("abb", "outflow"):
+            return -src + wall_value(i, b, sl, t)
+        if b[0] == "links":
+            pick = np.broadcast_to(self._bvalue(b[1], i, sl, t), src.shape)
+            return np.where(pick, self._wall_rule(b[2], i, sl, src, wall_value, t),
+                            self._wall_rule(b[3], i, sl, src, wall_value, t))
+        raise ValueError(b)
 
     # ------------------------------------------------------- pressure lattice
     def _f_wall(self, i, b, sl, t):

@@ -33,6 +33,7 @@ struct lbtp_ctx {
   int has_Fp = 0, has_Fs = 0;
   float *S = nullptr, *itau = nullptr, *scratch = nullptr;
   float *wallP[6] = {}, *wallS[6] = {};   // per-link Dirichlet data (lbtp_set_wall_values)
+  int *wallTF[4] = {}, *wallTG[4] = {};     // per-link conditions, D2Q9 (lbtp_set_wall_types)
   float *itg = nullptr;                    // 1/tau_g per node (cap_B > 0)
   double *partials = nullptr;
   int nblk = 0;
@@ -279,6 +280,10 @@ void lbtp_destroy(lbtp_ctx *c) {
     if (c->wallP[f]) (void)hipFree(c->wallP[f]);
     if (c->wallS[f]) (void)hipFree(c->wallS[f]);
   }
+  for (int f = 0; f < 4; ++f) {
+    if (c->wallTF[f]) (void)hipFree(c->wallTF[f]);
+    if (c->wallTG[f]) (void)hipFree(c->wallTG[f]);
+  }
   if (c->partials) (void)hipFree(c->partials);
   if (c->ctl) (void)hipFree(c->ctl);
   if (c->ctl_host) (void)hipHostFree(c->ctl_host);
@@ -406,8 +411,10 @@ int lbtp_set_sources(lbtp_ctx *c, const float *Fp, const float *Fs, int on_devic
 
 int lbtp_set_wall_values(lbtp_ctx *c, int face, const float *P, const float *S, int on_device) {
   if (!c || face < 0 || face >= 2 * c->dim) return LBTP_EINVAL;
-  if (P && c->p.bc_f[face] != LBTP_BC_DIRICHLET) return LBTP_EINVAL;
-  if (S && c->p.bc_g[face] != LBTP_BC_DIRICHLET) return LBTP_EINVAL;
+  // Dirichlet faces, and faces whose links carry their own conditions
+  const bool mixed_f = face < 4 && c->wallTF[face], mixed_g = face < 4 && c->wallTG[face];
+  if (P && c->p.bc_f[face] != LBTP_BC_DIRICHLET && !mixed_f) return LBTP_EINVAL;
+  if (S && c->p.bc_g[face] != LBTP_BC_DIRICHLET && !mixed_g) return LBTP_EINVAL;
   const int a = face / 2;
   const long long nface = c->ncell / (a == 0 ? c->p.nx : (a == 1 ? c->p.ny : c->p.nz));
   const size_t n = (size_t)nface * (c->p.lattice == LBTP_D2Q9 ? 3 : 1);
@@ -421,6 +428,41 @@ int lbtp_set_wall_values(lbtp_ctx *c, int face, const float *P, const float *S, 
   }
   c->kc.wP[face] = c->wallP[face];
   c->kc.wS[face] = c->wallS[face];
+  c->kc_ver += 1;
+  return LBTP_OK;
+}
+
+int lbtp_set_wall_types(lbtp_ctx *c, int face, const int *f_types, const int *g_types, int on_device) {
+  if (!c || c->p.lattice != LBTP_D2Q9 || face < 0 || face >= 4) return LBTP_EINVAL;
+  if (f_types && c->p.bc_f[face] == LBTP_BC_PERIODIC) return LBTP_EINVAL;
+  if (g_types && c->p.bc_g[face] == LBTP_BC_PERIODIC) return LBTP_EINVAL;
+  const size_t n = (size_t)(face < 2 ? c->p.ny : c->p.nx) * 3;
+  int **dst[2] = {&c->wallTF[face], &c->wallTG[face]};
+  const int *src[2] = {f_types, g_types};
+  std::vector<int> h[2];
+  // validate every list before changing anything
+  for (int i = 0; i < 2; ++i) {
+    if (!src[i]) continue;
+    h[i].resize(n);
+    if (on_device) {
+      HIP_TRY(hipMemcpyAsync(h[i].data(), src[i], n * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+    } else {
+      memcpy(h[i].data(), src[i], n * sizeof(int));
+    }
+    for (int t : h[i]) {
+      const bool ok = t == LBTP_BC_DIRICHLET || t == LBTP_BC_NOFLUX || (i == 1 && t == LBTP_BC_OUTFLOW);
+      if (!ok) return LBTP_EINVAL;
+    }
+  }
+  for (int i = 0; i < 2; ++i) {
+    if (!src[i]) continue;
+    if (!*dst[i] && hipMalloc((void **)dst[i], n * sizeof(int)) != hipSuccess) return LBTP_ENOMEM;
+    HIP_TRY(hipMemcpyAsync(*dst[i], h[i].data(), n * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  c->kc.wtF[face] = c->wallTF[face];
+  c->kc.wtG[face] = c->wallTG[face];
   c->kc_ver += 1;
   return LBTP_OK;
 }

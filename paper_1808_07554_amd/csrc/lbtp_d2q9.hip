@@ -60,6 +60,14 @@ __device__ inline int q9_wall_slot(int face, int ax, int ay) {
   return t == 0 ? 0 : (t < 0 ? 1 : 2);
 }
 
+// Condition of one link of a face: the per-link list if one is set
+// (lbtp_set_wall_types), else the face's own.  along = y on the x faces, x
+// on the y faces; slot as in q9_wall_slot.
+__device__ inline int q9_link_bc(const int *bc, const int *const *wt, int face, int along, int slot) {
+  const int *t = wt[face];
+  return t ? t[along * 3 + slot] : bc[face];
+}
+
 // Pre-collision deviations e_j at node c = (x, y) against P_b(c) = pb:
 // streamed from (x - e_x, y - e_y) (eq. 3-1) and re-expressed against the
 // node's base, or the Section 4 rule of the wall the link comes through:
@@ -83,8 +91,9 @@ __device__ inline void q9_load_e(const FP<T> &fin, const float *__restrict__ Pb,
       e[j] = Storage<T>::load(fin.p[j], src, is) + w * (Pb[src] - pb);
     } else {
       const float o = Storage<T>::load(fin.p[q9opp(j)], c, is);
-      e[j] = (kc.bc_f[face] == LBTP_BC_DIRICHLET)
-                 ? (2.0f * w * (wall_P(kc, face, x, y, 0, 3, q9_wall_slot(face, ex, ey)) - pb) - o)
+      const int slot = q9_wall_slot(face, ex, ey);
+      e[j] = (q9_link_bc(kc.bc_f, kc.wtF, face, face < 2 ? y : x, slot) == LBTP_BC_DIRICHLET)
+                 ? (2.0f * w * (wall_P(kc, face, x, y, 0, 3, slot) - pb) - o)
                  : o;
     }
   }
@@ -236,9 +245,18 @@ __device__ inline void q9_quad_core(const KC &kc, const FP<T> &fin, const FP<T> 
     if (!has) {
       // the whole quad takes the y-face rule (it also wins at the corners)
       const int face = ey > 0 ? 2 : 3;
+      const int slot = q9_wall_slot(face, ex, ey);
       const float4 o = Vec4<T>::load(fin.p[q9opp(j)], c, is);
-      if (kc.bc_f[face] == LBTP_BC_DIRICHLET) {
-        const float4 pw = q9_wall_P4(kc, face, x0, q9_wall_slot(face, ex, ey));
+      if (kc.wtF[face]) {
+        // conditions link by link
+        const float4 pw = q9_wall_P4(kc, face, x0, slot);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const bool abb = kc.wtF[face][(x0 + i) * 3 + slot] == LBTP_BC_DIRICHLET;
+          f4set(e[j], i, abb ? 2.0f * w * (f4get(pw, i) - f4get(pb, i)) - f4get(o, i) : f4get(o, i));
+        }
+      } else if (kc.bc_f[face] == LBTP_BC_DIRICHLET) {
+        const float4 pw = q9_wall_P4(kc, face, x0, slot);
         e[j] = make_float4(2.0f * w * (pw.x - pb.x) - o.x, 2.0f * w * (pw.y - pb.y) - o.y,
                            2.0f * w * (pw.z - pb.z) - o.z, 2.0f * w * (pw.w - pb.w) - o.w);
       } else {
@@ -266,8 +284,9 @@ __device__ inline void q9_quad_core(const KC &kc, const FP<T> &fin, const FP<T> 
         e[j].x = Storage<T>::load(fin.p[j], s0, is) + w * (Pb_in[s0] - pb.x);
       } else {
         const float o = Storage<T>::load(fin.p[q9opp(j)], c, is);
-        e[j].x = kc.bc_f[0] == LBTP_BC_DIRICHLET
-                     ? 2.0f * w * (wall_P(kc, 0, 0, y, 0, 3, q9_wall_slot(0, ex, ey)) - pb.x) - o
+        const int slot = q9_wall_slot(0, ex, ey);
+        e[j].x = q9_link_bc(kc.bc_f, kc.wtF, 0, y, slot) == LBTP_BC_DIRICHLET
+                     ? 2.0f * w * (wall_P(kc, 0, 0, y, 0, 3, slot) - pb.x) - o
                      : o;
       }
     } else if (ex < 0 && x0 + 4 == kc.nx) {
@@ -276,8 +295,9 @@ __device__ inline void q9_quad_core(const KC &kc, const FP<T> &fin, const FP<T> 
         e[j].w = Storage<T>::load(fin.p[j], s3, is) + w * (Pb_in[s3] - pb.w);
       } else {
         const float o = Storage<T>::load(fin.p[q9opp(j)], c + 3, is);
-        e[j].w = kc.bc_f[1] == LBTP_BC_DIRICHLET
-                     ? 2.0f * w * (wall_P(kc, 1, kc.nx - 1, y, 0, 3, q9_wall_slot(1, ex, ey)) - pb.w) - o
+        const int slot = q9_wall_slot(1, ex, ey);
+        e[j].w = q9_link_bc(kc.bc_f, kc.wtF, 1, y, slot) == LBTP_BC_DIRICHLET
+                     ? 2.0f * w * (wall_P(kc, 1, kc.nx - 1, y, 0, 3, slot) - pb.w) - o
                      : o;
       }
     }
@@ -439,10 +459,11 @@ __global__ __launch_bounds__(kThreads) void q9_g_sweep_kernel(KC kc, GPtrs gin, 
       if (face < 0) {
         gout.p[j + 1][q9_wrap(y + ey, kc.ny) * kc.nx + q9_wrap(x + ex, kc.nx)] = o;
       } else {
-        const int bc = kc.bc_g[face];
+        const int slot = q9_wall_slot(face, -ex, -ey);
+        const int bc = q9_link_bc(kc.bc_g, kc.wtG, face, face < 2 ? y : x, slot);
         float r;
         if (bc == LBTP_BC_NOFLUX) r = o;
-        else if (bc == LBTP_BC_DIRICHLET) r = 2.0f * G * wall_S(kc, face, x, y, 0, 3, q9_wall_slot(face, -ex, -ey)) - o;
+        else if (bc == LBTP_BC_DIRICHLET) r = 2.0f * G * wall_S(kc, face, x, y, 0, 3, slot) - o;
         else r = 2.0f * G * Sv - o;      // outflow: S_b = S of this node
         gout.p[q9opp(j) + 1][c] = r;
         flux += (double)r - (double)o;

@@ -48,6 +48,11 @@ struct KC {
   // the face constants above
   const float *wP[6];
   const float *wS[6];
+  // D2Q9: condition per link of a face (lbtp_set_wall_types; three per face
+  // node, the layout of the wall data), or null where the face condition
+  // above holds for every link
+  const int *wtF[4];
+  const int *wtG[4];
   // saturation diffusivity D_s(x) = Ds + cap_B K lambda_n f_w (eq. 2-16 with
   // the capillary curve P_c = cap_B (1 - S)); itg holds 1/tau_g per node
   // when cap_B > 0 (written with the coefficients), else null

@@ -18,6 +18,9 @@ Workloads (lattice units, dx = dt = 1 unless stated):
     relative permeabilities, pressure 1 and saturation 1 imposed on the x = 0
     face, pressure 0 and a zero-gradient saturation outlet on the x = L face,
     no flux on the other faces, S0 = 0, P0 the linear ramp.
+  * ``five_spot``: the quarter five-spot of Section 4.3 (Table 1 values) on
+    the unit square, D2Q9; injection and production wells as short
+    Dirichlet segments of the walls at opposite corners (see five_spot).
 """
 import math
 
@@ -196,3 +199,50 @@ def ensemble(n_members=256, seed0=5000, sizes=(128, 256, 512, 1024), sigma_range
         sigma = float(rng.uniform(*sigma_range))
         out.append(injection_problem((n, n), sigma, ell, 2 * (seed0 + j), 2 * (seed0 + j) + 1))
     return out
+
+
+# ----------------------------------------------------------------------------
+# Five-spot problem (Section 4.3)
+# ----------------------------------------------------------------------------
+FIVE_SPOT_WELL = 0.12
+
+
+def five_spot(N=96, well=FIVE_SPOT_WELL, P_inj=1.0, P_prod=0.0, beta=1.0, tau_g=1.0):
+    """Inputs of the quarter five-spot problem of Section 4.3.
+
+    Table 1: phi = 1, mu_w = mu_n = 1e-3, K = 1e-5, D_s = 1e-2, quadratic
+    relative permeabilities, on [0, 1]^2.  The figure with the well layout is
+    not available, so the layout here is the usual quarter pattern: the
+    injector at corner (0, 0), the producer at (1, 1), each a Dirichlet
+    segment of the two walls meeting at its corner: every link whose
+    midpoint lies within `well` of the corner along the wall (0.12, so
+    that no midpoint falls on a segment end at N = 32, 64, 96 and each
+    segment is 1/8 long there).  Injector: P = P_inj and S_w = 1; producer:
+    P = P_prod and a zero-gradient saturation outlet; no flux elsewhere.
+    S0 = 0, P0 = P_inj + (P_prod - P_inj)(x + y)/2.  Lattice: N x N nodes,
+    dx = 1/N, and c = 3 D_s / (beta (tau_g - 1/2) dx) so that the saturation
+    relaxation time is tau_g at every N (diffusive scaling, dt ~ dx^2).
+    Returns (params dict, fields dict) with float64 arrays laid out [z][y][x].
+    """
+    K0, phi0, mu, Ds = 1e-5, 1.0, 1e-3, 1e-2
+    dx = 1.0 / N
+    c = 3.0 * Ds / (beta * (tau_g - 0.5) * dx)
+    dt = dx / c
+
+    def inj(x, y, z, t):
+        return (x < well) & (y < well)
+
+    def prod(x, y, z, t):
+        return (x > 1.0 - well) & (y > 1.0 - well)
+
+    # faces -x, +x, -y, +y
+    bc_f = [("links", inj, ("abb", P_inj), ("bb",)), ("links", prod, ("abb", P_prod), ("bb",))] * 2
+    bc_g = [("links", inj, ("abb", 1.0), ("bb",)), ("links", prod, ("outflow",), ("bb",)),
+            ("links", inj, ("abb", 1.0), ("bb",)), ("links", prod, ("outflow",), ("bb",))]
+    x = (np.arange(N) + 0.5) * dx
+    X, Y = np.meshgrid(x, x)
+    params = dict(lattice="D2Q9", shape=(N, N, 1), dx=dx, dt=dt, beta=beta, Ds=Ds, mu_w=mu, mu_n=mu,
+                  bc_f=bc_f, bc_g=bc_g)
+    fields = dict(K=np.full((1, N, N), K0), phi=np.full((1, N, N), phi0),
+                  P0=(P_inj + (P_prod - P_inj) * (X + Y) / 2).reshape(1, N, N), S0=np.zeros((1, N, N)))
+    return params, fields

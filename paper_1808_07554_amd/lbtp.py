@@ -55,6 +55,8 @@ EXPORTS = {
     "lbtp_phase_velocities": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "lbtp_set_wall_values": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_int]),
+    "lbtp_set_wall_types": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_int]),
     "lbtp_set_state": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4 + [ctypes.c_int]),
     "lbtp_update_coefficients": (ctypes.c_int, [ctypes.c_void_p]),
     "lbtp_pressure_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_longlong,
@@ -163,6 +165,47 @@ class _Arg:
             self.ptr, self.dev, self.keep = h.ctypes.data, 0, h
 
 
+def _face_constant(b, lattice):
+    """(condition, value) of a face rule for lbtp_params.  A mixed face
+    ("links", pick, rule_a, rule_b) takes the condition and value of its
+    rule that is not bounce-back; its links get their own conditions from
+    link_types after lbtp_init."""
+    if b[0] != "links":
+        return _BC[b[0]], (float(b[1]) if len(b) > 1 else 0.0)
+    if lattice != "D2Q9":
+        raise ValueError("per-link conditions need D2Q9")
+    rules = [r for r in (b[2], b[3]) if r[0] != "bb"]
+    if len(rules) > 1 and tuple(rules[0]) != tuple(rules[1]):
+        raise ValueError("a mixed face holds one condition besides bounce-back")
+    return _face_constant(rules[0] if rules else b[2], lattice)
+
+
+def link_types(shape, dx, face, rule, periodic_axes=()):
+    """Per-link conditions of a D2Q9 face (the lbtp_set_wall_types layout)
+    from a ("links", pick, rule_a, rule_b) rule: pick(x, y, z, t) is taken at
+    the midpoint of each link, node - c_i dt / 2, with nodes at (j + 1/2) dx
+    on walled axes and j dx on periodic ones."""
+    _, pick, ra, rb = rule
+    nx, ny = shape[0], shape[1]
+    off = [0.0 if a in periodic_axes else 0.5 for a in range(2)]
+    n_along = ny if face < 2 else nx
+    along = (np.arange(n_along) + off[1 if face < 2 else 0]) * dx
+    inward = (1, -1, 1, -1)[face]
+    X = np.empty((n_along, 3))
+    Y = np.empty((n_along, 3))
+    for k, t in enumerate((0, -1, 1)):           # slots: normal, tangential -1, +1
+        if face < 2:
+            ex, ey = inward, t
+            X[:, k] = (off[0] if face == 0 else nx - 1 + off[0]) * dx - 0.5 * ex * dx
+            Y[:, k] = along - 0.5 * ey * dx
+        else:
+            ex, ey = t, inward
+            X[:, k] = along - 0.5 * ex * dx
+            Y[:, k] = (off[1] if face == 2 else ny - 1 + off[1]) * dx - 0.5 * ey * dx
+    sel = np.broadcast_to(np.asarray(pick(X, Y, np.zeros_like(X), 0.0), dtype=bool), X.shape)
+    return np.where(sel, _BC[ra[0]], _BC[rb[0]]).astype(np.int32).ravel()
+
+
 def make_params(lattice, shape, *, beta, Ds, mu_w=1.0, mu_n=1.0, bc_f, bc_g, dx=1.0, dt=1.0, m=64,
                 storage="fp32", init_neq=True, stream_ptr=None, coef=None, cap_B=0.0, **_):
     """lbtp_params from keyword values.  coef: None for the quadratic relative
@@ -178,11 +221,9 @@ def make_params(lattice, shape, *, beta, Ds, mu_w=1.0, mu_n=1.0, bc_f, bc_g, dx=
     p.storage = _STORAGE[storage] if isinstance(storage, str) else storage
     p.residual_stride = m
     for f, b in enumerate(bc_f):
-        p.bc_f[f] = _BC[b[0]]
-        p.bc_P[f] = float(b[1]) if len(b) > 1 else 0.0
+        p.bc_f[f], p.bc_P[f] = _face_constant(b, lattice)
     for f, b in enumerate(bc_g):
-        p.bc_g[f] = _BC[b[0]]
-        p.bc_S[f] = float(b[1]) if len(b) > 1 else 0.0
+        p.bc_g[f], p.bc_S[f] = _face_constant(b, lattice)
     p.init_neq = 1 if init_neq else 0
     p.stream = stream_ptr
     p.cap_B = float(cap_B)
@@ -372,7 +413,10 @@ class Solver:
     """One realisation on the GPU.  Same calls as the C ABI.
 
     bc_f / bc_g: per face (-x, +x, -y, +y[, -z, +z]) a tuple ("periodic",),
-    ("abb", value), ("bb",) or ("outflow",).
+    ("abb", value), ("bb",) or ("outflow",); on D2Q9 also
+    ("links", pick, rule_a, rule_b), a face whose links take rule_a where
+    pick(x, y, z, t) holds at the link midpoint and rule_b elsewhere (one of
+    the two bounce-back), passed to lbtp_set_wall_types.
     """
 
     def __init__(self, lattice, shape, *, beta, Ds, mu_w=1.0, mu_n=1.0, bc_f, bc_g, dx=1.0, dt=1.0, m=64,
@@ -394,6 +438,12 @@ class Solver:
         _check(lib.lbtp_init(ctypes.byref(p), ctypes.byref(h)), "lbtp_init")
         self._h = h
         self._lib = lib
+        periodic = tuple(a for a in range(self.dim) if bc_f[2 * a][0] == "periodic")
+        for face in range(len(bc_f)):
+            tf, tg = (link_types(shape, dx, face, b[face], periodic) if b[face][0] == "links" else None
+                      for b in (bc_f, bc_g))
+            if tf is not None or tg is not None:
+                self.set_wall_types(face, tf, tg)
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
@@ -439,6 +489,22 @@ class Solver:
         a, b = self._arg(P, n), self._arg(S, n)
         _check(self._lib.lbtp_set_wall_values(self._h, int(face), a.ptr, b.ptr, self._both(a, b)),
                "lbtp_set_wall_values")
+
+    def set_wall_types(self, face, f=None, g=None):
+        """Per-link conditions of one D2Q9 face (lbtp_set_wall_types): int
+        arrays of lbtp_bc values, three per face node, or None to keep."""
+        n = 3 * (self.shape[1] if face < 2 else self.shape[0])
+        arrs = []
+        for a in (f, g):
+            if a is None:
+                arrs.append(None)
+                continue
+            a = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+            if a.size != n:
+                raise ValueError(f"expected {n} values, got {a.size}")
+            arrs.append(a)
+        ptrs = [None if a is None else a.ctypes.data for a in arrs]
+        _check(self._lib.lbtp_set_wall_types(self._h, int(face), ptrs[0], ptrs[1], 0), "lbtp_set_wall_types")
 
     def set_state(self, P0, S0, dP0=None, dS0=None):
         a = [self._arg(P0), self._arg(S0), self._arg(dP0, self.dim * self.ncell),

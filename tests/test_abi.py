@@ -93,3 +93,18 @@ def test_null_handles_rejected():
     assert lib.lbtp_init(None, None) == lbtp.EINVAL
     lib.lbtp_destroy(None)
     assert lib.lbtp_strerror(lbtp.EUNSTABLE).startswith(b"unstable")
+    assert lib.lbtp_set_wall_types(None, 0, None, None, 0) == lbtp.EINVAL
+
+
+def test_mixed_face_rules_map_to_params():
+    """A ("links", ...) face sets the face constant of its non-bounce-back
+    rule; D2Q5 refuses per-link conditions."""
+    from paper_1808_07554_amd import inputs
+    p, _ = inputs.five_spot(16)
+    prm, _ = lbtp.make_params(p["lattice"], p["shape"], beta=p["beta"], Ds=p["Ds"], bc_f=p["bc_f"],
+                              bc_g=p["bc_g"], dx=p["dx"], dt=p["dt"])
+    assert list(prm.bc_f)[:4] == [lbtp.BC_DIRICHLET] * 4
+    assert list(prm.bc_P)[:4] == [1.0, 0.0, 1.0, 0.0]
+    assert list(prm.bc_g)[:4] == [lbtp.BC_DIRICHLET, lbtp.BC_OUTFLOW, lbtp.BC_DIRICHLET, lbtp.BC_OUTFLOW]
+    with pytest.raises(ValueError):
+        lbtp.make_params("D2Q5", p["shape"], beta=0.1, Ds=p["Ds"], bc_f=p["bc_f"], bc_g=p["bc_g"])
