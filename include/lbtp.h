@@ -120,10 +120,16 @@ typedef struct lbtp_params {
                                   cap_B K lambda_n f_w to Ds (eq. 2-16), so D_s and tau_g
                                   vary with S and K from node to node; 0 = constant Ds.
                                   Single contexts only (ensembles: LBTP_EINVAL). */
+  int sweep_block;             /* plain pressure sweeps fused into one launch inside the
+                                  captured chunks of m sweeps (temporal blocking through
+                                  LDS; D2Q5 only, float32 results bitwise unchanged):
+                                  0 = library default (7 on D2Q5, none elsewhere),
+                                  1 = one sweep per launch, or an odd number 3..23 (D2Q5) */
 } lbtp_params;
 
 /* Fill *p with defaults: D2Q5, 1x1x1, dx = dt = 1, beta = 1, Ds = 0, mu = 1,
- * FP32, m = 64, periodic faces, init_neq = 1, null stream, QUADRATIC_KR. */
+ * FP32, m = 64, periodic faces, init_neq = 1, null stream, QUADRATIC_KR,
+ * sweep_block = 0. */
 LBTP_API void lbtp_default_params(lbtp_params *p);
 
 /* Validate *p (tau_g > 1/2, beta >= 0, periodicity consistent, sizes > 0,

@@ -49,6 +49,7 @@ struct lbtp_ctx {
   hipGraphExec_t chunk[16] = {};
   int chunk_ver[16] = {};
   int kc_ver = 1;
+  int sweep_block = 0;      // plain sweeps per launch inside chunks (0 or 1: one)
 };
 
 namespace {
@@ -95,6 +96,8 @@ int validate(const lbtp_params *p) {
   if (p->coef_model != LBTP_COEF_QUADRATIC_KR && p->coef_model != LBTP_COEF_RATIONAL) return LBTP_EINVAL;
   if (!(p->cap_B >= 0.0) || !isfinite(p->cap_B)) return LBTP_EINVAL;
   if (p->coef_model == LBTP_COEF_QUADRATIC_KR && (!(p->mu_w > 0) || !(p->mu_n > 0))) return LBTP_EINVAL;
+  if (p->sweep_block < 0 || (p->sweep_block > 1 && (p->sweep_block % 2 == 0 || p->lattice != LBTP_D2Q5)))
+    return LBTP_EINVAL;
   if (p->coef_model == LBTP_COEF_RATIONAL) {
     for (int i = 0; i < 6; ++i)
       if (!isfinite(p->coef[i])) return LBTP_EINVAL;
@@ -311,6 +314,16 @@ int lbtp_init(const lbtp_params *p, lbtp_ctx **out) {
   c->stream = (hipStream_t)p->stream;
   c->nblk = nblocks(c->ncell);
   fill_kc(c);
+  {
+    const int H = p->sweep_block == 0 ? (p->lattice == LBTP_D2Q5 ? 7 : 1) : p->sweep_block;
+    if (H > 1) {
+      if (!block_sweeps_supported(c->dim, c->kc, H)) {
+        delete c;
+        return LBTP_EINVAL;
+      }
+      c->sweep_block = H;
+    }
+  }
   const size_t n = (size_t)c->ncell;
   const size_t fbytes = n * c->nf * storage_bytes(p->storage);
   struct {
@@ -538,7 +551,19 @@ namespace {
 // alternates from chunk to chunk.
 hipError_t enqueue_chunk(lbtp_ctx *c, long long k0, int pb, bool checks, hipStream_t s) {
   const int m = c->p.residual_stride;
-  for (int i = 1; i <= m; ++i) {
+  int i = 1;
+  // plain sweeps in blocks of H (H odd: a block ends in the buffer where H
+  // single sweeps would), the rest one by one
+  const int H = c->sweep_block;
+  for (; H > 1 && i + H - 1 <= m - 1; i += H) {
+    const long long k = k0 + i;
+    const int parity = (int)((c->fs + k) & 1);
+    const hipError_t e = launch_f_block(c->p.storage, c->kc, fptrs(c, c->fbuf[parity]),
+                                        fptrs(c, c->fbuf[parity ^ 1]), c->Pb[pb], c->itau, Fp_or_null(c), c->ctl,
+                                        k, H, s);
+    if (e != hipSuccess) return e;
+  }
+  for (; i <= m; ++i) {
     const long long k = k0 + i;
     const int parity = (int)((c->fs + k) & 1);
     const int mode = i < m ? 0 : (checks ? 2 : 1);

@@ -42,6 +42,7 @@ class Params(ctypes.Structure):
         ("coef_model", ctypes.c_int),
         ("coef", ctypes.c_double * 6),
         ("cap_B", ctypes.c_double),
+        ("sweep_block", ctypes.c_int),
     ]
 
 
@@ -207,7 +208,7 @@ def link_types(shape, dx, face, rule, periodic_axes=()):
 
 
 def make_params(lattice, shape, *, beta, Ds, mu_w=1.0, mu_n=1.0, bc_f, bc_g, dx=1.0, dt=1.0, m=64,
-                storage="fp32", init_neq=True, stream_ptr=None, coef=None, cap_B=0.0, **_):
+                storage="fp32", init_neq=True, stream_ptr=None, coef=None, cap_B=0.0, sweep_block=0, **_):
     """lbtp_params from keyword values.  coef: None for the quadratic relative
     permeabilities with mu_w, mu_n, or ("rational", a0, a1, c0, c1, b0, b1)
     for D_p = K (a0 + a1 S)/(b0 + b1 S), lambda_w K = K (c0 + c1 S)/(b0 + b1 S)."""
@@ -227,6 +228,7 @@ def make_params(lattice, shape, *, beta, Ds, mu_w=1.0, mu_n=1.0, bc_f, bc_g, dx=
     p.init_neq = 1 if init_neq else 0
     p.stream = stream_ptr
     p.cap_B = float(cap_B)
+    p.sweep_block = int(sweep_block)
     if coef is not None:
         if coef[0] != "rational" or len(coef) != 7:
             raise ValueError(f"unknown coefficient model {coef!r}")
@@ -420,7 +422,7 @@ class Solver:
     """
 
     def __init__(self, lattice, shape, *, beta, Ds, mu_w=1.0, mu_n=1.0, bc_f, bc_g, dx=1.0, dt=1.0, m=64,
-                 storage="fp32", init_neq=True, stream=None, coef=None, cap_B=0.0, **_):
+                 storage="fp32", init_neq=True, stream=None, coef=None, cap_B=0.0, sweep_block=0, **_):
         self.torch = _torch()
         lib = load()
         if stream is None:
@@ -428,7 +430,7 @@ class Solver:
         self.stream = stream
         p, shape = make_params(lattice, shape, beta=beta, Ds=Ds, mu_w=mu_w, mu_n=mu_n, bc_f=bc_f, bc_g=bc_g,
                                dx=dx, dt=dt, m=m, storage=storage, init_neq=init_neq,
-                               stream_ptr=stream.cuda_stream, coef=coef, cap_B=cap_B)
+                               stream_ptr=stream.cuda_stream, coef=coef, cap_B=cap_B, sweep_block=sweep_block)
         self.params = p
         self.dim = 3 if p.lattice == D3Q7 else 2
         self.Q = _Q[p.lattice]

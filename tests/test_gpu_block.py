@@ -1,0 +1,89 @@
+"""Temporal blocking of the plain pressure sweeps (several sweeps per launch
+through LDS, D2Q5) against one sweep per launch, through the C ABI.
+
+With float32 storage the blocked launches perform the same arithmetic in the
+same order, so populations, pressure and saturation must agree bitwise: on
+walled, periodic and mixed boxes, boxes narrower than a tile or than the
+halo, ragged tile counts, per-link Dirichlet data, a pressure source and
+every block length.  16-bit storage rounds to its format once per launch
+instead of once per sweep, so there the blocked path must stay within the
+format's bound of the one-sweep path.  The oracle parity of the blocked path
+itself is covered by every other D2Q5 test, which runs it by default."""
+import numpy as np
+import pytest
+
+from paper_1808_07554_amd import inputs
+from tests.lbhelp import f32, gpu_solver, mean_free, smooth_state
+from tests.test_gpu_parity import UNIT_ROUNDOFF
+
+pytestmark = pytest.mark.gpu
+
+WALLS = ([("abb", 1.0), ("abb", 0.0), ("bb",), ("bb",)], [("abb", 1.0), ("outflow",), ("bb",), ("bb",)])
+PERIODIC = ([("periodic",)] * 4, [("periodic",)] * 4)
+MIXED = ([("periodic",), ("periodic",), ("abb", 0.7), ("abb", 0.2)],
+         [("periodic",), ("periodic",), ("abb", 0.9), ("bb",)])
+
+
+def _run(shape, bcs, sweep_block, storage="fp32", Fp=False, wall_face=None, iters=(200, 130)):
+    nx, ny = shape
+    params, _ = inputs.injection_problem(shape, 1.0, 4.0, 11, 12)
+    params = dict(params, bc_f=bcs[0], bc_g=bcs[1])
+    fshape = (1, ny, nx)
+    K = f32(np.exp(inputs.gaussian_random_field((ny, nx), 4.0, nx + ny)).reshape(fshape) * params["mu_n"] / 6)
+    phi = f32(inputs.uniform_field(fshape, 0.15, 0.3, 7))
+    P0, S0 = (f32(a) for a in smooth_state(fshape, 5))
+    fp = f32(mean_free(np.sin(np.arange(nx * ny) * 0.37)) * 1e-3).reshape(fshape) if Fp else None
+    g = gpu_solver(params, m=64, storage=storage, sweep_block=sweep_block)
+    g.set_fields(K, phi, Fp=fp)
+    g.set_state(P0, S0)
+    if wall_face is not None:
+        n_along = ny if wall_face < 2 else nx
+        g.set_wall_values(wall_face, P=f32(1.0 + 0.1 * np.cos(np.arange(n_along) * 0.2)))
+    for n, k in enumerate(iters):
+        g.update_coefficients()
+        assert g.pressure_solve(-1.0, k)[0] == k
+        if n + 1 < len(iters):
+            g.saturation_step()
+    f, gg = g.populations()
+    out = dict(f=f.cpu().numpy(), g=gg.cpu().numpy(), P=g.pressure().cpu().numpy(), S=g.saturation().cpu().numpy())
+    g.close()
+    return out
+
+
+CASES = [
+    ((200, 150), WALLS, {}),
+    ((64, 64), PERIODIC, dict(Fp=True)),
+    ((20, 12), PERIODIC, dict(Fp=True)),         # narrower than the halo: the region wraps several times
+    ((130, 70), MIXED, {}),
+    ((96, 47), WALLS, dict(wall_face=0)),
+    ((90, 40), MIXED, dict(wall_face=2)),         # per-link data along a periodic axis
+    ((300, 7), WALLS, {}),
+    ((7, 300), MIXED, {}),
+]
+
+
+@pytest.mark.parametrize("shape,bcs,kw", CASES)
+def test_blocked_sweeps_bitwise_equal_single_sweeps(shape, bcs, kw):
+    ref = _run(shape, bcs, 1, **kw)
+    got = _run(shape, bcs, 9, **kw)
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), (shape, k, float(np.abs(ref[k] - got[k]).max()))
+
+
+@pytest.mark.parametrize("H", [3, 5, 7, 21, 23])
+def test_every_block_length_bitwise(H):
+    ref = _run((150, 110), WALLS, 1)
+    got = _run((150, 110), WALLS, H)
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), (H, k)
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_blocked_16bit_within_format_bound(storage):
+    ref = _run((200, 150), WALLS, 1, storage=storage)
+    got = _run((200, 150), WALLS, 9, storage=storage)
+    ur = UNIT_ROUNDOFF[storage]
+    for k in ("P", "S"):
+        err = float(np.abs(ref[k] - got[k]).max())
+        print(storage, k, f"{err:.2e}")
+        assert err <= 16 * ur, (storage, k, err)
