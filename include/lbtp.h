@@ -123,7 +123,7 @@ typedef struct lbtp_params {
   int sweep_block;             /* plain pressure sweeps fused into one launch inside the
                                   captured chunks of m sweeps (temporal blocking through
                                   LDS; D2Q5 only, float32 results bitwise unchanged):
-                                  0 = library default (7 on D2Q5, none elsewhere),
+                                  0 = library default (9 on D2Q5, none elsewhere),
                                   1 = one sweep per launch, or an odd number 3..23 (D2Q5) */
 } lbtp_params;
 

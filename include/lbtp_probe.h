@@ -21,6 +21,16 @@ extern "C" {
 
 LBTP_API int lbtp_copy_probe(void *dst, const void *src, long long bytes, void *stream);
 
+/* Timing aid for the dominant kernel: enqueue `launches` launches of the
+ * plain pressure sweep on the context's stream, each running sweep_block
+ * sweeps (eq. 3-1; one when blocking is off), continuing the current
+ * pressure state without re-basing or evaluating the stopping rule, so the
+ * launches can be timed back to back.  The state afterwards is that of
+ * launches x sweep_block more plain sweeps.  Needs a pressure solve since the
+ * last lbtp_set_state / lbtp_put_state (LBTP_ESTATE otherwise), launches >= 0
+ * (LBTP_EINVAL otherwise).  Returns the sweeps per launch (> 0) or an error. */
+LBTP_API int lbtp_probe_sweeps(lbtp_ctx *ctx, long long launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -315,7 +315,7 @@ int lbtp_init(const lbtp_params *p, lbtp_ctx **out) {
   c->nblk = nblocks(c->ncell);
   fill_kc(c);
   {
-    const int H = p->sweep_block == 0 ? (p->lattice == LBTP_D2Q5 ? 7 : 1) : p->sweep_block;
+    const int H = p->sweep_block == 0 ? (p->lattice == LBTP_D2Q5 ? 9 : 1) : p->sweep_block;
     if (H > 1) {
       if (!block_sweeps_supported(c->dim, c->kc, H)) {
         delete c;
@@ -711,6 +711,27 @@ int lbtp_pressure_solve(lbtp_ctx *c, double tol, long long max_iters, long long 
   if (resid) *resid = h.resid;
   if (!checks && status == LBTP_OK && max_iters > 0) status = LBTP_NOT_CONVERGED;
   return status;
+}
+
+int lbtp_probe_sweeps(lbtp_ctx *c, long long launches) {
+  if (!c || launches < 0) return LBTP_EINVAL;
+  if (!c->have_coef || c->f_local) return LBTP_ESTATE;
+  const int H = c->sweep_block > 1 ? c->sweep_block : 1;
+  // no stopping rule: clear a finished solve's flag so the sweeps run
+  HIP_TRY(launch_ctl_reset(c->ctl, 1LL << 62, -1.0, c->stream));
+  for (long long i = 0; i < launches; ++i) {
+    const int parity = c->fs & 1;
+    if (H > 1) {
+      HIP_TRY(launch_f_block(c->p.storage, c->kc, fptrs(c, c->fbuf[parity]), fptrs(c, c->fbuf[parity ^ 1]),
+                             c->Pb[c->pbs], c->itau, Fp_or_null(c), c->ctl, 1, H, c->stream));
+    } else {
+      HIP_TRY(launch_f_sweep(c->lk, c->p.storage, c->kc, fptrs(c, c->fbuf[parity]), fptrs(c, c->fbuf[parity ^ 1]),
+                             c->Pb[c->pbs], c->Pb[c->pbs ^ 1], c->itau, Fp_or_null(c), c->partials, c->ctl, 1, 0, 0,
+                             c->stream));
+    }
+    c->fs ^= 1;       // H is odd: every launch leaves the state in the other buffer
+  }
+  return H;
 }
 
 int lbtp_saturation_step(lbtp_ctx *c) {

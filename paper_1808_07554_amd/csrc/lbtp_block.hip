@@ -3,13 +3,16 @@
 // The pressure lattice is iterated many times per coupled step (eq. 3-1
 // "iterated to a steady state", Section 3), and a plain sweep (one that
 // neither re-bases nor evaluates the stopping rule) only needs the previous
-// state within one link.  So one launch here runs H consecutive plain sweeps:
-// each workgroup loads a square region of kBR x kBR nodes (its tile of
-// kBR - 2H nodes per side plus a halo of H) into LDS, sweeps it H times
-// between two LDS copies, and writes back only the tile, whose nodes lie at least H links
-// from any cut edge of the region and so never see the stale halo.  Walls
-// and periodic faces are handled where the region meets them, with the same
-// rules as the one-sweep kernels.
+// state within one link.  So one launch here runs H consecutive plain sweeps
+// over a region of 64 columns x (W * RW) rows held in registers: each lane
+// of a wavefront owns one column, each wavefront RW consecutive rows.  The
+// x-streamed populations move between adjacent lanes (lane shuffles), the
+// y-streamed ones between the rows of a lane's registers, and across
+// wavefronts through a small LDS exchange (one barrier per sweep).  Only the
+// tile, the nodes at least H links from any cut edge of the region, is
+// written back; the halo around it is recomputed by the neighbouring
+// workgroups.  Walls and periodic faces are handled where the region meets
+// them, with the same rules as the one-sweep kernels.
 //
 // Arithmetic and its order are those of sweep_cell (lbtp_device.h) for a
 // plain sweep, so float32 storage gives bitwise the same populations as H
@@ -26,148 +29,176 @@
 namespace lbtp {
 namespace {
 
-constexpr int kBR = 64;                          // region side (tile + 2 H)
-constexpr int kBN = kBR * kBR;                   // region nodes
-constexpr int kBT = 1024;                        // threads per workgroup
-constexpr int kBPer = kBN / kBT;                 // region nodes per thread
-static_assert(kBN % kBT == 0, "whole region rows per pass");
+
+constexpr int kBX = 64;        // region columns: one per lane
+constexpr int kBWmax = 16;     // most wavefronts per workgroup
+// The launch shape in use: 8 wavefronts of 8 rows (a 64 x 64 region), so
+// that two workgroups fit a compute unit and one loads while the other
+// sweeps (measured on the 4096^2 injection problem against 16 x 6, 16 x 8,
+// 8 x 6 and 8 x 10).
+constexpr int kUseW = 8, kUseRW = 8;
 
 __device__ inline int wrap_mod(int v, int n) {
   const int r = v % n;
   return r < 0 ? r + n : r;
 }
 
-template <typename T, bool HAS_FP>
-__global__ __launch_bounds__(kBT) void f_block_kernel(KC kc, FPtrs fin_, FPtrs fout_, const float *__restrict__ Pb,
-                                                      const float *__restrict__ itau, const float *__restrict__ Fp,
-                                                      const Ctl *__restrict__ ctl, long long k, int H,
-                                                      int tiles_x) {
-  if (ctl->done || k > ctl->kmax) return;
-  // deviations d_j of the region (against the base of their node), two
-  // copies: sweep s reads copy (s - 1) & 1 and writes the other
-  __shared__ float sd[2][4][kBN];
-  __shared__ float sp[kBN];       // base pressure P_b of the region
-  __shared__ float st[kBN];       // 1 / tau_f of the region
-  const FP<T> fin = typed<T>(fin_), fout = typed<T>(fout_);
-  const float is = kc.inv_dev_scale;
-  const int tile = kBR - 2 * H;
-  const int gx0 = (int)(blockIdx.x % tiles_x) * tile - H;   // global coordinates of region node (0, 0)
-  const int gy0 = (int)(blockIdx.x / tiles_x) * tile - H;
-  const bool perx = kc.bc_f[0] == LBTP_BC_PERIODIC, pery = kc.bc_f[2] == LBTP_BC_PERIODIC;
-  // region nodes inside the domain: [lo, hi) per axis (all of them on a periodic axis)
-  const int xlo = perx ? 0 : max(0, -gx0), xhi = perx ? kBR : min(kBR, kc.nx - gx0);
-  const int ylo = pery ? 0 : max(0, -gy0), yhi = pery ? kBR : min(kBR, kc.ny - gy0);
-  // a region edge that cuts through the domain (not a wall) loses one valid
-  // node row per sweep
-  const bool cut_l = perx || gx0 > 0, cut_r = perx || gx0 + kBR < kc.nx;
-  const bool cut_b = pery || gy0 > 0, cut_t = pery || gy0 + kBR < kc.ny;
-  const int rx = threadIdx.x % kBR;               // each thread keeps one column
-  const int ry0 = threadIdx.x / kBR;              // and every (kBT / kBR)-th row from ry0
+// Anti-bounce-back / bounce-back value of the population arriving through a
+// wall face at node (x, y) whose opposite population is o.
+__device__ inline float wall_rule(const KC &kc, int face, int x, int y, float pb, float o) {
+  return kc.bc_f[face] == LBTP_BC_DIRICHLET ? 2.0f * kc.w1 * (wall_P(kc, face, x, y, 0, 1, 0) - pb) - o : o;
+}
 
-  float fpv[HAS_FP ? kBPer : 1];
-#pragma unroll
-  for (int t = 0; t < kBPer; ++t) {
-    const int ry = ry0 + t * (kBT / kBR);
-    const int idx = ry * kBR + rx;
-    if (HAS_FP) fpv[t] = 0.0f;
-    if (rx < xlo || rx >= xhi || ry < ylo || ry >= yhi) continue;
-    const int gx = perx ? wrap_mod(gx0 + rx, kc.nx) : gx0 + rx;
-    const int gy = pery ? wrap_mod(gy0 + ry, kc.ny) : gy0 + ry;
-    const int c = gy * kc.nx + gx;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) sd[0][j][idx] = Storage<T>::load(fin.p[j], c, is);
-    sp[idx] = Pb[c];
-    st[idx] = itau[c];
-    if (HAS_FP) fpv[t] = kc.dt * kc.wbar * Fp[c];
-  }
-  __syncthreads();
+// State of one lane: RW rows of its column.
+template <int RW, bool HAS_FP>
+struct Rows {
+  float d[RW][4];              // deviations
+  float pb[RW + 2];            // base of rows -1 .. RW
+  float pbl[RW], pbr[RW];      // base of the x-neighbours
+  float it[RW];                // 1 / tau_f
+  float fp[HAS_FP ? RW : 1];   // dt wbar F_p
+};
 
-  const int ux = gx0 + rx;                        // global x (unwrapped)
+// H sweeps of the region.  walls: the region holds wall nodes (uniform over
+// the workgroup, so regions inside the domain skip every wall test).  Rows
+// are updated in place from the bottom up; the old +y population of the row
+// below, which the next row still pulls, is kept aside.
+template <int W, int RW, bool HAS_FP>
+__device__ inline void sweep_rows(const KC &kc, Rows<RW, HAS_FP> &r, float (*xup)[kBWmax][kBX],
+                                  float (*xdn)[kBWmax][kBX], int H, int lane, int wv, int ux, int gx, int uy0,
+                                  bool perx, bool pery, bool walls) {
+  const bool wall_l = !perx && ux == 0, wall_r = !perx && ux == kc.nx - 1;
   for (int s = 1; s <= H; ++s) {
-    const int wxl = cut_l ? s : xlo, wxh = cut_r ? kBR - s : xhi;
-    const int wyl = cut_b ? s : ylo, wyh = cut_t ? kBR - s : yhi;
     const int rd = (s - 1) & 1;
-    const bool last = s == H;
-    if (rx >= wxl && rx < wxh) {
+    // the neighbouring wavefronts' rows (garbage at the region's outer rows,
+    // which are cut edges or walls)
+    float prev1 = wv > 0 ? xup[rd][wv - 1][lane] : 0.0f;
+    const float above = wv < W - 1 ? xdn[rd][wv + 1][lane] : 0.0f;
 #pragma unroll
-      for (int t = 0; t < kBPer; ++t) {
-        const int ry = ry0 + t * (kBT / kBR);
-        if (ry < wyl || ry >= wyh) continue;
-        const int idx = ry * kBR + rx;
-        const int uy = gy0 + ry;
-        const float pb = sp[idx];
-        float e[4];
+    for (int t = 0; t < RW; ++t) {
+      const float p = r.pb[t + 1];
+      const float v0 = __shfl_up(r.d[t][0], 1, 64);
+      const float v2 = __shfl_down(r.d[t][2], 1, 64);
+      const float v3 = t < RW - 1 ? r.d[t + 1][3] : above;
+      float e[4];
+      e[0] = v0 + kc.w1 * (r.pbl[t] - p);
+      e[1] = prev1 + kc.w1 * (r.pb[t] - p);
+      e[2] = v2 + kc.w1 * (r.pbr[t] - p);
+      e[3] = v3 + kc.w1 * (r.pb[t + 2] - p);
+      if (walls) {
+        const int uy = uy0 + t;
+        const int wy = pery ? wrap_mod(uy, kc.ny) : uy;
+        if (wall_l) e[0] = wall_rule(kc, 0, 0, wy, p, r.d[t][2]);
+        if (wall_r) e[2] = wall_rule(kc, 1, kc.nx - 1, wy, p, r.d[t][0]);
+        if (!pery && uy == 0) e[1] = wall_rule(kc, 2, gx, 0, p, r.d[t][3]);
+        if (!pery && uy == kc.ny - 1) e[3] = wall_rule(kc, 3, gx, kc.ny - 1, p, r.d[t][1]);
+      }
+      const float dP = dpressure<2>(e, kc);
+      const float wdP = kc.w1 * dP;
+      prev1 = r.d[t][1];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int a = dir_axis(j), sg = dir_sign(j);
-          // walls only on non-periodic axes, where the coordinates need no wrapping
-          const bool out = (a == 0) ? (!perx && (sg > 0 ? ux == 0 : ux == kc.nx - 1))
-                                    : (!pery && (sg > 0 ? uy == 0 : uy == kc.ny - 1));
-          if (!out) {
-            const int src = idx - sg * (a == 0 ? 1 : kBR);
-            e[j] = sd[rd][j][src] + kc.w1 * (sp[src] - pb);
-          } else {
-            const int face = 2 * a + (sg > 0 ? 0 : 1);
-            const float o = sd[rd][dir_opp(j)][idx];
-            if (kc.bc_f[face] == LBTP_BC_DIRICHLET) {
-              // the coordinate along the wall may run over a periodic axis
-              const int wx = perx ? wrap_mod(ux, kc.nx) : ux, wy = pery ? wrap_mod(uy, kc.ny) : uy;
-              e[j] = 2.0f * kc.w1 * (wall_P(kc, face, wx, wy, 0, 1, 0) - pb) - o;
-            } else {
-              e[j] = o;
-            }
-          }
-        }
-        const float dP = dpressure<2>(e, kc);
-        const float wdP = kc.w1 * dP;
-        const float it = st[idx];
-        float o[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          o[j] = e[j] + (wdP - e[j]) * it;
-          if (HAS_FP) o[j] += fpv[t];
-        }
-        if (!last) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) sd[rd ^ 1][j][idx] = o[j];
-        } else if (rx >= H && rx < H + tile && ry >= H && ry < H + tile && ux < kc.nx && uy < kc.ny) {
-          // the tile (region nodes [H, H + tile) per axis inside the domain)
-          // goes from the last sweep straight to global memory
-          const int c = uy * kc.nx + ux;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) Storage<T>::store(fout.p[j], c, o[j], kc.dev_scale);
-        }
+      for (int j = 0; j < 4; ++j) {
+        float o = e[j] + (wdP - e[j]) * r.it[t];
+        if (HAS_FP) o += r.fp[t];
+        r.d[t][j] = o;
       }
     }
-    if (!last) __syncthreads();
+    if (s == H) break;
+    xup[s & 1][wv][lane] = r.d[RW - 1][1];
+    xdn[s & 1][wv][lane] = r.d[0][3];
+    __syncthreads();
   }
 }
 
-template <typename T>
+template <typename T, bool HAS_FP, int W, int RW>
+__global__ __launch_bounds__(kBX * W) void f_block_kernel(
+    KC kc, FPtrs fin_, FPtrs fout_, const float *__restrict__ Pb, const float *__restrict__ itau,
+    const float *__restrict__ Fp, const Ctl *__restrict__ ctl, long long k, int H, int tiles_x) {
+  if (ctl->done || k > ctl->kmax) return;
+  constexpr int kBY = W * RW;     // region rows
+  // boundary rows exchanged between wavefronts, two copies (sweep s reads
+  // copy (s - 1) & 1): the +y population of each wavefront's last row and
+  // the -y population of its first row
+  __shared__ float xup[2][kBWmax][kBX];
+  __shared__ float xdn[2][kBWmax][kBX];
+  const FP<T> fin = typed<T>(fin_), fout = typed<T>(fout_);
+  const float is = kc.inv_dev_scale;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int tcols = kBX - 2 * H, trows = kBY - 2 * H;
+  const int gx0 = (int)(blockIdx.x % tiles_x) * tcols - H;   // global coordinates of region node (0, 0)
+  const int gy0 = (int)(blockIdx.x / tiles_x) * trows - H;
+  const bool perx = kc.bc_f[0] == LBTP_BC_PERIODIC, pery = kc.bc_f[2] == LBTP_BC_PERIODIC;
+  const int ux = gx0 + lane;                                // this lane's column (unwrapped)
+  const bool colin = perx || (ux >= 0 && ux < kc.nx);
+  const int gx = perx ? wrap_mod(ux, kc.nx) : ux;
+  const int uy0 = gy0 + wv * RW;                            // this wavefront's first row (unwrapped)
+
+  auto row_in = [&](int uy) { return pery || (uy >= 0 && uy < kc.ny); };
+  auto gidx = [&](int uy) { return (pery ? wrap_mod(uy, kc.ny) : uy) * kc.nx + gx; };
+
+  Rows<RW, HAS_FP> r;
+#pragma unroll
+  for (int t = 0; t < RW + 2; ++t) {
+    const int uy = uy0 + t - 1;
+    r.pb[t] = (colin && row_in(uy)) ? Pb[gidx(uy)] : 0.0f;
+  }
+#pragma unroll
+  for (int t = 0; t < RW; ++t) {
+    const int uy = uy0 + t;
+    const bool in = colin && row_in(uy);
+    const int c = in ? gidx(uy) : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) r.d[t][j] = in ? Storage<T>::load(fin.p[j], c, is) : 0.0f;
+    r.it[t] = in ? itau[c] : 0.0f;
+    if (HAS_FP) r.fp[t] = in ? kc.dt * kc.wbar * Fp[c] : 0.0f;
+    r.pbl[t] = __shfl_up(r.pb[t + 1], 1, 64);
+    r.pbr[t] = __shfl_down(r.pb[t + 1], 1, 64);
+  }
+  xup[0][wv][lane] = r.d[RW - 1][1];
+  xdn[0][wv][lane] = r.d[0][3];
+  __syncthreads();
+
+  // wall nodes in the region: x = 0 or nx - 1 on a walled x axis, likewise y
+  const bool walls = (!perx && (gx0 <= 0 || gx0 + kBX > kc.nx - 1)) || (!pery && (gy0 <= 0 || gy0 + kBY > kc.ny - 1));
+  sweep_rows<W, RW, HAS_FP>(kc, r, xup, xdn, H, lane, wv, ux, gx, uy0, perx, pery, walls);
+
+  // the tile: columns and rows [H, extent - H) of the region inside the domain
+  if (lane < H || lane >= kBX - H || ux >= kc.nx) return;
+#pragma unroll
+  for (int t = 0; t < RW; ++t) {
+    const int ry = wv * RW + t, uy = uy0 + t;
+    if (ry < H || ry >= kBY - H || uy >= kc.ny) continue;
+    const int c = uy * kc.nx + ux;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Storage<T>::store(fout.p[j], c, r.d[t][j], kc.dev_scale);
+  }
+}
+
+template <typename T, int W, int RW>
 void block_launch(const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, const float *itau, const float *Fp,
                   const Ctl *ctl, long long k, int H, hipStream_t s) {
-  const int tile = kBR - 2 * H;
-  const int tx = (kc.nx + tile - 1) / tile, ty = (kc.ny + tile - 1) / tile;
+  const int tcols = kBX - 2 * H, trows = W * RW - 2 * H;
+  const int tx = (kc.nx + tcols - 1) / tcols, ty = (kc.ny + trows - 1) / trows;
   if (Fp)
-    hipLaunchKernelGGL((f_block_kernel<T, true>), dim3(tx * ty), dim3(kBT), 0, s, kc, fin, fout, Pb, itau, Fp, ctl, k,
-                       H, tx);
+    hipLaunchKernelGGL((f_block_kernel<T, true, W, RW>), dim3(tx * ty), dim3(kBX * W), 0, s, kc, fin, fout, Pb,
+                       itau, Fp, ctl, k, H, tx);
   else
-    hipLaunchKernelGGL((f_block_kernel<T, false>), dim3(tx * ty), dim3(kBT), 0, s, kc, fin, fout, Pb, itau, Fp, ctl,
-                       k, H, tx);
+    hipLaunchKernelGGL((f_block_kernel<T, false, W, RW>), dim3(tx * ty), dim3(kBX * W), 0, s, kc, fin, fout, Pb,
+                       itau, Fp, ctl, k, H, tx);
 }
 
 }  // namespace
 
 int block_sweeps_supported(int dim, const KC &kc, int H) {
-  return dim == 2 && kc.nz == 1 && H >= 3 && H % 2 == 1 && kBR - 2 * H >= 16;
+  return dim == 2 && kc.nz == 1 && H >= 3 && H % 2 == 1 && kBX - 2 * H >= 16 && kUseW * kUseRW - 2 * H >= 16;
 }
 
 hipError_t launch_f_block(int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, const float *itau,
                           const float *Fp, const Ctl *ctl, long long k, int H, hipStream_t s) {
   switch (storage) {
-    case LBTP_FP16_DEV: block_launch<_Float16>(kc, fin, fout, Pb, itau, Fp, ctl, k, H, s); break;
-    case LBTP_BF16_DEV: block_launch<bf16_t>(kc, fin, fout, Pb, itau, Fp, ctl, k, H, s); break;
-    default: block_launch<float>(kc, fin, fout, Pb, itau, Fp, ctl, k, H, s); break;
+    case LBTP_FP16_DEV: block_launch<_Float16, kUseW, kUseRW>(kc, fin, fout, Pb, itau, Fp, ctl, k, H, s); break;
+    case LBTP_BF16_DEV: block_launch<bf16_t, kUseW, kUseRW>(kc, fin, fout, Pb, itau, Fp, ctl, k, H, s); break;
+    default: block_launch<float, kUseW, kUseRW>(kc, fin, fout, Pb, itau, Fp, ctl, k, H, s); break;
   }
   return hipGetLastError();
 }

@@ -59,6 +59,7 @@ EXPORTS = {
     "lbtp_set_wall_types": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_int]),
     "lbtp_set_state": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4 + [ctypes.c_int]),
+    "lbtp_probe_sweeps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_longlong]),
     "lbtp_update_coefficients": (ctypes.c_int, [ctypes.c_void_p]),
     "lbtp_pressure_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_longlong,
                                            ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]),
@@ -524,6 +525,11 @@ class Solver:
 
     def saturation_step(self):
         _check(self._lib.lbtp_saturation_step(self._h), "lbtp_saturation_step")
+
+    def probe_sweeps(self, launches):
+        """lbtp_probe_sweeps: `launches` back-to-back launches of the plain
+        pressure sweep (timing aid); returns the sweeps per launch."""
+        return _check(self._lib.lbtp_probe_sweeps(self._h, int(launches)), "lbtp_probe_sweeps")
 
     def step(self, nsteps, tol, max_iters):
         its = (ctypes.c_longlong * max(1, nsteps))()

@@ -4,8 +4,9 @@ Run under rocprofv3 (one counter per run):
     rocprofv3 --pmc FETCH_SIZE -d DIR -o run -- python -m paper_1808_07554_amd.profile_sweep
     rocprofv3 --pmc WRITE_SIZE -d DIR -o run -- python -m paper_1808_07554_amd.profile_sweep
 The workload is a 1 GiB plain copy (lbtp_copy_probe, the known-size
-reference) followed by a burst of plain pressure sweeps on the 4096 x 4096
-injection problem.  Then, on any machine:
+reference) followed by a burst of launches of the blocked plain pressure
+sweep (lbtp_probe_sweeps, 9 sweeps per launch) on the 4096 x 4096 injection
+problem.  Then, on any machine:
     python -m paper_1808_07554_amd.profile_sweep --summarize FETCH.csv WRITE.csv OUT.txt [--storage S]
 converts the counters of the sweep into HBM bytes per launch with the
 copy's bytes-per-count scale and writes a short text summary.
@@ -19,7 +20,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 1 << 30
 # the sources the sweep kernels are compiled from
-SWEEP_SOURCES = ("lbtp_kernels.hip", "lbtp_device.h", "lbtp_internal.h")
+SWEEP_SOURCES = ("lbtp_kernels.hip", "lbtp_device.h", "lbtp_internal.h", "lbtp_block.hip")
 
 
 def source_digest():
@@ -32,13 +33,18 @@ def source_digest():
     return h.hexdigest()
 
 
-def sweep_kernel_name(storage, dim=2):
-    """The kernel of a plain pull-form pressure sweep with nx % 4 == 0 (the
-    same for every storage and dimension)."""
+def sweep_kernel_name(storage, dim=2, lattice=None, sweeps_per_launch=9):
+    """The kernel that runs the plain pull-form pressure sweeps of a full
+    chunk with nx % 4 == 0: the blocked kernel on D2Q5 (several sweeps per
+    launch), else the 4-nodes-per-thread sweep."""
+    if lattice == "D2Q9":
+        return "q9_f_sweep_vec_kernel"
+    if dim == 2 and sweeps_per_launch > 1:
+        return "f_block_kernel"
     return "f_sweep_vec_kernel"
 
 
-def run(storage, n, sweeps):
+def run(storage, n, launches):
     import ctypes
 
     import torch
@@ -62,9 +68,11 @@ def run(storage, n, sweeps):
     s.set_state(torch.from_numpy(inputs.f32(fl["P0"]).ravel()).to(dev),
                 torch.from_numpy(inputs.f32(fl["S0"]).ravel()).to(dev))
     s.update_coefficients()
-    s.pressure_solve(-1.0, sweeps)
+    s.pressure_solve(-1.0, 20)
+    H = s.probe_sweeps(launches)
     torch.cuda.synchronize()
-    print(f"profile workload done: copy {COPY_BYTES} B x3, {sweeps} sweeps at {n}^2 ({storage})", flush=True)
+    print(f"profile workload done: copy {COPY_BYTES} B x3, {launches} launches of {H} plain sweeps at {n}^2 "
+          f"({storage})", flush=True)
 
 
 def _counter_rows(path):
@@ -91,7 +99,7 @@ def summarize(fetch_csv, write_csv, out_txt, storage, n, command):
     w_rows = _counter_rows(write_csv)
     copy_f, ncf = _per_dispatch(f_rows, "copy_probe")
     copy_w, ncw = _per_dispatch(w_rows, "copy_probe")
-    # plain sweeps of the 4-node kernel
+    # launches of the blocked plain sweep (each moves the state in and out once)
     kname = sweep_kernel_name(storage)
     sw_f, nsf = _per_dispatch(f_rows, kname)
     sw_w, nsw = _per_dispatch(w_rows, kname)
@@ -103,7 +111,7 @@ def summarize(fetch_csv, write_csv, out_txt, storage, n, command):
     alg_read = n * n * (q1 * pop + 8)
     alg_write = n * n * q1 * pop
     sha = source_digest()
-    text = f"""Pressure sweep HBM traffic, heterogeneous injection 2-D {n}x{n}, D2Q5, {storage} storage
+    text = f"""Blocked pressure sweep HBM traffic per launch (9 plain sweeps), heterogeneous injection 2-D {n}x{n}, D2Q5, {storage} storage
 command: {command}
 counters: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each from its own rocprofv3 --pmc run
 calibration: lbtp_copy_probe of {COPY_BYTES} B: FETCH_SIZE {copy_f:.1f} ({ncf} dispatches), WRITE_SIZE {copy_w:.1f} ({ncw}) -> {scale_f:.2f} / {scale_w:.2f} B per count
@@ -122,12 +130,12 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--storage", default="fp32")
     ap.add_argument("--n", type=int, default=4096)
-    ap.add_argument("--sweeps", type=int, default=40)
+    ap.add_argument("--launches", type=int, default=20)
     ap.add_argument("--summarize", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_TXT"))
     ap.add_argument("--command", default="rocprofv3 --pmc <COUNTER> -d DIR -o run -- python -m paper_1808_07554_amd.profile_sweep")
     a = ap.parse_args()
     if a.summarize:
         summarize(*a.summarize, a.storage, a.n, a.command)
     else:
-        run(a.storage, a.n, a.sweeps)
+        run(a.storage, a.n, a.launches)
         sys.exit(0)
