@@ -65,8 +65,9 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--m", type=int, default=64)
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"])
-    ap.add_argument("--workload", default="injection2d", choices=["injection2d", "injection3d", "ensemble"],
-                    help="injection2d (default): 4096^2 D2Q5; injection3d: 512^3 D3Q7; ensemble: 256 uneven 2-D realisations")
+    ap.add_argument("--workload", default="injection2d", choices=["injection2d", "injection3d", "ensemble", "five-spot"],
+                    help="injection2d (default): 4096^2 D2Q5; injection3d: 512^3 D3Q7; ensemble: 256 uneven 2-D "
+                         "realisations; five-spot: the Section 4.3 problem on D2Q9 (--n 96 by default)")
     ap.add_argument("--lattice", default="D2Q5", choices=["D2Q5", "D2Q9"],
                     help="lattice of the 2-D injection workload (D2Q9: the paper's own, beta = 0.2)")
     ap.add_argument("--members", type=int, default=256)
@@ -199,6 +200,11 @@ def main():
     if a.workload == "injection3d":
         params, fl = inputs.injection_3d(512 if a.n == 4096 else a.n)
         ncell = int(np.prod(params["shape"]))
+    elif a.workload == "five-spot":
+        if a.n == 4096:
+            a.n = 96
+        params, fl = inputs.five_spot(a.n)
+        ncell = a.n * a.n
     else:
         params, fl = inputs.injection_2d(a.n)
         if a.lattice == "D2Q9":
@@ -325,6 +331,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": (f"heterogeneous injection 2-D {a.n}x{a.n} (log-normal K sigma 1, corr. length 16)"
                                 if a.workload == "injection2d" else
+                                f"five-spot (Section 4.3, Table 1 values) {a.n}x{a.n}, dt = {params['dt']:.4g}"
+                                if a.workload == "five-spot" else
                                 "heterogeneous injection 3-D %dx%dx%d (log-normal K sigma 1.5, corr. length 8)"
                                 % tuple(params["shape"])),
                    "lattice": params["lattice"], "storage": a.storage, "tol": a.tol, "residual_stride": a.m,
