@@ -82,3 +82,20 @@ def d3q7():
 
 def get(name):
     return {"D2Q9": d2q9, "D2Q5": d2q5, "D3Q7": d3q7}[name]()
+
+
+def d2q9_moment_basis():
+    """Moment basis of the D2Q9 multiple-relaxation-time collision (the
+    orthogonal basis of Lallemand and Luo, Phys. Rev. E 61 (2000) 6546, which
+    the paper cites for MRT), rows in the order
+        rho, e, epsilon, j_x, q_x, j_y, q_y, p_xx, p_xy
+    built from the velocities e_i of d2q9() (|e|^2 = e_x^2 + e_y^2):
+        1, -4 + 3|e|^2, 4 - 21/2 |e|^2 + 9/2 |e|^4, e_x, (-5 + 3|e|^2) e_x,
+        e_y, (-5 + 3|e|^2) e_y, e_x^2 - e_y^2, e_x e_y.
+    Returns a (9, 9) float array M with m = M f."""
+    e = d2q9().e.astype(np.float64)
+    ex, ey = e[:, 0], e[:, 1]
+    c2 = ex * ex + ey * ey
+    rows = [np.ones(9), -4.0 + 3.0 * c2, 4.0 - 10.5 * c2 + 4.5 * c2 * c2, ex, (-5.0 + 3.0 * c2) * ex,
+            ey, (-5.0 + 3.0 * c2) * ey, ex * ex - ey * ey, ex * ey]
+    return np.stack(rows)

@@ -42,6 +42,10 @@ Readings where the paper is silent (each is also listed in the design notes):
     S_wb = S^n at the boundary node (a zero-gradient outlet; the paper has
     only Dirichlet and no-flux walls).
   * the D2Q9 anti-bounce-back equilibrium uses phi at the boundary node.
+  * collision: BGK as in the paper; optionally (D2Q9, pressure lattice) the
+    multiple-relaxation-time form the paper says the model extends to, with
+    the Lallemand-Luo moment basis (lattice.d2q9_moment_basis), the fluxes
+    relaxed at 1/tau_f and the other rates given (rho, e, epsilon share one).
   * a face may mix rules link by link (wells on a no-flux wall, the
     five-spot problem of Section 4.3): a predicate of the cut link's
     midpoint picks one of two rules for that link.
@@ -97,7 +101,7 @@ class Solver:
     """
 
     def __init__(self, lattice, shape, *, beta, Ds, coef, bc_f, bc_g,
-                 dx=1.0, dt=1.0, m=1, dtype=np.float64, cap_B=0.0):
+                 dx=1.0, dt=1.0, m=1, dtype=np.float64, cap_B=0.0, collision=None):
         self.lat = _lat.get(lattice) if isinstance(lattice, str) else lattice
         shape = tuple(int(s) for s in shape)
         if len(shape) == 2:
@@ -112,6 +116,16 @@ class Solver:
         self.cs2 = self.lat.cs2_c2 * self.c * self.c
         self.beta, self.Ds = float(beta), float(Ds)
         self.cap_B = float(cap_B)
+        # pressure-lattice collision: BGK (None), or ("mrt", s0, sq, sp) on D2Q9
+        self.mrt = None
+        if collision is not None:
+            if collision[0] != "mrt" or len(collision) != 4 or self.lat.name != "D2Q9":
+                raise ValueError("collision: None or ('mrt', s0, sq, sp) on D2Q9")
+            rates = [float(v) for v in collision[1:]]
+            if not all(0.0 < v < 2.0 for v in rates):
+                raise ValueError("MRT rates must lie in (0, 2)")
+            M = _lat.d2q9_moment_basis()
+            self.mrt = (M, np.linalg.inv(M), rates)
         if self.cap_B < 0:
             raise ValueError("capillary coefficient must be non-negative")
         self.coef = coef
@@ -335,11 +349,27 @@ class Solver:
         j = self.lat.opp[i]
         return 2.0 * self.lat.w[j] * self._bvalue(b[1], i, sl, t)
 
+    def _mrt_relax(self, neq):
+        """M^-1 S M (f - f^eq): the multiple-relaxation-time collision the paper
+        says the model extends to (Section 3).  Rates: s0 for rho, e and epsilon
+        (equal, so the rest population, which no output uses, stays decoupled
+        from the moving ones), 1/tau_f for the fluxes j_x, j_y (they carry the
+        diffusivity, eq. 3-11a), sq for q_x, q_y and sp for p_xx, p_xy."""
+        M, Minv, (s0, sq, sp) = self.mrt
+        m = np.einsum("ki,i...->k...", M, neq)
+        sj = 1.0 / self.tau_f
+        rates = [s0, s0, s0, sj, sq, sj, sq, sp, sp]
+        sm = np.stack([r * m[k] for k, r in enumerate(rates)])
+        return np.einsum("ik,k...->i...", Minv, sm)
+
     def f_iteration(self):
         """One iteration of eq. (3-1): collide (eq. 2-1b a), stream, wall rules."""
         lat = self.lat
         P = self.pressure()
-        post = self.f - (self.f - self.feq(P)) / self.tau_f
+        if self.mrt is None:
+            post = self.f - (self.f - self.feq(P)) / self.tau_f
+        else:
+            post = self.f - self._mrt_relax(self.f - self.feq(P))
         for i in range(1, lat.Q):
             post[i] = post[i] + self.dt * lat.wbar[i] * self.Fp
         self.f, _ = self._stream(post, self.bc_f, self._f_wall, self.t)
