@@ -88,6 +88,16 @@ enum lbtp_bc { LBTP_BC_PERIODIC = 0, LBTP_BC_DIRICHLET = 1, LBTP_BC_NOFLUX = 2, 
  * u = -D_p grad P in both. */
 enum lbtp_coef_model { LBTP_COEF_QUADRATIC_KR = 0, LBTP_COEF_RATIONAL = 1 };
 
+/* Collision of the pressure lattice.  BGK: eq. 3-1 as the paper states it.
+ * MRT (D2Q9 only): the multiple-relaxation-time form the paper says the
+ * model extends to (Section 3), f^+ = f - M^-1 S M (f - f^eq) with the
+ * orthogonal D2Q9 moment basis of Lallemand and Luo (rows rho, e, epsilon,
+ * j_x, q_x, j_y, q_y, p_xx, p_xy), the fluxes j relaxed at 1/tau_f (eq. 3-11a,
+ * which keeps D_p) and the other rates from params.mrt_rates = {s0 (rho, e and
+ * epsilon, one rate so the rest population stays decoupled), s_q, s_p}, each
+ * in (0, 2).  The saturation lattice keeps BGK. */
+enum lbtp_collision { LBTP_COLLISION_BGK = 0, LBTP_COLLISION_MRT = 1 };
+
 enum lbtp_status {
   LBTP_OK = 0,
   LBTP_NOT_CONVERGED = 1,   /* max_iters reached before the residual met tol */
@@ -125,11 +135,13 @@ typedef struct lbtp_params {
                                   LDS; D2Q5 only, float32 results bitwise unchanged):
                                   0 = library default (9 on D2Q5, none elsewhere),
                                   1 = one sweep per launch, or an odd number 3..23 (D2Q5) */
+  int collision;               /* lbtp_collision of the pressure lattice */
+  double mrt_rates[3];         /* MRT: s0, s_q, s_p (unused for BGK) */
 } lbtp_params;
 
 /* Fill *p with defaults: D2Q5, 1x1x1, dx = dt = 1, beta = 1, Ds = 0, mu = 1,
  * FP32, m = 64, periodic faces, init_neq = 1, null stream, QUADRATIC_KR,
- * sweep_block = 0. */
+ * sweep_block = 0, BGK collision. */
 LBTP_API void lbtp_default_params(lbtp_params *p);
 
 /* Validate *p (tau_g > 1/2, beta >= 0, periodicity consistent, sizes > 0,

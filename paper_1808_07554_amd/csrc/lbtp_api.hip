@@ -98,6 +98,12 @@ int validate(const lbtp_params *p) {
   if (p->coef_model == LBTP_COEF_QUADRATIC_KR && (!(p->mu_w > 0) || !(p->mu_n > 0))) return LBTP_EINVAL;
   if (p->sweep_block < 0 || (p->sweep_block > 1 && (p->sweep_block % 2 == 0 || p->lattice != LBTP_D2Q5)))
     return LBTP_EINVAL;
+  if (p->collision != LBTP_COLLISION_BGK && p->collision != LBTP_COLLISION_MRT) return LBTP_EINVAL;
+  if (p->collision == LBTP_COLLISION_MRT) {
+    if (p->lattice != LBTP_D2Q9) return LBTP_EINVAL;
+    for (int i = 0; i < 3; ++i)
+      if (!(p->mrt_rates[i] > 0.0 && p->mrt_rates[i] < 2.0)) return LBTP_EINVAL;
+  }
   if (p->coef_model == LBTP_COEF_RATIONAL) {
     for (int i = 0; i < 6; ++i)
       if (!isfinite(p->coef[i])) return LBTP_EINVAL;
@@ -153,6 +159,10 @@ void fill_kc(lbtp_ctx *c) {
   k.inv_mu_n = p.mu_n > 0 ? (float)(1.0 / p.mu_n) : 0.0f;
   k.coef = p.coef_model;
   for (int i = 0; i < 6; ++i) k.cf[i] = (float)p.coef[i];
+  k.mrt = p.collision == LBTP_COLLISION_MRT;
+  k.ms0 = (float)p.mrt_rates[0];
+  k.msq = (float)p.mrt_rates[1];
+  k.msp = (float)p.mrt_rates[2];
   k.Ds = (float)p.Ds;
   k.cap_B = (float)p.cap_B;
   k.inv_bcs2dt = (float)(1.0 / (p.beta * cs2 * p.dt));

@@ -125,6 +125,47 @@ __device__ inline float q9_sum_g(const float *g) {
   return s;
 }
 
+// Collision of the pressure lattice: o_j = e_j minus the relaxation of the
+// non-equilibrium part n_j = e_j - w_j dP (the base part of f^eq cancels in
+// the deviation form).  BGK: n_j / tau_f.  MRT: M^-1 S M n with the
+// orthogonal D2Q9 basis (rows rho, e, epsilon, j_x, q_x, j_y, q_y, p_xx,
+// p_xy; squared norms 9, 36, 36, 6, 12, 6, 12, 4, 4).  With rho, e and epsilon
+// at one rate s0, M^-1 S M = s0 I + M^-1 (S - s0 I) M, and the second term
+// only involves the flux and stress moments, none of which sees the rest
+// population; it is written out here moment by moment.
+__device__ inline void q9_collide(const KC &kc, const float *e, float dP, float it, float *o) {
+  if (!kc.mrt) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o[j] = e[j] + (q9w(kc, j) * dP - e[j]) * it;
+    return;
+  }
+  float n[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) n[j] = e[j] - q9w(kc, j) * dP;
+  // directions j = 0..7: +x, +y, -x, -y, (1,1), (-1,1), (-1,-1), (1,-1)
+  const float jx = n[0] - n[2] + n[4] - n[5] - n[6] + n[7];
+  const float qx = -2.0f * n[0] + 2.0f * n[2] + n[4] - n[5] - n[6] + n[7];
+  const float jy = n[1] - n[3] + n[4] + n[5] - n[6] - n[7];
+  const float qy = -2.0f * n[1] + 2.0f * n[3] + n[4] + n[5] - n[6] - n[7];
+  const float pxx = n[0] - n[1] + n[2] - n[3];
+  const float pxy = n[4] - n[5] + n[6] - n[7];
+  const float s0 = kc.ms0;
+  const float ajx = (it - s0) * jx * (1.0f / 6.0f), ajy = (it - s0) * jy * (1.0f / 6.0f);
+  const float aqx = (kc.msq - s0) * qx * (1.0f / 12.0f), aqy = (kc.msq - s0) * qy * (1.0f / 12.0f);
+  const float apxx = (kc.msp - s0) * pxx * 0.25f, apxy = (kc.msp - s0) * pxy * 0.25f;
+  float d[8];
+  d[0] = ajx - 2.0f * aqx + apxx;
+  d[1] = ajy - 2.0f * aqy - apxx;
+  d[2] = -ajx + 2.0f * aqx + apxx;
+  d[3] = -ajy + 2.0f * aqy - apxx;
+  d[4] = ajx + aqx + ajy + aqy + apxy;
+  d[5] = -ajx - aqx + ajy + aqy - apxy;
+  d[6] = -ajx - aqx - ajy - aqy + apxy;
+  d[7] = ajx + aqx - ajy - aqy - apxy;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) o[j] = e[j] - (s0 * n[j] + d[j]);
+}
+
 // ------------------------------------------------------------ pressure sweep
 // One iteration of eq. 3-1 at one node; MODE as in the D2Q5 sweeps (0 plain,
 // 1 re-base, 2 re-base and stopping-rule terms).
@@ -158,10 +199,12 @@ __global__ __launch_bounds__(kThreads) void q9_f_sweep_kernel(KC kc, FPtrs fin_,
         acc[1] = (double)P * (double)P;
       }
     }
+    float oc[8];
+    q9_collide(kc, e, dP, it, oc);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const float w = q9w(kc, j);
-      float o = e[j] + (w * dP - e[j]) * it;
+      float o = oc[j];
       if (HAS_FP) o += add;
       if (MODE >= 1) o += w * rb;
       Storage<T>::store(fout.p[j], c, o, kc.dev_scale);
@@ -327,10 +370,12 @@ __device__ inline void q9_quad_core(const KC &kc, const FP<T> &fin, const FP<T> 
         acc[1] += (double)P * (double)P;
       }
     }
+    float oc[8];
+    q9_collide(kc, ev, dP, t, oc);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const float w = q9w(kc, j);
-      float v = ev[j] + (w * dP - ev[j]) * t;
+      float v = oc[j];
       if (HAS_FP) v += add;
       if (MODE >= 1) v += w * rb;
       f4set(o[j], i, v);

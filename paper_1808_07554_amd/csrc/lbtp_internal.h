@@ -53,6 +53,10 @@ struct KC {
   // above holds for every link
   const int *wtF[4];
   const int *wtG[4];
+  // pressure-lattice collision: 0 BGK, 1 MRT (D2Q9) with rates s0 (rho, e,
+  // epsilon), sq (energy fluxes), sp (stresses); the fluxes relax at 1/tau_f
+  int mrt;
+  float ms0, msq, msp;
   // saturation diffusivity D_s(x) = Ds + cap_B K lambda_n f_w (eq. 2-16 with
   // the capillary curve P_c = cap_B (1 - S)); itg holds 1/tau_g per node
   // when cap_B > 0 (written with the coefficients), else null

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "liblbtp.so")
 
 D2Q5, D3Q7, D2Q9 = 0, 1, 2
 COEF_QUADRATIC_KR, COEF_RATIONAL = 0, 1
+COLLISION_BGK, COLLISION_MRT = 0, 1
 _LATTICE = {"D2Q5": D2Q5, "D3Q7": D3Q7, "D2Q9": D2Q9}
 _Q = {D2Q5: 5, D3Q7: 7, D2Q9: 9}
 FP32, FP16_DEV, BF16_DEV = 0, 1, 2
@@ -43,6 +44,8 @@ class Params(ctypes.Structure):
         ("coef", ctypes.c_double * 6),
         ("cap_B", ctypes.c_double),
         ("sweep_block", ctypes.c_int),
+        ("collision", ctypes.c_int),
+        ("mrt_rates", ctypes.c_double * 3),
     ]
 
 
@@ -209,7 +212,8 @@ def link_types(shape, dx, face, rule, periodic_axes=()):
 
 
 def make_params(lattice, shape, *, beta, Ds, mu_w=1.0, mu_n=1.0, bc_f, bc_g, dx=1.0, dt=1.0, m=64,
-                storage="fp32", init_neq=True, stream_ptr=None, coef=None, cap_B=0.0, sweep_block=0, **_):
+                storage="fp32", init_neq=True, stream_ptr=None, coef=None, cap_B=0.0, sweep_block=0,
+                collision=None, **_):
     """lbtp_params from keyword values.  coef: None for the quadratic relative
     permeabilities with mu_w, mu_n, or ("rational", a0, a1, c0, c1, b0, b1)
     for D_p = K (a0 + a1 S)/(b0 + b1 S), lambda_w K = K (c0 + c1 S)/(b0 + b1 S)."""
@@ -230,6 +234,12 @@ def make_params(lattice, shape, *, beta, Ds, mu_w=1.0, mu_n=1.0, bc_f, bc_g, dx=
     p.stream = stream_ptr
     p.cap_B = float(cap_B)
     p.sweep_block = int(sweep_block)
+    if collision is not None:
+        if collision[0] != "mrt" or len(collision) != 4:
+            raise ValueError(f"unknown collision {collision!r}")
+        p.collision = COLLISION_MRT
+        for i, v in enumerate(collision[1:]):
+            p.mrt_rates[i] = float(v)
     if coef is not None:
         if coef[0] != "rational" or len(coef) != 7:
             raise ValueError(f"unknown coefficient model {coef!r}")
@@ -423,7 +433,8 @@ class Solver:
     """
 
     def __init__(self, lattice, shape, *, beta, Ds, mu_w=1.0, mu_n=1.0, bc_f, bc_g, dx=1.0, dt=1.0, m=64,
-                 storage="fp32", init_neq=True, stream=None, coef=None, cap_B=0.0, sweep_block=0, **_):
+                 storage="fp32", init_neq=True, stream=None, coef=None, cap_B=0.0, sweep_block=0,
+                 collision=None, **_):
         self.torch = _torch()
         lib = load()
         if stream is None:
@@ -431,7 +442,8 @@ class Solver:
         self.stream = stream
         p, shape = make_params(lattice, shape, beta=beta, Ds=Ds, mu_w=mu_w, mu_n=mu_n, bc_f=bc_f, bc_g=bc_g,
                                dx=dx, dt=dt, m=m, storage=storage, init_neq=init_neq,
-                               stream_ptr=stream.cuda_stream, coef=coef, cap_B=cap_B, sweep_block=sweep_block)
+                               stream_ptr=stream.cuda_stream, coef=coef, cap_B=cap_B, sweep_block=sweep_block,
+                               collision=collision)
         self.params = p
         self.dim = 3 if p.lattice == D3Q7 else 2
         self.Q = _Q[p.lattice]

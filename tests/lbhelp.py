@@ -10,7 +10,8 @@ def oracle_solver(params, m=1, dtype=np.float64):
     return oracle.Solver(params["lattice"], params["shape"], beta=params["beta"], Ds=params["Ds"],
                          coef=oracle.QuadraticKr(params["mu_w"], params["mu_n"]),
                          bc_f=params["bc_f"], bc_g=params["bc_g"], dx=params.get("dx", 1.0),
-                         dt=params.get("dt", 1.0), m=m, dtype=dtype, cap_B=params.get("cap_B", 0.0))
+                         dt=params.get("dt", 1.0), m=m, dtype=dtype, cap_B=params.get("cap_B", 0.0),
+                         collision=params.get("collision"))
 
 
 def gpu_solver(params, m=64, **kw):

@@ -47,6 +47,7 @@ def _params(**kw):
     dict(lattice=lbtp.D2Q9, nz=2), dict(cap_B=-1.0), dict(coef_model=5),
     dict(sweep_block=-1), dict(sweep_block=8), dict(sweep_block=25),
     dict(lattice=lbtp.D2Q9, sweep_block=9), dict(lattice=lbtp.D3Q7, nz=8, sweep_block=9),
+    dict(collision=2), dict(collision=lbtp.COLLISION_MRT),
 ])
 def test_invalid_params_rejected_without_device(kw):
     lib = lbtp.load()
@@ -110,3 +111,13 @@ def test_mixed_face_rules_map_to_params():
     assert list(prm.bc_g)[:4] == [lbtp.BC_DIRICHLET, lbtp.BC_OUTFLOW, lbtp.BC_DIRICHLET, lbtp.BC_OUTFLOW]
     with pytest.raises(ValueError):
         lbtp.make_params("D2Q5", p["shape"], beta=0.1, Ds=p["Ds"], bc_f=p["bc_f"], bc_g=p["bc_g"])
+
+
+@pytest.mark.parametrize("rates", [(0.0, 1.0, 1.0), (1.0, 2.0, 1.0), (1.0, 1.0, float("nan"))])
+def test_mrt_rates_outside_the_open_interval_rejected(rates):
+    lib = lbtp.load()
+    p = _params(lattice=lbtp.D2Q9, beta=0.2, collision=lbtp.COLLISION_MRT)
+    for i, v in enumerate(rates):
+        p.mrt_rates[i] = v
+    h = ctypes.c_void_p()
+    assert lib.lbtp_init(ctypes.byref(p), ctypes.byref(h)) == lbtp.EINVAL
