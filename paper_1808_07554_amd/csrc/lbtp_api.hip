@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/lbtp_probe.h"
+#include "lbtp_block.h"
 #include "lbtp_internal.h"
 
 using namespace lbtp;
@@ -993,6 +994,10 @@ struct lbtp_batch {
   int *d_tm_s = nullptr, *d_ti_s = nullptr;     // sweep tiling (4*nt nodes per tile)
   int *d_tm_c = nullptr, *d_ti_c = nullptr;     // cell tiling (kCellTile nodes per tile)
   int ntiles_s = 0, ntiles_c = 0, tiles_cap = 0;
+  int H = 1;                                    // plain sweeps per launch (blocked tiling if > 1)
+  int *d_tm_b = nullptr, *d_ti_b = nullptr;     // blocked tiling
+  int ntiles_b = 0, tiles_b_cap = 0;
+  bool any_fp = false, any_nofp = false;        // members with / without a pressure source
   double *partials = nullptr;
   int *d_active = nullptr, *h_active = nullptr;  // h_active: pinned, two slots
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -1006,7 +1011,8 @@ namespace {
 void batch_free(lbtp_batch *b) {
   if (!b) return;
   if (b->chunk) (void)hipGraphExecDestroy(b->chunk);
-  void *bufs[] = {b->d_mem, b->d_ctl, b->d_tm_s, b->d_ti_s, b->d_tm_c, b->d_ti_c, b->partials, b->d_active};
+  void *bufs[] = {b->d_mem, b->d_ctl, b->d_tm_s, b->d_ti_s, b->d_tm_c, b->d_ti_c, b->d_tm_b, b->d_ti_b, b->partials,
+                  b->d_active};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   if (b->h_ctl) (void)hipHostFree(b->h_ctl);
@@ -1021,8 +1027,9 @@ void batch_free(lbtp_batch *b) {
 // (Re)build the member table and both tile tables for sweep width nt.
 int batch_tables(lbtp_batch *b, int nt) {
   std::vector<Member> mem(b->n);
-  std::vector<int> tm_s, ti_s, tm_c, ti_c;
+  std::vector<int> tm_s, ti_s, tm_c, ti_c, tm_b, ti_b;
   const int tile_s = 4 * nt;
+  b->any_fp = b->any_nofp = false;
   for (int i = 0; i < b->n; ++i) {
     lbtp_ctx *c = b->ctx[i];
     Member &M = mem[i];
@@ -1054,6 +1061,28 @@ int batch_tables(lbtp_batch *b, int nt) {
       tm_c.push_back(i);
       ti_c.push_back(t);
     }
+    if (b->H > 1) {
+      int tx, ty;
+      block_tile_counts(c->kc, b->H, &tx, &ty);
+      for (int t = 0; t < tx * ty; ++t) {
+        tm_b.push_back(i);
+        ti_b.push_back(t);
+      }
+    }
+    (M.Fp ? b->any_fp : b->any_nofp) = true;
+  }
+  if ((int)tm_b.size() > b->tiles_b_cap) {
+    for (int **p : {&b->d_tm_b, &b->d_ti_b}) {
+      if (*p) (void)hipFree(*p);
+      *p = nullptr;
+      if (hipMalloc((void **)p, tm_b.size() * sizeof(int)) != hipSuccess) return LBTP_ENOMEM;
+    }
+    b->tiles_b_cap = (int)tm_b.size();
+  }
+  b->ntiles_b = (int)tm_b.size();
+  if (!tm_b.empty()) {
+    HIP_TRY(hipMemcpyAsync(b->d_tm_b, tm_b.data(), tm_b.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->d_ti_b, ti_b.data(), ti_b.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
   }
   const int need = (int)(tm_s.size() > tm_c.size() ? tm_s.size() : tm_c.size());
   if (need > b->tiles_cap) {
@@ -1086,7 +1115,16 @@ int batch_tables(lbtp_batch *b, int nt) {
 // Enqueue one chunk: sweeps j = 1 .. m (the last one evaluates the stopping
 // rule and re-bases), then the per-member finish.
 int batch_enqueue_chunk(lbtp_batch *b) {
-  for (int j = 1; j <= b->m; ++j) {
+  int j = 1;
+  // plain sweeps in blocks of H (H odd: a block ends in the buffer where H
+  // single sweeps would), the rest one by one
+  for (; b->H > 1 && j + b->H - 1 <= b->m - 1; j += b->H) {
+    for (int fp = 0; fp < 2; ++fp)
+      if (fp ? b->any_fp : b->any_nofp)
+        HIP_TRY(batch_launch_block(b->storage, fp != 0, b->ntiles_b, b->d_mem, b->d_ctl, b->d_tm_b, b->d_ti_b, j, b->H,
+                                   b->stream));
+  }
+  for (; j <= b->m; ++j) {
     const int mode = (j == b->m) ? 2 : 0;
     HIP_TRY(batch_launch_sweep(b->nt, b->dim, b->storage, mode, 0, b->ntiles_s, b->d_mem, b->d_ctl, b->d_tm_s,
                                b->d_ti_s, b->partials, j, b->stream));
@@ -1136,7 +1174,7 @@ int lbtp_batch_init(const lbtp_params *members, int n, lbtp_batch **out) {
   for (int i = 0; i < n; ++i) {
     const lbtp_params &p = members[i];
     if (p.lattice != p0.lattice || p.storage != p0.storage || p.residual_stride != p0.residual_stride ||
-        p.stream != p0.stream)
+        p.stream != p0.stream || p.sweep_block != p0.sweep_block)
       return LBTP_EINVAL;
     if (p.nx % 4) return LBTP_EINVAL;   // the ensemble sweep runs four nodes per thread
     int rc = validate(&p);
@@ -1187,6 +1225,7 @@ int lbtp_batch_init(const lbtp_params *members, int n, lbtp_batch **out) {
     batch_free(b);
     return LBTP_EHIP;
   }
+  b->H = b->ctx[0]->sweep_block > 1 ? b->ctx[0]->sweep_block : 1;
   int rc = batch_tables(b, 256);
   if (rc) {
     batch_free(b);

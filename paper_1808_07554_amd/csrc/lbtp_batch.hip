@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "../../include/lbtp.h"
+#include "lbtp_block.h"
 #include "lbtp_device.h"
 
 namespace lbtp {
@@ -66,6 +67,36 @@ __global__ __launch_bounds__(NT) void batch_sweep_kernel(const Member *__restric
     else sweep_quad<DIM, T, MODE, false>(kc, fin, fout, Pb_in, Pb_out, M.itau, M.Fp, qi, acc);
   }
   if (MODE == 2) block_sum<2, NT>(acc, partials);
+}
+
+// Plain sweeps j .. j + H - 1 of every member, blocked (block_region of
+// lbtp_block.h, D2Q5): one workgroup per (member, tile) of the blocked
+// tiling.  Members with a pressure source run in the HAS_FP launch, the others
+// in the plain one.
+template <typename T, bool HAS_FP>
+__global__ __launch_bounds__(kBX * kUseW) void batch_block_kernel(const Member *__restrict__ mem,
+                                                                  const BCtl *__restrict__ ctl,
+                                                                  const int *__restrict__ tmember,
+                                                                  const int *__restrict__ tindex, int j, int H) {
+  const int m = tmember[blockIdx.x], t = tindex[blockIdx.x];
+  const BCtl &bc = ctl[m];
+  if (bc.done || bc.kbase + j > bc.kmax) return;
+  const Member &M = mem[m];
+  if ((M.Fp != nullptr) != HAS_FP) return;
+  int tx, ty;
+  block_tile_counts(M.kc, H, &tx, &ty);
+  const int in = j & 1;
+  block_region<T, HAS_FP, kUseW, kUseRW>(M.kc, typed<T>(M.f[in]), typed<T>(M.f[in ^ 1]), M.Pb[bc.pb], M.itau, M.Fp,
+                                         H, t % tx, t / tx);
+}
+
+template <typename T>
+void batch_block_launch(bool has_fp, int nblk, const Member *mem, const BCtl *ctl, const int *tm, const int *ti, int j,
+                        int H, hipStream_t s) {
+  if (has_fp)
+    hipLaunchKernelGGL((batch_block_kernel<T, true>), dim3(nblk), dim3(kBX * kUseW), 0, s, mem, ctl, tm, ti, j, H);
+  else
+    hipLaunchKernelGGL((batch_block_kernel<T, false>), dim3(nblk), dim3(kBX * kUseW), 0, s, mem, ctl, tm, ti, j, H);
 }
 
 // Stopping rule of every member (one block each) after the check sweep j = m of
@@ -254,6 +285,16 @@ template <int DIM, int NT>
 static void moments_launch(int nblk, const Member *mem, const int *tm, const int *ti, double *part, int gs,
                            int write_coef, hipStream_t s) {
   hipLaunchKernelGGL((batch_moments_kernel<DIM, NT>), dim3(nblk), dim3(NT), 0, s, mem, tm, ti, part, gs, write_coef);
+}
+
+hipError_t batch_launch_block(int storage, bool has_fp, int nblk, const Member *mem, const BCtl *ctl, const int *tm,
+                              const int *ti, int j, int H, hipStream_t s) {
+  switch (storage) {
+    case LBTP_FP16_DEV: batch_block_launch<_Float16>(has_fp, nblk, mem, ctl, tm, ti, j, H, s); break;
+    case LBTP_BF16_DEV: batch_block_launch<bf16_t>(has_fp, nblk, mem, ctl, tm, ti, j, H, s); break;
+    default: batch_block_launch<float>(has_fp, nblk, mem, ctl, tm, ti, j, H, s); break;
+  }
+  return hipGetLastError();
 }
 
 hipError_t batch_launch_moments(int dim, int nblk, const Member *mem, const int *tm, const int *ti, double *part,

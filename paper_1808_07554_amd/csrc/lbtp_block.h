@@ -1,0 +1,184 @@
+// Register-resident temporal blocking of the plain D2Q5 pressure sweep: the
+// work of one workgroup, shared by the single-context kernel
+// (lbtp_block.hip) and the ensemble kernel (lbtp_batch.hip).
+//
+// A workgroup of W wavefronts runs H consecutive plain sweeps (eq. 3-1, no
+// re-basing, no stopping-rule terms) over a region of 64 columns x (W * RW)
+// rows held in registers: each lane of a wavefront owns one column, each
+// wavefront RW consecutive rows.  The x-streamed populations move between
+// adjacent lanes (lane shuffles), the y-streamed ones between the rows of a
+// lane's registers, and across wavefronts through a small LDS exchange (one
+// barrier per sweep).  Only the tile, the nodes at least H links from any cut
+// edge of the region, is written back; the halo around it is recomputed by
+// the neighbouring workgroups.  Walls and periodic faces are handled where the
+// region meets them, with the same rules as the one-sweep kernels.
+//
+// Arithmetic and its order are those of sweep_cell (lbtp_device.h) for a
+// plain sweep, so float32 storage gives bitwise the same populations as H
+// single sweeps.  16-bit storage rounds to the storage format only when the
+// tile is written back (once per launch instead of once per sweep).
+//
+// H must be odd: a launch reads one population buffer and writes the other,
+// which is where H single sweeps would leave the state.
+#ifndef LBTP_BLOCK_H
+#define LBTP_BLOCK_H
+
+#include "lbtp_device.h"
+
+namespace lbtp {
+
+constexpr int kBX = 64;        // region columns: one per lane
+constexpr int kBWmax = 16;     // most wavefronts per workgroup
+// The launch shape in use: 8 wavefronts of 8 rows (a 64 x 64 region), so
+// that two workgroups fit a compute unit and one loads while the other
+// sweeps (measured on the 4096^2 injection problem against 16 x 6, 16 x 8,
+// 8 x 6 and 8 x 10).
+constexpr int kUseW = 8, kUseRW = 8;
+
+__device__ inline int blk_wrap(int v, int n) {
+  const int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+// Anti-bounce-back / bounce-back value of the population arriving through a
+// wall face at node (x, y) whose opposite population is o.
+__device__ inline float blk_wall_rule(const KC &kc, int face, int x, int y, float pb, float o) {
+  return kc.bc_f[face] == LBTP_BC_DIRICHLET ? 2.0f * kc.w1 * (wall_P(kc, face, x, y, 0, 1, 0) - pb) - o : o;
+}
+
+// State of one lane: RW rows of its column.
+template <int RW, bool HAS_FP>
+struct BlkRows {
+  float d[RW][4];              // deviations
+  float pb[RW + 2];            // base of rows -1 .. RW
+  float pbl[RW], pbr[RW];      // base of the x-neighbours
+  float it[RW];                // 1 / tau_f
+  float fp[HAS_FP ? RW : 1];   // dt wbar F_p
+};
+
+// H sweeps of the region.  walls: the region holds wall nodes (uniform over
+// the workgroup, so regions inside the domain skip every wall test).  Rows
+// are updated in place from the bottom up; the old +y population of the row
+// below, which the next row still pulls, is kept aside.
+template <int W, int RW, bool HAS_FP>
+__device__ inline void blk_sweep_rows(const KC &kc, BlkRows<RW, HAS_FP> &r, float (*xup)[kBWmax][kBX],
+                                  float (*xdn)[kBWmax][kBX], int H, int lane, int wv, int ux, int gx, int uy0,
+                                  bool perx, bool pery, bool walls) {
+  const bool wall_l = !perx && ux == 0, wall_r = !perx && ux == kc.nx - 1;
+  for (int s = 1; s <= H; ++s) {
+    const int rd = (s - 1) & 1;
+    // the neighbouring wavefronts' rows (garbage at the region's outer rows,
+    // which are cut edges or walls)
+    float prev1 = wv > 0 ? xup[rd][wv - 1][lane] : 0.0f;
+    const float above = wv < W - 1 ? xdn[rd][wv + 1][lane] : 0.0f;
+#pragma unroll
+    for (int t = 0; t < RW; ++t) {
+      const float p = r.pb[t + 1];
+      const float v0 = __shfl_up(r.d[t][0], 1, 64);
+      const float v2 = __shfl_down(r.d[t][2], 1, 64);
+      const float v3 = t < RW - 1 ? r.d[t + 1][3] : above;
+      float e[4];
+      e[0] = v0 + kc.w1 * (r.pbl[t] - p);
+      e[1] = prev1 + kc.w1 * (r.pb[t] - p);
+      e[2] = v2 + kc.w1 * (r.pbr[t] - p);
+      e[3] = v3 + kc.w1 * (r.pb[t + 2] - p);
+      if (walls) {
+        const int uy = uy0 + t;
+        const int wy = pery ? blk_wrap(uy, kc.ny) : uy;
+        if (wall_l) e[0] = blk_wall_rule(kc, 0, 0, wy, p, r.d[t][2]);
+        if (wall_r) e[2] = blk_wall_rule(kc, 1, kc.nx - 1, wy, p, r.d[t][0]);
+        if (!pery && uy == 0) e[1] = blk_wall_rule(kc, 2, gx, 0, p, r.d[t][3]);
+        if (!pery && uy == kc.ny - 1) e[3] = blk_wall_rule(kc, 3, gx, kc.ny - 1, p, r.d[t][1]);
+      }
+      const float dP = dpressure<2>(e, kc);
+      const float wdP = kc.w1 * dP;
+      prev1 = r.d[t][1];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float o = e[j] + (wdP - e[j]) * r.it[t];
+        if (HAS_FP) o += r.fp[t];
+        r.d[t][j] = o;
+      }
+    }
+    if (s == H) break;
+    xup[s & 1][wv][lane] = r.d[RW - 1][1];
+    xdn[s & 1][wv][lane] = r.d[0][3];
+    __syncthreads();
+  }
+}
+
+// The work of one workgroup (kBX * W threads): H plain sweeps of the region
+// of tile (tile_x, tile_y) of a context, reading fin and writing the tile to
+// fout.
+template <typename T, bool HAS_FP, int W, int RW>
+__device__ inline void block_region(const KC &kc, const FP<T> &fin, const FP<T> &fout, const float *__restrict__ Pb,
+                                    const float *__restrict__ itau, const float *__restrict__ Fp, int H, int tile_x,
+                                    int tile_y) {
+  constexpr int kBY = W * RW;     // region rows
+  // boundary rows exchanged between wavefronts, two copies (sweep s reads
+  // copy (s - 1) & 1): the +y population of each wavefront's last row and
+  // the -y population of its first row
+  __shared__ float xup[2][kBWmax][kBX];
+  __shared__ float xdn[2][kBWmax][kBX];
+  const float is = kc.inv_dev_scale;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int tcols = kBX - 2 * H, trows = kBY - 2 * H;
+  const int gx0 = tile_x * tcols - H;   // global coordinates of region node (0, 0)
+  const int gy0 = tile_y * trows - H;
+  const bool perx = kc.bc_f[0] == LBTP_BC_PERIODIC, pery = kc.bc_f[2] == LBTP_BC_PERIODIC;
+  const int ux = gx0 + lane;                                // this lane's column (unwrapped)
+  const bool colin = perx || (ux >= 0 && ux < kc.nx);
+  const int gx = perx ? blk_wrap(ux, kc.nx) : ux;
+  const int uy0 = gy0 + wv * RW;                            // this wavefront's first row (unwrapped)
+
+  auto row_in = [&](int uy) { return pery || (uy >= 0 && uy < kc.ny); };
+  auto gidx = [&](int uy) { return (pery ? blk_wrap(uy, kc.ny) : uy) * kc.nx + gx; };
+
+  BlkRows<RW, HAS_FP> r;
+#pragma unroll
+  for (int t = 0; t < RW + 2; ++t) {
+    const int uy = uy0 + t - 1;
+    r.pb[t] = (colin && row_in(uy)) ? Pb[gidx(uy)] : 0.0f;
+  }
+#pragma unroll
+  for (int t = 0; t < RW; ++t) {
+    const int uy = uy0 + t;
+    const bool in = colin && row_in(uy);
+    const int c = in ? gidx(uy) : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) r.d[t][j] = in ? Storage<T>::load(fin.p[j], c, is) : 0.0f;
+    r.it[t] = in ? itau[c] : 0.0f;
+    if (HAS_FP) r.fp[t] = in ? kc.dt * kc.wbar * Fp[c] : 0.0f;
+    r.pbl[t] = __shfl_up(r.pb[t + 1], 1, 64);
+    r.pbr[t] = __shfl_down(r.pb[t + 1], 1, 64);
+  }
+  xup[0][wv][lane] = r.d[RW - 1][1];
+  xdn[0][wv][lane] = r.d[0][3];
+  __syncthreads();
+
+  // wall nodes in the region: x = 0 or nx - 1 on a walled x axis, likewise y
+  const bool walls = (!perx && (gx0 <= 0 || gx0 + kBX > kc.nx - 1)) || (!pery && (gy0 <= 0 || gy0 + kBY > kc.ny - 1));
+  blk_sweep_rows<W, RW, HAS_FP>(kc, r, xup, xdn, H, lane, wv, ux, gx, uy0, perx, pery, walls);
+
+  // the tile: columns and rows [H, extent - H) of the region inside the domain
+  if (lane < H || lane >= kBX - H || ux >= kc.nx) return;
+#pragma unroll
+  for (int t = 0; t < RW; ++t) {
+    const int ry = wv * RW + t, uy = uy0 + t;
+    if (ry < H || ry >= kBY - H || uy >= kc.ny) continue;
+    const int c = uy * kc.nx + ux;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Storage<T>::store(fout.p[j], c, r.d[t][j], kc.dev_scale);
+  }
+}
+
+// Tiles of a context per axis for block length H.
+__host__ __device__ inline void block_tile_counts(const KC &kc, int H, int *tx, int *ty) {
+  const int tcols = kBX - 2 * H, trows = kUseW * kUseRW - 2 * H;
+  *tx = (kc.nx + tcols - 1) / tcols;
+  *ty = (kc.ny + trows - 1) / trows;
+}
+
+}  // namespace lbtp
+
+#endif  // LBTP_BLOCK_H

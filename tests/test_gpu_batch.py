@@ -1,9 +1,11 @@
 """Ensembles on the GPU: every member of a batched run equals a separate
 single-realisation run (bit for bit), and the per-member solves stop on their
 own.  (Single-realisation runs are checked against the oracle in
-test_gpu_parity.py.)  Ensembles run one sweep per launch, so with 16-bit
-storage the single runs they are compared with do too (a blocked single run
-rounds to the storage format once per launch, not once per sweep)."""
+test_gpu_parity.py.)  With float32 storage the blocked plain sweeps equal
+single sweeps bit for bit, so both sides run their defaults; with 16-bit
+storage a blocked launch rounds to the storage format once, and a single
+context runs its last partial chunk one sweep per launch where an ensemble
+runs whole chunks, so both sides run one sweep per launch there."""
 import numpy as np
 import pytest
 
@@ -34,12 +36,14 @@ def test_batch_members_equal_single_runs(storage):
     from paper_1808_07554_amd import lbtp
     shapes = [(32, 32), (64, 40), (128, 24), (36, 60), (100, 8)]
     ms = _members(shapes)
+    if storage != "fp32":
+        ms = [(dict(p, sweep_block=1), fl) for p, fl in ms]
     b = lbtp.Batch([p for p, _ in ms], m=16, storage=storage)
     singles = []
     for i, (p, fl) in enumerate(ms):
         b.set_fields(i, fl["K"], fl["phi"])
         b.set_state(i, fl["P0"], fl["S0"])
-        s = gpu_solver(p, m=16, storage=storage, sweep_block=0 if storage == "fp32" else 1)
+        s = gpu_solver(p, m=16, storage=storage)
         s.set_fields(fl["K"], fl["phi"])
         s.set_state(fl["P0"], fl["S0"])
         singles.append(s)
