@@ -97,7 +97,7 @@ int validate(const lbtp_params *p) {
   if (p->coef_model != LBTP_COEF_QUADRATIC_KR && p->coef_model != LBTP_COEF_RATIONAL) return LBTP_EINVAL;
   if (!(p->cap_B >= 0.0) || !isfinite(p->cap_B)) return LBTP_EINVAL;
   if (p->coef_model == LBTP_COEF_QUADRATIC_KR && (!(p->mu_w > 0) || !(p->mu_n > 0))) return LBTP_EINVAL;
-  if (p->sweep_block < 0 || (p->sweep_block > 1 && (p->sweep_block % 2 == 0 || p->lattice != LBTP_D2Q5)))
+  if (p->sweep_block < 0 || (p->sweep_block > 1 && (p->sweep_block % 2 == 0 || p->lattice == LBTP_D3Q7)))
     return LBTP_EINVAL;
   if (p->collision != LBTP_COLLISION_BGK && p->collision != LBTP_COLLISION_MRT) return LBTP_EINVAL;
   if (p->collision == LBTP_COLLISION_MRT) {
@@ -326,9 +326,9 @@ int lbtp_init(const lbtp_params *p, lbtp_ctx **out) {
   c->nblk = nblocks(c->ncell);
   fill_kc(c);
   {
-    const int H = p->sweep_block == 0 ? (p->lattice == LBTP_D2Q5 ? 9 : 1) : p->sweep_block;
+    const int H = p->sweep_block == 0 ? (p->lattice == LBTP_D3Q7 ? 1 : 9) : p->sweep_block;
     if (H > 1) {
-      if (!block_sweeps_supported(c->dim, c->kc, H)) {
+      if (!block_sweeps_supported(c->lk, c->kc, H)) {
         delete c;
         return LBTP_EINVAL;
       }
@@ -569,7 +569,7 @@ hipError_t enqueue_chunk(lbtp_ctx *c, long long k0, int pb, bool checks, hipStre
   for (; H > 1 && i + H - 1 <= m - 1; i += H) {
     const long long k = k0 + i;
     const int parity = (int)((c->fs + k) & 1);
-    const hipError_t e = launch_f_block(c->p.storage, c->kc, fptrs(c, c->fbuf[parity]),
+    const hipError_t e = launch_f_block(c->lk, c->p.storage, c->kc, fptrs(c, c->fbuf[parity]),
                                         fptrs(c, c->fbuf[parity ^ 1]), c->Pb[pb], c->itau, Fp_or_null(c), c->ctl,
                                         k, H, s);
     if (e != hipSuccess) return e;
@@ -733,7 +733,7 @@ int lbtp_probe_sweeps(lbtp_ctx *c, long long launches) {
   for (long long i = 0; i < launches; ++i) {
     const int parity = c->fs & 1;
     if (H > 1) {
-      HIP_TRY(launch_f_block(c->p.storage, c->kc, fptrs(c, c->fbuf[parity]), fptrs(c, c->fbuf[parity ^ 1]),
+      HIP_TRY(launch_f_block(c->lk, c->p.storage, c->kc, fptrs(c, c->fbuf[parity]), fptrs(c, c->fbuf[parity ^ 1]),
                              c->Pb[c->pbs], c->itau, Fp_or_null(c), c->ctl, 1, H, c->stream));
     } else {
       HIP_TRY(launch_f_sweep(c->lk, c->p.storage, c->kc, fptrs(c, c->fbuf[parity]), fptrs(c, c->fbuf[parity ^ 1]),

@@ -421,6 +421,205 @@ __global__ __launch_bounds__(kThreads) void q9_f_sweep_vec_kernel(KC kc, FPtrs f
   if (MODE == 2) block_sum<2>(acc, partials);
 }
 
+// ------------------------------------------------ blocked plain sweeps
+// H plain sweeps per launch with the region held in registers, as the D2Q5
+// blocked kernel (lbtp_block.h) does: each lane owns one column of a
+// 64-column region, each of the kQ9W wavefronts kQ9RW consecutive rows.
+// Populations moving along x or diagonally come from the adjacent lanes
+// (shuffles), those moving along y from the lane's own rows or, across
+// wavefronts, through an LDS exchange of the three populations that leave a
+// row upwards (j = 1, 4, 5) or downwards (j = 3, 6, 7).  Only the tile at
+// least H links from every cut edge of the region is written back.  The
+// arithmetic is that of q9_f_sweep_kernel for a plain sweep (bitwise the
+// same populations with float32 storage); walls follow q9_load_e, with the
+// y face's priority at corners and per-link conditions.  H odd: a launch
+// reads one population buffer and writes the other.
+constexpr int kQ9BX = 64, kQ9W = 16, kQ9RW = 4;
+
+__device__ inline int q9_wrap_any(int v, int n) {
+  const int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+template <typename T, bool HAS_FP>
+__global__ __launch_bounds__(kQ9BX * kQ9W) void q9_f_block_kernel(KC kc, FPtrs fin_, FPtrs fout_,
+                                                                  const float *__restrict__ Pb,
+                                                                  const float *__restrict__ itau,
+                                                                  const float *__restrict__ Fp,
+                                                                  const Ctl *__restrict__ ctl, long long k, int H,
+                                                                  int tiles_x) {
+  if (ctl->done || k > ctl->kmax) return;
+  constexpr int W = kQ9W, RW = kQ9RW, BY = W * RW;
+  // two copies (sweep s reads copy (s - 1) & 1): the upward populations of
+  // each wavefront's last row, the downward ones of its first row
+  __shared__ float xup[2][3][W][kQ9BX];
+  __shared__ float xdn[2][3][W][kQ9BX];
+  const FP<T> fin = typed<T>(fin_), fout = typed<T>(fout_);
+  const float is = kc.inv_dev_scale;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int tcols = kQ9BX - 2 * H, trows = BY - 2 * H;
+  const int gx0 = (int)(blockIdx.x % tiles_x) * tcols - H;   // global coordinates of region node (0, 0)
+  const int gy0 = (int)(blockIdx.x / tiles_x) * trows - H;
+  const bool perx = kc.bc_f[0] == LBTP_BC_PERIODIC, pery = kc.bc_f[2] == LBTP_BC_PERIODIC;
+  const int ux = gx0 + lane;                                // this lane's column (unwrapped)
+  const bool colin = perx || (ux >= 0 && ux < kc.nx);
+  const int gx = perx ? q9_wrap_any(ux, kc.nx) : ux;
+  const int uy0 = gy0 + wv * RW;                            // this wavefront's first row (unwrapped)
+  auto row_in = [&](int uy) { return pery || (uy >= 0 && uy < kc.ny); };
+  auto gidx = [&](int uy) { return (pery ? q9_wrap_any(uy, kc.ny) : uy) * kc.nx + gx; };
+
+  float d[RW][8], it[RW];
+  float fpv[HAS_FP ? RW : 1];
+  float pb[RW + 2], pbl[RW + 2], pbr[RW + 2];   // base of rows -1 .. RW at x, x - 1, x + 1
+#pragma unroll
+  for (int t = 0; t < RW + 2; ++t) {
+    const int uy = uy0 + t - 1;
+    pb[t] = (colin && row_in(uy)) ? Pb[gidx(uy)] : 0.0f;
+    pbl[t] = __shfl_up(pb[t], 1, 64);
+    pbr[t] = __shfl_down(pb[t], 1, 64);
+  }
+#pragma unroll
+  for (int t = 0; t < RW; ++t) {
+    const int uy = uy0 + t;
+    const bool in = colin && row_in(uy);
+    const int c = in ? gidx(uy) : 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) d[t][j] = in ? Storage<T>::load(fin.p[j], c, is) : 0.0f;
+    it[t] = in ? itau[c] : 0.0f;
+    if (HAS_FP) fpv[t] = in ? kc.dt * kc.wbar * Fp[c] : 0.0f;
+  }
+  xup[0][0][wv][lane] = d[RW - 1][1];
+  xup[0][1][wv][lane] = d[RW - 1][4];
+  xup[0][2][wv][lane] = d[RW - 1][5];
+  xdn[0][0][wv][lane] = d[0][3];
+  xdn[0][1][wv][lane] = d[0][6];
+  xdn[0][2][wv][lane] = d[0][7];
+
+  // wall nodes in the region: x = 0 or nx - 1 on a walled x axis, likewise y
+  const bool walls = (!perx && (gx0 <= 0 || gx0 + kQ9BX > kc.nx - 1)) || (!pery && (gy0 <= 0 || gy0 + BY > kc.ny - 1));
+  const bool wall_l = !perx && ux == 0, wall_r = !perx && ux == kc.nx - 1;
+  // The wall rules of q9_load_e as e = c + m o per link arriving through a
+  // wall (m = -1, c = 2 w (P_w - P_b) for anti-bounce-back; m = 1, c = 0 for
+  // bounce-back); fixed while no sweep re-bases.  Three links per face and
+  // node: x faces per region row, y faces per column.
+  __shared__ float wc_x[2][BY][3], wm_x[2][BY][3], wc_y[2][kQ9BX][3], wm_y[2][kQ9BX][3];
+  if (walls) {
+    auto rule = [&](int face, int j, int along_x, int along_y, float p, float &c, float &m) {
+      const int slot = q9_wall_slot(face, q9x(j), q9y(j));
+      if (q9_link_bc(kc.bc_f, kc.wtF, face, face < 2 ? along_y : along_x, slot) == LBTP_BC_DIRICHLET) {
+        c = 2.0f * q9w(kc, j) * (wall_P(kc, face, along_x, along_y, 0, 3, slot) - p);
+        m = -1.0f;
+      } else {
+        c = 0.0f;
+        m = 1.0f;
+      }
+    };
+    const int jl[3] = {0, 4, 7}, jr[3] = {2, 5, 6}, jb[3] = {1, 4, 5}, jt[3] = {3, 6, 7};
+#pragma unroll
+    for (int t = 0; t < RW; ++t) {
+      const int uy = uy0 + t, ry = wv * RW + t;
+      const bool in = row_in(uy) && colin;
+      const int wy = pery ? q9_wrap_any(uy, kc.ny) : uy;
+      const float p = pb[t + 1];
+      if (in && wall_l)
+        for (int k = 0; k < 3; ++k) rule(0, jl[k], 0, wy, p, wc_x[0][ry][k], wm_x[0][ry][k]);
+      if (in && wall_r)
+        for (int k = 0; k < 3; ++k) rule(1, jr[k], kc.nx - 1, wy, p, wc_x[1][ry][k], wm_x[1][ry][k]);
+      if (in && !pery && uy == 0)
+        for (int k = 0; k < 3; ++k) rule(2, jb[k], gx, 0, p, wc_y[0][lane][k], wm_y[0][lane][k]);
+      if (in && !pery && uy == kc.ny - 1)
+        for (int k = 0; k < 3; ++k) rule(3, jt[k], gx, kc.ny - 1, p, wc_y[1][lane][k], wm_y[1][lane][k]);
+    }
+  }
+  __syncthreads();
+  for (int s = 1; s <= H; ++s) {
+    const int rd = (s - 1) & 1;
+    // the row below the first and the row above the last (garbage at the
+    // region's outer rows, which are cut edges or walls)
+    float p1 = wv > 0 ? xup[rd][0][wv - 1][lane] : 0.0f;
+    float p4 = wv > 0 ? xup[rd][1][wv - 1][lane] : 0.0f;
+    float p5 = wv > 0 ? xup[rd][2][wv - 1][lane] : 0.0f;
+    const float a3 = wv < W - 1 ? xdn[rd][0][wv + 1][lane] : 0.0f;
+    const float a6 = wv < W - 1 ? xdn[rd][1][wv + 1][lane] : 0.0f;
+    const float a7 = wv < W - 1 ? xdn[rd][2][wv + 1][lane] : 0.0f;
+#pragma unroll
+    for (int t = 0; t < RW; ++t) {
+      // rows are updated in place from the bottom up: p1, p4, p5 hold the old
+      // upward populations of the row below, the row above is still old
+      const float q3 = t < RW - 1 ? d[t + 1][3] : a3;
+      const float q6 = t < RW - 1 ? d[t + 1][6] : a6;
+      const float q7 = t < RW - 1 ? d[t + 1][7] : a7;
+      const float p = pb[t + 1];
+      float e[8];
+      e[0] = __shfl_up(d[t][0], 1, 64) + kc.w1 * (pbl[t + 1] - p);    // from (x - 1, y)
+      e[1] = p1 + kc.w1 * (pb[t] - p);                                // (x, y - 1)
+      e[2] = __shfl_down(d[t][2], 1, 64) + kc.w1 * (pbr[t + 1] - p);  // (x + 1, y)
+      e[3] = q3 + kc.w1 * (pb[t + 2] - p);                            // (x, y + 1)
+      e[4] = __shfl_up(p4, 1, 64) + kc.w2 * (pbl[t] - p);             // (x - 1, y - 1)
+      e[5] = __shfl_down(p5, 1, 64) + kc.w2 * (pbr[t] - p);           // (x + 1, y - 1)
+      e[6] = __shfl_down(q6, 1, 64) + kc.w2 * (pbr[t + 2] - p);       // (x + 1, y + 1)
+      e[7] = __shfl_up(q7, 1, 64) + kc.w2 * (pbl[t + 2] - p);         // (x - 1, y + 1)
+      if (walls) {
+        // links whose pull source lies beyond a wall: e = c + m o with the
+        // node's old opposite population o (tables filled at load); x faces
+        // first, then y faces, so the y face decides at corners
+        const int ry = wv * RW + t, uy = uy0 + t;
+        if (wall_l) {
+          e[0] = wc_x[0][ry][0] + wm_x[0][ry][0] * d[t][2];
+          e[4] = wc_x[0][ry][1] + wm_x[0][ry][1] * d[t][6];
+          e[7] = wc_x[0][ry][2] + wm_x[0][ry][2] * d[t][5];
+        }
+        if (wall_r) {
+          e[2] = wc_x[1][ry][0] + wm_x[1][ry][0] * d[t][0];
+          e[5] = wc_x[1][ry][1] + wm_x[1][ry][1] * d[t][7];
+          e[6] = wc_x[1][ry][2] + wm_x[1][ry][2] * d[t][4];
+        }
+        if (!pery && uy == 0) {
+          e[1] = wc_y[0][lane][0] + wm_y[0][lane][0] * d[t][3];
+          e[4] = wc_y[0][lane][1] + wm_y[0][lane][1] * d[t][6];
+          e[5] = wc_y[0][lane][2] + wm_y[0][lane][2] * d[t][7];
+        }
+        if (!pery && uy == kc.ny - 1) {
+          e[3] = wc_y[1][lane][0] + wm_y[1][lane][0] * d[t][1];
+          e[6] = wc_y[1][lane][1] + wm_y[1][lane][1] * d[t][4];
+          e[7] = wc_y[1][lane][2] + wm_y[1][lane][2] * d[t][5];
+        }
+      }
+      const float dP = q9_dpressure(e, kc);
+      float oc[8];
+      q9_collide(kc, e, dP, it[t], oc);
+      p1 = d[t][1];
+      p4 = d[t][4];
+      p5 = d[t][5];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        float o = oc[j];
+        if (HAS_FP) o += fpv[t];
+        d[t][j] = o;
+      }
+    }
+    if (s == H) break;
+    xup[s & 1][0][wv][lane] = d[RW - 1][1];
+    xup[s & 1][1][wv][lane] = d[RW - 1][4];
+    xup[s & 1][2][wv][lane] = d[RW - 1][5];
+    xdn[s & 1][0][wv][lane] = d[0][3];
+    xdn[s & 1][1][wv][lane] = d[0][6];
+    xdn[s & 1][2][wv][lane] = d[0][7];
+    __syncthreads();
+  }
+
+  // the tile: columns and rows [H, extent - H) of the region inside the domain
+  if (lane < H || lane >= kQ9BX - H || ux >= kc.nx) return;
+#pragma unroll
+  for (int t = 0; t < RW; ++t) {
+    const int ry = wv * RW + t, uy = uy0 + t;
+    if (ry < H || ry >= BY - H || uy >= kc.ny) continue;
+    const int c = uy * kc.nx + ux;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) Storage<T>::store(fout.p[j], c, d[t][j], kc.dev_scale);
+  }
+}
+
 // ------------------------------------------------------------------ moments
 template <bool HAS_FS>
 __global__ __launch_bounds__(kThreads) void q9_moments_kernel(KC kc, GPtrs g, const float *__restrict__ K,
@@ -671,6 +870,24 @@ hipError_t launch_f_sweep_q9(int storage, const KC &kc, FPtrs fin, FPtrs fout, c
       else Q9_SWEEP(2, false);
     }
 #undef Q9_SWEEP
+  });
+  return hipGetLastError();
+}
+
+int block_sweeps_supported_q9(int H) { return H >= 3 && H % 2 == 1 && kQ9BX - 2 * H >= 16 && kQ9W * kQ9RW - 2 * H >= 16; }
+
+hipError_t launch_f_block_q9(int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, const float *itau,
+                             const float *Fp, const Ctl *ctl, long long k, int H, hipStream_t s) {
+  const int tcols = kQ9BX - 2 * H, trows = kQ9W * kQ9RW - 2 * H;
+  const int tx = (kc.nx + tcols - 1) / tcols, ty = (kc.ny + trows - 1) / trows;
+  q9_dispatch(storage, 0, [&](auto t, auto) {
+    using T = std::remove_pointer_t<decltype(t)>;
+    if (Fp)
+      hipLaunchKernelGGL((q9_f_block_kernel<T, true>), dim3(tx * ty), dim3(kQ9BX * kQ9W), 0, s, kc, fin, fout, Pb,
+                         itau, Fp, ctl, k, H, tx);
+    else
+      hipLaunchKernelGGL((q9_f_block_kernel<T, false>), dim3(tx * ty), dim3(kQ9BX * kQ9W), 0, s, kc, fin, fout, Pb,
+                         itau, Fp, ctl, k, H, tx);
   });
   return hipGetLastError();
 }

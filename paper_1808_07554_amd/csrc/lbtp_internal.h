@@ -93,11 +93,15 @@ hipError_t launch_f_sweep(int dim, int storage, const KC &kc, FPtrs fin, FPtrs f
                           float *Pb_out, const float *itau, const float *Fp, double *partials, const Ctl *ctl,
                           long long k, int local, int mode, hipStream_t s);
 // H consecutive plain pressure sweeps (no re-basing, no stopping-rule terms)
-// in one launch, sweeps k .. k + H - 1 (temporal blocking through LDS, D2Q5
-// 2-D, H odd); fin holds the state before sweep k, fout receives it after.
+// in one launch, sweeps k .. k + H - 1 (temporal blocking, the region in
+// registers; D2Q5 and D2Q9, H odd); fin holds the state before sweep k, fout
+// receives it after.  dim is the lattice kind (2, 3 or kD2Q9).
 int block_sweeps_supported(int dim, const KC &kc, int H);
-hipError_t launch_f_block(int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, const float *itau,
-                          const float *Fp, const Ctl *ctl, long long k, int H, hipStream_t s);
+hipError_t launch_f_block(int dim, int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb,
+                          const float *itau, const float *Fp, const Ctl *ctl, long long k, int H, hipStream_t s);
+int block_sweeps_supported_q9(int H);
+hipError_t launch_f_block_q9(int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, const float *itau,
+                             const float *Fp, const Ctl *ctl, long long k, int H, hipStream_t s);
 // Check of the stopping rule at iteration ctl->kcheck + m (device-side
 // count, so a captured chunk serves every position in the solve).
 hipError_t launch_finish_residual(const double *partials, int nblk, Ctl *ctl, int m, hipStream_t s);

@@ -1,5 +1,6 @@
-"""Temporal blocking of the plain pressure sweeps (several sweeps per launch
-through LDS, D2Q5) against one sweep per launch, through the C ABI.
+"""Temporal blocking of the plain pressure sweeps (several sweeps per launch,
+the region held in registers; D2Q5 and D2Q9) against one sweep per launch,
+through the C ABI.
 
 With float32 storage the blocked launches perform the same arithmetic in the
 same order, so populations, pressure and saturation must agree bitwise: on
@@ -7,8 +8,11 @@ walled, periodic and mixed boxes, boxes narrower than a tile or than the
 halo, ragged tile counts, per-link Dirichlet data, a pressure source and
 every block length.  16-bit storage rounds to its format once per launch
 instead of once per sweep, so there the blocked path must stay within the
-format's bound of the one-sweep path.  The oracle parity of the blocked path
-itself is covered by every other D2Q5 test, which runs it by default."""
+format's bound of the one-sweep path.  D2Q9 adds corners (the y face's rule),
+diagonals that wrap across a periodic axis beside a wall, per-link wall data
+and conditions (the five-spot) and the MRT collision.  The oracle parity of
+the blocked path itself is covered by every other D2Q5 and D2Q9 test, which
+run it by default."""
 import numpy as np
 import pytest
 
@@ -87,3 +91,76 @@ def test_blocked_16bit_within_format_bound(storage):
         err = float(np.abs(ref[k] - got[k]).max())
         print(storage, k, f"{err:.2e}")
         assert err <= 16 * ur, (storage, k, err)
+
+
+# ----------------------------------------------------------------- D2Q9
+def _run_q9(shape, bcs, sweep_block, storage="fp32", Fp=False, wall_face=None, collision=None, params=None,
+            fields=None, iters=(200, 130)):
+    nx, ny = shape
+    if params is None:
+        params, _ = inputs.injection_problem(shape, 1.0, 4.0, 11, 12)
+        params = dict(params, lattice="D2Q9", beta=0.2, bc_f=bcs[0], bc_g=bcs[1])
+    if collision is not None:
+        params = dict(params, collision=collision)
+    fshape = (1, ny, nx)
+    if fields is None:
+        K = f32(np.exp(inputs.gaussian_random_field((ny, nx), 4.0, nx + ny)).reshape(fshape) * params["mu_n"] / 6)
+        phi = f32(inputs.uniform_field(fshape, 0.15, 0.3, 7))
+        P0, S0 = (f32(a) for a in smooth_state(fshape, 5))
+    else:
+        K, phi, P0, S0 = (f32(fields[k]) for k in ("K", "phi", "P0", "S0"))
+    fp = f32(mean_free(np.sin(np.arange(nx * ny) * 0.37)) * 1e-3).reshape(fshape) if Fp else None
+    g = gpu_solver(params, m=64, storage=storage, sweep_block=sweep_block)
+    g.set_fields(K, phi, Fp=fp)
+    g.set_state(P0, S0)
+    if wall_face is not None:
+        n_along = ny if wall_face < 2 else nx
+        g.set_wall_values(wall_face, P=f32(1.0 + 0.1 * np.cos(np.arange(3 * n_along) * 0.2)))
+    for n, k in enumerate(iters):
+        g.update_coefficients()
+        assert g.pressure_solve(-1.0, k)[0] == k
+        if n + 1 < len(iters):
+            g.saturation_step()
+    f, gg = g.populations()
+    out = dict(f=f.cpu().numpy(), g=gg.cpu().numpy(), P=g.pressure().cpu().numpy(), S=g.saturation().cpu().numpy())
+    g.close()
+    return out
+
+
+Q9_WALLS = ([("abb", 1.0), ("abb", 0.0), ("bb",), ("abb", 0.4)], [("abb", 1.0), ("outflow",), ("bb",), ("bb",)])
+
+Q9_CASES = [
+    ((200, 150), Q9_WALLS, {}),                                   # corners: the y face decides
+    ((64, 64), PERIODIC, dict(Fp=True)),
+    ((20, 12), PERIODIC, dict(Fp=True)),
+    ((130, 70), MIXED, {}),                                       # diagonals wrap in x, reflect in y
+    ((96, 47), Q9_WALLS, dict(wall_face=0)),                      # per-link wall data, three slots
+    ((90, 40), MIXED, dict(wall_face=3)),
+    ((7, 300), MIXED, {}),
+    ((200, 150), Q9_WALLS, dict(collision=("mrt", 1.4, 1.7, 0.6))),
+]
+
+
+@pytest.mark.parametrize("shape,bcs,kw", Q9_CASES)
+def test_q9_blocked_sweeps_bitwise_equal_single_sweeps(shape, bcs, kw):
+    ref = _run_q9(shape, bcs, 1, **kw)
+    got = _run_q9(shape, bcs, 9, **kw)
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), (shape, k, float(np.abs(ref[k] - got[k]).max()))
+
+
+def test_q9_five_spot_blocked_bitwise():
+    """Per-link wall conditions (wells in no-flux walls) on the blocked path."""
+    params, fl = inputs.five_spot(96)
+    ref = _run_q9((96, 96), None, 1, params=params, fields=fl, iters=(300, 128))
+    got = _run_q9((96, 96), None, 9, params=params, fields=fl, iters=(300, 128))
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), k
+
+
+@pytest.mark.parametrize("H", [3, 5, 7, 21, 23])
+def test_q9_every_block_length_bitwise(H):
+    ref = _run_q9((150, 110), Q9_WALLS, 1)
+    got = _run_q9((150, 110), Q9_WALLS, H)
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), (H, k)
