@@ -41,10 +41,12 @@ HBM_PEAK_GBS = 8000.0
 # 256 compute units at 2.4 GHz (the 157.3 TFLOP/s figure counts packed FMA,
 # four flops per lane and clock)
 ALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
-# flops of one plain D2Q5 pressure sweep per node: four pulls against the
-# node's base (sub, mul, add each), P - P_b (three adds, one multiply),
-# w P, four BGK relaxations (sub, mul, add each)
-BLOCK_FLOPS_PER_NODE_SWEEP = 29
+# flops of one plain pressure sweep per node.  D2Q5: four pulls against the
+# node's base (sub, mul, add each), P - P_b (three adds, one multiply), w P,
+# four BGK relaxations (sub, mul, add each).  D2Q9: eight pulls (sub, mul,
+# add), P - P_b (seven adds, one multiply), eight BGK relaxations (w_j P,
+# sub, mul, add each).
+BLOCK_FLOPS_PER_NODE_SWEEP = {"D2Q5": 29, "D2Q9": 64}
 # algorithmic bytes of one plain pressure sweep per node: the Q-1 stored
 # deviations read and written, 1/tau_f and the base pressure P_b read
 POP_BYTES = {"fp32": 4, "fp16": 2, "bf16": 2}
@@ -301,7 +303,7 @@ def main():
                if (a.workload == "injection2d" and a.n == 4096 and a.lattice == "D2Q5") else None)
     kname = sweep_kernel_name(a.storage, 3 if a.workload == "injection3d" else 2, params["lattice"], H)
     if H > 1:
-        flops = BLOCK_FLOPS_PER_NODE_SWEEP * ncell * H
+        flops = BLOCK_FLOPS_PER_NODE_SWEEP[params["lattice"]] * ncell * H
         achieved = flops / launch_s / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(ALU_PEAK_TFLOPS, 2),
                     "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": traffic,

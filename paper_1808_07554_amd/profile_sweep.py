@@ -35,10 +35,10 @@ def source_digest():
 
 def sweep_kernel_name(storage, dim=2, lattice=None, sweeps_per_launch=9):
     """The kernel that runs the plain pull-form pressure sweeps of a full
-    chunk with nx % 4 == 0: the blocked kernel on D2Q5 (several sweeps per
-    launch), else the 4-nodes-per-thread sweep."""
+    chunk with nx % 4 == 0: the blocked kernels on D2Q5 and D2Q9 (several
+    sweeps per launch), else the 4-nodes-per-thread sweep."""
     if lattice == "D2Q9":
-        return "q9_f_sweep_vec_kernel"
+        return "q9_f_block_kernel" if sweeps_per_launch > 1 else "q9_f_sweep_vec_kernel"
     if dim == 2 and sweeps_per_launch > 1:
         return "f_block_kernel"
     return "f_sweep_vec_kernel"
