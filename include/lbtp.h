@@ -131,10 +131,11 @@ typedef struct lbtp_params {
                                   vary with S and K from node to node; 0 = constant Ds.
                                   Single contexts only (ensembles: LBTP_EINVAL). */
   int sweep_block;             /* plain pressure sweeps fused into one launch inside the
-                                  captured chunks of m sweeps (temporal blocking through
-                                  LDS; D2Q5 only, float32 results bitwise unchanged):
-                                  0 = library default (9 on D2Q5, none elsewhere),
-                                  1 = one sweep per launch, or an odd number 3..23 (D2Q5) */
+                                  captured chunks of m sweeps (temporal blocking with the
+                                  region in registers; D2Q5 and D2Q9, float32 results
+                                  bitwise unchanged; 16-bit storage rounds once per launch):
+                                  0 = library default (9 on D2Q5 and D2Q9, none on D3Q7),
+                                  1 = one sweep per launch, or an odd number 3..23 */
   int collision;               /* lbtp_collision of the pressure lattice */
   double mrt_rates[3];         /* MRT: s0, s_q, s_p (unused for BGK) */
 } lbtp_params;
