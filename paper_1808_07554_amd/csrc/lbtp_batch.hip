@@ -9,13 +9,16 @@
 // launch sequence serves members whose pressure solves need different
 // iteration counts.  A chunk of m sweeps plus the stopping-rule reduction is
 // captured once in a HIP graph and replayed until every member has stopped;
-// the host reads one counter per chunk, one chunk behind the GPU.
+// the host reads one counter per chunk, one chunk behind the GPU.  Inside a
+// chunk the plain sweeps run blocked as in a single context (several sweeps
+// per launch over a second (member, tile) table; block_region of
+// lbtp_block.h).
 //
 // The pressure state of every member is always in buffer 0 between solves:
 // sweep k reads buffer k & 1, the residual stride m is even and solves stop
 // on multiples of m.  Member arithmetic is the single-realisation arithmetic
 // (the same device functions), so a member's results are bit-identical to a
-// lbtp_ctx run of that member.
+// lbtp_ctx run of that member with the same sweeps per launch.
 #include <string.h>
 
 #include <vector>
