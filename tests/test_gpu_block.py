@@ -164,3 +164,14 @@ def test_q9_every_block_length_bitwise(H):
     got = _run_q9((150, 110), Q9_WALLS, H)
     for k in ref:
         assert np.array_equal(ref[k], got[k]), (H, k)
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_q9_blocked_16bit_within_format_bound(storage):
+    ref = _run_q9((200, 150), Q9_WALLS, 1, storage=storage)
+    got = _run_q9((200, 150), Q9_WALLS, 9, storage=storage)
+    ur = UNIT_ROUNDOFF[storage]
+    for k in ("P", "S"):
+        err = float(np.abs(ref[k] - got[k]).max())
+        print("D2Q9", storage, k, f"{err:.2e}")
+        assert err <= 16 * ur, (storage, k, err)
