@@ -74,8 +74,8 @@ __device__ inline void blk_sweep_rows(const KC &kc, BlkRows<RW, HAS_FP> &r, floa
 #pragma unroll
     for (int t = 0; t < RW; ++t) {
       const float p = r.pb[t + 1];
-      const float v0 = __shfl_up(r.d[t][0], 1, 64);
-      const float v2 = __shfl_down(r.d[t][2], 1, 64);
+      const float v0 = lane_from_left(r.d[t][0]);
+      const float v2 = lane_from_right(r.d[t][2]);
       const float v3 = t < RW - 1 ? r.d[t + 1][3] : above;
       float e[4];
       e[0] = v0 + kc.w1 * (r.pbl[t] - p);
@@ -145,8 +145,14 @@ __device__ inline void block_region(const KC &kc, const FP<T> &fin, const FP<T> 
     const int uy = uy0 + t;
     const bool in = colin && row_in(uy);
     const int c = in ? gidx(uy) : 0;
+    // every load is issued (from node 0 outside the domain) and the value
+    // selected afterwards: a load made conditional on the row would make the
+    // compiler wait for each one before issuing the next
 #pragma unroll
-    for (int j = 0; j < 4; ++j) r.d[t][j] = in ? Storage<T>::load(fin.p[j], c, is) : 0.0f;
+    for (int j = 0; j < 4; ++j) {
+      const float v = Storage<T>::load(fin.p[j], c, is);
+      r.d[t][j] = in ? v : 0.0f;
+    }
     r.it[t] = in ? itau[c] : 0.0f;
     if (HAS_FP) r.fp[t] = in ? kc.dt * kc.wbar * Fp[c] : 0.0f;
     r.pbl[t] = __shfl_up(r.pb[t + 1], 1, 64);

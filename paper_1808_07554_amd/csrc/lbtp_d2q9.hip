@@ -484,7 +484,10 @@ __global__ __launch_bounds__(kQ9BX * kQ9W) void q9_f_block_kernel(KC kc, FPtrs f
     const bool in = colin && row_in(uy);
     const int c = in ? gidx(uy) : 0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) d[t][j] = in ? Storage<T>::load(fin.p[j], c, is) : 0.0f;
+    for (int j = 0; j < 8; ++j) {   // unconditional loads, selected afterwards (as in block_region)
+      const float v = Storage<T>::load(fin.p[j], c, is);
+      d[t][j] = in ? v : 0.0f;
+    }
     it[t] = in ? itau[c] : 0.0f;
     if (HAS_FP) fpv[t] = in ? kc.dt * kc.wbar * Fp[c] : 0.0f;
   }
@@ -551,14 +554,14 @@ __global__ __launch_bounds__(kQ9BX * kQ9W) void q9_f_block_kernel(KC kc, FPtrs f
       const float q7 = t < RW - 1 ? d[t + 1][7] : a7;
       const float p = pb[t + 1];
       float e[8];
-      e[0] = __shfl_up(d[t][0], 1, 64) + kc.w1 * (pbl[t + 1] - p);    // from (x - 1, y)
-      e[1] = p1 + kc.w1 * (pb[t] - p);                                // (x, y - 1)
-      e[2] = __shfl_down(d[t][2], 1, 64) + kc.w1 * (pbr[t + 1] - p);  // (x + 1, y)
-      e[3] = q3 + kc.w1 * (pb[t + 2] - p);                            // (x, y + 1)
-      e[4] = __shfl_up(p4, 1, 64) + kc.w2 * (pbl[t] - p);             // (x - 1, y - 1)
-      e[5] = __shfl_down(p5, 1, 64) + kc.w2 * (pbr[t] - p);           // (x + 1, y - 1)
-      e[6] = __shfl_down(q6, 1, 64) + kc.w2 * (pbr[t + 2] - p);       // (x + 1, y + 1)
-      e[7] = __shfl_up(q7, 1, 64) + kc.w2 * (pbl[t + 2] - p);         // (x - 1, y + 1)
+      e[0] = lane_from_left(d[t][0]) + kc.w1 * (pbl[t + 1] - p);     // from (x - 1, y)
+      e[1] = p1 + kc.w1 * (pb[t] - p);                               // (x, y - 1)
+      e[2] = lane_from_right(d[t][2]) + kc.w1 * (pbr[t + 1] - p);    // (x + 1, y)
+      e[3] = q3 + kc.w1 * (pb[t + 2] - p);                           // (x, y + 1)
+      e[4] = lane_from_left(p4) + kc.w2 * (pbl[t] - p);              // (x - 1, y - 1)
+      e[5] = lane_from_right(p5) + kc.w2 * (pbr[t] - p);             // (x + 1, y - 1)
+      e[6] = lane_from_right(q6) + kc.w2 * (pbr[t + 2] - p);         // (x + 1, y + 1)
+      e[7] = lane_from_left(q7) + kc.w2 * (pbl[t + 2] - p);          // (x - 1, y + 1)
       if (walls) {
         // links whose pull source lies beyond a wall: e = c + m o with the
         // node's old opposite population o (tables filled at load); x faces

@@ -181,6 +181,17 @@ __device__ inline float inv_tau_g_of(float S, float K, const KC &kc) {
   return 1.0f / (0.5f + Ds * kc.inv_bcs2dt);
 }
 
+// The value of the lane one below (from_left) or one above (from_right) in
+// the wavefront, moved by the data-parallel primitives' wavefront shift
+// (a VALU operation, no LDS round trip).  Lane 0, respectively lane 63, gets
+// 0: callers use these only where the edge lanes hold halo columns whose
+// values are never kept.
+__device__ inline float lane_from_left(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));   // wave_shr:1
+}
+__device__ inline float lane_from_right(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));   // wave_shl:1
+}
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
