@@ -81,7 +81,8 @@ __global__ __launch_bounds__(kBX * kUseW) void batch_block_kernel(const Member *
                                                                   const BCtl *__restrict__ ctl,
                                                                   const int *__restrict__ tmember,
                                                                   const int *__restrict__ tindex, int j, int H) {
-  const int m = tmember[blockIdx.x], t = tindex[blockIdx.x];
+  const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const int m = tmember[b], t = tindex[b];
   const BCtl &bc = ctl[m];
   if (bc.done || bc.kbase + j > bc.kmax) return;
   const Member &M = mem[m];

@@ -14,8 +14,9 @@ __global__ __launch_bounds__(kBX * W) void f_block_kernel(
     KC kc, FPtrs fin_, FPtrs fout_, const float *__restrict__ Pb, const float *__restrict__ itau,
     const float *__restrict__ Fp, const Ctl *__restrict__ ctl, long long k, int H, int tiles_x) {
   if (ctl->done || k > ctl->kmax) return;
-  block_region<T, HAS_FP, W, RW>(kc, typed<T>(fin_), typed<T>(fout_), Pb, itau, Fp, H, (int)(blockIdx.x % tiles_x),
-                                 (int)(blockIdx.x / tiles_x));
+  // tiles row by row (measured faster here than in bands)
+  const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  block_region<T, HAS_FP, W, RW>(kc, typed<T>(fin_), typed<T>(fout_), Pb, itau, Fp, H, t % tiles_x, t / tiles_x);
 }
 
 template <typename T, int W, int RW>

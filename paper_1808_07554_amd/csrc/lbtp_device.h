@@ -193,6 +193,26 @@ __device__ inline float lane_from_right(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));   // wave_shl:1
 }
 
+// Tile handled by workgroup b of a launch over n tiles.  Workgroups are dealt
+// to the 8 XCDs in turn (b % 8); this gives each XCD a contiguous run of
+// tiles, so that the halos neighbouring tiles share stay in that XCD's L2.
+__device__ inline int xcd_tile(int b, int n) {
+  constexpr int kXcd = 8;
+  const int q = n / kXcd, r = n % kXcd, x = b % kXcd;
+  return x * q + (x < r ? x : r) + b / kXcd;
+}
+
+// Position (tile_x, tile_y) of tile t of a tiles_x x tiles_y grid taken in
+// bands of `band` tiles' width, each band row by row: runs of consecutive
+// tiles form patches that overlap in x and y.
+__host__ __device__ inline void band_tile(int t, int tiles_x, int tiles_y, int band, int *tile_x, int *tile_y) {
+  const int full = tiles_x / band, b = t / (band * tiles_y);
+  const int w = b < full ? band : tiles_x - full * band;
+  const int r = t - b * band * tiles_y;
+  *tile_x = b * band + r % w;
+  *tile_y = r / w;
+}
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
