@@ -132,10 +132,16 @@ if __name__ == "__main__":
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--launches", type=int, default=20)
     ap.add_argument("--summarize", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_TXT"))
-    ap.add_argument("--command", default="rocprofv3 --pmc <COUNTER> -d DIR -o run -- python -m paper_1808_07554_amd.profile_sweep")
+    ap.add_argument("--command", default=None, help="command line recorded in the summary (default: the one "
+                    "that profiles this module with --storage and --n as given)")
     a = ap.parse_args()
     if a.summarize:
-        summarize(*a.summarize, a.storage, a.n, a.command)
+        args = f"--storage {a.storage}" + (f" --n {a.n}" if a.n != 4096 else "")
+        command = a.command or (
+            "cd /tmp && export TMPDIR=/tmp; rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR -o run -- "
+            f"python -u -m paper_1808_07554_amd.profile_sweep {args}  (then the same with --pmc WRITE_SIZE); "
+            f"summary: python -m paper_1808_07554_amd.profile_sweep --summarize FETCH.csv WRITE.csv OUT.txt {args}")
+        summarize(*a.summarize, a.storage, a.n, command)
     else:
         run(a.storage, a.n, a.launches)
         sys.exit(0)

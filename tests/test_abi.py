@@ -46,7 +46,7 @@ def _params(**kw):
     dict(Ds=0.0), dict(mu_w=0.0), dict(storage=9), dict(residual_stride=0),
     dict(lattice=lbtp.D2Q9, nz=2), dict(cap_B=-1.0), dict(coef_model=5),
     dict(sweep_block=-1), dict(sweep_block=8), dict(sweep_block=25),
-    dict(lattice=lbtp.D2Q9, sweep_block=9), dict(lattice=lbtp.D3Q7, nz=8, sweep_block=9),
+    dict(lattice=lbtp.D2Q9, sweep_block=25), dict(lattice=lbtp.D3Q7, nz=8, sweep_block=9),
     dict(collision=2), dict(collision=lbtp.COLLISION_MRT),
 ])
 def test_invalid_params_rejected_without_device(kw):
