@@ -16,8 +16,8 @@ cells x (pressure iterations + saturation steps) / time / 1e6.
 
 Also reported: the dominant kernel against its roofline (average launch
 duration from HIP events around a burst of launches on the solver's
-stream): on D2Q5 the blocked plain pressure sweep (9 sweeps per launch
-through registers, bound by vector ALU issue), elsewhere the one-sweep
+stream): on D2Q5 and D2Q9 the blocked plain pressure sweep (9 sweeps per
+launch through registers, against the vector ALU rate), elsewhere the one-sweep
 kernel against HBM; and the CPU oracle timed on a bounded sample of the same
 workload.
 """
@@ -36,11 +36,12 @@ sys.path.insert(0, ROOT)
 from paper_1808_07554_amd.profile_sweep import source_digest, sweep_kernel_name  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# vector fp32 rate without FMA contraction or packed math (both off in this
-# build): one add or multiply per lane per clock, 64 lanes per compute unit,
-# 256 compute units at 2.4 GHz (the 157.3 TFLOP/s figure counts packed FMA,
-# four flops per lane and clock)
-ALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
+# vector fp32 rate without packed math (off in this build): one fused
+# multiply-add (two flops) per lane per clock, 64 lanes per compute unit, 256
+# compute units at 2.4 GHz (the 157.3 TFLOP/s figure counts packed FMA, four
+# flops per lane and clock).  The BGK relaxation of the pressure sweeps is one
+# FMA per population; the other operations are single adds or multiplies.
+ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 # flops of one plain pressure sweep per node.  D2Q5: four pulls against the
 # node's base (sub, mul, add each), P - P_b (three adds, one multiply), w P,
 # four BGK relaxations (sub, mul, add each).  D2Q9: eight pulls (sub, mul,

@@ -92,10 +92,15 @@ __device__ inline void blk_sweep_rows(const KC &kc, BlkRows<RW, HAS_FP> &r, floa
       }
       const float dP = dpressure<2>(e, kc);
       const float wdP = kc.w1 * dP;
+      // keep = 1 - 1/tau_f is formed again every sweep: held for all rows
+      // it would cost 8 registers and one wavefront per SIMD
+      float it = r.it[t];
+      asm volatile("" : "+v"(it));
+      const float keep = 1.0f - it, gain = wdP * it;
       prev1 = r.d[t][1];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        float o = e[j] + (wdP - e[j]) * r.it[t];
+        float o = bgk_relax(e[j], keep, gain);
         if (HAS_FP) o += r.fp[t];
         r.d[t][j] = o;
       }

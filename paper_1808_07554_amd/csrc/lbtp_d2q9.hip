@@ -135,8 +135,11 @@ __device__ inline float q9_sum_g(const float *g) {
 // population; it is written out here moment by moment.
 __device__ inline void q9_collide(const KC &kc, const float *e, float dP, float it, float *o) {
   if (!kc.mrt) {
+    // e_j + (w_j dP - e_j) / tau_f as e_j (1 - 1/tau_f) + (w_j dP) / tau_f,
+    // one fused multiply-add per population (both sweep kernels call this)
+    const float keep = 1.0f - it, g1 = (kc.w1 * dP) * it, g2 = (kc.w2 * dP) * it;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) o[j] = e[j] + (q9w(kc, j) * dP - e[j]) * it;
+    for (int j = 0; j < 8; ++j) o[j] = __builtin_fmaf(e[j], keep, j < 4 ? g1 : g2);
     return;
   }
   float n[8];

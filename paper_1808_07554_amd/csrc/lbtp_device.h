@@ -241,6 +241,13 @@ __device__ inline void block_sum(double *v, double *out) {
   }
 }
 
+// BGK relaxation of one deviation (eq. 2-1b a), e + (w dP - e) / tau_f,
+// evaluated as e (1 - 1/tau_f) + (w dP) / tau_f: keep = 1 - 1/tau_f and
+// gain = (w dP) / tau_f once per node, then one fused multiply-add per
+// population.  Every D2Q5 / D3Q7 pressure kernel relaxes through this
+// function, so all of them round alike.
+__device__ inline float bgk_relax(float e, float keep, float gain) { return __builtin_fmaf(e, keep, gain); }
+
 // One node of the pressure sweep (eq. 3-1): stream (pull, or in place in
 // the local form), P (eq. 3-9a), BGK collision with 1/tau_f (eq. 2-1b a) and
 // the source dt wbar_i F_p.  MODE as in f_sweep_kernel; the stopping-rule
@@ -256,6 +263,7 @@ __device__ inline void sweep_cell(const KC &kc, const FP<T> &fin, const FP<T> &f
   const float dP = dpressure<DIM>(e, kc);
   const float wdP = kc.w1 * dP;
   const float it = itau[c];
+  const float keep = 1.0f - it, gain = wdP * it;
   float add = HAS_FP ? kc.dt * kc.wbar * Fp[c] : 0.0f;
   if (MODE >= 1) {
     const float P = pb + dP;
@@ -268,7 +276,7 @@ __device__ inline void sweep_cell(const KC &kc, const FP<T> &fin, const FP<T> &f
   }
 #pragma unroll
   for (int j = 0; j < 2 * DIM; ++j) {
-    float o = e[j] + (wdP - e[j]) * it;
+    float o = bgk_relax(e[j], keep, gain);
     if (HAS_FP || MODE >= 1) o += add;
     Storage<T>::store(fout.p[j], c, o, kc.dev_scale);
   }
@@ -479,6 +487,7 @@ __device__ inline void collide_quad(const KC &kc, const float4 *e, const float4 
     const float dP = dpressure<DIM>(ev, kc);
     const float wdP = kc.w1 * dP;
     const float t = f4get(it, i);
+    const float keep = 1.0f - t, gain = wdP * t;
     float add = HAS_FP ? kc.dt * kc.wbar * f4get(fp, i) : 0.0f;
     if (MODE >= 1) {
       const float pbi = f4get(pb, i);
@@ -492,7 +501,7 @@ __device__ inline void collide_quad(const KC &kc, const float4 *e, const float4 
     }
 #pragma unroll
     for (int j = 0; j < 2 * DIM; ++j) {
-      float v = ev[j] + (wdP - ev[j]) * t;
+      float v = bgk_relax(ev[j], keep, gain);
       if (HAS_FP || MODE >= 1) v += add;
       f4set(o[j], i, v);
     }
