@@ -87,11 +87,14 @@ __global__ __launch_bounds__(kBX * kUseW) void batch_block_kernel(const Member *
   if (bc.done || bc.kbase + j > bc.kmax) return;
   const Member &M = mem[m];
   if ((M.Fp != nullptr) != HAS_FP) return;
+  // the member's launch constants as a local copy: read once into scalar
+  // registers instead of from memory inside the sweep loop
+  const KC kc = M.kc;
   int tx, ty;
-  block_tile_counts(M.kc, H, &tx, &ty);
+  block_tile_counts(kc, H, &tx, &ty);
   const int in = j & 1;
-  block_region<T, HAS_FP, kUseW, kUseRW>(M.kc, typed<T>(M.f[in]), typed<T>(M.f[in ^ 1]), M.Pb[bc.pb], M.itau, M.Fp,
-                                         H, t % tx, t / tx);
+  block_region<T, HAS_FP, kUseW, kUseRW>(kc, typed<T>(M.f[in]), typed<T>(M.f[in ^ 1]), M.Pb[bc.pb], M.itau, M.Fp, H,
+                                         t % tx, t / tx);
 }
 
 template <typename T>

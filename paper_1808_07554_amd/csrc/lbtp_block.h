@@ -81,7 +81,10 @@ __device__ inline void blk_sweep_rows(const KC &kc, BlkRows<RW, HAS_FP> &r, floa
       e[0] = v0 + kc.w1 * (r.pbl[t] - p);
       e[1] = prev1 + kc.w1 * (r.pb[t] - p);
       e[2] = v2 + kc.w1 * (r.pbr[t] - p);
-      e[3] = v3 + kc.w1 * (r.pb[t + 2] - p);
+      // w (P_b(y+1) - P_b(y)) is minus the term row t + 1 adds to its e[1]
+      // (exactly: negation commutes with the subtraction and the product),
+      // so inner rows reuse that value instead of holding one of their own
+      e[3] = t < RW - 1 ? v3 - kc.w1 * (r.pb[t + 1] - r.pb[t + 2]) : v3 + kc.w1 * (r.pb[t + 2] - p);
       if (walls) {
         const int uy = uy0 + t;
         const int wy = pery ? blk_wrap(uy, kc.ny) : uy;
