@@ -95,10 +95,10 @@ __device__ inline void blk_sweep_rows(const KC &kc, BlkRows<RW, HAS_FP> &r, floa
       }
       const float dP = dpressure<2>(e, kc);
       const float wdP = kc.w1 * dP;
-      // keep = 1 - 1/tau_f is formed again every sweep: held for all rows
-      // it would cost 8 registers and one wavefront per SIMD
+      // with a source, keep = 1 - 1/tau_f is formed again every sweep: held
+      // for all rows it would cost 8 registers and one wavefront per SIMD
       float it = r.it[t];
-      asm volatile("" : "+v"(it));
+      if (HAS_FP) asm volatile("" : "+v"(it));
       const float keep = 1.0f - it, gain = wdP * it;
       prev1 = r.d[t][1];
 #pragma unroll
