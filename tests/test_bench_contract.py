@@ -1,0 +1,43 @@
+"""Host-side checks of bench.py that need no GPU: the one-GPU rule, the
+algorithmic bytes of a plain pressure sweep per node, the ALU peak derived
+from the unit counts, and that the committed counter summaries are used only
+while they were taken on the current sweep sources."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
+
+
+def test_algorithmic_bytes_per_node():
+    # Q - 1 deviations read and written, 1/tau_f and the base pressure read
+    assert bench.f_sweep_bytes("D2Q5", "fp32") == 2 * 4 * 4 + 8 == 40
+    assert bench.f_sweep_bytes("D2Q5", "fp16") == 2 * 4 * 2 + 8
+    assert bench.f_sweep_bytes("D3Q7", "fp32") == 2 * 6 * 4 + 8
+    assert bench.f_sweep_bytes("D2Q9", "bf16") == 2 * 8 * 2 + 8
+
+
+def test_alu_peak_from_unit_counts():
+    # 256 compute units x 64 lanes x one FMA (2 flops) per clock x 2.4 GHz
+    assert abs(bench.ALU_PEAK_TFLOPS - 78.6432) < 1e-9
+    assert bench.HBM_PEAK_GBS == 8000.0
+
+
+def test_traffic_only_for_matching_sources(monkeypatch, tmp_path):
+    path = tmp_path / "traffic_{}.txt"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
+    assert bench.measured_traffic("fp32") is None                  # no summary
+    (tmp_path / "traffic_fp32.txt").write_text(
+        f"bytes_per_launch: 8.0e+08\nsource_sha256: {bench.source_digest()}  (sources)\n")
+    assert bench.measured_traffic("fp32") == 8.0e8
+    monkeypatch.setattr(bench, "source_digest", lambda: "0" * 64)   # sources changed since
+    assert bench.measured_traffic("fp32") is None
