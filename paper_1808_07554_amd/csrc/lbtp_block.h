@@ -41,8 +41,13 @@ __device__ inline int blk_wrap(int v, int n) {
 }
 
 // Anti-bounce-back / bounce-back value of the population arriving through a
-// wall face at node (x, y) whose opposite population is o.
+// wall face at node (x, y) whose opposite population is o.  The sweep also
+// applies it at region rows and columns beyond the wall, which hold no node
+// (their values are never read by a node of the domain); the coordinates are
+// clamped so that the wall data are read within their arrays there too.
 __device__ inline float blk_wall_rule(const KC &kc, int face, int x, int y, float pb, float o) {
+  x = min(max(x, 0), kc.nx - 1);
+  y = min(max(y, 0), kc.ny - 1);
   return kc.bc_f[face] == LBTP_BC_DIRICHLET ? 2.0f * kc.w1 * (wall_P(kc, face, x, y, 0, 1, 0) - pb) - o : o;
 }
 
@@ -65,7 +70,6 @@ __device__ inline void blk_sweep_rows(const KC &kc, BlkRows<RW, HAS_FP> &r, floa
                                   float (*xdn)[kBWmax][kBX], int H, int lane, int wv, int ux, int gx, int uy0,
                                   bool perx, bool pery, bool walls) {
   const bool wall_l = !perx && ux == 0, wall_r = !perx && ux == kc.nx - 1;
-  const bool col_in = perx || (ux >= 0 && ux < kc.nx);
   for (int s = 1; s <= H; ++s) {
     const int rd = (s - 1) & 1;
     // the neighbouring wavefronts' rows (garbage at the region's outer rows,
@@ -87,15 +91,12 @@ __device__ inline void blk_sweep_rows(const KC &kc, BlkRows<RW, HAS_FP> &r, floa
       // so inner rows reuse that value instead of holding one of their own
       e[3] = t < RW - 1 ? v3 - kc.w1 * (r.pb[t + 1] - r.pb[t + 2]) : v3 + kc.w1 * (r.pb[t + 2] - p);
       if (walls) {
-        // only at nodes of the domain: the wall data are indexed along the
-        // face, and region rows or columns beyond a wall hold no node
         const int uy = uy0 + t;
-        const bool row_in = pery || (uy >= 0 && uy < kc.ny);
         const int wy = pery ? blk_wrap(uy, kc.ny) : uy;
-        if (wall_l && row_in) e[0] = blk_wall_rule(kc, 0, 0, wy, p, r.d[t][2]);
-        if (wall_r && row_in) e[2] = blk_wall_rule(kc, 1, kc.nx - 1, wy, p, r.d[t][0]);
-        if (col_in && !pery && uy == 0) e[1] = blk_wall_rule(kc, 2, gx, 0, p, r.d[t][3]);
-        if (col_in && !pery && uy == kc.ny - 1) e[3] = blk_wall_rule(kc, 3, gx, kc.ny - 1, p, r.d[t][1]);
+        if (wall_l) e[0] = blk_wall_rule(kc, 0, 0, wy, p, r.d[t][2]);
+        if (wall_r) e[2] = blk_wall_rule(kc, 1, kc.nx - 1, wy, p, r.d[t][0]);
+        if (!pery && uy == 0) e[1] = blk_wall_rule(kc, 2, gx, 0, p, r.d[t][3]);
+        if (!pery && uy == kc.ny - 1) e[3] = blk_wall_rule(kc, 3, gx, kc.ny - 1, p, r.d[t][1]);
       }
       const float dP = dpressure<2>(e, kc);
       const float wdP = kc.w1 * dP;
