@@ -133,8 +133,8 @@ __device__ inline float q9_sum_g(const float *g) {
 // at one rate s0, M^-1 S M = s0 I + M^-1 (S - s0 I) M, and the second term
 // only involves the flux and stress moments, none of which sees the rest
 // population; it is written out here moment by moment.
-__device__ inline void q9_collide(const KC &kc, const float *e, float dP, float it, float *o) {
-  if (!kc.mrt) {
+__device__ inline void q9_collide(const KC &kc, bool mrt, const float *e, float dP, float it, float *o) {
+  if (!mrt) {
     // e_j + (w_j dP - e_j) / tau_f as e_j (1 - 1/tau_f) + (w_j dP) / tau_f,
     // one fused multiply-add per population (both sweep kernels call this)
     const float keep = 1.0f - it, g1 = (kc.w1 * dP) * it, g2 = (kc.w2 * dP) * it;
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kThreads) void q9_f_sweep_kernel(KC kc, FPtrs fin_,
       }
     }
     float oc[8];
-    q9_collide(kc, e, dP, it, oc);
+    q9_collide(kc, kc.mrt, e, dP, it, oc);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const float w = q9w(kc, j);
@@ -374,7 +374,7 @@ __device__ inline void q9_quad_core(const KC &kc, const FP<T> &fin, const FP<T> 
       }
     }
     float oc[8];
-    q9_collide(kc, ev, dP, t, oc);
+    q9_collide(kc, kc.mrt, ev, dP, t, oc);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const float w = q9w(kc, j);
@@ -444,7 +444,10 @@ __device__ inline int q9_wrap_any(int v, int n) {
   return r < 0 ? r + n : r;
 }
 
-template <typename T, bool HAS_FP>
+// BGK_ONLY: the collision is BGK, so the sweep loop carries no MRT code (4 %
+// of its time); otherwise kc.mrt chooses at run time (a fixed MRT would
+// need more than 128 registers).
+template <typename T, bool HAS_FP, bool BGK_ONLY>
 __global__ __launch_bounds__(kQ9BX * kQ9W) void q9_f_block_kernel(KC kc, FPtrs fin_, FPtrs fout_,
                                                                   const float *__restrict__ Pb,
                                                                   const float *__restrict__ itau,
@@ -596,7 +599,7 @@ __global__ __launch_bounds__(kQ9BX * kQ9W) void q9_f_block_kernel(KC kc, FPtrs f
       }
       const float dP = q9_dpressure(e, kc);
       float oc[8];
-      q9_collide(kc, e, dP, it[t], oc);
+      q9_collide(kc, BGK_ONLY ? false : kc.mrt, e, dP, it[t], oc);
       p1 = d[t][1];
       p4 = d[t][4];
       p5 = d[t][5];
@@ -891,12 +894,16 @@ hipError_t launch_f_block_q9(int storage, const KC &kc, FPtrs fin, FPtrs fout, c
   const int tx = (kc.nx + tcols - 1) / tcols, ty = (kc.ny + trows - 1) / trows;
   q9_dispatch(storage, 0, [&](auto t, auto) {
     using T = std::remove_pointer_t<decltype(t)>;
-    if (Fp)
-      hipLaunchKernelGGL((q9_f_block_kernel<T, true>), dim3(tx * ty), dim3(kQ9BX * kQ9W), 0, s, kc, fin, fout, Pb,
-                         itau, Fp, ctl, k, H, tx);
-    else
-      hipLaunchKernelGGL((q9_f_block_kernel<T, false>), dim3(tx * ty), dim3(kQ9BX * kQ9W), 0, s, kc, fin, fout, Pb,
-                         itau, Fp, ctl, k, H, tx);
+    auto go = [&](auto kernel) {
+      hipLaunchKernelGGL(kernel, dim3(tx * ty), dim3(kQ9BX * kQ9W), 0, s, kc, fin, fout, Pb, itau, Fp, ctl, k, H, tx);
+    };
+    if (Fp) {
+      if (kc.mrt) go(q9_f_block_kernel<T, true, false>);
+      else go(q9_f_block_kernel<T, true, true>);
+    } else {
+      if (kc.mrt) go(q9_f_block_kernel<T, false, false>);
+      else go(q9_f_block_kernel<T, false, true>);
+    }
   });
   return hipGetLastError();
 }
