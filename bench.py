@@ -57,6 +57,7 @@ def f_sweep_bytes(lattice, storage):
     q1 = {"D2Q5": 4, "D3Q7": 6, "D2Q9": 8}[lattice]
     return 2 * q1 * POP_BYTES[storage] + 4 + 4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "f_block_traffic_injection2d_4096_{}.txt")
+TRAFFIC_FILE_Q9 = os.path.join(ROOT, "profiles", "f_block_traffic_injection2d_4096_d2q9_{}.txt")
 
 
 def parse():
@@ -83,17 +84,17 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(storage):
+def measured_traffic(storage, lattice="D2Q5"):
     """HBM bytes per f-sweep launch from the committed rocprofv3 counter summary
-    for this storage format, if it was taken on the current kernel sources
-    (else None)."""
-    path = TRAFFIC_FILE.format(storage)
+    for this lattice and storage format, if it was taken on the current kernel
+    sources (else None)."""
+    path = (TRAFFIC_FILE_Q9 if lattice == "D2Q9" else TRAFFIC_FILE).format(storage)
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m = re.search(r"source_sha256:\s*([0-9a-f]{64})", txt)
     b = re.search(r"bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m or not b or source_digest() != m.group(1):
+    if not m or not b or source_digest(lattice) != m.group(1):
         return None
     return float(b.group(1))
 
@@ -300,8 +301,8 @@ def main():
         torch.cuda.synchronize()
         gstep_s += e0.elapsed_time(e1) / 1e3 / nsat
     alg_bytes = f_sweep_bytes(params["lattice"], a.storage) * ncell
-    traffic = (measured_traffic(a.storage)
-               if (a.workload == "injection2d" and a.n == 4096 and a.lattice == "D2Q5") else None)
+    traffic = (measured_traffic(a.storage, a.lattice)
+               if (a.workload == "injection2d" and a.n == 4096 and H > 1) else None)
     kname = sweep_kernel_name(a.storage, 3 if a.workload == "injection3d" else 2, params["lattice"], H)
     if H > 1:
         flops = BLOCK_FLOPS_PER_NODE_SWEEP[params["lattice"]] * ncell * H

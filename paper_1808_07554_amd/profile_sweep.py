@@ -6,8 +6,8 @@ Run under rocprofv3 (one counter per run):
 The workload is a 1 GiB plain copy (lbtp_copy_probe, the known-size
 reference) followed by a burst of launches of the blocked plain pressure
 sweep (lbtp_probe_sweeps, 9 sweeps per launch) on the 4096 x 4096 injection
-problem.  Then, on any machine:
-    python -m paper_1808_07554_amd.profile_sweep --summarize FETCH.csv WRITE.csv OUT.txt [--storage S]
+problem, on D2Q5 or (--lattice D2Q9) on D2Q9.  Then, on any machine:
+    python -m paper_1808_07554_amd.profile_sweep --summarize FETCH.csv WRITE.csv OUT.txt [--storage S] [--lattice L]
 converts the counters of the sweep into HBM bytes per launch with the
 copy's bytes-per-count scale and writes a short text summary.
 """
@@ -21,13 +21,18 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 1 << 30
 # the sources the sweep kernels are compiled from
 SWEEP_SOURCES = ("lbtp_kernels.hip", "lbtp_device.h", "lbtp_internal.h", "lbtp_block.hip", "lbtp_block.h")
+SWEEP_SOURCES_Q9 = ("lbtp_d2q9.hip", "lbtp_device.h", "lbtp_internal.h")
 
 
-def source_digest():
-    """sha256 over the sweep kernel sources (in SWEEP_SOURCES order): a counter
-    summary is valid only for the kernels it was taken on."""
+def sweep_sources(lattice="D2Q5"):
+    return SWEEP_SOURCES_Q9 if lattice == "D2Q9" else SWEEP_SOURCES
+
+
+def source_digest(lattice="D2Q5"):
+    """sha256 over the sweep kernel sources of the lattice (in order): a
+    counter summary is valid only for the kernels it was taken on."""
     h = hashlib.sha256()
-    for name in SWEEP_SOURCES:
+    for name in sweep_sources(lattice):
         with open(os.path.join(HERE, "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -44,7 +49,7 @@ def sweep_kernel_name(storage, dim=2, lattice=None, sweeps_per_launch=9):
     return "f_sweep_vec_kernel"
 
 
-def run(storage, n, launches):
+def run(storage, n, launches, lattice="D2Q5"):
     import ctypes
 
     import torch
@@ -62,6 +67,9 @@ def run(storage, n, launches):
     torch.cuda.synchronize()
     del a, b
     params, fl = inputs.injection_2d(n)
+    if lattice == "D2Q9":
+        # the equilibrium of eq. 3-4 needs max(phi)/2 <= beta <= 2 min(phi)
+        params = dict(params, lattice="D2Q9", beta=0.2)
     s = lbtp.from_problem(params, m=64, storage=storage)
     s.set_fields(torch.from_numpy(inputs.f32(fl["K"]).ravel()).to(dev),
                  torch.from_numpy(inputs.f32(fl["phi"]).ravel()).to(dev))
@@ -72,7 +80,7 @@ def run(storage, n, launches):
     H = s.probe_sweeps(launches)
     torch.cuda.synchronize()
     print(f"profile workload done: copy {COPY_BYTES} B x3, {launches} launches of {H} plain sweeps at {n}^2 "
-          f"({storage})", flush=True)
+          f"({lattice}, {storage})", flush=True)
 
 
 def _counter_rows(path):
@@ -94,24 +102,24 @@ def _per_dispatch(rows, pattern, exclude=None):
     return sum(vals) / len(vals) if vals else None, len(vals)
 
 
-def summarize(fetch_csv, write_csv, out_txt, storage, n, command):
+def summarize(fetch_csv, write_csv, out_txt, storage, n, command, lattice="D2Q5"):
     f_rows = _counter_rows(fetch_csv)
     w_rows = _counter_rows(write_csv)
     copy_f, ncf = _per_dispatch(f_rows, "copy_probe")
     copy_w, ncw = _per_dispatch(w_rows, "copy_probe")
     # launches of the blocked plain sweep (each moves the state in and out once)
-    kname = sweep_kernel_name(storage)
+    kname = sweep_kernel_name(storage, 2, lattice)
     sw_f, nsf = _per_dispatch(f_rows, kname)
     sw_w, nsw = _per_dispatch(w_rows, kname)
     scale_f = COPY_BYTES / copy_f
     scale_w = COPY_BYTES / copy_w
     fetch_b = sw_f * scale_f
     write_b = sw_w * scale_w
-    q1, pop = 4, (4 if storage == "fp32" else 2)
+    q1, pop = (8 if lattice == "D2Q9" else 4), (4 if storage == "fp32" else 2)
     alg_read = n * n * (q1 * pop + 8)
     alg_write = n * n * q1 * pop
-    sha = source_digest()
-    text = f"""Blocked pressure sweep HBM traffic per launch (9 plain sweeps), heterogeneous injection 2-D {n}x{n}, D2Q5, {storage} storage
+    sha = source_digest(lattice)
+    text = f"""Blocked pressure sweep HBM traffic per launch (9 plain sweeps), heterogeneous injection 2-D {n}x{n}, {lattice}, {storage} storage
 command: {command}
 counters: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each from its own rocprofv3 --pmc run
 calibration: lbtp_copy_probe of {COPY_BYTES} B: FETCH_SIZE {copy_f:.1f} ({ncf} dispatches), WRITE_SIZE {copy_w:.1f} ({ncw}) -> {scale_f:.2f} / {scale_w:.2f} B per count
@@ -119,7 +127,7 @@ calibration: lbtp_copy_probe of {COPY_BYTES} B: FETCH_SIZE {copy_f:.1f} ({ncf} d
 {kname} ({nsw} dispatches): WRITE_SIZE {sw_w:.1f} -> {write_b / 1e6:.1f} MB written (algorithmic {alg_write / 1e6:.1f} MB, ratio {write_b / alg_write:.3f})
 bytes_per_launch: {fetch_b + write_b:.6e}
 algorithmic_bytes_per_launch: {alg_read + alg_write:.6e}
-source_sha256: {sha}  (csrc/{", csrc/".join(SWEEP_SOURCES)})
+source_sha256: {sha}  (csrc/{", csrc/".join(sweep_sources(lattice))})
 """
     with open(out_txt, "w") as f:
         f.write(text)
@@ -131,17 +139,19 @@ if __name__ == "__main__":
     ap.add_argument("--storage", default="fp32")
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--launches", type=int, default=20)
+    ap.add_argument("--lattice", default="D2Q5", choices=["D2Q5", "D2Q9"])
     ap.add_argument("--summarize", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_TXT"))
     ap.add_argument("--command", default=None, help="command line recorded in the summary (default: the one "
                     "that profiles this module with --storage and --n as given)")
     a = ap.parse_args()
     if a.summarize:
-        args = f"--storage {a.storage}" + (f" --n {a.n}" if a.n != 4096 else "")
+        args = (f"--storage {a.storage}" + (f" --n {a.n}" if a.n != 4096 else "")
+                + (f" --lattice {a.lattice}" if a.lattice != "D2Q5" else ""))
         command = a.command or (
             "cd /tmp && export TMPDIR=/tmp; rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR -o run -- "
             f"python -u -m paper_1808_07554_amd.profile_sweep {args}  (then the same with --pmc WRITE_SIZE); "
             f"summary: python -m paper_1808_07554_amd.profile_sweep --summarize FETCH.csv WRITE.csv OUT.txt {args}")
-        summarize(*a.summarize, a.storage, a.n, command)
+        summarize(*a.summarize, a.storage, a.n, command, a.lattice)
     else:
-        run(a.storage, a.n, a.launches)
+        run(a.storage, a.n, a.launches, a.lattice)
         sys.exit(0)

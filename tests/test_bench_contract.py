@@ -39,5 +39,7 @@ def test_traffic_only_for_matching_sources(monkeypatch, tmp_path):
     (tmp_path / "traffic_fp32.txt").write_text(
         f"bytes_per_launch: 8.0e+08\nsource_sha256: {bench.source_digest()}  (sources)\n")
     assert bench.measured_traffic("fp32") == 8.0e8
-    monkeypatch.setattr(bench, "source_digest", lambda: "0" * 64)   # sources changed since
+    monkeypatch.setattr(bench, "TRAFFIC_FILE_Q9", str(tmp_path / "q9_{}.txt"))
+    assert bench.measured_traffic("fp32", "D2Q9") is None          # none for the other lattice
+    monkeypatch.setattr(bench, "source_digest", lambda *a: "0" * 64)  # sources changed since
     assert bench.measured_traffic("fp32") is None
