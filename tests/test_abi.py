@@ -48,6 +48,9 @@ def _params(**kw):
     dict(sweep_block=-1), dict(sweep_block=8), dict(sweep_block=25),
     dict(lattice=lbtp.D2Q9, sweep_block=25), dict(lattice=lbtp.D3Q7, nz=8, sweep_block=9),
     dict(collision=2), dict(collision=lbtp.COLLISION_MRT),
+    # cell indices are 32-bit: Q x nodes must stay below 2^31
+    dict(nx=23171, ny=23171), dict(lattice=lbtp.D2Q9, nx=15447, ny=15447),
+    dict(lattice=lbtp.D3Q7, nx=700, ny=700, nz=700),
 ])
 def test_invalid_params_rejected_without_device(kw):
     lib = lbtp.load()
