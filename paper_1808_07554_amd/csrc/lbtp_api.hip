@@ -152,6 +152,7 @@ void fill_kc(lbtp_ctx *c) {
   k.w1 = (float)w1;
   k.w2 = (float)(1.0 / 36.0);
   k.inv_1mw0 = (float)(1.0 / (1.0 - w0));
+  k.w1_1mw0 = (float)(w1 / (1.0 - w0));
   k.wbar = (float)(1.0 / c->nf);      // bar-omega_i = 1/(Q-1) for every moving direction
   k.beta = (float)p.beta;
   k.inv_tau_g = (float)(1.0 / tau_g);

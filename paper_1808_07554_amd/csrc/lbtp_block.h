@@ -98,8 +98,7 @@ __device__ inline void blk_sweep_rows(const KC &kc, BlkRows<RW, HAS_FP> &r, floa
         if (!pery && uy == 0) e[1] = blk_wall_rule(kc, 2, gx, 0, p, r.d[t][3]);
         if (!pery && uy == kc.ny - 1) e[3] = blk_wall_rule(kc, 3, gx, kc.ny - 1, p, r.d[t][1]);
       }
-      const float dP = dpressure<2>(e, kc);
-      const float wdP = kc.w1 * dP;
+      const float wdP = dsum<2>(e) * kc.w1_1mw0;
       // with a source, keep = 1 - 1/tau_f is formed again every sweep: held
       // for all rows it would cost 8 registers and one wavefront per SIMD
       float it = r.it[t];

@@ -124,13 +124,21 @@ __device__ inline void load_e(const FP<T> &fin, const float *__restrict__ Pb, co
   }
 }
 
-// P - P_b from the deviations (eq. 3-9a).
+// Sum of the deviations of the moving directions; P - P_b is this sum over
+// 1 - w0 (eq. 3-9a), and w1 (P - P_b) this sum times w1 / (1 - w0) (one
+// product, 1/4 on D2Q5).
 template <int DIM>
-__device__ inline float dpressure(const float *e, const KC &kc) {
+__device__ inline float dsum(const float *e) {
   float s = e[0];
 #pragma unroll
   for (int j = 1; j < 2 * DIM; ++j) s += e[j];
-  return s * kc.inv_1mw0;
+  return s;
+}
+
+// P - P_b from the deviations (eq. 3-9a).
+template <int DIM>
+__device__ inline float dpressure(const float *e, const KC &kc) {
+  return dsum<DIM>(e) * kc.inv_1mw0;
 }
 
 // First moment sum_i c_i f_i = sum_i c_i e_i along each axis (the base part cancels).
@@ -260,8 +268,8 @@ __device__ inline void sweep_cell(const KC &kc, const FP<T> &fin, const FP<T> &f
   const float pb = Pb_in[c];
   float e[2 * DIM];
   load_e<DIM, T, LOCAL>(fin, Pb_in, q, kc, pb, e);
-  const float dP = dpressure<DIM>(e, kc);
-  const float wdP = kc.w1 * dP;
+  const float sum = dsum<DIM>(e);
+  const float dP = sum * kc.inv_1mw0, wdP = sum * kc.w1_1mw0;
   const float it = itau[c];
   const float keep = 1.0f - it, gain = wdP * it;
   float add = HAS_FP ? kc.dt * kc.wbar * Fp[c] : 0.0f;
@@ -484,8 +492,8 @@ __device__ inline void collide_quad(const KC &kc, const float4 *e, const float4 
     float ev[2 * DIM];
 #pragma unroll
     for (int j = 0; j < 2 * DIM; ++j) ev[j] = f4get(e[j], i);
-    const float dP = dpressure<DIM>(ev, kc);
-    const float wdP = kc.w1 * dP;
+    const float sum = dsum<DIM>(ev);
+    const float dP = sum * kc.inv_1mw0, wdP = sum * kc.w1_1mw0;
     const float t = f4get(it, i);
     const float keep = 1.0f - t, gain = wdP * t;
     float add = HAS_FP ? kc.dt * kc.wbar * f4get(fp, i) : 0.0f;

@@ -26,6 +26,7 @@ struct KC {
   float w0, w1;     // rest and moving weights (D2Q9: w1 of the axis directions)
   float w2;         // D2Q9: weight of the diagonal directions
   float inv_1mw0;   // 1 / (1 - w0)
+  float w1_1mw0;    // w1 / (1 - w0): w1 (P - P_b) from the sum of the deviations
   float wbar;       // source weight of a moving direction (eq. 3-5a pattern)
   float beta;
   float inv_tau_g;  // 1 / tau_g
