@@ -99,12 +99,16 @@ __device__ inline void q9_load_e(const FP<T> &fin, const float *__restrict__ Pb,
   }
 }
 
-__device__ inline float q9_dpressure(const float *e, const KC &kc) {
+// Sum of the deviations of the moving directions; P - P_b is this sum over
+// 1 - w0 (eq. 3-9a).
+__device__ inline float q9_dsum(const float *e) {
   float s = e[0];
 #pragma unroll
   for (int j = 1; j < 8; ++j) s += e[j];
-  return s * kc.inv_1mw0;
+  return s;
 }
+
+__device__ inline float q9_dpressure(const float *e, const KC &kc) { return q9_dsum(e) * kc.inv_1mw0; }
 
 // sum_j c_j e_j (the base part cancels: sum_j w_j c_j = 0)
 __device__ inline void q9_moment(const float *e, const KC &kc, float *m1) {
@@ -133,15 +137,18 @@ __device__ inline float q9_sum_g(const float *g) {
 // at one rate s0, M^-1 S M = s0 I + M^-1 (S - s0 I) M, and the second term
 // only involves the flux and stress moments, none of which sees the rest
 // population; it is written out here moment by moment.
-__device__ inline void q9_collide(const KC &kc, bool mrt, const float *e, float dP, float it, float *o) {
+__device__ inline void q9_collide(const KC &kc, bool mrt, const float *e, float sum, float it, float *o) {
   if (!mrt) {
     // e_j + (w_j dP - e_j) / tau_f as e_j (1 - 1/tau_f) + (w_j dP) / tau_f,
-    // one fused multiply-add per population (both sweep kernels call this)
-    const float keep = 1.0f - it, g1 = (kc.w1 * dP) * it, g2 = (kc.w2 * dP) * it;
+    // one fused multiply-add per population (every sweep kernel calls this);
+    // w_j dP is the sum of the deviations times w_j / (1 - w0)
+    const float keep = 1.0f - it;
+    const float g1 = (sum * (kc.w1 * kc.inv_1mw0)) * it, g2 = (sum * (kc.w2 * kc.inv_1mw0)) * it;
 #pragma unroll
     for (int j = 0; j < 8; ++j) o[j] = __builtin_fmaf(e[j], keep, j < 4 ? g1 : g2);
     return;
   }
+  const float dP = sum * kc.inv_1mw0;
   float n[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) n[j] = e[j] - q9w(kc, j) * dP;
@@ -189,7 +196,7 @@ __global__ __launch_bounds__(kThreads) void q9_f_sweep_kernel(KC kc, FPtrs fin_,
     const float pb = Pb_in[c];
     float e[8];
     q9_load_e<T, LOCAL>(fin, Pb_in, c, x, y, kc, pb, e);
-    const float dP = q9_dpressure(e, kc);
+    const float sum = q9_dsum(e), dP = sum * kc.inv_1mw0;
     const float it = itau[c];
     const float add = HAS_FP ? kc.dt * kc.wbar * Fp[c] : 0.0f;
     float rb = 0.0f;
@@ -203,7 +210,7 @@ __global__ __launch_bounds__(kThreads) void q9_f_sweep_kernel(KC kc, FPtrs fin_,
       }
     }
     float oc[8];
-    q9_collide(kc, kc.mrt, e, dP, it, oc);
+    q9_collide(kc, kc.mrt, e, sum, it, oc);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const float w = q9w(kc, j);
@@ -359,7 +366,7 @@ __device__ inline void q9_quad_core(const KC &kc, const FP<T> &fin, const FP<T> 
     float ev[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) ev[j] = f4get(e[j], i);
-    const float dP = q9_dpressure(ev, kc);
+    const float sum = q9_dsum(ev), dP = sum * kc.inv_1mw0;
     const float t = f4get(it, i);
     const float add = HAS_FP ? kc.dt * kc.wbar * f4get(fp, i) : 0.0f;
     float rb = 0.0f;
@@ -374,7 +381,7 @@ __device__ inline void q9_quad_core(const KC &kc, const FP<T> &fin, const FP<T> 
       }
     }
     float oc[8];
-    q9_collide(kc, kc.mrt, ev, dP, t, oc);
+    q9_collide(kc, kc.mrt, ev, sum, t, oc);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const float w = q9w(kc, j);
@@ -597,9 +604,8 @@ __global__ __launch_bounds__(kQ9BX * kQ9W) void q9_f_block_kernel(KC kc, FPtrs f
           e[7] = wc_y[1][lane][2] + wm_y[1][lane][2] * d[t][5];
         }
       }
-      const float dP = q9_dpressure(e, kc);
       float oc[8];
-      q9_collide(kc, BGK_ONLY ? false : kc.mrt, e, dP, it[t], oc);
+      q9_collide(kc, BGK_ONLY ? false : kc.mrt, e, q9_dsum(e), it[t], oc);
       p1 = d[t][1];
       p4 = d[t][4];
       p5 = d[t][5];
