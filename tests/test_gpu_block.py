@@ -63,6 +63,8 @@ CASES = [
     ((90, 40), MIXED, dict(wall_face=2)),         # per-link data along a periodic axis
     ((300, 7), WALLS, {}),
     ((7, 300), MIXED, {}),
+    ((150, 90), WALLS, dict(Fp=True)),            # a pressure source with walls on every face
+    ((90, 60), MIXED, dict(Fp=True, wall_face=2)),
     # the smallest boxes: walled axes of 3 nodes, periodic axes of 1 and 2
     ((3, 3), WALLS, dict(wall_face=1)),
     ((3, 41), WALLS, dict(wall_face=0)),
@@ -143,6 +145,8 @@ Q9_CASES = [
     ((90, 40), MIXED, dict(wall_face=3)),
     ((7, 300), MIXED, {}),
     ((200, 150), Q9_WALLS, dict(collision=("mrt", 1.4, 1.7, 0.6))),
+    ((130, 70), Q9_WALLS, dict(Fp=True)),
+    ((130, 70), Q9_WALLS, dict(Fp=True, collision=("mrt", 1.4, 1.7, 0.6))),
     ((3, 3), Q9_WALLS, dict(wall_face=1)),
     ((1, 29), MIXED, {}),
     ((2, 2), PERIODIC, dict(Fp=True)),
