@@ -14,12 +14,20 @@ Pins (each checked by a test that needs no GPU):
     on the 5/7-point Laplacian, and its local gradient to central differences;
   * tau_g = 1 on D2Q5 reduces the saturation step to forward-time
     central-space differencing;
-  * the fixed point of the pressure iteration equals a dense linear solve of
-    the affine sweep on tiny grids (any heterogeneous tau_f);
+  * the tau_f = 1 fixed point with walls equals a direct sparse solve of the
+    matching finite-difference system;
+  * a layered medium (tau_f from about 0.5 to 50 along x, D2Q5 and D3Q7):
+    the fixed point is the series-resistance closed form and the local
+    velocity is the constant flux, to rounding;
+  * the initial non-equilibrium parts have the moments of Appendices A and B;
   * collision invariants and the exact mass ledger;
-  * Examples 1 and 2 of Section 4 (D2Q9): the printed error bounds and
-    second-order convergence;
-  * second-order convergence of the D2Q5 manufactured problem;
+  * Example 1 of Section 4: the printed error bound and second order;
+  * Example 2: the printed bound for P and u; second order of S at fixed
+    tau_g (Fig. 10); errors falling with beta at phi = 0.5 (Fig. 11); the
+    saturation error at fixed c is the modified-equation term of eq. (3-2)
+    (its size, its 1/c^2 scaling, and its removal by the compensating source);
+  * second-order convergence of the manufactured problem on D2Q5 (P, u, S)
+    and D3Q7 (P, u, S);
   * agreement with a finite-volume Darcy solve as the grid is refined.
 """
 from . import lattice

@@ -36,8 +36,12 @@ Readings where the paper is silent (each is also listed in the design notes):
     f_0 = (w_0 - 1) P0.
   * walls sit halfway between nodes (nodes at (j + 1/2) dx on walled axes,
     j dx on periodic axes); a boundary value given as a function is evaluated
-    at the midpoint of the cut link, at the time of the step that sets it
-    (time-dependent pressure at t_n, saturation at t_n + dt/2).
+    where and when the reflected population meets the wall: at the midpoint
+    of the cut link and, for the saturation lattice, at t_n + dt/2 (the
+    population leaves the node after the collision at t_n and is back at
+    t_n + dt, so it is at the halfway wall half a step in between).  The
+    pressure lattice iterates in pseudo time at the fixed physical time t_n,
+    so its wall values are taken at t_n.
   * "outflow" for the saturation lattice is anti-bounce-back with
     S_wb = S^n at the boundary node (a zero-gradient outlet; the paper has
     only Dirichlet and no-flux walls).

@@ -125,6 +125,66 @@ class ManufacturedPeriodic:
         return Fp, Fs
 
 
+class ManufacturedPeriodic3D:
+    """The manufactured problem of ManufacturedPeriodic on a periodic N^3 box:
+    P_e = a sin(kx) sin(ky) sin(kz), S_e = 0.5 + b cos(kx) cos(ky) cos(kz) cos(w t),
+    with the sources that make them exact for eq. (2-15) and eq. (2-18).
+    Nodes at integer positions; fields are [z][y][x], float64."""
+
+    def __init__(self, N=16, amp_p=0.1, amp_s=0.1, period=1000.0, K=1.0, phi=0.2,
+                 mu_w=1.0, mu_n=5.0, beta=0.15, Ds=0.01875):
+        self.N = N
+        self.k = 2 * np.pi / N
+        self.w = 2 * np.pi / period
+        self.ap, self.as_ = amp_p, amp_s
+        self.K, self.phi, self.mu_w, self.mu_n = K, phi, mu_w, mu_n
+        self.beta, self.Ds = beta, Ds
+        j = np.arange(N, dtype=np.float64)
+        self.Z, self.Y, self.X = np.meshgrid(j, j, j, indexing="ij")
+
+    def _trig(self):
+        k = self.k
+        return [(np.sin(k * a), np.cos(k * a)) for a in (self.X, self.Y, self.Z)]
+
+    def P(self):
+        (sx, _), (sy, _), (sz, _) = self._trig()
+        return self.ap * sx * sy * sz
+
+    def gradP(self):
+        (sx, cx), (sy, cy), (sz, cz) = self._trig()
+        a = self.ap * self.k
+        return np.stack([a * cx * sy * sz, a * sx * cy * sz, a * sx * sy * cz])
+
+    def S(self, t):
+        (_, cx), (_, cy), (_, cz) = self._trig()
+        return 0.5 + self.as_ * cx * cy * cz * math.cos(self.w * t)
+
+    def gradS(self, t):
+        (sx, cx), (sy, cy), (sz, cz) = self._trig()
+        a = -self.as_ * self.k * math.cos(self.w * t)
+        return np.stack([a * sx * cy * cz, a * cx * sy * cz, a * cx * cy * sz])
+
+    def velocity(self, t):
+        S = self.S(t)
+        lam_t = S * S / self.mu_w + (1 - S) ** 2 / self.mu_n
+        return -self.K * lam_t * self.gradP()
+
+    def sources(self, t):
+        S = self.S(t)
+        lap_p = -3 * self.k ** 2 * self.P()
+        lap_s = -3 * self.k ** 2 * (S - 0.5)
+        gsgp = np.sum(self.gradS(t) * self.gradP(), axis=0)
+        (_, cx), (_, cy), (_, cz) = self._trig()
+        dSdt = -self.as_ * self.w * cx * cy * cz * math.sin(self.w * t)
+        lam_w = S * S / self.mu_w
+        lam_t = lam_w + (1 - S) ** 2 / self.mu_n
+        dlam_w = 2 * S / self.mu_w
+        dlam_t = dlam_w - 2 * (1 - S) / self.mu_n
+        Fp = -self.K * (lam_t * lap_p + dlam_t * gsgp)
+        Fs = self.phi * dSdt - self.Ds * lap_s - self.K * (lam_w * lap_p + dlam_w * gsgp)
+        return Fp, Fs
+
+
 def manufactured_problem(N=64):
     """Parameters of the manufactured periodic workload as a plain dict."""
     m = ManufacturedPeriodic(N)
