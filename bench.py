@@ -42,12 +42,14 @@ HBM_PEAK_GBS = 8000.0
 # flops per lane and clock).  The BGK relaxation of the pressure sweeps is one
 # FMA per population; the other operations are single adds or multiplies.
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
-# flops of one plain pressure sweep per node.  D2Q5: four pulls against the
-# node's base (sub, mul, add each), P - P_b (three adds, one multiply), w P,
-# four BGK relaxations (sub, mul, add each).  D2Q9: eight pulls (sub, mul,
-# add), P - P_b (seven adds, one multiply), eight BGK relaxations (w_j P,
-# sub, mul, add each).
-BLOCK_FLOPS_PER_NODE_SWEEP = {"D2Q5": 29, "D2Q9": 64}
+# flops the method itself does in one plain pressure sweep per node (eq. 3-1,
+# eq. 3-9a): D2Q5: P = sum of 4 populations / (1 - w0) (3 adds, 1 multiply),
+# w1 P (1 multiply), 4 BGK relaxations f - (f - w P)/tau (sub, mul, add each)
+# = 17.  D2Q9: P (7 adds, 1 multiply), w1 P and w2 P (2 multiplies), 8 BGK
+# relaxations = 34.  The pull corrections of the stored deviations,
+# w (P_b(src) - P_b(node)), are a cost of the storage form, not of the
+# method, and are not counted.
+BLOCK_FLOPS_PER_NODE_SWEEP = {"D2Q5": 17, "D2Q9": 34}
 # algorithmic bytes of one plain pressure sweep per node: the Q-1 stored
 # deviations read and written, 1/tau_f and the base pressure P_b read
 POP_BYTES = {"fp32": 4, "fp16": 2, "bf16": 2}
@@ -81,6 +83,10 @@ def parse():
     ap.add_argument("--burst", type=int, default=30, help="launches of the dominant kernel timed for the roofline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tail", action="store_true",
+                    help="2-D injection: skip running the rest of the 5000 configured coupled steps")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="2-D injection: skip the fp16 / bf16 storage legs")
     return ap.parse_args()
 
 
@@ -120,7 +126,7 @@ def cpu_baseline(seconds):
             break
     dt = time.perf_counter() - t0
     updates = n * n * steps * (64 + 1)
-    return {"value": updates / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+    return {"value": updates / dt / 1e6, "unit": "MLUPS", "cores": 1, "host_cores": os.cpu_count(), "kind": "oracle",
             "sample": f"float64 NumPy oracle, 512x512 crop of the same recipe, {steps} coupled steps "
                       f"of 64 pressure iterations + 1 saturation step, {dt:.1f} s"}
 
@@ -215,25 +221,27 @@ def main():
             # eq. 3-4 needs max(phi)/2 <= beta <= 2 min(phi): phi in [0.15, 0.3] -> beta 0.2
             params = dict(params, lattice="D2Q9", beta=0.2)
         ncell = a.n * a.n
-    K = torch.from_numpy(inputs.f32(fl["K"]).ravel()).to(dev)
-    phi = torch.from_numpy(inputs.f32(fl["phi"]).ravel()).to(dev)
-    P0 = torch.from_numpy(inputs.f32(fl["P0"]).ravel()).to(dev)
-    S0 = torch.from_numpy(inputs.f32(fl["S0"]).ravel()).to(dev)
-    s = lbtp.from_problem(params, m=a.m, storage=a.storage)
-    s.set_fields(K, phi)
-    s.set_state(P0, S0)
-    del K, phi, P0, S0
-    torch.cuda.synchronize()
+    def make_solver(storage):
+        K = torch.from_numpy(inputs.f32(fl["K"]).ravel()).to(dev)
+        phi = torch.from_numpy(inputs.f32(fl["phi"]).ravel()).to(dev)
+        P0 = torch.from_numpy(inputs.f32(fl["P0"]).ravel()).to(dev)
+        S0 = torch.from_numpy(inputs.f32(fl["S0"]).ravel()).to(dev)
+        solver = lbtp.from_problem(params, m=a.m, storage=storage)
+        solver.set_fields(K, phi)
+        solver.set_state(P0, S0)
+        del K, phi, P0, S0
+        torch.cuda.synchronize()
+        return solver
 
-    def coupled_step(progress=False):
+    def coupled_step(solver, progress=False):
         """One coupled step: coefficients, pressure solve to tol, saturation step.
         The solve runs in calls of 64k iterations so a long (cold) solve reports
         progress; each call continues the same iteration (checks stay on
         multiples of m)."""
-        s.update_coefficients()
+        solver.update_coefficients()
         total, t0 = 0, time.perf_counter()
         while True:
-            k, r, st = s.pressure_solve(a.tol, min(65536, a.max_iters - total))
+            k, r, st = solver.pressure_solve(a.tol, min(65536, a.max_iters - total))
             total += k
             if progress:
                 print(f"  cold solve: {total} iterations, r = {r:.3e}, {time.perf_counter() - t0:.1f} s",
@@ -242,32 +250,64 @@ def main():
                 break
             if st < 0:
                 raise RuntimeError(f"pressure solve failed: {st}")
-        s.saturation_step()
+        solver.saturation_step()
         return total
 
-    warm_its = []
-    t_cold = None
-    for w in range(a.warmup):
-        t0 = time.perf_counter()
-        warm_its.append(coupled_step(progress=(w == 0)))
+    def run_leg(solver, label):
+        """W warm-up coupled steps (the first is the cold solve), then K timed
+        steps between two synchronisations."""
+        warm, t_cold = [], None
+        for w in range(a.warmup):
+            t0 = time.perf_counter()
+            warm.append(coupled_step(solver, progress=(w == 0)))
+            torch.cuda.synchronize()
+            if w == 0:
+                t_cold = time.perf_counter() - t0
+            print(f"{label} warmup step {w}: {warm[-1]} iterations, {time.perf_counter() - t0:.3f} s",
+                  file=sys.stderr, flush=True)
         torch.cuda.synchronize()
-        if w == 0:
-            t_cold = time.perf_counter() - t0
-        print(f"warmup step {w}: {warm_its[-1]} iterations, {time.perf_counter() - t0:.3f} s",
-              file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        its = []
+        for k in range(a.steps):
+            its.append(coupled_step(solver))
+            if (k + 1) % 10 == 0:
+                print(f"{label} timed step {k + 1}: {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t_run = time.perf_counter() - t0
+        print(f"{label} timed: {a.steps} steps in {t_run:.3f} s, iterations {sum(its)}", file=sys.stderr, flush=True)
+        return dict(warm=warm, t_cold=t_cold, its=its, t_run=t_run,
+                    mlups=ncell * (sum(its) + a.steps) / t_run / 1e6)
 
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    its_all = []
-    for k in range(a.steps):
-        its_all.append(coupled_step())
-        if (k + 1) % 10 == 0:
-            print(f"timed step {k + 1}: {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t_run = time.perf_counter() - t0
+    s = make_solver(a.storage)
+    main_leg = run_leg(s, a.storage)
+    warm_its, t_cold, its_all, t_run = main_leg["warm"], main_leg["t_cold"], main_leg["its"], main_leg["t_run"]
     f_updates = sum(its_all)
-    mlups = ncell * (f_updates + a.steps) / t_run / 1e6
-    print(f"timed: {a.steps} steps in {t_run:.3f} s, iterations {f_updates}", file=sys.stderr, flush=True)
+    mlups = main_leg["mlups"]
+
+    # the rest of the configured 5000 coupled steps (2-D injection), timed on
+    # their own: the timed window above covers only the early steps after the
+    # cold solve, when the front is young and the solves are longest
+    config_steps = 5000 if (a.workload == "injection2d" and not a.no_tail) else 0
+    tail = None
+    done = a.warmup + a.steps
+    if config_steps > done:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tail_its = []
+        for k in range(config_steps - done):
+            tail_its.append(coupled_step(s))
+            if (k + 1) % 1000 == 0:
+                print(f"tail step {done + k + 1}: {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t_tail = time.perf_counter() - t0
+        warm_all = warm_its[1:] + its_all + tail_its
+        t_warm_all = t_run + t_tail            # warm-up steps 2..W are not timed; steps W+1..5000 are
+        n_warm_timed = len(its_all) + len(tail_its)
+        tail = {"steps": f"{a.warmup + 1}..{config_steps}", "s_per_coupled_step": t_warm_all / n_warm_timed,
+                "iterations_per_step_mean": (sum(its_all) + sum(tail_its)) / n_warm_timed,
+                "mlups": round(ncell * (sum(its_all) + sum(tail_its) + n_warm_timed) / t_warm_all / 1e6, 1),
+                "iterations_per_step_percentiles": {q: int(np.percentile(warm_all, q)) for q in (50, 90, 99)}}
+        print(f"steps {a.warmup + 1}..{config_steps}: {t_warm_all:.2f} s", file=sys.stderr, flush=True)
 
     # dominant kernel: a burst of back-to-back launches of the plain pressure
     # sweep (lbtp_probe_sweeps), HIP events on the solver's stream
@@ -311,8 +351,16 @@ def main():
                     "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": traffic,
                     "kernel": f"{kname} ({H} plain pressure sweeps per launch)",
                     "avg_launch_us": round(launch_s * 1e6, 2), "flops_per_launch": flops,
-                    "hbm_GBps_measured": round(traffic / launch_s / 1e9, 1) if traffic else None,
-                    "streaming_equivalent_GBps": round(alg_bytes * H / launch_s / 1e9, 1)}
+                    "method_flops_per_node_sweep": BLOCK_FLOPS_PER_NODE_SWEEP[params["lattice"]],
+                    # temporal blocking: H sweeps per HBM round trip of the populations
+                    "blocking_factor": H,
+                    "one_pass_bytes_per_launch": alg_bytes,
+                    "one_pass_GBps": round(alg_bytes / launch_s / 1e9, 1),
+                    "counter_GBps": round(traffic / launch_s / 1e9, 1) if traffic else None,
+                    "counter_over_one_pass": round(traffic / alg_bytes, 3) if traffic else None,
+                    # what H one-sweep launches would have to stream per second for the
+                    # same work; above the HBM peak because the H sweeps share one pass
+                    "sweep_equivalent_GBps": round(alg_bytes * H / launch_s / 1e9, 1)}
     else:
         achieved = alg_bytes / sweep_s / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -355,6 +403,29 @@ def main():
         "f_sweep_us": round(sweep_s * 1e6, 2),
         "roofline": roofline,
     }
+    if tail is not None:
+        out["config_mean"] = tail
+    if a.workload == "injection2d" and a.storage == "fp32" and not a.no_legs:
+        # the reduced-precision storage forms on the same workload and tolerance
+        s.close()
+        del s
+        torch.cuda.synchronize()
+        legs = {}
+        for st in ("fp16", "bf16"):
+            sl = make_solver(st)
+            leg = run_leg(sl, st)
+            sl.close()
+            del sl
+            torch.cuda.synchronize()
+            legs[st] = {"value": round(leg["mlups"], 1), "unit": "MLUPS",
+                        "s_per_coupled_step": leg["t_run"] / a.steps,
+                        "iterations_per_step_mean": sum(leg["its"]) / a.steps,
+                        "cold_first_step_s": leg["t_cold"],
+                        "cold_first_step_iterations": leg["warm"][0] if leg["warm"] else None,
+                        "mlups_over_fp32": round(leg["mlups"] / mlups, 3),
+                        "step_time_fp32_over_this": round(t_run / leg["t_run"], 3),
+                        "cold_solve_fp32_over_this": round(t_cold / leg["t_cold"], 3) if t_cold else None}
+        out["storage_legs"] = legs
     if not a.no_cpu and a.workload == "injection2d":
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -59,7 +59,7 @@ extern "C" {
 
 typedef struct lbtp_ctx lbtp_ctx;
 
-/* D2Q9 runs one node per thread and is not available to ensembles. */
+/* D2Q9 plain pressure sweeps run blocked (several per launch) or four nodes per thread. */
 enum lbtp_lattice { LBTP_D2Q5 = 0, LBTP_D3Q7 = 1, LBTP_D2Q9 = 2 };
 
 /* Storage of the pressure-lattice populations.  Every form stores the

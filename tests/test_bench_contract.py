@@ -26,6 +26,12 @@ def test_algorithmic_bytes_per_node():
     assert bench.f_sweep_bytes("D2Q9", "bf16") == 2 * 8 * 2 + 8
 
 
+def test_method_flops_per_node_sweep():
+    # D2Q5: P (3 adds, 1 mul), w1 P (1 mul), 4 x BGK (sub, mul, add);
+    # D2Q9: P (7 adds, 1 mul), w1 P, w2 P, 8 x BGK
+    assert bench.BLOCK_FLOPS_PER_NODE_SWEEP == {"D2Q5": 3 + 1 + 1 + 4 * 3, "D2Q9": 7 + 1 + 2 + 8 * 3}
+
+
 def test_alu_peak_from_unit_counts():
     # 256 compute units x 64 lanes x one FMA (2 flops) per clock x 2.4 GHz
     assert abs(bench.ALU_PEAK_TFLOPS - 78.6432) < 1e-9
