@@ -167,3 +167,57 @@ def test_example2_matches_stored_oracle_errors():
         assert E[k] < gold["paper_bound"], (k, E[k])
     for k, v in E.items():
         assert abs(v - gold["errors"][k]) <= 0.02 * gold["errors"][k], (k, v, gold["errors"][k])
+
+
+@pytest.mark.parametrize("N", [32])
+def test_example2_replay_matches_oracle_fields(N):
+    """Example 2 (c = 10, T = 0.2) at 32^2: the GPU replays the oracle's
+    pressure iteration counts (solves to r <= 1e-10 with m = 1 in the oracle)
+    and must match the oracle's P, u and S field by field (relative L2 <=
+    1e-5, float32 storage)."""
+    from tests.paper_examples import example2
+    out = {}
+    example2(N, tol=1e-10, out=out)
+    o = out["solver"]
+    iters = out["iters"]
+    c, T, L, Ds, phi = 10.0, 0.2, 1.0, 0.01, 1.0
+    dx = L / N
+    dt = dx / c
+    g = gpu_solver(N, L, c, 1.0, Ds, ("rational", 1.0, 0.0, 0.0, 1.0, 0.5, -0.2))
+    X, Y = o.X[0], o.Y[0]
+    th = lambda x, y, t: np.pi * (x + y - 2 * t)
+    Pex = lambda x, y, t: -np.cos(th(x, y, t)) / (5 * np.pi) - (x + y) / 2
+    Sex = lambda x, y, t: np.sin(th(x, y, t))
+
+    def Fs(t):
+        return f32(2 * np.pi ** 2 * Ds * np.sin(th(X, Y, t)) + 2 * np.pi * (1 - phi) * np.cos(th(X, Y, t))).ravel()
+
+    n = N * N
+    g.set_fields(np.ones(n), np.full(n, phi), None, Fs(0.0))
+    S0 = Sex(X, Y, 0.0)
+    gp = S0 / 5 - 0.5
+    gs = np.pi * np.cos(th(X, Y, 0.0))
+    g.set_state(f32(Pex(X, Y, 0.0)).ravel(), f32(S0).ravel(), dP0=f32(np.stack([gp, gp])).ravel(),
+                dS0=f32(np.stack([gs, gs])).ravel())
+    for step, k in enumerate(iters[:-1]):
+        t = step * dt
+        g.set_sources(None, Fs(t))
+        set_walls(g, N, dx, P=Pex, t=t)
+        g.update_coefficients()
+        kg, _, _ = g.pressure_solve(-1.0, k)
+        assert kg == k
+        set_walls(g, N, dx, S=Sex, t=t + 0.5 * dt)
+        g.saturation_step()
+    t = (len(iters) - 1) * dt
+    g.set_sources(None, Fs(t))
+    set_walls(g, N, dx, P=Pex, t=t)
+    g.update_coefficients()
+    g.pressure_solve(-1.0, iters[-1])
+    P = g.pressure().cpu().numpy().reshape(N, N).astype(np.float64)
+    u = g.velocity().cpu().numpy().reshape(2, N, N).astype(np.float64)
+    S = g.saturation().cpu().numpy().reshape(N, N).astype(np.float64)
+    err = {"P": rel_l2(o.pressure()[0], P), "u": rel_l2(o.velocity()[:2, 0], u), "S": rel_l2(o.saturation()[0], S)}
+    print(f"Example 2 at {N}^2, GPU vs oracle ({sum(iters)} iterations replayed, rel L2):",
+          {k: f"{v:.2e}" for k, v in err.items()})
+    for k, v in err.items():
+        assert v <= 1e-5, (k, v)

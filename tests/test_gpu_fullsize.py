@@ -108,7 +108,7 @@ def _samples(full, rng, n_interior, R):
     return pts
 
 
-@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
 def test_injection_2d_4096_sampled_parity(storage):
     params, fl = inputs.injection_2d(4096)
     rng = np.random.default_rng(17)
@@ -118,12 +118,17 @@ def test_injection_2d_4096_sampled_parity(storage):
         assert v <= tol, (k, v, tol)
 
 
-def test_injection_3d_512_sampled_parity():
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
+def test_injection_3d_512_sampled_parity(storage):
+    """512^3 D3Q7 in every storage format: float32 within 1e-5, the 16-bit
+    deviation forms within 16 unit roundoffs of their format (the bound of
+    the 2-D case: they round once per sweep here)."""
     params, fl = inputs.injection_3d(512)
     rng = np.random.default_rng(19)
-    worst = _check_samples(params, fl, _samples((512, 512, 512), rng, 2, reach(K1_3D)), "fp32", K1_3D)
+    worst = _check_samples(params, fl, _samples((512, 512, 512), rng, 2, reach(K1_3D)), storage, K1_3D)
+    tol = 1e-5 if storage == "fp32" else 16 * UNIT_ROUNDOFF[storage]
     for k, v in worst.items():
-        assert v <= 1e-5, (k, v)
+        assert v <= tol, (k, v, tol)
 
 
 def test_ensemble_256_sampled_parity():
