@@ -53,6 +53,23 @@ LBTP_API int lbtp_nn_get_params(lbtp_nn *nn, float *theta, int on_device);
  * w/factor multiples of 2^(levels-1). */
 LBTP_API int lbtp_nn_predict(lbtp_nn *nn, const float *lnK, const float *S, int n, int h, int w, int factor,
                              float *P, int on_device);
+/* lbtp_nn_predict without any device allocation, for callers that cannot
+ * allocate: code being captured into a HIP graph, tight serving loops, hosts
+ * that forbid hipMalloc.  Same result as lbtp_nn_predict (the same kernels
+ * in the same order).  lnK, S and P are device pointers of the current
+ * device; the activations, the head output and the coarsened inputs live in
+ * a static device array of LBTP_NN_SCRATCH_BYTES per device, held from
+ * library load until the process ends (its address is looked up once per
+ * device, at lbtp_nn_create or at the first call on another device).  A
+ * shape whose buffers do not fit -- about 1.2 kB per coarse node
+ * n * (h/factor) * (w/factor) with base 32 and 4 levels, so up to 128 x 128
+ * coarse nodes -- is rejected with LBTP_EINVAL before anything is launched.
+ * Every call on one device shares that array: calls that overlap on one
+ * device (several streams, several threads) race and must be serialised by
+ * the caller.  Enqueued on the network's stream; does not synchronise. */
+#define LBTP_NN_SCRATCH_BYTES (32ll << 20)
+LBTP_API int lbtp_nn_predict_noalloc(lbtp_nn *nn, const float *lnK, const float *S, int n, int h, int w, int factor,
+                                     float *P);
 /* Weighted mean squared error L = (1 / (n h w)) sum_k weight[k] sum_nodes
  * (P_net - P)^2 against the target P, and its gradient (flat, may be NULL).
  * weight: one float per sample, or NULL for all ones. */

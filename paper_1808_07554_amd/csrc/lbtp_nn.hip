@@ -23,6 +23,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "../../include/lbtp_nn.h"
@@ -437,6 +438,25 @@ int pad16(int c) { return (c + 15) / 16 * 16; }
 
 }  // namespace
 
+namespace {
+// Bump allocation from a caller-independent device buffer (the no-allocation
+// predict): offsets aligned to 256 bytes, never beyond cap.
+struct Arena {
+  char *base = nullptr;
+  size_t cap = 0, used = 0;
+};
+
+void *arena_take(Arena *a, size_t bytes, int *rc) {
+  const size_t off = (a->used + 255) & ~(size_t)255;
+  if (off > a->cap || bytes > a->cap - off) {
+    *rc = LBTP_ENOMEM;
+    return nullptr;
+  }
+  a->used = off + bytes;
+  return a->base + off;
+}
+}  // namespace
+
 struct lbtp_nn {
   int base = 32, levels = 4;
   float scale = 1.0f;
@@ -451,6 +471,9 @@ struct lbtp_nn {
   size_t part_cap = 0;
   float *head = nullptr;
   size_t head_cap = 0;
+  float *head_cur = nullptr;   // head output of the last forward pass
+  Arena *arena = nullptr;      // set: forward takes its buffers from here
+  int device = -1;             // HIP device current at creation
   double *lpart = nullptr, *dloss = nullptr;
   size_t lpart_cap = 0;
 };
@@ -474,6 +497,7 @@ int ensure(void **p, size_t *cap, size_t bytes) {
 }
 
 bf16 *tensor(lbtp_nn *nn, int slot, size_t elems, int *rc) {
+  if (nn->arena) return (bf16 *)arena_take(nn->arena, elems * sizeof(bf16), rc);
   if ((int)nn->act.size() <= slot) nn->act.resize(slot + 1);
   Tensor &t = nn->act[slot];
   if (ensure((void **)&t.p, &t.cap, elems * sizeof(bf16))) *rc = LBTP_ENOMEM;
@@ -571,14 +595,20 @@ int forward(lbtp_nn *nn, const float *lnK, const float *S, int N, int H, int W, 
   }
   // head (float output)
   const NNLayer &hl = nn->L[nconv - 1];
-  if ((rc = ensure((void **)&nn->head, &nn->head_cap, (size_t)npix * 16 * sizeof(float)))) return rc;
+  if (nn->arena) {
+    nn->head_cur = (float *)arena_take(nn->arena, (size_t)npix * 16 * sizeof(float), &rc);
+    if (rc) return rc;
+  } else {
+    if ((rc = ensure((void **)&nn->head, &nn->head_cap, (size_t)npix * 16 * sizeof(float)))) return rc;
+    nn->head_cur = nn->head;
+  }
   if (tape) {
     tape->x.push_back(cur);
     tape->y.push_back(nullptr);
     tape->H.push_back(h);
     tape->W.push_back(wd);
   }
-  if ((rc = conv_fwd(nn, cur, hl.w, hl.b, nn->head, N, h, wd, hl.cip, hl.cop, false, true))) return rc;
+  if ((rc = conv_fwd(nn, cur, hl.w, hl.b, nn->head_cur, N, h, wd, hl.cip, hl.cop, false, true))) return rc;
   return LBTP_OK;
 }
 
@@ -702,7 +732,7 @@ int loss_grad(lbtp_nn *nn, const float *lnK, const float *S, const float *T, con
   size_t pcap = 0;
   // predicted pressure in a scratch tensor (float) placed after the head
   if ((rc = ensure((void **)&P, &pcap, (size_t)npix * sizeof(float)))) return rc;
-  hipLaunchKernelGGL(head_out_kernel, GRID1(npix), 0, nn->stream, nn->head, P, npix, W, nn->scale);
+  hipLaunchKernelGGL(head_out_kernel, GRID1(npix), 0, nn->stream, nn->head_cur, P, npix, W, nn->scale);
   int nb = (int)((npix + 255) / 256);
   if ((rc = ensure((void **)&nn->lpart, &nn->lpart_cap, (size_t)(nb + 1) * sizeof(double)))) {
     (void)hipFree(P);
@@ -755,6 +785,60 @@ void free_tmp(lbtp_nn *nn, std::vector<void *> &tmp) {
   tmp.clear();
 }
 
+// Device scratch of the no-allocation predict: the activations, the head
+// output and the coarsened inputs of one forward pass.  Each device holds its
+// own copy from module load until the process ends.  Host code must use the
+// address hipGetSymbolAddress returns for the current device, never the
+// array's name.
+constexpr size_t kNNScratchBytes = (size_t)LBTP_NN_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char nn_scratch[kNNScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Address of nn_scratch on the current device (looked up once per device).
+int scratch_of_current_device(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return LBTP_EHIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(nn_scratch)) != hipSuccess || !p) return LBTP_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBTP_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Bytes forward() takes from an arena for N x H x W (the same sequence of
+// buffers, each rounded up to 256 bytes as arena_take places them).
+size_t forward_bytes(const lbtp_nn *nn, int N, int H, int W) {
+  const size_t npix = (size_t)N * H * W;
+  size_t b = align256(npix * 16 * sizeof(bf16));
+  size_t h = H, w = W;
+  int li = 0;
+  for (int lv = 0; lv < nn->levels; ++lv) {
+    if (lv > 0) {
+      b += align256((size_t)N * (h / 2) * (w / 2) * nn->L[li - 1].cop * sizeof(bf16));
+      h /= 2;
+      w /= 2;
+    }
+    for (int k = 0; k < 2; ++k, ++li) b += align256((size_t)N * h * w * nn->L[li].cop * sizeof(bf16));
+  }
+  for (int lv = nn->levels - 2; lv >= 0; --lv) {
+    const size_t Cu = nn->L[li - 1].cop, Cs = nn->L[2 * lv + 1].cop;
+    b += align256((size_t)N * (2 * h) * (2 * w) * Cu * sizeof(bf16));
+    h *= 2;
+    w *= 2;
+    b += align256((size_t)N * h * w * (Cu + Cs) * sizeof(bf16));
+    for (int k = 0; k < 2; ++k, ++li) b += align256((size_t)N * h * w * nn->L[li].cop * sizeof(bf16));
+  }
+  return b + align256(npix * 16 * sizeof(float));
+}
+
 }  // namespace
 
 extern "C" {
@@ -767,6 +851,18 @@ int lbtp_nn_create(int base, int levels, double scale, void *stream, lbtp_nn **o
   nn->levels = levels;
   nn->scale = (float)scale;
   nn->stream = (hipStream_t)stream;
+  if (hipGetDevice(&nn->device) != hipSuccess) {
+    delete nn;
+    return LBTP_EHIP;
+  }
+  {
+    // the device scratch of lbtp_nn_predict_noalloc, looked up at set-up
+    void *scratch = nullptr;
+    if (scratch_of_current_device(&scratch) != LBTP_OK) {
+      delete nn;
+      return LBTP_EHIP;
+    }
+  }
   // layer list (same order as the flat parameter vector)
   std::vector<int> c(levels);
   for (int l = 0; l < levels; ++l) c[l] = base << l;
@@ -888,10 +984,10 @@ int lbtp_nn_predict(lbtp_nn *nn, const float *lnK, const float *S, int N, int H,
   if (!rc) rc = forward(nn, cK, cS, N, Hc, Wc, nullptr);
   if (!rc) {
     if (factor == 1)
-      hipLaunchKernelGGL(head_out_kernel, GRID1((long long)npix), 0, nn->stream, nn->head, dP, (long long)npix, W,
+      hipLaunchKernelGGL(head_out_kernel, GRID1((long long)npix), 0, nn->stream, nn->head_cur, dP, (long long)npix, W,
                          nn->scale);
     else
-      hipLaunchKernelGGL(upsample_kernel, GRID1((long long)npix), 0, nn->stream, nn->head, dP, (long long)npix, H,
+      hipLaunchKernelGGL(upsample_kernel, GRID1((long long)npix), 0, nn->stream, nn->head_cur, dP, (long long)npix, H,
                          W, factor, nn->scale / (float)Wc);
     if (hipGetLastError() != hipSuccess) rc = LBTP_EHIP;
   }
@@ -900,6 +996,44 @@ int lbtp_nn_predict(lbtp_nn *nn, const float *lnK, const float *S, int N, int H,
     rc = LBTP_EHIP;
   free_tmp(nn, tmp);
   return rc;
+}
+
+int lbtp_nn_predict_noalloc(lbtp_nn *nn, const float *lnK, const float *S, int N, int H, int W, int factor,
+                            float *P) {
+  if (!nn || !lnK || !S || !P || factor < 1 || H < 1 || W < 1 || H % factor || W % factor) return LBTP_EINVAL;
+  const int Hc = H / factor, Wc = W / factor;
+  int rc = check_shape(nn, N, Hc, Wc);
+  if (rc) return rc;
+  const size_t npix = (size_t)N * H * W, ncoarse = (size_t)N * Hc * Wc;
+  const size_t need = forward_bytes(nn, N, Hc, Wc) + (factor > 1 ? align256(2 * ncoarse * sizeof(float)) : 0);
+  if (need > kNNScratchBytes) return LBTP_EINVAL;
+  void *scratch = nullptr;
+  if ((rc = scratch_of_current_device(&scratch))) return rc;
+  Arena arena;
+  arena.base = (char *)scratch;
+  arena.cap = kNNScratchBytes;
+  const float *cK = lnK, *cS = S;
+  if (factor > 1) {
+    float *c = (float *)arena_take(&arena, 2 * ncoarse * sizeof(float), &rc);
+    if (rc) return rc;
+    hipLaunchKernelGGL(coarsen_kernel, GRID1((long long)ncoarse), 0, nn->stream, lnK, S, c, c + ncoarse,
+                       (long long)ncoarse, Hc, Wc, factor);
+    if (hipGetLastError() != hipSuccess) return LBTP_EHIP;
+    cK = c;
+    cS = c + ncoarse;
+  }
+  nn->arena = &arena;
+  rc = forward(nn, cK, cS, N, Hc, Wc, nullptr);
+  nn->arena = nullptr;
+  if (rc) return rc;
+  if (factor == 1)
+    hipLaunchKernelGGL(head_out_kernel, GRID1((long long)npix), 0, nn->stream, nn->head_cur, P, (long long)npix, W,
+                       nn->scale);
+  else
+    hipLaunchKernelGGL(upsample_kernel, GRID1((long long)npix), 0, nn->stream, nn->head_cur, P, (long long)npix, H,
+                       W, factor, nn->scale / (float)Wc);
+  nn->head_cur = nullptr;
+  return hipGetLastError() == hipSuccess ? LBTP_OK : LBTP_EHIP;
 }
 
 int lbtp_nn_loss_grad(lbtp_nn *nn, const float *lnK, const float *S, const float *P, const float *weight, int N,

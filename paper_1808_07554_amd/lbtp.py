@@ -103,6 +103,8 @@ EXPORTS = {
     "lbtp_nn_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "lbtp_nn_predict": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
+    "lbtp_nn_predict_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                               ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
     "lbtp_nn_loss_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_int]),
@@ -396,6 +398,22 @@ class WarmStartNet:
         P = self.torch.empty_like(lnK)
         _check(self._lib.lbtp_nn_predict(self._h, ctypes.c_void_p(lnK.data_ptr()), ctypes.c_void_p(S.data_ptr()),
                                          n, h, w, int(factor), ctypes.c_void_p(P.data_ptr()), 1), "lbtp_nn_predict")
+        return P
+
+    def predict_noalloc(self, lnK, S, P, factor=1):
+        """lbtp_nn_predict_noalloc: like predict, into the caller's device
+        tensor P [n, h, w]; lnK, S and P must be contiguous float32 tensors on
+        the device (the library allocates nothing)."""
+        t = self.torch
+        for a in (lnK, S, P):
+            if not (isinstance(a, t.Tensor) and a.is_cuda and a.dtype == t.float32 and a.is_contiguous()):
+                raise ValueError("predict_noalloc takes contiguous float32 device tensors")
+        n, h, w = lnK.shape
+        if tuple(S.shape) != (n, h, w) or tuple(P.shape) != (n, h, w):
+            raise ValueError("lnK, S and P must have one shape")
+        _check(self._lib.lbtp_nn_predict_noalloc(self._h, ctypes.c_void_p(lnK.data_ptr()),
+                                                 ctypes.c_void_p(S.data_ptr()), n, h, w, int(factor),
+                                                 ctypes.c_void_p(P.data_ptr())), "lbtp_nn_predict_noalloc")
         return P
 
     def _weights(self, weight):
