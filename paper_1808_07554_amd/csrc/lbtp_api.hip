@@ -26,7 +26,8 @@ struct lbtp_ctx {
   hipStream_t stream = nullptr;
   KC kc;
   void *fbuf[2] = {nullptr, nullptr};    // nf * ncell deviations of the storage type each
-  float *gbuf[2] = {nullptr, nullptr};   // Q * ncell each
+  void *gbuf[2] = {nullptr, nullptr};    // Q * ncell of the storage type each
+  float *gB[2] = {nullptr, nullptr};     // 16-bit storage: base saturation of each g buffer
   float *Pb[2] = {nullptr, nullptr};     // base pressure of the f deviations
   int fs = 0, gs = 0, pbs = 0;           // index of the state buffers
   int f_local = 1;                       // state buffer holds pre-collision values
@@ -67,9 +68,12 @@ FPtrs fptrs(const lbtp_ctx *c, void *base) {
   for (int j = 0; j < c->nf; ++j) r.p[j] = (char *)base + (size_t)j * c->ncell * es;
   return r;
 }
-GPtrs gptrs(const lbtp_ctx *c, float *base) {
+GPtrs gptrs(const lbtp_ctx *c, int idx) {
   GPtrs r{};
-  for (int i = 0; i < c->Q; ++i) r.p[i] = base + (size_t)i * c->ncell;
+  const size_t es = storage_bytes(c->p.storage);
+  for (int i = 0; i < c->Q; ++i) r.p[i] = (char *)c->gbuf[idx] + (size_t)i * c->ncell * es;
+  r.B = c->gB[idx];
+  r.storage = c->p.storage;
   return r;
 }
 
@@ -175,6 +179,11 @@ void fill_kc(lbtp_ctx *c) {
   k.half_dt = (float)(0.5 * p.dt);
   k.dev_scale = 1.0f;
   k.inv_dev_scale = 1.0f;
+  // fp16 saturation deviations: about one step's change of S times the
+  // equilibrium weights, so 2^10 keeps them out of the subnormal range and
+  // far below the fp16 maximum
+  k.g_scale = p.storage == LBTP_FP16_DEV ? 1024.0f : 1.0f;
+  k.inv_g_scale = 1.0f / k.g_scale;
   for (int f = 0; f < 6; ++f) {
     const bool used = f < 2 * c->dim;
     k.bc_f[f] = used ? p.bc_f[f] : LBTP_BC_PERIODIC;
@@ -287,8 +296,8 @@ const char *lbtp_strerror(int s) {
 
 void lbtp_destroy(lbtp_ctx *c) {
   if (!c) return;
-  void *bufs[] = {c->fbuf[0], c->fbuf[1], c->gbuf[0], c->gbuf[1], c->Pb[0], c->Pb[1], c->K, c->phi,
-                  c->Fp, c->Fs, c->S, c->itau, c->scratch, c->itg};
+  void *bufs[] = {c->fbuf[0], c->fbuf[1], c->gbuf[0], c->gbuf[1], c->gB[0], c->gB[1], c->Pb[0], c->Pb[1],
+                  c->K, c->phi, c->Fp, c->Fs, c->S, c->itau, c->scratch, c->itg};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   for (int f = 0; f < 6; ++f) {
@@ -343,8 +352,10 @@ int lbtp_init(const lbtp_params *p, lbtp_ctx **out) {
     size_t bytes;
   } allocs[] = {{&c->fbuf[0], fbytes},
                 {&c->fbuf[1], fbytes},
-                {(void **)&c->gbuf[0], n * c->Q * 4},
-                {(void **)&c->gbuf[1], n * c->Q * 4},
+                {(void **)&c->gbuf[0], n * c->Q * storage_bytes(p->storage)},
+                {(void **)&c->gbuf[1], n * c->Q * storage_bytes(p->storage)},
+                {(void **)&c->gB[0], p->storage == LBTP_FP32 ? 0 : n * 4},
+                {(void **)&c->gB[1], p->storage == LBTP_FP32 ? 0 : n * 4},
                 {(void **)&c->Pb[0], n * 4},
                 {(void **)&c->Pb[1], n * 4},
                 {(void **)&c->K, n * 4},
@@ -532,7 +543,7 @@ int lbtp_set_state(lbtp_ctx *c, const float *P0, const float *S0, const float *d
     dS = (const float *)c->fbuf[1];
   }
   HIP_TRY(launch_init(c->lk, c->p.storage, c->kc, c->Pb[1], c->S, dP, dS, c->K, c->phi, Fs_or_null(c),
-                      c->p.init_neq, fptrs(c, c->fbuf[0]), c->Pb[0], gptrs(c, c->gbuf[0]), c->stream));
+                      c->p.init_neq, fptrs(c, c->fbuf[0]), c->Pb[0], gptrs(c, 0), c->stream));
   c->fs = 0;
   c->gs = 0;
   c->pbs = 0;
@@ -549,7 +560,7 @@ int lbtp_set_state(lbtp_ctx *c, const float *P0, const float *S0, const float *d
 int lbtp_update_coefficients(lbtp_ctx *c) {
   if (!c) return LBTP_EINVAL;
   if (!c->have_state) return LBTP_ESTATE;
-  HIP_TRY(launch_moments(c->lk, c->kc, gptrs(c, c->gbuf[c->gs]), c->K, c->phi, Fs_or_null(c), c->S, c->itau,
+  HIP_TRY(launch_moments(c->lk, c->kc, gptrs(c, c->gs), c->K, c->phi, Fs_or_null(c), c->S, c->itau,
                          c->partials, 1, c->stream));
   HIP_TRY(launch_finish_sum(c->partials, c->nblk, &c->ctl->mass, 0, nullptr, c->stream));
   c->have_coef = 1;
@@ -749,9 +760,9 @@ int lbtp_probe_sweeps(lbtp_ctx *c, long long launches) {
 int lbtp_saturation_step(lbtp_ctx *c) {
   if (!c) return LBTP_EINVAL;
   if (!c->have_coef) return LBTP_ESTATE;
-  HIP_TRY(launch_g_sweep(c->lk, c->p.storage, c->kc, gptrs(c, c->gbuf[c->gs]), gptrs(c, c->gbuf[c->gs ^ 1]),
+  HIP_TRY(launch_g_sweep(c->lk, c->p.storage, c->kc, gptrs(c, c->gs), gptrs(c, c->gs ^ 1),
                          fptrs(c, c->fbuf[c->fs]), c->f_local, c->Pb[c->pbs], c->itau, c->K, c->phi, Fs_or_null(c),
-                         c->partials, c->stream));
+                         c->S, c->partials, c->stream));
   HIP_TRY(launch_finish_sum(c->partials, c->nblk, &c->ctl->ledger, 1, &c->ctl->last_flux, c->stream));
   c->gs ^= 1;
   c->step += 1;
@@ -804,7 +815,7 @@ int lbtp_grad_p(lbtp_ctx *c, float *g, int on_device) { return grad_common(c, g,
 int lbtp_saturation(lbtp_ctx *c, float *S, int on_device) {
   if (!c || !S) return LBTP_EINVAL;
   if (!c->have_state) return LBTP_ESTATE;
-  HIP_TRY(launch_saturation(c->lk, c->kc, gptrs(c, c->gbuf[c->gs]), c->phi, Fs_or_null(c), c->scratch,
+  HIP_TRY(launch_saturation(c->lk, c->kc, gptrs(c, c->gs), c->phi, Fs_or_null(c), c->scratch,
                             c->stream));
   return download(c, S, c->scratch, c->ncell, on_device);
 }
@@ -812,7 +823,7 @@ int lbtp_saturation(lbtp_ctx *c, float *S, int on_device) {
 int lbtp_mass(lbtp_ctx *c, double *mass, double *ledger) {
   if (!c) return LBTP_EINVAL;
   if (!c->have_state) return LBTP_ESTATE;
-  HIP_TRY(launch_moments(c->lk, c->kc, gptrs(c, c->gbuf[c->gs]), c->K, c->phi, Fs_or_null(c), nullptr, nullptr,
+  HIP_TRY(launch_moments(c->lk, c->kc, gptrs(c, c->gs), c->K, c->phi, Fs_or_null(c), nullptr, nullptr,
                          c->partials, 0, c->stream));
   HIP_TRY(launch_finish_sum(c->partials, c->nblk, &c->ctl->mass, 0, nullptr, c->stream));
   int rc = read_ctl(c);
@@ -860,8 +871,20 @@ int lbtp_populations(lbtp_ctx *c, float *f, float *g, int on_device) {
     if (e != hipSuccess) return LBTP_EHIP;
   }
   if (g) {
-    int rc = download(c, g, c->gbuf[c->gs], n * c->Q, on_device);
-    if (rc) return rc;
+    if (c->p.storage == LBTP_FP32) {
+      int rc = download(c, g, (const float *)c->gbuf[c->gs], n * c->Q, on_device);
+      if (rc) return rc;
+    } else {
+      // 16-bit deviations: reconstruct g_i = e_i + g_i^eq(B) in float32
+      float *dst = g;
+      if (!on_device && hipMalloc((void **)&dst, n * c->Q * sizeof(float)) != hipSuccess) return LBTP_ENOMEM;
+      hipError_t e = launch_g_populations(c->lk, c->kc, gptrs(c, c->gs), c->phi, dst, c->stream);
+      if (e == hipSuccess && !on_device)
+        e = hipMemcpyAsync(g, dst, n * c->Q * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (!on_device) (void)hipFree(dst);
+      if (e != hipSuccess) return LBTP_EHIP;
+    }
   }
   return LBTP_OK;
 }
@@ -880,7 +903,9 @@ size_t ckpt_parts(const lbtp_ctx *c, size_t *fb, size_t *pb, size_t *gb) {
   const size_t n = (size_t)c->ncell;
   *fb = n * c->nf * storage_bytes(c->p.storage);
   *pb = n * sizeof(float);
-  *gb = n * c->Q * sizeof(float);
+  // g populations of the storage type, and with 16-bit storage their base
+  // saturation (float32) after them
+  *gb = n * c->Q * storage_bytes(c->p.storage) + (c->p.storage == LBTP_FP32 ? 0 : n * sizeof(float));
   return sizeof(CkptHeader) + *fb + *pb + *gb;
 }
 
@@ -905,7 +930,7 @@ int lbtp_get_state(lbtp_ctx *c, void *buf, long long nbytes, int on_device) {
   if (rc) return rc;
   CkptHeader h{};
   h.magic = kCkptMagic;
-  h.version = 1;
+  h.version = 2;
   h.lattice = c->p.lattice;
   h.nx = c->p.nx;
   h.ny = c->p.ny;
@@ -928,7 +953,9 @@ int lbtp_get_state(lbtp_ctx *c, void *buf, long long nbytes, int on_device) {
   out += sizeof(h);
   if ((rc = copy_bytes(c, out, c->fbuf[c->fs], fb, d2x))) return rc;
   if ((rc = copy_bytes(c, out + fb, c->Pb[c->pbs], pb, d2x))) return rc;
-  if ((rc = copy_bytes(c, out + fb + pb, c->gbuf[c->gs], gb, d2x))) return rc;
+  const size_t gpop = (size_t)c->ncell * c->Q * storage_bytes(c->p.storage);
+  if ((rc = copy_bytes(c, out + fb + pb, c->gbuf[c->gs], gpop, d2x))) return rc;
+  if (gb > gpop && (rc = copy_bytes(c, out + fb + pb + gpop, c->gB[c->gs], gb - gpop, d2x))) return rc;
   HIP_TRY(hipStreamSynchronize(c->stream));
   return LBTP_OK;
 }
@@ -946,7 +973,7 @@ int lbtp_put_state(lbtp_ctx *c, const void *buf, long long nbytes, int on_device
   } else {
     memcpy(&h, in, sizeof(h));
   }
-  if (h.magic != kCkptMagic || h.version != 1 || h.lattice != c->p.lattice || h.nx != c->p.nx ||
+  if (h.magic != kCkptMagic || h.version != 2 || h.lattice != c->p.lattice || h.nx != c->p.nx ||
       h.ny != c->p.ny || h.nz != c->p.nz || h.storage != c->p.storage)
     return LBTP_EINVAL;
   in += sizeof(h);
@@ -954,7 +981,9 @@ int lbtp_put_state(lbtp_ctx *c, const void *buf, long long nbytes, int on_device
   int rc;
   if ((rc = copy_bytes(c, c->fbuf[0], in, fb, x2d))) return rc;
   if ((rc = copy_bytes(c, c->Pb[0], in + fb, pb, x2d))) return rc;
-  if ((rc = copy_bytes(c, c->gbuf[0], in + fb + pb, gb, x2d))) return rc;
+  const size_t gpop = (size_t)c->ncell * c->Q * storage_bytes(c->p.storage);
+  if ((rc = copy_bytes(c, c->gbuf[0], in + fb + pb, gpop, x2d))) return rc;
+  if (gb > gpop && (rc = copy_bytes(c, c->gB[0], in + fb + pb + gpop, gb - gpop, x2d))) return rc;
   c->ctl_host->ledger = h.ledger;
   if ((rc = copy_bytes(c, &c->ctl->ledger, &c->ctl_host->ledger, sizeof(double), hipMemcpyHostToDevice))) return rc;
   HIP_TRY(hipStreamSynchronize(c->stream));
@@ -1038,8 +1067,8 @@ int batch_tables(lbtp_batch *b, int nt) {
     M.kc = c->kc;
     M.f[0] = fptrs(c, c->fbuf[0]);
     M.f[1] = fptrs(c, c->fbuf[1]);
-    M.g[0] = gptrs(c, c->gbuf[0]);
-    M.g[1] = gptrs(c, c->gbuf[1]);
+    M.g[0] = gptrs(c, 0);
+    M.g[1] = gptrs(c, 1);
     M.Pb[0] = c->Pb[0];
     M.Pb[1] = c->Pb[1];
     M.K = c->K;
@@ -1278,8 +1307,8 @@ int lbtp_batch_step(lbtp_batch *b, long long nsteps, double tol, long long max_i
   int worst = LBTP_OK;
   for (long long s = 0; s < nsteps; ++s) {
     // coefficients of every member
-    HIP_TRY(batch_launch_moments(b->dim, b->ntiles_c, b->d_mem, b->d_tm_c, b->d_ti_c, b->partials, b->gs, 1,
-                                 b->stream));
+    HIP_TRY(batch_launch_moments(b->dim, b->storage, b->ntiles_c, b->d_mem, b->d_tm_c, b->d_ti_c, b->partials,
+                                 b->gs, 1, b->stream));
     HIP_TRY(batch_launch_sum(b->n, b->d_mem, b->d_ctl, b->partials, 0, b->stream));
     // pressure solve of every member: first sweep (re-base), then chunks
     HIP_TRY(batch_launch_reset(b->n, b->d_ctl, max_iters, tol, b->d_active, b->stream));

@@ -178,7 +178,7 @@ __global__ void batch_flip_kernel(BCtl *ctl, int n) {
 __global__ void zero_int_kernel(int *p) { *p = 0; }
 
 // Moments of every member (S, 1/tau_f, mass partials per tile).
-template <int DIM, int NT>
+template <int DIM, int NT, typename TG>
 __global__ __launch_bounds__(NT) void batch_moments_kernel(const Member *__restrict__ mem,
                                                            const int *__restrict__ tmember,
                                                            const int *__restrict__ tindex,
@@ -191,8 +191,8 @@ __global__ __launch_bounds__(NT) void batch_moments_kernel(const Member *__restr
   for (int i = 0; i < 4; ++i) {
     const int c = t * 4 * NT + i * NT + threadIdx.x;
     if (c < M.kc.ncell) {
-      if (M.Fs) acc[0] += moments_cell<DIM, true>(M.kc, M.g[gs], M.K, M.phi, M.Fs, M.S, M.itau, c, write_coef);
-      else acc[0] += moments_cell<DIM, false>(M.kc, M.g[gs], M.K, M.phi, M.Fs, M.S, M.itau, c, write_coef);
+      if (M.Fs) acc[0] += moments_cell<DIM, true, TG>(M.kc, M.g[gs], M.K, M.phi, M.Fs, M.S, M.itau, c, write_coef);
+      else acc[0] += moments_cell<DIM, false, TG>(M.kc, M.g[gs], M.K, M.phi, M.Fs, M.S, M.itau, c, write_coef);
     }
   }
   block_sum<1, NT>(acc, partials);
@@ -215,9 +215,11 @@ __global__ __launch_bounds__(NT) void batch_gsweep_kernel(const Member *__restri
     const int c = t * 4 * NT + i * NT + threadIdx.x;
     if (c < M.kc.ncell) {
       if (M.Fs)
-        acc[0] += g_sweep_cell<DIM, T, FLOCAL, true>(M.kc, M.g[gs], M.g[gs ^ 1], f, Pb, M.itau, M.K, M.phi, M.Fs, c);
+        acc[0] += g_sweep_cell<DIM, T, FLOCAL, true>(M.kc, M.g[gs], M.g[gs ^ 1], f, Pb, M.itau, M.K, M.phi, M.Fs,
+                                                     M.S, c);
       else
-        acc[0] += g_sweep_cell<DIM, T, FLOCAL, false>(M.kc, M.g[gs], M.g[gs ^ 1], f, Pb, M.itau, M.K, M.phi, M.Fs, c);
+        acc[0] += g_sweep_cell<DIM, T, FLOCAL, false>(M.kc, M.g[gs], M.g[gs ^ 1], f, Pb, M.itau, M.K, M.phi, M.Fs,
+                                                      M.S, c);
     }
   }
   block_sum<1, NT>(acc, partials);
@@ -288,10 +290,19 @@ hipError_t batch_launch_sweep(int nt, int dim, int storage, int mode, int local,
   return hipGetLastError();
 }
 
-template <int DIM, int NT>
+template <int DIM, int NT, typename TG>
 static void moments_launch(int nblk, const Member *mem, const int *tm, const int *ti, double *part, int gs,
                            int write_coef, hipStream_t s) {
-  hipLaunchKernelGGL((batch_moments_kernel<DIM, NT>), dim3(nblk), dim3(NT), 0, s, mem, tm, ti, part, gs, write_coef);
+  hipLaunchKernelGGL((batch_moments_kernel<DIM, NT, TG>), dim3(nblk), dim3(NT), 0, s, mem, tm, ti, part, gs,
+                     write_coef);
+}
+
+template <int DIM>
+static void moments_by_storage(int storage, int nblk, const Member *mem, const int *tm, const int *ti, double *part,
+                               int gs, int write_coef, hipStream_t s) {
+  if (storage == LBTP_FP16_DEV) moments_launch<DIM, 256, _Float16>(nblk, mem, tm, ti, part, gs, write_coef, s);
+  else if (storage == LBTP_BF16_DEV) moments_launch<DIM, 256, bf16_t>(nblk, mem, tm, ti, part, gs, write_coef, s);
+  else moments_launch<DIM, 256, float>(nblk, mem, tm, ti, part, gs, write_coef, s);
 }
 
 hipError_t batch_launch_block(int storage, bool has_fp, int nblk, const Member *mem, const BCtl *ctl, const int *tm,
@@ -304,11 +315,11 @@ hipError_t batch_launch_block(int storage, bool has_fp, int nblk, const Member *
   return hipGetLastError();
 }
 
-hipError_t batch_launch_moments(int dim, int nblk, const Member *mem, const int *tm, const int *ti, double *part,
-                                int gs, int write_coef, hipStream_t s) {
+hipError_t batch_launch_moments(int dim, int storage, int nblk, const Member *mem, const int *tm, const int *ti,
+                                double *part, int gs, int write_coef, hipStream_t s) {
   // moments and the saturation step use tiles of kCellTile nodes (256 threads x 4)
-  if (dim == 2) moments_launch<2, 256>(nblk, mem, tm, ti, part, gs, write_coef, s);
-  else moments_launch<3, 256>(nblk, mem, tm, ti, part, gs, write_coef, s);
+  if (dim == 2) moments_by_storage<2>(storage, nblk, mem, tm, ti, part, gs, write_coef, s);
+  else moments_by_storage<3>(storage, nblk, mem, tm, ti, part, gs, write_coef, s);
   return hipGetLastError();
 }
 

@@ -639,8 +639,13 @@ __global__ __launch_bounds__(kQ9BX * kQ9W) void q9_f_block_kernel(KC kc, FPtrs f
 }
 
 // ------------------------------------------------------------------ moments
-template <bool HAS_FS>
-__global__ __launch_bounds__(kThreads) void q9_moments_kernel(KC kc, GPtrs g, const float *__restrict__ K,
+// g_i^eq(B) of eq. 3-4 for population i (0 rest, j + 1 moving) at porosity phi.
+__device__ inline float q9_geq(const KC &kc, int i, float B, float phi) {
+  return (i == 0 ? q9_gamma0(kc, phi) : q9_gamma(kc, i - 1, phi)) * B;
+}
+
+template <bool HAS_FS, typename TG>
+__global__ __launch_bounds__(kThreads) void q9_moments_kernel(KC kc, GPtrs g_, const float *__restrict__ K,
                                                               const float *__restrict__ phi,
                                                               const float *__restrict__ Fs,
                                                               float *__restrict__ S, float *__restrict__ itau,
@@ -648,15 +653,17 @@ __global__ __launch_bounds__(kThreads) void q9_moments_kernel(KC kc, GPtrs g, co
   const int c = blockIdx.x * kThreads + threadIdx.x;
   double acc[1] = {0.0};
   if (c < kc.ncell) {
+    const GP<TG> g = gtyped<TG>(g_);
+    const float ph = phi[c], B = gdev<TG>() ? g.B[c] : 0.0f;
     float gv[9];
     double dm = 0.0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      gv[i] = g.p[i][c];
+      gv[i] = gload(g.p[i], c, gdev<TG>() ? q9_geq(kc, i, B, ph) : 0.0f, kc);
       dm += (double)gv[i];
     }
     const float fs = HAS_FS ? Fs[c] : 0.0f;
-    const float Sv = saturation_of(q9_sum_g(gv), fs, phi[c], kc);
+    const float Sv = saturation_of(q9_sum_g(gv), fs, ph, kc);
     if (write_coef) {
       S[c] = Sv;
       itau[c] = inv_tau_f_of(Sv, K[c], kc);
@@ -674,22 +681,29 @@ __global__ __launch_bounds__(kThreads) void q9_moments_kernel(KC kc, GPtrs g, co
 // (anti-bounce-back with g^eq(S_b, phi(x)), S_b the face value or, for an
 // outflow face, S of the node; bounce-back for no-flux faces).
 template <typename T, bool FLOCAL, bool HAS_FS>
-__global__ __launch_bounds__(kThreads) void q9_g_sweep_kernel(KC kc, GPtrs gin, GPtrs gout, FPtrs f_,
+__global__ __launch_bounds__(kThreads) void q9_g_sweep_kernel(KC kc, GPtrs gin_, GPtrs gout_, FPtrs f_,
                                                               const float *__restrict__ Pb,
                                                               const float *__restrict__ itau,
                                                               const float *__restrict__ K,
                                                               const float *__restrict__ phi,
                                                               const float *__restrict__ Fs,
+                                                              const float *__restrict__ Sn,
                                                               double *__restrict__ partials) {
   const int c = blockIdx.x * kThreads + threadIdx.x;
   double acc[1] = {0.0};
   if (c < kc.ncell) {
     const int y = c / kc.nx, x = c - y * kc.nx;
+    // 16-bit storage: read against the input's base, write as deviations
+    // from g^eq(S^n, phi) of the node written (the output's base is S^n)
+    const GP<T> gin = gtyped<T>(gin_), gout = gtyped<T>(gout_);
+    const float ph = phi[c];
+    const float Bc = gdev<T>() ? gin.B[c] : 0.0f;
     float gv[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) gv[i] = gin.p[i][c];
+    for (int i = 0; i < 9; ++i) gv[i] = gload(gin.p[i], c, gdev<T>() ? q9_geq(kc, i, Bc, ph) : 0.0f, kc);
     const float fs = HAS_FS ? Fs[c] : 0.0f;
-    const float ph = phi[c];
+    const float Snc = gdev<T>() ? Sn[c] : 0.0f;
+    if (gdev<T>()) gout.B[c] = Snc;
     const float Sv = saturation_of(q9_sum_g(gv), fs, ph, kc);
     float e[8];
     q9_load_e<T, FLOCAL>(typed<T>(f_), Pb, c, x, y, kc, Pb[c], e);
@@ -706,7 +720,7 @@ __global__ __launch_bounds__(kThreads) void q9_g_sweep_kernel(KC kc, GPtrs gin, 
       const float geq = q9_gamma0(kc, ph) * Sv;
       float o = gv[0] + (geq - gv[0]) * itg;
       if (HAS_FS) o += kc.w0 * srcw;
-      gout.p[0][c] = o;
+      gstore(gout.p[0], c, o, gdev<T>() ? q9_geq(kc, 0, Snc, ph) : 0.0f, kc);
     }
     double flux = 0.0;
 #pragma unroll
@@ -719,7 +733,8 @@ __global__ __launch_bounds__(kThreads) void q9_g_sweep_kernel(KC kc, GPtrs gin, 
       o += conv * w * (kc.c * ((float)ex * gx + (float)ey * gy));
       const int face = q9_exit_face(kc, kc.bc_g, x, y, ex, ey);
       if (face < 0) {
-        gout.p[j + 1][q9_wrap(y + ey, kc.ny) * kc.nx + q9_wrap(x + ex, kc.nx)] = o;
+        const int d = q9_wrap(y + ey, kc.ny) * kc.nx + q9_wrap(x + ex, kc.nx);
+        gstore(gout.p[j + 1], d, o, gdev<T>() ? q9_geq(kc, j + 1, Sn[d], phi[d]) : 0.0f, kc);
       } else {
         const int slot = q9_wall_slot(face, -ex, -ey);
         const int bc = q9_link_bc(kc.bc_g, kc.wtG, face, face < 2 ? y : x, slot);
@@ -727,7 +742,7 @@ __global__ __launch_bounds__(kThreads) void q9_g_sweep_kernel(KC kc, GPtrs gin, 
         if (bc == LBTP_BC_NOFLUX) r = o;
         else if (bc == LBTP_BC_DIRICHLET) r = 2.0f * G * wall_S(kc, face, x, y, 0, 3, slot) - o;
         else r = 2.0f * G * Sv - o;      // outflow: S_b = S of this node
-        gout.p[q9opp(j) + 1][c] = r;
+        gstore(gout.p[q9opp(j) + 1], c, r, gdev<T>() ? q9_geq(kc, q9opp(j) + 1, Snc, ph) : 0.0f, kc);
         flux += (double)r - (double)o;
       }
     }
@@ -748,10 +763,11 @@ __global__ __launch_bounds__(kThreads) void q9_init_kernel(KC kc, const float *_
                                                            const float *__restrict__ K,
                                                            const float *__restrict__ phi,
                                                            const float *__restrict__ Fs, int neq, FPtrs f_,
-                                                           float *__restrict__ Pb, GPtrs g) {
+                                                           float *__restrict__ Pb, GPtrs g_) {
   const int c = blockIdx.x * kThreads + threadIdx.x;
   if (c >= kc.ncell) return;
   const FP<T> f = typed<T>(f_);
+  const GP<T> g = gtyped<T>(g_);
   const Cell q = cell_of(c, kc);
   const float P = P0[c], S = S0[c], ph = phi[c];
   const float fs = Fs ? Fs[c] : 0.0f;
@@ -774,7 +790,8 @@ __global__ __launch_bounds__(kThreads) void q9_init_kernel(KC kc, const float *_
     const float G0 = q9_gamma0(kc, ph);
     float v = G0 * S;
     if (neq) v -= tau_g * kc.dt * ((G0 / ph - kc.w0 * wsrc) * fs);
-    g.p[0][c] = v;
+    if (gdev<T>()) g.B[c] = S;
+    gstore(g.p[0], c, v, gdev<T>() ? q9_geq(kc, 0, S, ph) : 0.0f, kc);
   }
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
@@ -785,7 +802,7 @@ __global__ __launch_bounds__(kThreads) void q9_init_kernel(KC kc, const float *_
     const float G = q9_gamma(kc, j, ph);
     float v = G * S;
     if (neq) v -= tau_g * kc.dt * ((G / ph - w * wsrc) * fs + G * cds - gamma * w * cdp * itg);
-    g.p[j + 1][c] = v;
+    gstore(g.p[j + 1], c, v, gdev<T>() ? q9_geq(kc, j + 1, S, ph) : 0.0f, kc);
   }
 }
 
@@ -821,16 +838,30 @@ __global__ __launch_bounds__(kThreads) void q9_grad_kernel(KC kc, FPtrs f_, cons
   out[kc.ncell + c] = scale * m1[1];
 }
 
-template <bool HAS_FS>
-__global__ __launch_bounds__(kThreads) void q9_saturation_kernel(KC kc, GPtrs g, const float *__restrict__ phi,
+template <bool HAS_FS, typename TG>
+__global__ __launch_bounds__(kThreads) void q9_saturation_kernel(KC kc, GPtrs g_, const float *__restrict__ phi,
                                                                  const float *__restrict__ Fs,
                                                                  float *__restrict__ S) {
   const int c = blockIdx.x * kThreads + threadIdx.x;
   if (c >= kc.ncell) return;
+  const GP<TG> g = gtyped<TG>(g_);
+  const float ph = phi[c], B = gdev<TG>() ? g.B[c] : 0.0f;
   float gv[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) gv[i] = g.p[i][c];
-  S[c] = saturation_of(q9_sum_g(gv), HAS_FS ? Fs[c] : 0.0f, phi[c], kc);
+  for (int i = 0; i < 9; ++i) gv[i] = gload(g.p[i], c, gdev<TG>() ? q9_geq(kc, i, B, ph) : 0.0f, kc);
+  S[c] = saturation_of(q9_sum_g(gv), HAS_FS ? Fs[c] : 0.0f, ph, kc);
+}
+
+template <typename TG>
+__global__ __launch_bounds__(kThreads) void q9_gpop_kernel(KC kc, GPtrs g_, const float *__restrict__ phi,
+                                                           float *__restrict__ out) {
+  const int c = blockIdx.x * kThreads + threadIdx.x;
+  if (c >= kc.ncell) return;
+  const GP<TG> g = gtyped<TG>(g_);
+  const float ph = phi[c], B = gdev<TG>() ? g.B[c] : 0.0f;
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+    out[(size_t)i * kc.ncell + c] = gload(g.p[i], c, gdev<TG>() ? q9_geq(kc, i, B, ph) : 0.0f, kc);
 }
 
 template <typename T, bool LOCAL>
@@ -916,22 +947,29 @@ hipError_t launch_f_block_q9(int storage, const KC &kc, FPtrs fin, FPtrs fout, c
 
 hipError_t launch_moments_q9(const KC &kc, GPtrs g, const float *K, const float *phi, const float *Fs, float *S,
                              float *itau, double *partials, int write_coef, hipStream_t s) {
-  if (Fs) hipLaunchKernelGGL((q9_moments_kernel<true>), Q9_GRID(kc), kc, g, K, phi, Fs, S, itau, partials, write_coef);
-  else hipLaunchKernelGGL((q9_moments_kernel<false>), Q9_GRID(kc), kc, g, K, phi, Fs, S, itau, partials, write_coef);
+  q9_dispatch(g.storage, 0, [&](auto t, auto) {
+    using TG = std::remove_pointer_t<decltype(t)>;
+    if (Fs)
+      hipLaunchKernelGGL((q9_moments_kernel<true, TG>), Q9_GRID(kc), kc, g, K, phi, Fs, S, itau, partials,
+                         write_coef);
+    else
+      hipLaunchKernelGGL((q9_moments_kernel<false, TG>), Q9_GRID(kc), kc, g, K, phi, Fs, S, itau, partials,
+                         write_coef);
+  });
   return hipGetLastError();
 }
 
 hipError_t launch_g_sweep_q9(int storage, const KC &kc, GPtrs gin, GPtrs gout, FPtrs f, int f_local,
                              const float *Pb, const float *itau, const float *K, const float *phi, const float *Fs,
-                             double *partials, hipStream_t s) {
+                             const float *Sn, double *partials, hipStream_t s) {
   q9_dispatch(storage, f_local, [&](auto t, auto l) {
     using T = std::remove_pointer_t<decltype(t)>;
     constexpr bool L = decltype(l)::value;
     if (Fs)
-      hipLaunchKernelGGL((q9_g_sweep_kernel<T, L, true>), Q9_GRID(kc), kc, gin, gout, f, Pb, itau, K, phi, Fs,
+      hipLaunchKernelGGL((q9_g_sweep_kernel<T, L, true>), Q9_GRID(kc), kc, gin, gout, f, Pb, itau, K, phi, Fs, Sn,
                          partials);
     else
-      hipLaunchKernelGGL((q9_g_sweep_kernel<T, L, false>), Q9_GRID(kc), kc, gin, gout, f, Pb, itau, K, phi, Fs,
+      hipLaunchKernelGGL((q9_g_sweep_kernel<T, L, false>), Q9_GRID(kc), kc, gin, gout, f, Pb, itau, K, phi, Fs, Sn,
                          partials);
   });
   return hipGetLastError();
@@ -966,8 +1004,19 @@ hipError_t launch_grad_q9(int storage, const KC &kc, FPtrs f, int f_local, const
 }
 
 hipError_t launch_saturation_q9(const KC &kc, GPtrs g, const float *phi, const float *Fs, float *S, hipStream_t s) {
-  if (Fs) hipLaunchKernelGGL((q9_saturation_kernel<true>), Q9_GRID(kc), kc, g, phi, Fs, S);
-  else hipLaunchKernelGGL((q9_saturation_kernel<false>), Q9_GRID(kc), kc, g, phi, Fs, S);
+  q9_dispatch(g.storage, 0, [&](auto t, auto) {
+    using TG = std::remove_pointer_t<decltype(t)>;
+    if (Fs) hipLaunchKernelGGL((q9_saturation_kernel<true, TG>), Q9_GRID(kc), kc, g, phi, Fs, S);
+    else hipLaunchKernelGGL((q9_saturation_kernel<false, TG>), Q9_GRID(kc), kc, g, phi, Fs, S);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_g_populations_q9(const KC &kc, GPtrs g, const float *phi, float *out, hipStream_t s) {
+  q9_dispatch(g.storage, 0, [&](auto t, auto) {
+    using TG = std::remove_pointer_t<decltype(t)>;
+    hipLaunchKernelGGL((q9_gpop_kernel<TG>), Q9_GRID(kc), kc, g, phi, out);
+  });
   return hipGetLastError();
 }
 

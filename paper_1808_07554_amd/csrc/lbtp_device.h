@@ -5,6 +5,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lbtp_internal.h"
 
 namespace lbtp {
@@ -76,6 +78,42 @@ __host__ __device__ inline FP<T> typed(const FPtrs &f) {
   for (int j = 0; j < 8; ++j) r.p[j] = (T *)f.p[j];
   return r;
 }
+
+// Typed view of a saturation buffer (GPtrs).
+template <typename T>
+struct GP {
+  T *p[9];
+  float *B;
+};
+template <typename T>
+__host__ __device__ inline GP<T> gtyped(const GPtrs &g) {
+  GP<T> r;
+  for (int i = 0; i < 9; ++i) r.p[i] = (T *)g.p[i];
+  r.B = g.B;
+  return r;
+}
+
+// g_i^eq(B) of eq. 3-4b on D2Q5 / D3Q7: [(w0 - 1) beta + phi] B for the rest
+// population, w1 beta B for the moving ones.
+__device__ inline float geq_odd(const KC &kc, int i, float B, float phi) {
+  return i == 0 ? (kc.geq0_phi + phi) * B : kc.w1beta * B;
+}
+
+// Saturation population i at node c: stored as is (float32), or as the
+// 16-bit deviation from geq (the caller's g_i^eq(B) of the node, from the
+// buffer's base B) in FP32 arithmetic.
+template <typename T>
+__device__ inline float gload(const T *p, int c, float geq, const KC &kc) {
+  if constexpr (std::is_same<T, float>::value) return p[c];
+  else return Storage<T>::load(p, c, kc.inv_g_scale) + geq;
+}
+template <typename T>
+__device__ inline void gstore(T *p, int c, float v, float geq, const KC &kc) {
+  if constexpr (std::is_same<T, float>::value) p[c] = v;
+  else Storage<T>::store(p, c, v - geq, kc.g_scale);
+}
+template <typename T>
+constexpr bool gdev() { return !std::is_same<T, float>::value; }
 
 // Node index within the wall-value arrays of a face: y + ny z (x faces),
 // x + nx z (y faces), x + nx y (z faces).
@@ -557,19 +595,22 @@ __device__ inline void sweep_quad(const KC &kc, const FP<T> &fin, const FP<T> &f
 
 // S^n (eq. 3-9b) and 1/tau_f (eq. 3-11a, 2-9, 2-16) at node c; returns the
 // node's mass sum_i g_i + dt F_s / 2 (= phi S) in float64.
-template <int DIM, bool HAS_FS>
-__device__ inline double moments_cell(const KC &kc, const GPtrs &g, const float *__restrict__ K,
+template <int DIM, bool HAS_FS, typename TG>
+__device__ inline double moments_cell(const KC &kc, const GPtrs &g_, const float *__restrict__ K,
                                       const float *__restrict__ phi, const float *__restrict__ Fs,
                                       float *__restrict__ S, float *__restrict__ itau, int c, int write_coef) {
+  const GP<TG> g = gtyped<TG>(g_);
+  const float ph = phi[c];
+  const float B = gdev<TG>() ? g.B[c] : 0.0f;
   float gv[2 * DIM + 1];
   double dm = 0.0;
 #pragma unroll
   for (int i = 0; i <= 2 * DIM; ++i) {
-    gv[i] = g.p[i][c];
+    gv[i] = gload(g.p[i], c, gdev<TG>() ? geq_odd(kc, i, B, ph) : 0.0f, kc);
     dm += (double)gv[i];
   }
   const float fs = HAS_FS ? Fs[c] : 0.0f;
-  const float Sv = saturation_of(sum_g<DIM>(gv), fs, phi[c], kc);
+  const float Sv = saturation_of(sum_g<DIM>(gv), fs, ph, kc);
   if (write_coef) {
     S[c] = Sv;
     itau[c] = inv_tau_f_of(Sv, K[c], kc);
@@ -583,17 +624,25 @@ __device__ inline double moments_cell(const KC &kc, const GPtrs &g, const float 
 // grad P of eq. 3-10a read from the pressure lattice as in the pressure sweep,
 // gamma = -lambda_w K / (c_s^2 dt), eq. 3-8): collide and push to x + c_i, or
 // reflect at walls (Section 4).  Returns the net flux through reflected links.
+// With 16-bit storage (T) both lattices are stored in 16 bits: the
+// saturation populations are read against the input buffer's base and
+// written as deviations from g^eq(S^n) of the node they land on (Sn, the
+// saturation of this coupled step, which becomes the output buffer's base).
 template <int DIM, typename T, bool FLOCAL, bool HAS_FS>
-__device__ inline double g_sweep_cell(const KC &kc, const GPtrs &gin, const GPtrs &gout, const FP<T> &f,
+__device__ inline double g_sweep_cell(const KC &kc, const GPtrs &gin_, const GPtrs &gout_, const FP<T> &f,
                                       const float *__restrict__ Pb, const float *__restrict__ itau,
                                       const float *__restrict__ K, const float *__restrict__ phi,
-                                      const float *__restrict__ Fs, int c) {
+                                      const float *__restrict__ Fs, const float *__restrict__ Sn, int c) {
   const Cell q = cell_of(c, kc);
+  const GP<T> gin = gtyped<T>(gin_), gout = gtyped<T>(gout_);
+  const float ph = phi[c];
+  const float Bc = gdev<T>() ? gin.B[c] : 0.0f;
   float gv[2 * DIM + 1];
 #pragma unroll
-  for (int i = 0; i <= 2 * DIM; ++i) gv[i] = gin.p[i][c];
+  for (int i = 0; i <= 2 * DIM; ++i) gv[i] = gload(gin.p[i], c, gdev<T>() ? geq_odd(kc, i, Bc, ph) : 0.0f, kc);
   const float fs = HAS_FS ? Fs[c] : 0.0f;
-  const float ph = phi[c];
+  const float Snc = gdev<T>() ? Sn[c] : 0.0f;
+  if (gdev<T>()) gout.B[c] = Snc;
   const float Sv = saturation_of(sum_g<DIM>(gv), fs, ph, kc);
   float e[2 * DIM];
   load_e<DIM, T, FLOCAL>(f, Pb, q, kc, Pb[c], e);
@@ -611,7 +660,7 @@ __device__ inline double g_sweep_cell(const KC &kc, const GPtrs &gin, const GPtr
     const float geq = (kc.geq0_phi + ph) * Sv;
     float o = gv[0] + (geq - gv[0]) * itg;
     if (HAS_FS) o += kc.w0 * srcw;
-    gout.p[0][c] = o;
+    gstore(gout.p[0], c, o, gdev<T>() ? geq_odd(kc, 0, Snc, ph) : 0.0f, kc);
   }
   const float geq = kc.w1beta * Sv;
   double flux = 0.0;
@@ -624,19 +673,21 @@ __device__ inline double g_sweep_cell(const KC &kc, const GPtrs &gin, const GPtr
     const int x = coord(q, a), n = extent(kc, a), st = stride_of(kc, a);
     const bool out = (s > 0) ? (x == n - 1) : (x == 0);
     if (!out) {
-      gout.p[j + 1][c + s * st] = o;
+      const int d = c + s * st;
+      gstore(gout.p[j + 1], d, o, gdev<T>() ? kc.w1beta * Sn[d] : 0.0f, kc);
     } else {
       const int face = 2 * a + (s > 0 ? 1 : 0);
       const int bc = kc.bc_g[face];
       if (bc == LBTP_BC_PERIODIC) {
-        gout.p[j + 1][c + s * st - s * n * st] = o;
+        const int d = c + s * st - s * n * st;
+        gstore(gout.p[j + 1], d, o, gdev<T>() ? kc.w1beta * Sn[d] : 0.0f, kc);
       } else {
         float r;
         if (bc == LBTP_BC_NOFLUX) r = o;
         else if (bc == LBTP_BC_DIRICHLET)
           r = (kc.wS[face] ? 2.0f * kc.w1beta * wall_S(kc, face, q.x, q.y, q.z, 1, 0) : kc.abbS[face]) - o;
         else r = 2.0f * kc.w1beta * Sv - o;    // outflow: S_wb = S of this node
-        gout.p[dir_opp(j) + 1][c] = r;
+        gstore(gout.p[dir_opp(j) + 1], c, r, gdev<T>() ? kc.w1beta * Snc : 0.0f, kc);
         flux += (double)r - (double)o;
       }
     }
@@ -670,8 +721,9 @@ __device__ inline void init_cell(const KC &kc, const float *__restrict__ P0, con
                                  const float *__restrict__ dP0, const float *__restrict__ dS0,
                                  const float *__restrict__ K, const float *__restrict__ phi,
                                  const float *__restrict__ Fs, int neq, const FP<T> &f, float *__restrict__ Pb,
-                                 const GPtrs &g, int c) {
+                                 const GPtrs &g_, int c) {
   const Cell q = cell_of(c, kc);
+  const GP<T> g = gtyped<T>(g_);
   const float P = P0[c], S = S0[c], ph = phi[c];
   const float fs = Fs ? Fs[c] : 0.0f;
   float gp[3] = {0.f, 0.f, 0.f}, gs[3] = {0.f, 0.f, 0.f};
@@ -701,7 +753,8 @@ __device__ inline void init_cell(const KC &kc, const float *__restrict__ P0, con
     const float G0 = kc.geq0_phi + ph;
     float v = G0 * S;
     if (neq) v -= tau_g * kc.dt * ((G0 / ph - kc.w0 * wsrc) * fs);
-    g.p[0][c] = v;
+    if (gdev<T>()) g.B[c] = S;
+    gstore(g.p[0], c, v, gdev<T>() ? geq_odd(kc, 0, S, ph) : 0.0f, kc);
   }
   const float G = kc.w1beta;
 #pragma unroll
@@ -713,7 +766,7 @@ __device__ inline void init_cell(const KC &kc, const float *__restrict__ P0, con
       const float cds = (float)s * kc.c * gs[a];
       v -= tau_g * kc.dt * ((G / ph - kc.w1 * wsrc) * fs + G * cds - gamma * kc.w1 * cdp * itg);
     }
-    g.p[j + 1][c] = v;
+    gstore(g.p[j + 1], c, v, gdev<T>() ? kc.w1beta * S : 0.0f, kc);
   }
 }
 

@@ -38,6 +38,7 @@ struct KC {
   float half_dt;    // dt / 2
   float dev_scale;      // storage scale of 16-bit float deviations (a power of two)
   float inv_dev_scale;  // its inverse
+  float g_scale, inv_g_scale;   // the same for the saturation deviations
   int bc_f[6];
   float Pw[6];      // Dirichlet pressure of a face
   int bc_g[6];
@@ -84,7 +85,16 @@ struct Ctl {
 // Each returns the hipError_t of the launch.  Pointer arrays hold one base
 // pointer per stored population.
 struct FPtrs { void *p[8]; };
-struct GPtrs { float *p[9]; };
+// Saturation populations: Q arrays of the storage type.  With 16-bit
+// storage they hold deviations e_i = g_i - g_i^eq(B) from the equilibrium
+// (eq. 3-4b, or eq. 3-4 on D2Q9) of a per-node base saturation B, the
+// saturation the buffer was written against; B is null for float32 storage,
+// where the arrays hold g_i itself.
+struct GPtrs {
+  void *p[9];
+  float *B;
+  int storage;   // lbtp_storage of the arrays
+};
 
 // Lattice kind passed to the launchers: 2 = D2Q5, 3 = D3Q7 (the spatial
 // dimension of those), kD2Q9 = D2Q9.
@@ -114,7 +124,7 @@ hipError_t launch_finish_sum(const double *partials, int nblk, double *dst, int 
                              double *copy_to, hipStream_t s);
 hipError_t launch_g_sweep(int dim, int storage, const KC &kc, GPtrs gin, GPtrs gout, FPtrs f, int f_local,
                           const float *Pb, const float *itau, const float *K, const float *phi,
-                          const float *Fs, double *partials, hipStream_t s);
+                          const float *Fs, const float *Sn, double *partials, hipStream_t s);
 hipError_t launch_init(int dim, int storage, const KC &kc, const float *P0, const float *S0, const float *dP0,
                        const float *dS0, const float *K, const float *phi, const float *Fs, int neq, FPtrs f,
                        float *Pb, GPtrs g, hipStream_t s);
@@ -125,6 +135,9 @@ hipError_t launch_grad(int dim, int storage, const KC &kc, FPtrs f, int f_local,
                        hipStream_t s);
 hipError_t launch_saturation(int dim, const KC &kc, GPtrs g, const float *phi, const float *Fs,
                              float *S, hipStream_t s);
+// The saturation populations as float32 (Q x ncell, component-major).
+hipError_t launch_g_populations(int dim, const KC &kc, GPtrs g, const float *phi, float *out, hipStream_t s);
+hipError_t launch_g_populations_q9(const KC &kc, GPtrs g, const float *phi, float *out, hipStream_t s);
 hipError_t launch_populations(int dim, int storage, const KC &kc, FPtrs f, int f_local, const float *Pb,
                               float *out, hipStream_t s);
 
@@ -141,7 +154,7 @@ hipError_t launch_moments_q9(const KC &kc, GPtrs g, const float *K, const float 
                              float *itau, double *partials, int write_coef, hipStream_t s);
 hipError_t launch_g_sweep_q9(int storage, const KC &kc, GPtrs gin, GPtrs gout, FPtrs f, int f_local,
                              const float *Pb, const float *itau, const float *K, const float *phi, const float *Fs,
-                             double *partials, hipStream_t s);
+                             const float *Sn, double *partials, hipStream_t s);
 hipError_t launch_init_q9(int storage, const KC &kc, const float *P0, const float *S0, const float *dP0,
                           const float *dS0, const float *K, const float *phi, const float *Fs, int neq, FPtrs f,
                           float *Pb, GPtrs g, hipStream_t s);
@@ -191,7 +204,7 @@ hipError_t batch_launch_block(int storage, bool has_fp, int nblk, const Member *
                               const int *ti, int j, int H, hipStream_t s);
 hipError_t batch_launch_sweep(int nt, int dim, int storage, int mode, int local, int nblk, const Member *mem,
                               const BCtl *ctl, const int *tm, const int *ti, double *part, int j, hipStream_t s);
-hipError_t batch_launch_moments(int dim, int nblk, const Member *mem, const int *tm, const int *ti, double *part,
+hipError_t batch_launch_moments(int dim, int storage, int nblk, const Member *mem, const int *tm, const int *ti, double *part,
                                 int gs, int write_coef, hipStream_t s);
 hipError_t batch_launch_gsweep(int dim, int storage, int local, int nblk, const Member *mem, const BCtl *ctl,
                                const int *tm, const int *ti, double *part, int gs, hipStream_t s);

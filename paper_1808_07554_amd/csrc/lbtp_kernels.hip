@@ -150,7 +150,7 @@ __global__ __launch_bounds__(1024) void finish_sum_kernel(const double *__restri
 // ------------------------------------------------------------------ moments
 // S^n (eq. 3-9b) and 1/tau_f (eq. 3-11a, 2-9, 2-16) of the coupled step, and
 // the block partials of the mass sum_x (sum_i g_i + dt F_s / 2) = sum phi S.
-template <int DIM, bool HAS_FS>
+template <int DIM, bool HAS_FS, typename TG>
 __global__ __launch_bounds__(kThreads) void moments_kernel(KC kc, GPtrs g, const float *__restrict__ K,
                                                            const float *__restrict__ phi,
                                                            const float *__restrict__ Fs, float *__restrict__ S,
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(kThreads) void moments_kernel(KC kc, GPtrs g, const
                                                            double *__restrict__ partials, int write_coef) {
   const int c = blockIdx.x * kThreads + threadIdx.x;
   double acc[1] = {0.0};
-  if (c < kc.ncell) acc[0] = moments_cell<DIM, HAS_FS>(kc, g, K, phi, Fs, S, itau, c, write_coef);
+  if (c < kc.ncell) acc[0] = moments_cell<DIM, HAS_FS, TG>(kc, g, K, phi, Fs, S, itau, c, write_coef);
   block_sum<1>(acc, partials);
 }
 
@@ -175,11 +175,12 @@ __global__ __launch_bounds__(kThreads) void g_sweep_kernel(KC kc, GPtrs gin, GPt
                                                            const float *__restrict__ K,
                                                            const float *__restrict__ phi,
                                                            const float *__restrict__ Fs,
+                                                           const float *__restrict__ Sn,
                                                            double *__restrict__ partials) {
   const int c = blockIdx.x * kThreads + threadIdx.x;
   double acc[1] = {0.0};
   if (c < kc.ncell)
-    acc[0] = g_sweep_cell<DIM, T, FLOCAL, HAS_FS>(kc, gin, gout, typed<T>(f_), Pb, itau, K, phi, Fs, c);
+    acc[0] = g_sweep_cell<DIM, T, FLOCAL, HAS_FS>(kc, gin, gout, typed<T>(f_), Pb, itau, K, phi, Fs, Sn, c);
   block_sum<1>(acc, partials);
 }
 
@@ -229,16 +230,32 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(KC kc, FPtrs f_, const f
   for (int a = 0; a < DIM; ++a) out[a * kc.ncell + c] = scale * m1[a];
 }
 
-template <int DIM, bool HAS_FS>
-__global__ __launch_bounds__(kThreads) void saturation_kernel(KC kc, GPtrs g, const float *__restrict__ phi,
+template <int DIM, bool HAS_FS, typename TG>
+__global__ __launch_bounds__(kThreads) void saturation_kernel(KC kc, GPtrs g_, const float *__restrict__ phi,
                                                               const float *__restrict__ Fs,
                                                               float *__restrict__ S) {
   const int c = blockIdx.x * kThreads + threadIdx.x;
   if (c >= kc.ncell) return;
+  const GP<TG> g = gtyped<TG>(g_);
+  const float ph = phi[c], B = gdev<TG>() ? g.B[c] : 0.0f;
   float gv[2 * DIM + 1];
 #pragma unroll
-  for (int i = 0; i <= 2 * DIM; ++i) gv[i] = g.p[i][c];
-  S[c] = saturation_of(sum_g<DIM>(gv), HAS_FS ? Fs[c] : 0.0f, phi[c], kc);
+  for (int i = 0; i <= 2 * DIM; ++i) gv[i] = gload(g.p[i], c, gdev<TG>() ? geq_odd(kc, i, B, ph) : 0.0f, kc);
+  S[c] = saturation_of(sum_g<DIM>(gv), HAS_FS ? Fs[c] : 0.0f, ph, kc);
+}
+
+// The saturation populations as float32 (component-major), reconstructed
+// from 16-bit deviations where they are stored so.
+template <int DIM, typename TG>
+__global__ __launch_bounds__(kThreads) void gpop_kernel(KC kc, GPtrs g_, const float *__restrict__ phi,
+                                                        float *__restrict__ out) {
+  const int c = blockIdx.x * kThreads + threadIdx.x;
+  if (c >= kc.ncell) return;
+  const GP<TG> g = gtyped<TG>(g_);
+  const float ph = phi[c], B = gdev<TG>() ? g.B[c] : 0.0f;
+#pragma unroll
+  for (int i = 0; i <= 2 * DIM; ++i)
+    out[(size_t)i * kc.ncell + c] = gload(g.p[i], c, gdev<TG>() ? geq_odd(kc, i, B, ph) : 0.0f, kc);
 }
 
 // Phase velocities (eq. 2-12, 2-13) from the total velocity u (component-
@@ -367,38 +384,45 @@ hipError_t launch_finish_sum(const double *partials, int nblk, double *dst, int 
   return hipGetLastError();
 }
 
+template <int DIM, typename TG, bool LOCAL_UNUSED>
+struct MomentsLaunch {
+  static void run(const KC &kc, GPtrs g, const float *K, const float *phi, const float *Fs, float *S, float *itau,
+                  double *partials, int write_coef, hipStream_t s) {
+    if (Fs)
+      hipLaunchKernelGGL((moments_kernel<DIM, true, TG>), LBTP_GRID(kc), kc, g, K, phi, Fs, S, itau, partials,
+                         write_coef);
+    else
+      hipLaunchKernelGGL((moments_kernel<DIM, false, TG>), LBTP_GRID(kc), kc, g, K, phi, Fs, S, itau, partials,
+                         write_coef);
+  }
+};
+
 hipError_t launch_moments(int dim, const KC &kc, GPtrs g, const float *K, const float *phi, const float *Fs,
                           float *S, float *itau, double *partials, int write_coef, hipStream_t s) {
   if (dim == kD2Q9) return launch_moments_q9(kc, g, K, phi, Fs, S, itau, partials, write_coef, s);
-  if (dim == 2) {
-    if (Fs) hipLaunchKernelGGL((moments_kernel<2, true>), LBTP_GRID(kc), kc, g, K, phi, Fs, S, itau, partials, write_coef);
-    else hipLaunchKernelGGL((moments_kernel<2, false>), LBTP_GRID(kc), kc, g, K, phi, Fs, S, itau, partials, write_coef);
-  } else {
-    if (Fs) hipLaunchKernelGGL((moments_kernel<3, true>), LBTP_GRID(kc), kc, g, K, phi, Fs, S, itau, partials, write_coef);
-    else hipLaunchKernelGGL((moments_kernel<3, false>), LBTP_GRID(kc), kc, g, K, phi, Fs, S, itau, partials, write_coef);
-  }
+  dispatch<MomentsLaunch>(dim, g.storage, 0, kc, g, K, phi, Fs, S, itau, partials, write_coef, s);
   return hipGetLastError();
 }
 
 template <int DIM, typename T, bool LOCAL>
 struct GSweepLaunch {
   static void run(const KC &kc, GPtrs gin, GPtrs gout, FPtrs f, const float *Pb, const float *itau, const float *K,
-                  const float *phi, const float *Fs, double *partials, hipStream_t s) {
+                  const float *phi, const float *Fs, const float *Sn, double *partials, hipStream_t s) {
     if (Fs)
       hipLaunchKernelGGL((g_sweep_kernel<DIM, T, LOCAL, true>), LBTP_GRID(kc), kc, gin, gout, f, Pb, itau, K, phi,
-                         Fs, partials);
+                         Fs, Sn, partials);
     else
       hipLaunchKernelGGL((g_sweep_kernel<DIM, T, LOCAL, false>), LBTP_GRID(kc), kc, gin, gout, f, Pb, itau, K, phi,
-                         Fs, partials);
+                         Fs, Sn, partials);
   }
 };
 
 hipError_t launch_g_sweep(int dim, int storage, const KC &kc, GPtrs gin, GPtrs gout, FPtrs f, int f_local,
                           const float *Pb, const float *itau, const float *K, const float *phi, const float *Fs,
-                          double *partials, hipStream_t s) {
+                          const float *Sn, double *partials, hipStream_t s) {
   if (dim == kD2Q9)
-    return launch_g_sweep_q9(storage, kc, gin, gout, f, f_local, Pb, itau, K, phi, Fs, partials, s);
-  dispatch<GSweepLaunch>(dim, storage, f_local, kc, gin, gout, f, Pb, itau, K, phi, Fs, partials, s);
+    return launch_g_sweep_q9(storage, kc, gin, gout, f, f_local, Pb, itau, K, phi, Fs, Sn, partials, s);
+  dispatch<GSweepLaunch>(dim, storage, f_local, kc, gin, gout, f, Pb, itau, K, phi, Fs, Sn, partials, s);
   return hipGetLastError();
 }
 
@@ -448,16 +472,31 @@ hipError_t launch_grad(int dim, int storage, const KC &kc, FPtrs f, int f_local,
   return hipGetLastError();
 }
 
+template <int DIM, typename TG, bool LOCAL_UNUSED>
+struct SaturationLaunch {
+  static void run(const KC &kc, GPtrs g, const float *phi, const float *Fs, float *S, hipStream_t s) {
+    if (Fs) hipLaunchKernelGGL((saturation_kernel<DIM, true, TG>), LBTP_GRID(kc), kc, g, phi, Fs, S);
+    else hipLaunchKernelGGL((saturation_kernel<DIM, false, TG>), LBTP_GRID(kc), kc, g, phi, Fs, S);
+  }
+};
+
 hipError_t launch_saturation(int dim, const KC &kc, GPtrs g, const float *phi, const float *Fs, float *S,
                              hipStream_t s) {
   if (dim == kD2Q9) return launch_saturation_q9(kc, g, phi, Fs, S, s);
-  if (dim == 2) {
-    if (Fs) hipLaunchKernelGGL((saturation_kernel<2, true>), LBTP_GRID(kc), kc, g, phi, Fs, S);
-    else hipLaunchKernelGGL((saturation_kernel<2, false>), LBTP_GRID(kc), kc, g, phi, Fs, S);
-  } else {
-    if (Fs) hipLaunchKernelGGL((saturation_kernel<3, true>), LBTP_GRID(kc), kc, g, phi, Fs, S);
-    else hipLaunchKernelGGL((saturation_kernel<3, false>), LBTP_GRID(kc), kc, g, phi, Fs, S);
+  dispatch<SaturationLaunch>(dim, g.storage, 0, kc, g, phi, Fs, S, s);
+  return hipGetLastError();
+}
+
+template <int DIM, typename TG, bool LOCAL_UNUSED>
+struct GPopLaunch {
+  static void run(const KC &kc, GPtrs g, const float *phi, float *out, hipStream_t s) {
+    hipLaunchKernelGGL((gpop_kernel<DIM, TG>), LBTP_GRID(kc), kc, g, phi, out);
   }
+};
+
+hipError_t launch_g_populations(int dim, const KC &kc, GPtrs g, const float *phi, float *out, hipStream_t s) {
+  if (dim == kD2Q9) return launch_g_populations_q9(kc, g, phi, out, s);
+  dispatch<GPopLaunch>(dim, g.storage, 0, kc, g, phi, out, s);
   return hipGetLastError();
 }
 
