@@ -151,8 +151,14 @@ def ensemble_bench(a):
         dfields.append(d)
         b.set_fields(i, d["K"], d["phi"])
         b.set_state(i, d["P0"], d["S0"])
+    t_tune = time.perf_counter()
     nt = b.autotune(sweeps=5)
-    print(f"autotuned ensemble sweep: {nt} threads per block", file=sys.stderr, flush=True)
+    t_tune = time.perf_counter() - t_tune
+    tilings = {}
+    for i, (p, _) in enumerate(members):
+        tilings.setdefault(f"{p['shape'][0]}x{p['shape'][1]}", b.tiling(i))
+    print(f"autotuned ensemble sweep: {nt} threads per block; blocked tilings (waves, rows per wave, "
+          f"sweeps per launch) {tilings}, {t_tune:.1f} s", file=sys.stderr, flush=True)
     b.step(a.warmup, -1.0, it)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -187,7 +193,10 @@ def ensemble_bench(a):
         "data": "synthetic",
         "config": {"workload": f"ensemble of {len(members)} 2-D injection realisations, sides 128-1024, "
                                f"sigma_lnK in [0.5, 2], {it} pressure iterations per coupled step",
-                   "cells": cells, "storage": a.storage, "threads_per_block": nt},
+                   "cells": cells, "storage": a.storage, "threads_per_block": nt,
+                   "blocked_tilings": {k: {"waves": v[0], "rows_per_wave": v[1], "sweeps_per_launch": v[2]}
+                                       for k, v in tilings.items()},
+                   "autotune_s": round(t_tune, 2)},
         "sequential_mlups": round(mlups_seq, 1), "batched_over_sequential": round(t_seq / t_batch, 3),
     }
     print(json.dumps(out), flush=True)

@@ -310,9 +310,20 @@ LBTP_API int lbtp_batch_mass(lbtp_batch *b, int member, double *mass, double *le
 /* Block width of the ensemble pressure sweep: 64, 128, 256 (default) or 512
  * threads of four nodes each.  lbtp_batch_autotune times `sweeps` plain
  * sweeps of the whole ensemble for each width (leaving the state unchanged)
- * and keeps the fastest; *threads receives it. */
+ * and keeps the fastest; *threads receives it.  With blocked plain sweeps
+ * (D2Q5, sweep_block > 1) it then tunes, for each size class of members (one
+ * grid size), the region shape of the blocked kernel (8 x 8, 8 x 6, 16 x 4 or
+ * 4 x 8 wavefronts x rows) and the sweeps per launch (an odd divisor >= 3 of
+ * the m - 1 plain sweeps of a chunk), timing `sweeps` chunks' worth of
+ * blocked launches per candidate, and keeps the fastest per class; the
+ * choice is remembered for the process (by grid size, storage and m) and
+ * taken by later ensembles whose every size was tuned. */
 LBTP_API int lbtp_batch_set_threads(lbtp_batch *b, int threads);
 LBTP_API int lbtp_batch_autotune(lbtp_batch *b, int sweeps, int *threads);
+/* The blocked tiling a member's size class runs: regions of `waves`
+ * wavefronts x `rows_per_wave` rows (64 columns) and `sweeps_per_launch`
+ * plain sweeps per launch (1: one sweep per launch, waves = 0). */
+LBTP_API int lbtp_batch_tiling(lbtp_batch *b, int member, int *waves, int *rows_per_wave, int *sweeps_per_launch);
 
 /* Static description of a status code. */
 LBTP_API const char *lbtp_strerror(int status);

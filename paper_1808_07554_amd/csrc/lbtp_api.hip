@@ -10,6 +10,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "../../include/lbtp_probe.h"
@@ -1024,27 +1028,51 @@ struct lbtp_batch {
   int *d_tm_s = nullptr, *d_ti_s = nullptr;     // sweep tiling (4*nt nodes per tile)
   int *d_tm_c = nullptr, *d_ti_c = nullptr;     // cell tiling (kCellTile nodes per tile)
   int ntiles_s = 0, ntiles_c = 0, tiles_cap = 0;
-  int H = 1;                                    // plain sweeps per launch (blocked tiling if > 1)
-  int *d_tm_b = nullptr, *d_ti_b = nullptr;     // blocked tiling
-  int ntiles_b = 0, tiles_b_cap = 0;
+  int H = 1;                                    // plain sweeps per launch before tuning (blocked if > 1)
+  // members of one grid size share a class: its blocked tiling (region
+  // shape and block length, chosen by lbtp_batch_autotune) and tile tables
+  struct Class {
+    int nx = 0, ny = 0, nz = 0;
+    int shape = 0, H = 1;
+    int *d_tm = nullptr, *d_ti = nullptr;
+    int ntiles = 0, cap = 0;
+    bool any_fp = false, any_nofp = false;
+  };
+  std::vector<Class> cls;
+  std::vector<int> mclass;                      // class of each member
   bool any_fp = false, any_nofp = false;        // members with / without a pressure source
   double *partials = nullptr;
   int *d_active = nullptr, *h_active = nullptr;  // h_active: pinned, two slots
   hipEvent_t ev[2] = {nullptr, nullptr};
-  hipGraphExec_t chunk = nullptr;
+  // captured chunk sequences: graph k runs 2^k chunks back to back (members
+  // that stop return at once from the rest), so the host reads the active
+  // count once per 2^k chunks
+  static constexpr int kGraphs = 5;
+  hipGraphExec_t chunk[kGraphs] = {};
+  long long last_chunks = 1;                    // chunks the slowest member needed in the last step
   int gs = 0, f_local = 1;
   long long step = 0;
 };
 
 namespace {
 
+void batch_drop_graphs(lbtp_batch *b) {
+  for (auto &g : b->chunk) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+}
+
 void batch_free(lbtp_batch *b) {
   if (!b) return;
-  if (b->chunk) (void)hipGraphExecDestroy(b->chunk);
-  void *bufs[] = {b->d_mem, b->d_ctl, b->d_tm_s, b->d_ti_s, b->d_tm_c, b->d_ti_c, b->d_tm_b, b->d_ti_b, b->partials,
-                  b->d_active};
+  batch_drop_graphs(b);
+  void *bufs[] = {b->d_mem, b->d_ctl, b->d_tm_s, b->d_ti_s, b->d_tm_c, b->d_ti_c, b->partials, b->d_active};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
+  for (auto &k : b->cls) {
+    if (k.d_tm) (void)hipFree(k.d_tm);
+    if (k.d_ti) (void)hipFree(k.d_ti);
+  }
   if (b->h_ctl) (void)hipHostFree(b->h_ctl);
   if (b->h_active) (void)hipHostFree(b->h_active);
   for (int i = 0; i < 2; ++i)
@@ -1057,9 +1085,11 @@ void batch_free(lbtp_batch *b) {
 // (Re)build the member table and both tile tables for sweep width nt.
 int batch_tables(lbtp_batch *b, int nt) {
   std::vector<Member> mem(b->n);
-  std::vector<int> tm_s, ti_s, tm_c, ti_c, tm_b, ti_b;
+  std::vector<int> tm_s, ti_s, tm_c, ti_c;
+  std::vector<std::vector<int>> tm_b(b->cls.size()), ti_b(b->cls.size());
   const int tile_s = 4 * nt;
   b->any_fp = b->any_nofp = false;
+  for (auto &k : b->cls) k.any_fp = k.any_nofp = false;
   for (int i = 0; i < b->n; ++i) {
     lbtp_ctx *c = b->ctx[i];
     Member &M = mem[i];
@@ -1091,28 +1121,33 @@ int batch_tables(lbtp_batch *b, int nt) {
       tm_c.push_back(i);
       ti_c.push_back(t);
     }
-    if (b->H > 1) {
+    lbtp_batch::Class &k = b->cls[b->mclass[i]];
+    if (k.H > 1) {
       int tx, ty;
-      block_tile_counts(c->kc, b->H, &tx, &ty);
+      block_tile_counts_rows(c->kc, k.H, batch_shape_rows(k.shape), &tx, &ty);
       for (int t = 0; t < tx * ty; ++t) {
-        tm_b.push_back(i);
-        ti_b.push_back(t);
+        tm_b[b->mclass[i]].push_back(i);
+        ti_b[b->mclass[i]].push_back(t);
       }
     }
     (M.Fp ? b->any_fp : b->any_nofp) = true;
+    (M.Fp ? k.any_fp : k.any_nofp) = true;
   }
-  if ((int)tm_b.size() > b->tiles_b_cap) {
-    for (int **p : {&b->d_tm_b, &b->d_ti_b}) {
-      if (*p) (void)hipFree(*p);
-      *p = nullptr;
-      if (hipMalloc((void **)p, tm_b.size() * sizeof(int)) != hipSuccess) return LBTP_ENOMEM;
+  for (size_t ci = 0; ci < b->cls.size(); ++ci) {
+    lbtp_batch::Class &k = b->cls[ci];
+    if ((int)tm_b[ci].size() > k.cap) {
+      for (int **p : {&k.d_tm, &k.d_ti}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+        if (hipMalloc((void **)p, tm_b[ci].size() * sizeof(int)) != hipSuccess) return LBTP_ENOMEM;
+      }
+      k.cap = (int)tm_b[ci].size();
     }
-    b->tiles_b_cap = (int)tm_b.size();
-  }
-  b->ntiles_b = (int)tm_b.size();
-  if (!tm_b.empty()) {
-    HIP_TRY(hipMemcpyAsync(b->d_tm_b, tm_b.data(), tm_b.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
-    HIP_TRY(hipMemcpyAsync(b->d_ti_b, ti_b.data(), ti_b.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    k.ntiles = (int)tm_b[ci].size();
+    if (k.ntiles) {
+      HIP_TRY(hipMemcpyAsync(k.d_tm, tm_b[ci].data(), k.ntiles * sizeof(int), hipMemcpyHostToDevice, b->stream));
+      HIP_TRY(hipMemcpyAsync(k.d_ti, ti_b[ci].data(), k.ntiles * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    }
   }
   const int need = (int)(tm_s.size() > tm_c.size() ? tm_s.size() : tm_c.size());
   if (need > b->tiles_cap) {
@@ -1135,26 +1170,29 @@ int batch_tables(lbtp_batch *b, int nt) {
   HIP_TRY(hipMemcpyAsync(b->d_tm_c, tm_c.data(), tm_c.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
   HIP_TRY(hipMemcpyAsync(b->d_ti_c, ti_c.data(), ti_c.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
-  if (b->chunk) {
-    (void)hipGraphExecDestroy(b->chunk);
-    b->chunk = nullptr;
-  }
+  batch_drop_graphs(b);
   return LBTP_OK;
 }
 
 // Enqueue one chunk: sweeps j = 1 .. m (the last one evaluates the stopping
 // rule and re-bases), then the per-member finish.
 int batch_enqueue_chunk(lbtp_batch *b) {
-  int j = 1;
-  // plain sweeps in blocks of H (H odd: a block ends in the buffer where H
-  // single sweeps would), the rest one by one
-  for (; b->H > 1 && j + b->H - 1 <= b->m - 1; j += b->H) {
-    for (int fp = 0; fp < 2; ++fp)
-      if (fp ? b->any_fp : b->any_nofp)
-        HIP_TRY(batch_launch_block(b->storage, fp != 0, b->ntiles_b, b->d_mem, b->d_ctl, b->d_tm_b, b->d_ti_b, j, b->H,
-                                   b->stream));
+  // plain sweeps of each size class in blocks of its H (H odd: a block ends
+  // in the buffer where H single sweeps would); every class ends its blocks
+  // at the same sweep (one shared H, or tuned H that divide m - 1), and the
+  // rest run one by one over all members
+  int jend = -1;
+  for (const auto &k : b->cls) {
+    int j = 1;
+    for (; k.H > 1 && j + k.H - 1 <= b->m - 1; j += k.H)
+      for (int fp = 0; fp < 2; ++fp)
+        if (fp ? k.any_fp : k.any_nofp)
+          HIP_TRY(batch_launch_block(b->storage, k.shape, fp != 0, k.ntiles, b->d_mem, b->d_ctl, k.d_tm, k.d_ti, j,
+                                     k.H, b->stream));
+    if (jend >= 0 && j != jend) return LBTP_EINVAL;
+    jend = j;
   }
-  for (; j <= b->m; ++j) {
+  for (int j = jend < 1 ? 1 : jend; j <= b->m; ++j) {
     const int mode = (j == b->m) ? 2 : 0;
     HIP_TRY(batch_launch_sweep(b->nt, b->dim, b->storage, mode, 0, b->ntiles_s, b->d_mem, b->d_ctl, b->d_tm_s,
                                b->d_ti_s, b->partials, j, b->stream));
@@ -1163,10 +1201,12 @@ int batch_enqueue_chunk(lbtp_batch *b) {
   return LBTP_OK;
 }
 
-int batch_capture(lbtp_batch *b) {
-  if (b->chunk) return LBTP_OK;
+// Graph k: 2^k chunks.
+int batch_capture(lbtp_batch *b, int k) {
+  if (b->chunk[k]) return LBTP_OK;
   HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-  int rc = batch_enqueue_chunk(b);
+  int rc = LBTP_OK;
+  for (int i = 0; i < (1 << k) && !rc; ++i) rc = batch_enqueue_chunk(b);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(b->stream, &g);
   if (rc) {
@@ -1174,14 +1214,19 @@ int batch_capture(lbtp_batch *b) {
     return rc;
   }
   if (e != hipSuccess) return LBTP_EHIP;
-  e = hipGraphInstantiate(&b->chunk, g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(&b->chunk[k], g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
-    b->chunk = nullptr;
+    b->chunk[k] = nullptr;
     return LBTP_EHIP;
   }
   return LBTP_OK;
 }
+
+// Tuned blocked tilings, kept for the life of the process: (nx, ny,
+// storage, m) -> (region shape, block length).
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tuned;
 
 bool batch_ready(const lbtp_batch *b) {
   for (lbtp_ctx *c : b->ctx)
@@ -1256,6 +1301,35 @@ int lbtp_batch_init(const lbtp_params *members, int n, lbtp_batch **out) {
     return LBTP_EHIP;
   }
   b->H = b->ctx[0]->sweep_block > 1 ? b->ctx[0]->sweep_block : 1;
+  // size classes; a blocked tiling tuned earlier in the process for a
+  // class's size, storage and m is taken over
+  for (int i = 0; i < n; ++i) {
+    const lbtp_params &p = members[i];
+    int ci = 0;
+    while (ci < (int)b->cls.size() &&
+           !(b->cls[ci].nx == p.nx && b->cls[ci].ny == p.ny && b->cls[ci].nz == p.nz))
+      ++ci;
+    if (ci == (int)b->cls.size()) {
+      lbtp_batch::Class k;
+      k.nx = p.nx;
+      k.ny = p.ny;
+      k.nz = p.nz;
+      k.H = b->H;
+      b->cls.push_back(k);
+    }
+    b->mclass.push_back(ci);
+  }
+  if (b->H > 1) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    bool all = true;
+    for (const auto &k : b->cls) all = all && g_tuned.count(std::make_tuple(k.nx, k.ny, b->storage, b->m)) > 0;
+    if (all)
+      for (auto &k : b->cls) {
+        const auto v = g_tuned[std::make_tuple(k.nx, k.ny, b->storage, b->m)];
+        k.shape = v.first;
+        k.H = v.second;
+      }
+  }
   int rc = batch_tables(b, 256);
   if (rc) {
     batch_free(b);
@@ -1302,8 +1376,6 @@ int lbtp_batch_set_threads(lbtp_batch *b, int nt) {
 int lbtp_batch_step(lbtp_batch *b, long long nsteps, double tol, long long max_iters, long long *iters) {
   if (!b || nsteps < 0 || max_iters < b->m || max_iters % b->m) return LBTP_EINVAL;
   if (!batch_ready(b)) return LBTP_ESTATE;
-  int rc = batch_capture(b);
-  if (rc) return rc;
   int worst = LBTP_OK;
   for (long long s = 0; s < nsteps; ++s) {
     // coefficients of every member
@@ -1315,16 +1387,27 @@ int lbtp_batch_step(lbtp_batch *b, long long nsteps, double tol, long long max_i
     HIP_TRY(batch_launch_sweep(b->nt, b->dim, b->storage, 1, b->f_local, b->ntiles_s, b->d_mem, b->d_ctl, b->d_tm_s,
                                b->d_ti_s, b->partials, 0, b->stream));
     HIP_TRY(batch_launch_flip(b->n, b->d_ctl, b->stream));
+    // chunks in graphs of 2^k: as many as the slowest member needed in the
+    // last step at first (one in the first step), then doubling; the host
+    // reads the active count after each graph, one graph behind
     int slot = 0;
     bool pending[2] = {false, false};
-    for (long long chunk = 1;; ++chunk) {
-      HIP_TRY(hipGraphLaunch(b->chunk, b->stream));
+    const long long max_chunks = max_iters / b->m;
+    long long done = 0, want = b->last_chunks;
+    for (int launch = 0;; ++launch) {
+      int k = 0;
+      while (k + 1 < lbtp_batch::kGraphs && (2LL << k) <= want && done + (2LL << k) <= max_chunks) ++k;
+      int rc = batch_capture(b, k);
+      if (rc) return rc;
+      HIP_TRY(hipGraphLaunch(b->chunk[k], b->stream));
+      done += 1LL << k;
+      want = want > (1LL << k) ? want - (1LL << k) : 2 * (1LL << k);
       HIP_TRY(hipMemcpyAsync(&b->h_active[slot], b->d_active, sizeof(int), hipMemcpyDeviceToHost, b->stream));
       HIP_TRY(hipEventRecord(b->ev[slot], b->stream));
       pending[slot] = true;
       const int prev = slot ^ 1;
-      int wait = chunk == 1 ? slot : (pending[prev] ? prev : -1);
-      bool stop = chunk * b->m >= max_iters;
+      int wait = launch == 0 ? slot : (pending[prev] ? prev : -1);
+      bool stop = done >= max_chunks;
       if (wait >= 0) {
         HIP_TRY(hipEventSynchronize(b->ev[wait]));
         pending[wait] = false;
@@ -1342,6 +1425,9 @@ int lbtp_batch_step(lbtp_batch *b, long long nsteps, double tol, long long max_i
     b->gs ^= 1;
     b->f_local = 0;
     b->step += 1;
+    long long slowest = 1;
+    for (int i = 0; i < b->n; ++i) slowest = std::max(slowest, (b->h_ctl[i].K + b->m - 1) / b->m);
+    b->last_chunks = slowest;
     for (int i = 0; i < b->n; ++i) {
       const BCtl &h = b->h_ctl[i];
       if (iters) iters[s * b->n + i] = h.K;
@@ -1421,12 +1507,72 @@ int lbtp_batch_autotune(lbtp_batch *b, int sweeps, int *threads) {
       best = cand[ci];
     }
   }
+  if (rc) {
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    return rc;
+  }
+  rc = batch_tables(b, best);
+  // the blocked plain sweeps, class by class: every region shape and every
+  // odd block length H >= 3 that divides the m - 1 plain sweeps of a chunk
+  // and leaves tiles of at least 16 x 16 nodes; timed over the launches of
+  // one chunk (reading buffer 0, writing buffer 1: the state is untouched)
+  if (!rc && b->H > 1) {
+    std::vector<std::pair<int, int>> cands;
+    for (int sh = 0; sh < kBatchShapes; ++sh)
+      for (int H = 3; H <= b->m - 1; H += 2)
+        if ((b->m - 1) % H == 0 && kBX - 2 * H >= 16 && batch_shape_rows(sh) - 2 * H >= 16) cands.push_back({sh, H});
+    for (size_t ci = 0; ci < b->cls.size() && !rc && !cands.empty(); ++ci) {
+      lbtp_batch::Class &k = b->cls[ci];
+      float kbest_ms = 1e30f;
+      std::pair<int, int> kbest = cands[0];
+      for (const auto &cd : cands) {
+        k.shape = cd.first;
+        k.H = cd.second;
+        if ((rc = batch_tables(b, b->nt))) break;
+        const int nl = (b->m - 1) / k.H;
+        auto run = [&]() {
+          for (int l = 0; l < nl && !rc; ++l)
+            for (int fp = 0; fp < 2 && !rc; ++fp)
+              if ((fp ? k.any_fp : k.any_nofp) &&
+                  batch_launch_block(b->storage, k.shape, fp != 0, k.ntiles, b->d_mem, b->d_ctl, k.d_tm, k.d_ti, 0,
+                                     k.H, b->stream) != hipSuccess)
+                rc = LBTP_EHIP;
+        };
+        run();   // warm-up
+        if (!rc && hipEventRecord(t0, b->stream) != hipSuccess) rc = LBTP_EHIP;
+        for (int r = 0; r < sweeps && !rc; ++r) run();
+        if (!rc && (hipEventRecord(t1, b->stream) != hipSuccess || hipEventSynchronize(t1) != hipSuccess))
+          rc = LBTP_EHIP;
+        float ms = 0.f;
+        if (!rc && hipEventElapsedTime(&ms, t0, t1) != hipSuccess) rc = LBTP_EHIP;
+        if (!rc && ms < kbest_ms) {
+          kbest_ms = ms;
+          kbest = cd;
+        }
+      }
+      k.shape = kbest.first;
+      k.H = kbest.second;
+    }
+    if (!rc) {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      for (const auto &k : b->cls) g_tuned[std::make_tuple(k.nx, k.ny, b->storage, b->m)] = {k.shape, k.H};
+    }
+    if (!rc) rc = batch_tables(b, b->nt);
+  }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   if (rc) return rc;
-  rc = batch_tables(b, best);
-  if (rc) return rc;
   if (threads) *threads = best;
+  return LBTP_OK;
+}
+
+int lbtp_batch_tiling(lbtp_batch *b, int member, int *waves, int *rows_per_wave, int *sweeps_per_launch) {
+  if (!b || member < 0 || member >= b->n) return LBTP_EINVAL;
+  const lbtp_batch::Class &k = b->cls[b->mclass[member]];
+  if (waves) *waves = k.H > 1 ? batch_shape_w(k.shape) : 0;
+  if (rows_per_wave) *rows_per_wave = k.H > 1 ? batch_shape_rw(k.shape) : 0;
+  if (sweeps_per_launch) *sweeps_per_launch = k.H;
   return LBTP_OK;
 }
 

@@ -72,15 +72,16 @@ __global__ __launch_bounds__(NT) void batch_sweep_kernel(const Member *__restric
   if (MODE == 2) block_sum<2, NT>(acc, partials);
 }
 
-// Plain sweeps j .. j + H - 1 of every member, blocked (block_region of
-// lbtp_block.h, D2Q5): one workgroup per (member, tile) of the blocked
-// tiling.  Members with a pressure source run in the HAS_FP launch, the others
-// in the plain one.
-template <typename T, bool HAS_FP>
-__global__ __launch_bounds__(kBX * kUseW) void batch_block_kernel(const Member *__restrict__ mem,
-                                                                  const BCtl *__restrict__ ctl,
-                                                                  const int *__restrict__ tmember,
-                                                                  const int *__restrict__ tindex, int j, int H) {
+// Plain sweeps j .. j + H - 1 of the members of one size class, blocked
+// (block_region of lbtp_block.h, D2Q5, regions of W wavefronts x RW rows):
+// one workgroup per (member, tile) of the class's blocked tiling.  Members
+// with a pressure source run in the HAS_FP launch, the others in the plain
+// one.
+template <typename T, bool HAS_FP, int W, int RW>
+__global__ __launch_bounds__(kBX * W) void batch_block_kernel(const Member *__restrict__ mem,
+                                                              const BCtl *__restrict__ ctl,
+                                                              const int *__restrict__ tmember,
+                                                              const int *__restrict__ tindex, int j, int H) {
   const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
   const int m = tmember[b], t = tindex[b];
   const BCtl &bc = ctl[m];
@@ -91,19 +92,32 @@ __global__ __launch_bounds__(kBX * kUseW) void batch_block_kernel(const Member *
   // registers instead of from memory inside the sweep loop
   const KC kc = M.kc;
   int tx, ty;
-  block_tile_counts(kc, H, &tx, &ty);
+  block_tile_counts_rows(kc, H, W * RW, &tx, &ty);
   const int in = j & 1;
-  block_region<T, HAS_FP, kUseW, kUseRW>(kc, typed<T>(M.f[in]), typed<T>(M.f[in ^ 1]), M.Pb[bc.pb], M.itau, M.Fp, H,
-                                         t % tx, t / tx);
+  block_region<T, HAS_FP, W, RW>(kc, typed<T>(M.f[in]), typed<T>(M.f[in ^ 1]), M.Pb[bc.pb], M.itau, M.Fp, H,
+                                 t % tx, t / tx);
+}
+
+template <typename T, int W, int RW>
+void batch_block_launch_shape(bool has_fp, int nblk, const Member *mem, const BCtl *ctl, const int *tm,
+                              const int *ti, int j, int H, hipStream_t s) {
+  if (has_fp)
+    hipLaunchKernelGGL((batch_block_kernel<T, true, W, RW>), dim3(nblk), dim3(kBX * W), 0, s, mem, ctl, tm, ti, j, H);
+  else
+    hipLaunchKernelGGL((batch_block_kernel<T, false, W, RW>), dim3(nblk), dim3(kBX * W), 0, s, mem, ctl, tm, ti, j,
+                       H);
 }
 
 template <typename T>
-void batch_block_launch(bool has_fp, int nblk, const Member *mem, const BCtl *ctl, const int *tm, const int *ti, int j,
-                        int H, hipStream_t s) {
-  if (has_fp)
-    hipLaunchKernelGGL((batch_block_kernel<T, true>), dim3(nblk), dim3(kBX * kUseW), 0, s, mem, ctl, tm, ti, j, H);
-  else
-    hipLaunchKernelGGL((batch_block_kernel<T, false>), dim3(nblk), dim3(kBX * kUseW), 0, s, mem, ctl, tm, ti, j, H);
+void batch_block_launch(int shape, bool has_fp, int nblk, const Member *mem, const BCtl *ctl, const int *tm,
+                        const int *ti, int j, int H, hipStream_t s) {
+  static_assert(batch_shape_rows(0) == kUseW * kUseRW, "shape 0 is the single-context launch shape");
+  switch (shape) {
+    case 1: batch_block_launch_shape<T, batch_shape_w(1), batch_shape_rw(1)>(has_fp, nblk, mem, ctl, tm, ti, j, H, s); break;
+    case 2: batch_block_launch_shape<T, batch_shape_w(2), batch_shape_rw(2)>(has_fp, nblk, mem, ctl, tm, ti, j, H, s); break;
+    case 3: batch_block_launch_shape<T, batch_shape_w(3), batch_shape_rw(3)>(has_fp, nblk, mem, ctl, tm, ti, j, H, s); break;
+    default: batch_block_launch_shape<T, batch_shape_w(0), batch_shape_rw(0)>(has_fp, nblk, mem, ctl, tm, ti, j, H, s); break;
+  }
 }
 
 // Stopping rule of every member (one block each) after the check sweep j = m of
@@ -305,12 +319,12 @@ static void moments_by_storage(int storage, int nblk, const Member *mem, const i
   else moments_launch<DIM, 256, float>(nblk, mem, tm, ti, part, gs, write_coef, s);
 }
 
-hipError_t batch_launch_block(int storage, bool has_fp, int nblk, const Member *mem, const BCtl *ctl, const int *tm,
-                              const int *ti, int j, int H, hipStream_t s) {
+hipError_t batch_launch_block(int storage, int shape, bool has_fp, int nblk, const Member *mem, const BCtl *ctl,
+                              const int *tm, const int *ti, int j, int H, hipStream_t s) {
   switch (storage) {
-    case LBTP_FP16_DEV: batch_block_launch<_Float16>(has_fp, nblk, mem, ctl, tm, ti, j, H, s); break;
-    case LBTP_BF16_DEV: batch_block_launch<bf16_t>(has_fp, nblk, mem, ctl, tm, ti, j, H, s); break;
-    default: batch_block_launch<float>(has_fp, nblk, mem, ctl, tm, ti, j, H, s); break;
+    case LBTP_FP16_DEV: batch_block_launch<_Float16>(shape, has_fp, nblk, mem, ctl, tm, ti, j, H, s); break;
+    case LBTP_BF16_DEV: batch_block_launch<bf16_t>(shape, has_fp, nblk, mem, ctl, tm, ti, j, H, s); break;
+    default: batch_block_launch<float>(shape, has_fp, nblk, mem, ctl, tm, ti, j, H, s); break;
   }
   return hipGetLastError();
 }

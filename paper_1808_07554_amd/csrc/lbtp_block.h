@@ -190,12 +190,26 @@ __device__ inline void block_region(const KC &kc, const FP<T> &fin, const FP<T> 
   }
 }
 
-// Tiles of a context per axis for block length H.
-__host__ __device__ inline void block_tile_counts(const KC &kc, int H, int *tx, int *ty) {
-  const int tcols = kBX - 2 * H, trows = kUseW * kUseRW - 2 * H;
+// Tiles of a context per axis for block length H and regions of `rows` rows.
+__host__ __device__ inline void block_tile_counts_rows(const KC &kc, int H, int rows, int *tx, int *ty) {
+  const int tcols = kBX - 2 * H, trows = rows - 2 * H;
   *tx = (kc.nx + tcols - 1) / tcols;
   *ty = (kc.ny + trows - 1) / trows;
 }
+
+// The same for the launch shape of single contexts.
+__host__ __device__ inline void block_tile_counts(const KC &kc, int H, int *tx, int *ty) {
+  block_tile_counts_rows(kc, H, kUseW * kUseRW, tx, ty);
+}
+
+// Region shapes the ensemble autotuner chooses from: W wavefronts of RW rows.
+// Every one keeps the region in registers; they differ in region height
+// (the halo share and the ragged last tile of a small member) and in the
+// number of workgroups a compute unit holds.
+constexpr int kBatchShapes = 4;
+__host__ __device__ constexpr int batch_shape_w(int s) { return s == 0 ? 8 : s == 1 ? 8 : s == 2 ? 16 : 4; }
+__host__ __device__ constexpr int batch_shape_rw(int s) { return s == 0 ? 8 : s == 1 ? 6 : s == 2 ? 4 : 8; }
+__host__ __device__ constexpr int batch_shape_rows(int s) { return batch_shape_w(s) * batch_shape_rw(s); }
 
 }  // namespace lbtp
 

@@ -200,8 +200,8 @@ constexpr int kCellTile = 1024;   // nodes per tile of the ensemble cell kernels
 
 // Plain sweeps j .. j + H - 1 of every member through the blocked tiling
 // (tables tm / ti of (member, tile)), members with a pressure source or without.
-hipError_t batch_launch_block(int storage, bool has_fp, int nblk, const Member *mem, const BCtl *ctl, const int *tm,
-                              const int *ti, int j, int H, hipStream_t s);
+hipError_t batch_launch_block(int storage, int shape, bool has_fp, int nblk, const Member *mem, const BCtl *ctl,
+                              const int *tm, const int *ti, int j, int H, hipStream_t s);
 hipError_t batch_launch_sweep(int nt, int dim, int storage, int mode, int local, int nblk, const Member *mem,
                               const BCtl *ctl, const int *tm, const int *ti, double *part, int j, hipStream_t s);
 hipError_t batch_launch_moments(int dim, int storage, int nblk, const Member *mem, const int *tm, const int *ti, double *part,

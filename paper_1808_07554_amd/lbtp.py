@@ -95,6 +95,8 @@ EXPORTS = {
                                        ctypes.POINTER(ctypes.c_double)]),
     "lbtp_batch_set_threads": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "lbtp_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "lbtp_batch_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "lbtp_nn_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_void_p,
                                       ctypes.POINTER(ctypes.c_void_p)]),
     "lbtp_nn_destroy": (None, [ctypes.c_void_p]),
@@ -341,6 +343,13 @@ class Batch:
         t = ctypes.c_int()
         _check(self._lib.lbtp_batch_autotune(self._h, int(sweeps), ctypes.byref(t)), "lbtp_batch_autotune")
         return t.value
+
+    def tiling(self, i):
+        """(waves, rows per wave, sweeps per launch) of member i's blocked tiling."""
+        w, r, h = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(self._lib.lbtp_batch_tiling(self._h, int(i), ctypes.byref(w), ctypes.byref(r), ctypes.byref(h)),
+               "lbtp_batch_tiling")
+        return w.value, r.value, h.value
 
 
 def _ptr(t):

@@ -130,3 +130,40 @@ def test_batch_rejects_bad_arguments():
     b.set_state(0, ms[0][1]["P0"], ms[0][1]["S0"])
     with pytest.raises(lbtp.LbtpError):          # max_iters not a multiple of m
         b.step(1, -1.0, 20)
+
+
+def test_autotuned_tilings_per_size_class_keep_single_run_results():
+    """m = 64 and members of three sizes: the autotuner picks, per size class,
+    a region shape and an odd block length dividing the 63 plain sweeps of a
+    chunk; every member still equals its single-context run bit for bit
+    (float32 blocked sweeps equal single sweeps for any shape and block
+    length), through solves to a tolerance that take many chunks (the
+    ensemble runs them in graphs of several chunks)."""
+    from paper_1808_07554_amd import lbtp
+    shapes = [(128, 128), (256, 96), (64, 64), (128, 128)]
+    ms = _members(shapes, seed0=130)
+    b = lbtp.Batch([p for p, _ in ms], m=64)
+    singles = []
+    for i, (p, fl) in enumerate(ms):
+        b.set_fields(i, fl["K"], fl["phi"])
+        b.set_state(i, fl["P0"], fl["S0"])
+        s = gpu_solver(p, m=64)
+        s.set_fields(fl["K"], fl["phi"])
+        s.set_state(fl["P0"], fl["S0"])
+        singles.append(s)
+    b.autotune(sweeps=2)
+    shapes_ok = {(8, 8), (8, 6), (16, 4), (4, 8)}
+    tilings = [b.tiling(i) for i in range(len(ms))]
+    print("tuned tilings (waves, rows per wave, sweeps per launch):", tilings)
+    for (w, r, h) in tilings:
+        assert (w, r) in shapes_ok and h >= 3 and h % 2 == 1 and 63 % h == 0
+        assert w * r - 2 * h >= 16 and 64 - 2 * h >= 16
+    assert tilings[0] == tilings[3]              # one class per size
+    its_b, _ = b.step(3, 1e-7, 64 * 400)
+    assert its_b[0].max() > 4 * 64               # the first solve took several chunks
+    for i, s in enumerate(singles):
+        its_s, _ = s.step(3, 1e-7, 64 * 400)
+        assert list(its_b[:, i]) == its_s, (i, its_b[:, i], its_s)
+        assert bool((b.pressure(i) == s.pressure()).all()), i
+        assert bool((b.saturation(i) == s.saturation()).all()), i
+        assert bool((b.velocity(i) == s.velocity()).all()), i
