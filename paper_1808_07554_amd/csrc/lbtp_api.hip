@@ -1243,9 +1243,6 @@ int lbtp_batch_init(const lbtp_params *members, int n, lbtp_batch **out) {
   *out = nullptr;
   const lbtp_params &p0 = members[0];
   if (p0.residual_stride < 2 || p0.residual_stride % 2) return LBTP_EINVAL;
-  if (p0.lattice == LBTP_D2Q9) return LBTP_EINVAL;   // ensembles run D2Q5 / D3Q7
-  for (int i = 0; i < n; ++i)
-    if (members[i].cap_B != 0.0) return LBTP_EINVAL;  // and a uniform tau_g
   for (int i = 0; i < n; ++i) {
     const lbtp_params &p = members[i];
     if (p.lattice != p0.lattice || p.storage != p0.storage || p.residual_stride != p0.residual_stride ||
@@ -1257,7 +1254,8 @@ int lbtp_batch_init(const lbtp_params *members, int n, lbtp_batch **out) {
   }
   lbtp_batch *b = new lbtp_batch();
   b->n = n;
-  b->dim = p0.lattice == LBTP_D2Q5 ? 2 : 3;
+  // lattice kind of the ensemble launchers: 2 (D2Q5), 3 (D3Q7), kD2Q9
+  b->dim = p0.lattice == LBTP_D2Q5 ? 2 : (p0.lattice == LBTP_D3Q7 ? 3 : kD2Q9);
   b->storage = p0.storage;
   b->m = p0.residual_stride;
   if (p0.stream) {
@@ -1300,7 +1298,9 @@ int lbtp_batch_init(const lbtp_params *members, int n, lbtp_batch **out) {
     batch_free(b);
     return LBTP_EHIP;
   }
-  b->H = b->ctx[0]->sweep_block > 1 ? b->ctx[0]->sweep_block : 1;
+  // blocked plain sweeps: D2Q5 ensembles (D2Q9 and D3Q7 members sweep one
+  // sweep per launch, four nodes per thread on D2Q9)
+  b->H = (b->dim == 2 && b->ctx[0]->sweep_block > 1) ? b->ctx[0]->sweep_block : 1;
   // size classes; a blocked tiling tuned earlier in the process for a
   // class's size, storage and m is taken over
   for (int i = 0; i < n; ++i) {

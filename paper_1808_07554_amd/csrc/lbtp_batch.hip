@@ -25,6 +25,7 @@
 
 #include "../../include/lbtp.h"
 #include "lbtp_block.h"
+#include "lbtp_d2q9.h"
 #include "lbtp_device.h"
 
 namespace lbtp {
@@ -60,14 +61,24 @@ __global__ __launch_bounds__(NT) void batch_sweep_kernel(const Member *__restric
     for (int i = 0; i < 4; ++i) {
       const int c = t * 4 * NT + i * NT + threadIdx.x;
       if (c < kc.ncell) {
-        if (M.Fp) sweep_cell<DIM, T, true, MODE, true>(kc, fin, fout, Pb_in, Pb_out, M.itau, M.Fp, c, acc);
-        else sweep_cell<DIM, T, true, MODE, false>(kc, fin, fout, Pb_in, Pb_out, M.itau, M.Fp, c, acc);
+        if constexpr (DIM == kD2Q9) {
+          if (M.Fp) q9_sweep_cell<T, true, MODE, true>(kc, fin, fout, Pb_in, Pb_out, M.itau, M.Fp, c, acc);
+          else q9_sweep_cell<T, true, MODE, false>(kc, fin, fout, Pb_in, Pb_out, M.itau, M.Fp, c, acc);
+        } else {
+          if (M.Fp) sweep_cell<DIM, T, true, MODE, true>(kc, fin, fout, Pb_in, Pb_out, M.itau, M.Fp, c, acc);
+          else sweep_cell<DIM, T, true, MODE, false>(kc, fin, fout, Pb_in, Pb_out, M.itau, M.Fp, c, acc);
+        }
       }
     }
   } else {
     const int qi = t * NT + threadIdx.x;
-    if (M.Fp) sweep_quad<DIM, T, MODE, true>(kc, fin, fout, Pb_in, Pb_out, M.itau, M.Fp, qi, acc);
-    else sweep_quad<DIM, T, MODE, false>(kc, fin, fout, Pb_in, Pb_out, M.itau, M.Fp, qi, acc);
+    if constexpr (DIM == kD2Q9) {
+      if (M.Fp) q9_sweep_quad<T, MODE, true>(kc, fin, fout, Pb_in, Pb_out, M.itau, M.Fp, qi, acc);
+      else q9_sweep_quad<T, MODE, false>(kc, fin, fout, Pb_in, Pb_out, M.itau, M.Fp, qi, acc);
+    } else {
+      if (M.Fp) sweep_quad<DIM, T, MODE, true>(kc, fin, fout, Pb_in, Pb_out, M.itau, M.Fp, qi, acc);
+      else sweep_quad<DIM, T, MODE, false>(kc, fin, fout, Pb_in, Pb_out, M.itau, M.Fp, qi, acc);
+    }
   }
   if (MODE == 2) block_sum<2, NT>(acc, partials);
 }
@@ -205,8 +216,13 @@ __global__ __launch_bounds__(NT) void batch_moments_kernel(const Member *__restr
   for (int i = 0; i < 4; ++i) {
     const int c = t * 4 * NT + i * NT + threadIdx.x;
     if (c < M.kc.ncell) {
-      if (M.Fs) acc[0] += moments_cell<DIM, true, TG>(M.kc, M.g[gs], M.K, M.phi, M.Fs, M.S, M.itau, c, write_coef);
-      else acc[0] += moments_cell<DIM, false, TG>(M.kc, M.g[gs], M.K, M.phi, M.Fs, M.S, M.itau, c, write_coef);
+      if constexpr (DIM == kD2Q9) {
+        if (M.Fs) acc[0] += q9_moments_cell<true, TG>(M.kc, M.g[gs], M.K, M.phi, M.Fs, M.S, M.itau, c, write_coef);
+        else acc[0] += q9_moments_cell<false, TG>(M.kc, M.g[gs], M.K, M.phi, M.Fs, M.S, M.itau, c, write_coef);
+      } else {
+        if (M.Fs) acc[0] += moments_cell<DIM, true, TG>(M.kc, M.g[gs], M.K, M.phi, M.Fs, M.S, M.itau, c, write_coef);
+        else acc[0] += moments_cell<DIM, false, TG>(M.kc, M.g[gs], M.K, M.phi, M.Fs, M.S, M.itau, c, write_coef);
+      }
     }
   }
   block_sum<1, NT>(acc, partials);
@@ -228,12 +244,21 @@ __global__ __launch_bounds__(NT) void batch_gsweep_kernel(const Member *__restri
   for (int i = 0; i < 4; ++i) {
     const int c = t * 4 * NT + i * NT + threadIdx.x;
     if (c < M.kc.ncell) {
-      if (M.Fs)
-        acc[0] += g_sweep_cell<DIM, T, FLOCAL, true>(M.kc, M.g[gs], M.g[gs ^ 1], f, Pb, M.itau, M.K, M.phi, M.Fs,
+      if constexpr (DIM == kD2Q9) {
+        if (M.Fs)
+          acc[0] += q9_g_sweep_cell<T, FLOCAL, true>(M.kc, M.g[gs], M.g[gs ^ 1], f, Pb, M.itau, M.K, M.phi, M.Fs,
                                                      M.S, c);
-      else
-        acc[0] += g_sweep_cell<DIM, T, FLOCAL, false>(M.kc, M.g[gs], M.g[gs ^ 1], f, Pb, M.itau, M.K, M.phi, M.Fs,
+        else
+          acc[0] += q9_g_sweep_cell<T, FLOCAL, false>(M.kc, M.g[gs], M.g[gs ^ 1], f, Pb, M.itau, M.K, M.phi, M.Fs,
                                                       M.S, c);
+      } else {
+        if (M.Fs)
+          acc[0] += g_sweep_cell<DIM, T, FLOCAL, true>(M.kc, M.g[gs], M.g[gs ^ 1], f, Pb, M.itau, M.K, M.phi, M.Fs,
+                                                       M.S, c);
+        else
+          acc[0] += g_sweep_cell<DIM, T, FLOCAL, false>(M.kc, M.g[gs], M.g[gs ^ 1], f, Pb, M.itau, M.K, M.phi, M.Fs,
+                                                        M.S, c);
+      }
     }
   }
   block_sum<1, NT>(acc, partials);
@@ -290,7 +315,8 @@ template <int NT>
 static void sweep_by_dim(int dim, int storage, int mode, int local, int nblk, const Member *mem, const BCtl *ctl,
                          const int *tm, const int *ti, double *part, int j, hipStream_t s) {
   if (dim == 2) sweep_by_storage<2, NT>(storage, mode, local, nblk, mem, ctl, tm, ti, part, j, s);
-  else sweep_by_storage<3, NT>(storage, mode, local, nblk, mem, ctl, tm, ti, part, j, s);
+  else if (dim == 3) sweep_by_storage<3, NT>(storage, mode, local, nblk, mem, ctl, tm, ti, part, j, s);
+  else sweep_by_storage<kD2Q9, NT>(storage, mode, local, nblk, mem, ctl, tm, ti, part, j, s);
 }
 
 hipError_t batch_launch_sweep(int nt, int dim, int storage, int mode, int local, int nblk, const Member *mem,
@@ -333,7 +359,8 @@ hipError_t batch_launch_moments(int dim, int storage, int nblk, const Member *me
                                 double *part, int gs, int write_coef, hipStream_t s) {
   // moments and the saturation step use tiles of kCellTile nodes (256 threads x 4)
   if (dim == 2) moments_by_storage<2>(storage, nblk, mem, tm, ti, part, gs, write_coef, s);
-  else moments_by_storage<3>(storage, nblk, mem, tm, ti, part, gs, write_coef, s);
+  else if (dim == 3) moments_by_storage<3>(storage, nblk, mem, tm, ti, part, gs, write_coef, s);
+  else moments_by_storage<kD2Q9>(storage, nblk, mem, tm, ti, part, gs, write_coef, s);
   return hipGetLastError();
 }
 
@@ -352,10 +379,14 @@ hipError_t batch_launch_gsweep(int dim, int storage, int local, int nblk, const 
     if (storage == LBTP_FP16_DEV) gsweep_launch<2, _Float16>(local, nblk, mem, ctl, tm, ti, part, gs, s);
     else if (storage == LBTP_BF16_DEV) gsweep_launch<2, bf16_t>(local, nblk, mem, ctl, tm, ti, part, gs, s);
     else gsweep_launch<2, float>(local, nblk, mem, ctl, tm, ti, part, gs, s);
-  } else {
+  } else if (dim == 3) {
     if (storage == LBTP_FP16_DEV) gsweep_launch<3, _Float16>(local, nblk, mem, ctl, tm, ti, part, gs, s);
     else if (storage == LBTP_BF16_DEV) gsweep_launch<3, bf16_t>(local, nblk, mem, ctl, tm, ti, part, gs, s);
     else gsweep_launch<3, float>(local, nblk, mem, ctl, tm, ti, part, gs, s);
+  } else {
+    if (storage == LBTP_FP16_DEV) gsweep_launch<kD2Q9, _Float16>(local, nblk, mem, ctl, tm, ti, part, gs, s);
+    else if (storage == LBTP_BF16_DEV) gsweep_launch<kD2Q9, bf16_t>(local, nblk, mem, ctl, tm, ti, part, gs, s);
+    else gsweep_launch<kD2Q9, float>(local, nblk, mem, ctl, tm, ti, part, gs, s);
   }
   return hipGetLastError();
 }

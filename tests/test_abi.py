@@ -60,22 +60,16 @@ def test_invalid_params_rejected_without_device(kw):
     assert not h.value
 
 
-def test_d2q9_ensemble_rejected_without_device():
+def test_mixed_lattice_ensemble_rejected_without_device():
+    """Ensembles take D2Q5, D3Q7 or D2Q9 members (and capillary ones), but one
+    lattice for all members: a mixed set is refused before any device work."""
     lib = lbtp.load()
     arr = (lbtp.Params * 2)()
     arr[0] = _params(lattice=lbtp.D2Q9, nx=16)
-    arr[1] = _params(lattice=lbtp.D2Q9, nx=16)
+    arr[1] = _params(lattice=lbtp.D2Q5, nx=16)
     h = ctypes.c_void_p()
     assert lib.lbtp_batch_init(arr, 2, ctypes.byref(h)) == lbtp.EINVAL
     assert not h.value
-
-
-def test_capillary_ensemble_rejected_without_device():
-    lib = lbtp.load()
-    arr = (lbtp.Params * 1)()
-    arr[0] = _params(cap_B=0.5)
-    h = ctypes.c_void_p()
-    assert lib.lbtp_batch_init(arr, 1, ctypes.byref(h)) == lbtp.EINVAL
 
 
 def test_inconsistent_periodicity_rejected():

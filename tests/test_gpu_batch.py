@@ -167,3 +167,39 @@ def test_autotuned_tilings_per_size_class_keep_single_run_results():
         assert bool((b.pressure(i) == s.pressure()).all()), i
         assert bool((b.saturation(i) == s.saturation()).all()), i
         assert bool((b.velocity(i) == s.velocity()).all()), i
+
+
+@pytest.mark.parametrize("kind,storage", [("D2Q9", "fp32"), ("D2Q9", "fp16"), ("capillary", "fp32"),
+                                          ("D2Q9-capillary", "bf16")])
+def test_d2q9_and_capillary_members_equal_single_runs(kind, storage):
+    """Ensembles of the paper's D2Q9 lattice (beta inside the eq. 3-4 bounds)
+    and of members with the capillary diffusivity field D_s(S, x) (a tau_g
+    per node): every member equals its single-context run bit for bit, with
+    fixed iteration counts and with solves to a tolerance (one sweep per
+    launch on both sides for 16-bit storage, as in the other ensemble test)."""
+    from paper_1808_07554_amd import lbtp
+    shapes = [(32, 32), (64, 40), (48, 24)]
+    ms = _members(shapes, seed0=150)
+    ms = [(dict(p, lattice="D2Q9" if kind.startswith("D2Q9") else p["lattice"],
+                beta=0.2 if kind.startswith("D2Q9") else p["beta"],
+                cap_B=0.05 if kind.endswith("capillary") else 0.0,
+                **({} if storage == "fp32" else {"sweep_block": 1})), fl) for p, fl in ms]
+    b = lbtp.Batch([p for p, _ in ms], m=16, storage=storage)
+    singles = []
+    for i, (p, fl) in enumerate(ms):
+        b.set_fields(i, fl["K"], fl["phi"])
+        b.set_state(i, fl["P0"], fl["S0"])
+        s = gpu_solver(p, m=16, storage=storage)
+        s.set_fields(fl["K"], fl["phi"])
+        s.set_state(fl["P0"], fl["S0"])
+        singles.append(s)
+    its, _ = b.step(2, -1.0, 48)
+    assert (its == 48).all()
+    its_b, _ = b.step(2, 1e-6, 16 * 2000)
+    for i, s in enumerate(singles):
+        s.step(2, -1.0, 48)
+        its_s, _ = s.step(2, 1e-6, 16 * 2000)
+        assert list(its_b[:, i]) == its_s, (i, its_b[:, i], its_s)
+        assert bool((b.pressure(i) == s.pressure()).all()), i
+        assert bool((b.saturation(i) == s.saturation()).all()), i
+        assert bool((b.velocity(i) == s.velocity()).all()), i
