@@ -128,8 +128,7 @@ typedef struct lbtp_params {
   double coef[6];              /* RATIONAL: a0, a1, c0, c1, b0, b1 (unused otherwise) */
   double cap_B;                /* >= 0: capillary curve P_c = cap_B (1 - S), which adds
                                   cap_B K lambda_n f_w to Ds (eq. 2-16), so D_s and tau_g
-                                  vary with S and K from node to node; 0 = constant Ds.
-                                  Single contexts only (ensembles: LBTP_EINVAL). */
+                                  vary with S and K from node to node; 0 = constant Ds. */
   int sweep_block;             /* plain pressure sweeps fused into one launch inside the
                                   captured chunks of m sweeps (temporal blocking with the
                                   region in registers; D2Q5 and D2Q9, float32 results
@@ -278,14 +277,20 @@ LBTP_API int lbtp_put_state(lbtp_ctx *ctx, const void *buf, long long nbytes, in
 /* ------------------------------------------------------------------------
  * Ensembles: n independent realisations (their own size, K, phi, boundary
  * values and sources) advanced together, every coupled step covering all
- * members with one launch per kernel.  Each member's pressure solve stops on
- * its own; members that stopped drop out of the remaining sweeps.  The
- * members' numbers are bit-identical to separate lbtp_ctx runs with the same
- * parameters.  All members share lattice, storage, stream and the residual
- * stride m, which must be even; nx % 4 == 0 for every member; max_iters of a
- * step must be a positive multiple of m.  A NULL stream makes the ensemble
- * use a stream of its own (HIP graphs cannot be captured on the null
- * stream).
+ * members with one launch per kernel (the blocked plain sweeps of D2Q5: one
+ * per size class of members).  Each member's pressure solve stops on its
+ * own, on a device-side flag; members that stopped drop out of the
+ * remaining sweeps.  Chunks of m sweeps run as captured HIP graphs of 1, 2,
+ * 4, 8 or 16 chunks, sized from the iterations the slowest member needed in
+ * the previous step, and the host reads the number of active members once
+ * per graph.  The members' numbers are bit-identical to separate lbtp_ctx
+ * runs with the same parameters (float32; with 16-bit storage, with the
+ * same sweeps per launch).  Lattices D2Q5, D3Q7 and D2Q9 (D2Q9 and D3Q7
+ * members run one pressure sweep per launch), constant or capillary D_s.
+ * All members share lattice, storage, stream and the residual stride m,
+ * which must be even; nx % 4 == 0 for every member; max_iters of a step must
+ * be a positive multiple of m.  A NULL stream makes the ensemble use a
+ * stream of its own (HIP graphs cannot be captured on the null stream).
  * ------------------------------------------------------------------------ */
 typedef struct lbtp_batch lbtp_batch;
 
