@@ -12,8 +12,10 @@
 //
 // Tensors are [N][H][W][C] with C padded to a multiple of 16, activations in
 // bf16, accumulation in float32.  The 3x3 convolution is an implicit GEMM on
-// the bf16 matrix cores (16x16x16 MFMA): a wavefront computes 16 pixels x 16
-// output channels, with K running over the nine taps and the input channels.
+// the bf16 matrix cores (16x16x32 MFMA): a workgroup stages a block of input
+// pixels with its halo and the block's weights in LDS, and each wavefront
+// computes several 16-pixel x 16-channel products per fragment it reads, with
+// K running over the nine taps and the input channels.
 // The backward-data pass is the same kernel with the weights rotated by 180
 // degrees and input/output channels swapped; the weight gradient is a second
 // MFMA GEMM with the pixels as K, split into chunks whose partial sums are
@@ -44,50 +46,122 @@ __device__ inline bf16 f2bf(float f) {
 
 // ------------------------------------------------------------------ convolution
 // out[n,y,x,co] = act(bias[co] + sum_{ky,kx,ci} w[co][ky][kx][ci] in[n, y+ky-1, x+kx-1, ci])
-// grid (ceil(W/64) * H * N, Co/16), block 256: wave v covers pixels x0 + 16v .. + 15.
-template <bool RELU, bool OUT_F32>
-__global__ __launch_bounds__(256) void conv3x3_kernel(const bf16 *__restrict__ in, const bf16 *__restrict__ w,
-                                                      const float *__restrict__ bias, void *__restrict__ out, int N,
-                                                      int H, int W, int Ci, int Co) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ntx = (W + 63) / 64;
+//
+// Implicit GEMM on the 16x16x32 bf16 matrix cores, D[co][pixel] += W[co][k] X[k][pixel]
+// with k = (tap, input channel).  A workgroup (4 waves) computes a TR x TC block
+// of output pixels of one image for TN output channels.  Input channels are
+// taken CK at a time: the block's input pixels with a one-pixel halo,
+// (TR+2) x (TC+2) x CK, and the TN x 9 x CK weights are staged in LDS with a
+// pitch of CK + 8 bf16 per pixel / per weight row, which puts 16 consecutive
+// pixels (or output channels) of one 16-byte column on 16 distinct groups of
+// four banks.  Every wave then runs the nine taps out of LDS: wave v owns
+// SPW = TR*TC/64 runs of 16 consecutive pixels of a row; per tap it reads
+// TN/16 weight fragments and SPW input fragments and issues SPW * TN/16 MFMAs,
+// so each fragment read from LDS feeds several products.  With CK = 16 (an
+// input of 16 channels) one MFMA covers two taps: lanes 0-31 the even tap,
+// lanes 32-63 the odd one; the tenth tap is zero.  The result of a lane is
+// four consecutive output channels of one pixel, stored as one 8-byte (bf16)
+// or 16-byte (float) write.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+__device__ inline f32x4_t mfma_16x16x32(const uint4 &a, const uint4 &b, const f32x4_t &c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c,
+                                                 0, 0, 0);
+}
+
+__device__ inline uint32_t pack_bf16x2(float lo, float hi) {
+  return (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
+}
+
+template <int TR, int TC, int TN, int CK>
+__global__ __launch_bounds__(256, 2) void conv3x3_kernel(const bf16 *__restrict__ in, const bf16 *__restrict__ w,
+                                                         const float *__restrict__ bias, void *__restrict__ out,
+                                                         int H, int W, int Ci, int Co, int relu, int out_f32) {
+  constexpr int CKP = CK + 8;         // LDS pitch (bf16) of one pixel and of one weight row
+  constexpr int HR = TR + 2, HC = TC + 2;
+  constexpr int SEGR = TC / 16;       // 16-pixel runs per tile row
+  constexpr int SPW = TR * SEGR / 4;  // runs per wave
+  constexpr int NB = TN / 16;         // 16-channel output blocks
+  constexpr int Q = CK / 8;           // 16-byte pieces per pixel of a chunk
+  constexpr int KSTEPS = CK == 32 ? 9 : 5;
+  static_assert(CK == 16 || CK == 32, "chunk of 16 or 32 channels");
+  static_assert(TC % 16 == 0 && (TR * SEGR) % 4 == 0, "whole runs per wave");
+  __shared__ __align__(16) bf16 sx[HR * HC * CKP];
+  __shared__ __align__(16) bf16 sw[TN * 9 * CKP];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
+  const int ntx = (W + TC - 1) / TC, nty = (H + TR - 1) / TR;
   int b = blockIdx.x;
-  const int xt = b % ntx;
+  const int tx0 = (b % ntx) * TC;
   b /= ntx;
-  const int y = b % H;
-  const int n = b / H;
-  const int x0 = xt * 64 + wave * 16;
-  const int co0 = blockIdx.y * 16;
-  const int m = lane & 15, kq = lane >> 4;
-  const int x = x0 + m;
-  f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-  const bf16x4_t zero = {0, 0, 0, 0};
-  for (int ky = 0; ky < 3; ++ky) {
-    const int yy = y + ky - 1;
-    for (int kx = 0; kx < 3; ++kx) {
-      const int xx = x + kx - 1;
-      const bool valid = x < W && yy >= 0 && yy < H && xx >= 0 && xx < W;
-      const size_t ioff = valid ? ((size_t)(n * H + yy) * W + xx) * Ci + 4 * kq : 0;
-      const size_t woff = ((size_t)(co0 + m) * 9 + ky * 3 + kx) * Ci + 4 * kq;
-      for (int c0 = 0; c0 < Ci; c0 += 16) {
-        const bf16x4_t a = valid ? *(const bf16x4_t *)(in + ioff + c0) : zero;
-        const bf16x4_t bb = *(const bf16x4_t *)(w + woff + c0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc, 0, 0, 0);
+  const int ty0 = (b % nty) * TR;
+  const int n = b / nty;
+  const int co0 = blockIdx.y * TN;
+  const uint4 z4 = {0u, 0u, 0u, 0u};
+  f32x4_t acc[SPW][NB];
+#pragma unroll
+  for (int i = 0; i < SPW; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  const bf16 *img = in + (size_t)n * H * W * Ci;
+  for (int c0 = 0; c0 < Ci; c0 += CK) {
+    __syncthreads();  // the previous chunk's fragments have been read
+    for (int idx = tid; idx < HR * HC * Q; idx += 256) {
+      const int q = idx % Q, p = idx / Q;
+      const int gy = ty0 + p / HC - 1, gx = tx0 + p % HC - 1;
+      uint4 v = z4;
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = *(const uint4 *)(img + ((size_t)gy * W + gx) * Ci + c0 + 8 * q);
+      *(uint4 *)(sx + p * CKP + 8 * q) = v;
+    }
+    for (int idx = tid; idx < TN * 9 * Q; idx += 256) {
+      const int q = idx % Q, row = idx / Q;  // row = local output channel * 9 + tap
+      *(uint4 *)(sw + row * CKP + 8 * q) = *(const uint4 *)(w + ((size_t)co0 * 9 + row) * Ci + c0 + 8 * q);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < KSTEPS; ++s) {
+      const int tap = CK == 32 ? s : 2 * s + (g >> 1);
+      const int ch = CK == 32 ? 8 * g : 8 * (g & 1);
+      const bool live = tap < 9;
+      const int ky = live ? tap / 3 : 0, kx = live ? tap % 3 : 0;
+      uint4 a[NB], x[SPW];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) a[j] = live ? *(const uint4 *)(sw + ((16 * j + m) * 9 + tap) * CKP + ch) : z4;
+#pragma unroll
+      for (int i = 0; i < SPW; ++i) {
+        const int seg = wave * SPW + i;
+        const int r = seg / SEGR, c = (seg % SEGR) * 16 + m;
+        x[i] = live ? *(const uint4 *)(sx + ((r + ky) * HC + c + kx) * CKP + ch) : z4;
       }
+#pragma unroll
+      for (int i = 0; i < SPW; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[i][j] = mfma_16x16x32(a[j], x[i], acc[i][j]);
     }
   }
-  // lane holds D[4 kq + i][m]: pixel x0 + 4 kq + i, output channel co0 + m
-  const int co = co0 + m;
-  const float bv = bias ? bias[co] : 0.0f;
+  // lane holds D[4 g + r][m]: output channel co0 + 16 j + 4 g + r of pixel m of each run
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int px = x0 + 4 * kq + i;
-    if (px < W) {
-      float v = acc[i] + bv;
-      if (RELU) v = fmaxf(v, 0.0f);
-      const size_t o = ((size_t)(n * H + y) * W + px) * Co + co;
-      if (OUT_F32) ((float *)out)[o] = v;
-      else ((bf16 *)out)[o] = f2bf(v);
+  for (int j = 0; j < NB; ++j) {
+    const int co = co0 + 16 * j + 4 * g;
+    float bv[4] = {0.f, 0.f, 0.f, 0.f};
+    if (bias) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bv[r] = bias[co + r];
+    }
+#pragma unroll
+    for (int i = 0; i < SPW; ++i) {
+      const int seg = wave * SPW + i;
+      const int y = ty0 + seg / SEGR, x = tx0 + (seg % SEGR) * 16 + m;
+      if (y < H && x < W) {
+        float v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          v[r] = acc[i][j][r] + bv[r];
+          if (relu) v[r] = fmaxf(v[r], 0.0f);
+        }
+        const size_t o = (((size_t)n * H + y) * W + x) * Co + co;
+        if (out_f32) *(float4 *)((float *)out + o) = make_float4(v[0], v[1], v[2], v[3]);
+        else *(uint2 *)((bf16 *)out + o) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+      }
     }
   }
 }
@@ -504,12 +578,39 @@ bf16 *tensor(lbtp_nn *nn, int slot, size_t elems, int *rc) {
   return t.p;
 }
 
+template <int TR, int TC, int TN, int CK>
+void conv_launch(hipStream_t st, const bf16 *in, const bf16 *w, const float *b, void *out, int N, int H, int W,
+                 int Ci, int Co, bool relu, bool f32) {
+  const dim3 g((unsigned)(N * ((H + TR - 1) / TR) * ((W + TC - 1) / TC)), (unsigned)(Co / TN));
+  hipLaunchKernelGGL((conv3x3_kernel<TR, TC, TN, CK>), g, dim3(256), 0, st, in, w, b, out, H, W, Ci, Co, (int)relu,
+                     (int)f32);
+}
+
+// Tiles of 256 pixels for 64 output channels and of 512 pixels for 32 or 16
+// (64 accumulators per lane either way); 64 columns wide on grids at least 64
+// wide, 16 columns on narrower ones.  Input channels in chunks of 32, or of
+// 16 when the channel count is an odd multiple of 16.
+template <int CK>
+void conv_dispatch(hipStream_t st, const bf16 *in, const bf16 *w, const float *b, void *out, int N, int H, int W,
+                   int Ci, int Co, bool relu, bool f32) {
+  const bool wide = W >= 64;
+  if (Co % 64 == 0) {
+    if (wide) conv_launch<4, 64, 64, CK>(st, in, w, b, out, N, H, W, Ci, Co, relu, f32);
+    else conv_launch<16, 16, 64, CK>(st, in, w, b, out, N, H, W, Ci, Co, relu, f32);
+  } else if (Co % 32 == 0) {
+    if (wide) conv_launch<8, 64, 32, CK>(st, in, w, b, out, N, H, W, Ci, Co, relu, f32);
+    else conv_launch<32, 16, 32, CK>(st, in, w, b, out, N, H, W, Ci, Co, relu, f32);
+  } else {
+    if (wide) conv_launch<8, 64, 16, CK>(st, in, w, b, out, N, H, W, Ci, Co, relu, f32);
+    else conv_launch<32, 16, 16, CK>(st, in, w, b, out, N, H, W, Ci, Co, relu, f32);
+  }
+}
+
 int conv_fwd(lbtp_nn *nn, const bf16 *in, const bf16 *w, const float *b, void *out, int N, int H, int W, int Ci,
              int Co, bool relu, bool f32) {
-  const dim3 g((unsigned)(((W + 63) / 64) * H * N), (unsigned)(Co / 16)), bl(256);
-  if (f32) hipLaunchKernelGGL((conv3x3_kernel<false, true>), g, bl, 0, nn->stream, in, w, b, out, N, H, W, Ci, Co);
-  else if (relu) hipLaunchKernelGGL((conv3x3_kernel<true, false>), g, bl, 0, nn->stream, in, w, b, out, N, H, W, Ci, Co);
-  else hipLaunchKernelGGL((conv3x3_kernel<false, false>), g, bl, 0, nn->stream, in, w, b, out, N, H, W, Ci, Co);
+  if (Ci <= 0 || Ci % 16 || Co <= 0 || Co % 16) return LBTP_EINVAL;
+  if (Ci % 32 == 0) conv_dispatch<32>(nn->stream, in, w, b, out, N, H, W, Ci, Co, relu, f32);
+  else conv_dispatch<16>(nn->stream, in, w, b, out, N, H, W, Ci, Co, relu, f32);
   NN_TRY(hipGetLastError());
   return LBTP_OK;
 }

@@ -89,7 +89,7 @@ def summarize(trace_csv, out_path):
     ls = layers(*INFER)
     n = len(ls)
     passes = [conv[i * n:(i + 1) * n] for i in range(4)]
-    lines = ["Warm-start network, per-layer convolution (implicit GEMM on v_mfma_f32_16x16x16_bf16), "
+    lines = ["Warm-start network, per-layer convolution (implicit GEMM on v_mfma_f32_16x16x32_bf16, LDS-tiled), "
              f"inference of one {INFER[1]}x{INFER[2]} field at full resolution",
              "command: cd /tmp && export TMPDIR=/tmp; rocprofv3 --kernel-trace --stats --output-format csv -d DIR "
              "-o run -- python -m paper_1808_07554_amd.profile_nn; summary: python -m "
