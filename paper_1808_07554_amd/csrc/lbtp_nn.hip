@@ -49,7 +49,7 @@ __device__ inline bf16 f2bf(float f) {
 //
 // Implicit GEMM on the 16x16x32 bf16 matrix cores, D[co][pixel] += W[co][k] X[k][pixel]
 // with k = (tap, input channel).  A workgroup (4 waves) computes a TR x TC block
-// of output pixels of one image for TN output channels.  Input channels are
+// of output pixels for TN output channels.  Input channels are
 // taken CK at a time: the block's input pixels with a one-pixel halo,
 // (TR+2) x (TC+2) x CK, and the TN x 9 x CK weights are staged in LDS with a
 // pitch of CK + 8 bf16 per pixel / per weight row, which puts 16 consecutive
@@ -73,43 +73,68 @@ __device__ inline uint32_t pack_bf16x2(float lo, float hi) {
   return (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
 }
 
-template <int TR, int TC, int TN, int CK>
+// Tile of P = 256 (TN = 64) or 512 (TN <= 32) pixels, TR x TC with TC = 2^tcs
+// of 8, 16, 32 or 64 columns: the images of the batch are taken as one stack
+// of N*H rows, so a tile may span images; a lane masks the rows above and
+// below its output pixel where they belong to another image (the column halo
+// is zero where it leaves the grid).
+constexpr int conv_halo_max(int P) {
+  int best = 0;
+  for (int tc = 8; tc <= 64; tc *= 2) {
+    const int h = (P / tc + 2) * (tc + 2);
+    best = h > best ? h : best;
+  }
+  return best;
+}
+
+template <int TN, int CK>
 __global__ __launch_bounds__(256, 2) void conv3x3_kernel(const bf16 *__restrict__ in, const bf16 *__restrict__ w,
                                                          const float *__restrict__ bias, void *__restrict__ out,
-                                                         int H, int W, int Ci, int Co, int relu, int out_f32) {
-  constexpr int CKP = CK + 8;         // LDS pitch (bf16) of one pixel and of one weight row
-  constexpr int HR = TR + 2, HC = TC + 2;
-  constexpr int SEGR = TC / 16;       // 16-pixel runs per tile row
-  constexpr int SPW = TR * SEGR / 4;  // runs per wave
-  constexpr int NB = TN / 16;         // 16-channel output blocks
-  constexpr int Q = CK / 8;           // 16-byte pieces per pixel of a chunk
+                                                         int NH, int H, int W, int Ci, int Co, int tcs, int relu,
+                                                         int out_f32) {
+  constexpr int P = TN == 64 ? 256 : 512;  // pixels per tile
+  constexpr int CKP = CK + 8;              // LDS pitch (bf16) of one pixel and of one weight row
+  constexpr int SPW = P / 64;              // 16-pixel runs per wave
+  constexpr int NB = TN / 16;              // 16-channel output blocks
+  constexpr int Q = CK / 8;                // 16-byte pieces per pixel of a chunk
   constexpr int KSTEPS = CK == 32 ? 9 : 5;
   static_assert(CK == 16 || CK == 32, "chunk of 16 or 32 channels");
-  static_assert(TC % 16 == 0 && (TR * SEGR) % 4 == 0, "whole runs per wave");
-  __shared__ __align__(16) bf16 sx[HR * HC * CKP];
+  __shared__ __align__(16) bf16 sx[conv_halo_max(P) * CKP];
   __shared__ __align__(16) bf16 sw[TN * 9 * CKP];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
-  const int ntx = (W + TC - 1) / TC, nty = (H + TR - 1) / TR;
-  int b = blockIdx.x;
-  const int tx0 = (b % ntx) * TC;
-  b /= ntx;
-  const int ty0 = (b % nty) * TR;
-  const int n = b / nty;
+  const int TC = 1 << tcs, TR = P >> tcs, HC = TC + 2, HR = TR + 2;
+  const uint32_t hc_magic = 0xFFFFFFFFu / (uint32_t)HC + 1u;  // p / HC = umulhi(p, magic) for p < 2^16
+  const int ntx = (W + TC - 1) >> tcs;
+  const int tx0 = (int)(blockIdx.x % (unsigned)ntx) << tcs;
+  const int ty0 = (int)(blockIdx.x / (unsigned)ntx) * TR;  // first stacked row
   const int co0 = blockIdx.y * TN;
   const uint4 z4 = {0u, 0u, 0u, 0u};
+  // the wave's runs: LDS offset of the output pixel's halo origin, and whether
+  // the rows above / below it belong to its image
+  int base[SPW];
+  bool up_ok[SPW], dn_ok[SPW];
+#pragma unroll
+  for (int i = 0; i < SPW; ++i) {
+    const int pi = (wave * SPW + i) * 16 + m;
+    const int r = pi >> tcs, c = pi & (TC - 1);
+    const int y = (ty0 + r) % H;
+    base[i] = r * HC + c;
+    up_ok[i] = y > 0;
+    dn_ok[i] = y < H - 1;
+  }
   f32x4_t acc[SPW][NB];
 #pragma unroll
   for (int i = 0; i < SPW; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  const bf16 *img = in + (size_t)n * H * W * Ci;
   for (int c0 = 0; c0 < Ci; c0 += CK) {
     __syncthreads();  // the previous chunk's fragments have been read
     for (int idx = tid; idx < HR * HC * Q; idx += 256) {
       const int q = idx % Q, p = idx / Q;
-      const int gy = ty0 + p / HC - 1, gx = tx0 + p % HC - 1;
+      const int r = (int)__umulhi((uint32_t)p, hc_magic);
+      const int ys = ty0 + r - 1, gx = tx0 + (p - r * HC) - 1;
       uint4 v = z4;
-      if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = *(const uint4 *)(img + ((size_t)gy * W + gx) * Ci + c0 + 8 * q);
+      if (ys >= 0 && ys < NH && gx >= 0 && gx < W) v = *(const uint4 *)(in + ((size_t)ys * W + gx) * Ci + c0 + 8 * q);
       *(uint4 *)(sx + p * CKP + 8 * q) = v;
     }
     for (int idx = tid; idx < TN * 9 * Q; idx += 256) {
@@ -128,9 +153,8 @@ __global__ __launch_bounds__(256, 2) void conv3x3_kernel(const bf16 *__restrict_
       for (int j = 0; j < NB; ++j) a[j] = live ? *(const uint4 *)(sw + ((16 * j + m) * 9 + tap) * CKP + ch) : z4;
 #pragma unroll
       for (int i = 0; i < SPW; ++i) {
-        const int seg = wave * SPW + i;
-        const int r = seg / SEGR, c = (seg % SEGR) * 16 + m;
-        x[i] = live ? *(const uint4 *)(sx + ((r + ky) * HC + c + kx) * CKP + ch) : z4;
+        const bool ok = live && (ky != 0 || up_ok[i]) && (ky != 2 || dn_ok[i]);
+        x[i] = ok ? *(const uint4 *)(sx + (base[i] + ky * HC + kx) * CKP + ch) : z4;
       }
 #pragma unroll
       for (int i = 0; i < SPW; ++i)
@@ -149,16 +173,16 @@ __global__ __launch_bounds__(256, 2) void conv3x3_kernel(const bf16 *__restrict_
     }
 #pragma unroll
     for (int i = 0; i < SPW; ++i) {
-      const int seg = wave * SPW + i;
-      const int y = ty0 + seg / SEGR, x = tx0 + (seg % SEGR) * 16 + m;
-      if (y < H && x < W) {
+      const int pi = (wave * SPW + i) * 16 + m;
+      const int ys = ty0 + (pi >> tcs), x = tx0 + (pi & (TC - 1));
+      if (ys < NH && x < W) {
         float v[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           v[r] = acc[i][j][r] + bv[r];
           if (relu) v[r] = fmaxf(v[r], 0.0f);
         }
-        const size_t o = (((size_t)n * H + y) * W + x) * Co + co;
+        const size_t o = ((size_t)ys * W + x) * Co + co;
         if (out_f32) *(float4 *)((float *)out + o) = make_float4(v[0], v[1], v[2], v[3]);
         else *(uint2 *)((bf16 *)out + o) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
       }
@@ -166,71 +190,175 @@ __global__ __launch_bounds__(256, 2) void conv3x3_kernel(const bf16 *__restrict_
   }
 }
 
-// part[chunk][co][tap][ci] = sum over the chunk's pixels p of dy[p][co] x[p shifted by tap][ci]
-// grid ((Co/16) * (Ci/16) * 9, nchunk), block 64.
-__global__ __launch_bounds__(64) void conv3x3_wgrad_kernel(const bf16 *__restrict__ dy, const bf16 *__restrict__ x,
-                                                           float *__restrict__ part, int N, int H, int W, int Ci,
-                                                           int Co, int chunk) {
-  const int lane = threadIdx.x, m = lane & 15, kq = lane >> 4;
-  int t = blockIdx.x;
-  const int tap = t % 9;
-  t /= 9;
-  const int nci = Ci / 16;
-  const int ci0 = (t % nci) * 16, co0 = (t / nci) * 16;
-  const int ky = tap / 3, kx = tap % 3;
-  const long long total = (long long)N * H * W;
-  const long long pb = (long long)blockIdx.y * chunk;
-  const long long pe = pb + chunk < total ? pb + chunk : total;
-  f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-  for (long long p0 = pb; p0 < pe; p0 += 16) {
-    bf16x4_t a, bv;
+// Transpose of an 8 x 8 block of bf16: v[p] holds channels 0..7 of pixel p,
+// o[c] receives pixels 0..7 of channel c.
+__device__ inline uint32_t dword_of(const uint4 &v, int d) { return d == 0 ? v.x : d == 1 ? v.y : d == 2 ? v.z : v.w; }
+
+__device__ inline void transpose8x8(const uint4 (&v)[8], uint4 (&o)[8]) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const long long p = p0 + 4 * kq + i;
-      bf16 av = 0, xv = 0;
-      if (p < pe) {
-        av = dy[p * Co + co0 + m];
-        const int xq = (int)(p % W);
-        const long long r = p / W;
-        const int yq = (int)(r % H);
-        const long long nq = r / H;
-        const int ys = yq + ky - 1, xs = xq + kx - 1;
-        if (ys >= 0 && ys < H && xs >= 0 && xs < W) xv = x[((nq * H + ys) * W + xs) * Ci + ci0 + m];
-      }
-      a[i] = (short)av;
-      bv[i] = (short)xv;
+  for (int d = 0; d < 4; ++d) {  // channels 2d, 2d+1 sit in dword d of every pixel
+    uint32_t lo[4], hi[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t a = dword_of(v[2 * e], d), b = dword_of(v[2 * e + 1], d);
+      lo[e] = (a & 0xFFFFu) | (b << 16);
+      hi[e] = (a >> 16) | (b & 0xFFFF0000u);
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc, 0, 0, 0);
+    o[2 * d] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+    o[2 * d + 1] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
   }
-  // lane holds D[4 kq + i][m]: output channel co0 + 4 kq + i, input channel ci0 + m
+}
+
+// Weight gradient, an implicit GEMM with the pixels as K:
+// part[slice][co][tap][ci] = sum over the slice's pixels p of dy[p][co] x[p shifted by tap][ci].
+// A workgroup owns COT output x CIT input channels and a run of TR x TC pixel
+// tiles.  Per tile it stages dy (COT channels x TR*TC pixels) and the input
+// with one halo row above and below and eight columns either side
+// (CIT x (TR+2) x (TC+16)) in LDS, channel-major: the pixel-major tensors are
+// transposed 8 x 8 in registers on the way, so the eight K values of a lane
+// (eight consecutive pixels of a row) are one aligned 16-byte read.  The three
+// horizontal taps come out of the same three aligned reads per input row,
+// shifted by one bf16 with v_alignbyte.  Wave v takes input-channel block
+// v % (CIT/16) and every KS-th K step (KS = 64/CIT); its 16x16 products for
+// all COT/16 output blocks and the nine taps stay in registers over the whole
+// tile run, and it writes them as its own slice (chunk * KS + v / (CIT/16)),
+// so the fixed-order sum over the slices is deterministic.  The waves of input
+// block 0 also form the bias gradient, sum_p dy[p][co], as a product of the
+// same dy fragments with a matrix of ones, into bpart[slice][co].
+template <int TR, int TC, int COT, int CIT>
+__global__ __launch_bounds__(256, 2) void conv3x3_wgrad_kernel(const bf16 *__restrict__ dy,
+                                                               const bf16 *__restrict__ x, float *__restrict__ part,
+                                                               float *__restrict__ bpart, int N, int H, int W, int Ci,
+                                                               int Co, int tiles_per_chunk) {
+  constexpr int NA = COT / 16, NCB = CIT / 16, KS = 4 / NCB;
+  constexpr int TP = TR * TC, DYP = TP + 8;                    // pixels per tile; LDS pitch of a dy channel
+  constexpr int HR = TR + 2, HCW = TC + 16, HB = HCW / 8;      // halo rows, columns, 8-column blocks
+  constexpr int XP = HR * HCW + 8;                             // LDS pitch of an input channel
+  constexpr int RUNS = TP / 8, RPR = TC / 8, KSTEPS = RUNS / 4;
+  static_assert(TC % 8 == 0 && RUNS % 4 == 0, "whole K steps per tile");
+  static_assert((DYP / 8) % 2 == 1 && (XP / 8) % 2 == 1, "odd multiples of 16 bytes spread the 16 rows over the banks");
+  __shared__ __align__(16) bf16 sdy[COT * DYP];
+  __shared__ __align__(16) bf16 sx[CIT * XP];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
+  const int cb = wave % NCB, ks = wave / NCB;
+  const int ncit = Ci / CIT;
+  const int co0 = (blockIdx.x / ncit) * COT, ci0 = (blockIdx.x % ncit) * CIT;
+  const int ntx = (W + TC - 1) / TC, nty = (H + TR - 1) / TR;
+  const int ntiles = N * ntx * nty;
+  const int t0 = blockIdx.y * tiles_per_chunk;
+  const int t1 = t0 + tiles_per_chunk < ntiles ? t0 + tiles_per_chunk : ntiles;
+  const bool do_bias = (blockIdx.x % ncit) == 0 && cb == 0;
+  const uint4 ones = make_uint4(0x3F803F80u, 0x3F803F80u, 0x3F803F80u, 0x3F803F80u);  // bf16 1.0
+  f32x4_t acc[NA][9], bacc[NA];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-    part[(((size_t)blockIdx.y * Co + co0 + 4 * kq + i) * 9 + tap) * Ci + ci0 + m] = acc[i];
-}
-
-// dw[i] = sum over chunks of part[chunk][i] (fixed order)
-__global__ void sum_chunks_kernel(const float *__restrict__ part, float *__restrict__ dw, long long n, int nchunk) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float s = 0.0f;
-  for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * n + i];
-  dw[i] = s;
-}
-
-// db[co] = sum_p dy[p][co]; one block per channel, fixed-order tree.
-__global__ __launch_bounds__(256) void bias_grad_kernel(const bf16 *__restrict__ dy, float *__restrict__ db,
-                                                        long long npix, int Co) {
-  __shared__ float sh[256];
-  const int co = blockIdx.x;
-  float s = 0.0f;
-  for (long long p = threadIdx.x; p < npix; p += 256) s += bf2f(dy[p * Co + co]);
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
+  for (int ia = 0; ia < NA; ++ia) {
+    bacc[ia] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[ia][t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   }
-  if (threadIdx.x == 0) db[co] = sh[0];
+  for (int t = t0; t < t1; ++t) {
+    const int tx0 = (t % ntx) * TC, ty0 = ((t / ntx) % nty) * TR, n = t / (ntx * nty);
+    __syncthreads();  // the previous tile's fragments have been read
+    for (int it = tid; it < RUNS * (COT / 8); it += 256) {
+      const int cg = it % (COT / 8), run = it / (COT / 8);
+      const int y = ty0 + run / RPR, xb = tx0 + (run % RPR) * 8;
+      uint4 v[8], o[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        v[j] = make_uint4(0u, 0u, 0u, 0u);
+        if (y < H && xb + j < W) v[j] = *(const uint4 *)(dy + (((size_t)n * H + y) * W + xb + j) * Co + co0 + 8 * cg);
+      }
+      transpose8x8(v, o);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) *(uint4 *)(sdy + (8 * cg + c) * DYP + run * 8) = o[c];
+    }
+    for (int it = tid; it < HR * HB * (CIT / 8); it += 256) {
+      const int cg = it % (CIT / 8), rb = it / (CIT / 8);
+      const int hr = rb / HB, hb = rb % HB;
+      const int y = ty0 + hr - 1, xb = tx0 - 8 + hb * 8;
+      uint4 v[8], o[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        v[j] = make_uint4(0u, 0u, 0u, 0u);
+        if (y >= 0 && y < H && xb + j >= 0 && xb + j < W)
+          v[j] = *(const uint4 *)(x + (((size_t)n * H + y) * W + xb + j) * Ci + ci0 + 8 * cg);
+      }
+      transpose8x8(v, o);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) *(uint4 *)(sx + (8 * cg + c) * XP + hr * HCW + hb * 8) = o[c];
+    }
+    __syncthreads();
+    for (int k = ks; k < KSTEPS; k += KS) {
+      const int run = 4 * k + g;
+      const int r = run / RPR, c8 = run % RPR;
+      uint4 a[NA];
+#pragma unroll
+      for (int ia = 0; ia < NA; ++ia) a[ia] = *(const uint4 *)(sdy + (16 * ia + m) * DYP + run * 8);
+      if (do_bias) {
+#pragma unroll
+        for (int ia = 0; ia < NA; ++ia) bacc[ia] = mfma_16x16x32(a[ia], ones, bacc[ia]);
+      }
+      // halo column 8 (c8 + 1) + j holds the input under tile column 8 c8 + j
+      const bf16 *xr = sx + (16 * cb + m) * XP + r * HCW + c8 * 8;
+#pragma unroll
+      for (int ky = 0; ky < 3; ++ky) {
+        const uint4 b0 = *(const uint4 *)(xr + ky * HCW);
+        const uint4 b1 = *(const uint4 *)(xr + ky * HCW + 8);
+        const uint4 b2 = *(const uint4 *)(xr + ky * HCW + 16);
+        const uint32_t s1 = __builtin_amdgcn_alignbyte(b1.y, b1.x, 2), s2 = __builtin_amdgcn_alignbyte(b1.z, b1.y, 2),
+                       s3 = __builtin_amdgcn_alignbyte(b1.w, b1.z, 2);
+        const uint4 left = make_uint4(__builtin_amdgcn_alignbyte(b1.x, b0.w, 2), s1, s2, s3);   // columns - 1
+        const uint4 right = make_uint4(s1, s2, s3, __builtin_amdgcn_alignbyte(b2.x, b1.w, 2));  // columns + 1
+#pragma unroll
+        for (int ia = 0; ia < NA; ++ia) {
+          acc[ia][3 * ky] = mfma_16x16x32(a[ia], left, acc[ia][3 * ky]);
+          acc[ia][3 * ky + 1] = mfma_16x16x32(a[ia], b1, acc[ia][3 * ky + 1]);
+          acc[ia][3 * ky + 2] = mfma_16x16x32(a[ia], right, acc[ia][3 * ky + 2]);
+        }
+      }
+    }
+  }
+  // lane holds D[4 g + r][m]: output channel co0 + 16 ia + 4 g + r, input channel ci0 + 16 cb + m
+  const size_t slice = (size_t)blockIdx.y * KS + ks;
+  const int ci = ci0 + 16 * cb + m;
+#pragma unroll
+  for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        part[((slice * Co + co0 + 16 * ia + 4 * g + r) * 9 + tap) * Ci + ci] = acc[ia][tap][r];
+  if (do_bias && m == 0) {
+#pragma unroll
+    for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bpart[slice * Co + co0 + 16 * ia + 4 * g + r] = bacc[ia][r];
+  }
+}
+
+// dw[i] = sum over chunks of part[chunk][i] in a fixed order: lane l (of four
+// per column) adds chunks l, l + 4, l + 8, ... in turn, eight loads in flight,
+// and the four lane sums are added in lane order.  Block 256 = 64 columns x 4.
+__global__ __launch_bounds__(256) void sum_chunks_kernel(const float *__restrict__ part, float *__restrict__ dw,
+                                                         long long n, int nchunk) {
+  __shared__ float sh[4][64];
+  const int tx = threadIdx.x & 63, l = threadIdx.x >> 6;
+  const long long i = (long long)blockIdx.x * 64 + tx;
+  float s = 0.0f;
+  if (i < n) {
+    int c = l;
+    for (; c + 28 < nchunk; c += 32) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(c + 4 * u) * n + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; c < nchunk; c += 4) s += part[(size_t)c * n + i];
+  }
+  sh[l][tx] = s;
+  __syncthreads();
+  if (l == 0 && i < n) dw[i] = ((sh[0][tx] + sh[1][tx]) + sh[2][tx]) + sh[3][tx];
 }
 
 // ------------------------------------------------------------ element-wise
@@ -578,32 +706,33 @@ bf16 *tensor(lbtp_nn *nn, int slot, size_t elems, int *rc) {
   return t.p;
 }
 
-template <int TR, int TC, int TN, int CK>
+template <int TN, int CK>
 void conv_launch(hipStream_t st, const bf16 *in, const bf16 *w, const float *b, void *out, int N, int H, int W,
                  int Ci, int Co, bool relu, bool f32) {
-  const dim3 g((unsigned)(N * ((H + TR - 1) / TR) * ((W + TC - 1) / TC)), (unsigned)(Co / TN));
-  hipLaunchKernelGGL((conv3x3_kernel<TR, TC, TN, CK>), g, dim3(256), 0, st, in, w, b, out, H, W, Ci, Co, (int)relu,
-                     (int)f32);
+  // tile width: of 8, 16, 32 and 64 columns the one that wastes the fewest, the wider on a tie
+  int tcs = 6, waste = (W + 63) / 64 * 64 - W;
+  for (int t = 5; t >= 3; --t) {
+    const int wt = ((W + (1 << t) - 1) >> t << t) - W;
+    if (wt < waste) {
+      waste = wt;
+      tcs = t;
+    }
+  }
+  const int P = TN == 64 ? 256 : 512;
+  const int ntx = (W + (1 << tcs) - 1) >> tcs, nty = (N * H + (P >> tcs) - 1) / (P >> tcs);
+  const dim3 g((unsigned)(ntx * nty), (unsigned)(Co / TN));
+  hipLaunchKernelGGL((conv3x3_kernel<TN, CK>), g, dim3(256), 0, st, in, w, b, out, N * H, H, W, Ci, Co, tcs,
+                     (int)relu, (int)f32);
 }
 
-// Tiles of 256 pixels for 64 output channels and of 512 pixels for 32 or 16
-// (64 accumulators per lane either way); 64 columns wide on grids at least 64
-// wide, 16 columns on narrower ones.  Input channels in chunks of 32, or of
-// 16 when the channel count is an odd multiple of 16.
+// 64 output channels per workgroup where they divide Co, else 32, else 16;
+// input channels in chunks of 32, or of 16 when Ci is an odd multiple of 16.
 template <int CK>
 void conv_dispatch(hipStream_t st, const bf16 *in, const bf16 *w, const float *b, void *out, int N, int H, int W,
                    int Ci, int Co, bool relu, bool f32) {
-  const bool wide = W >= 64;
-  if (Co % 64 == 0) {
-    if (wide) conv_launch<4, 64, 64, CK>(st, in, w, b, out, N, H, W, Ci, Co, relu, f32);
-    else conv_launch<16, 16, 64, CK>(st, in, w, b, out, N, H, W, Ci, Co, relu, f32);
-  } else if (Co % 32 == 0) {
-    if (wide) conv_launch<8, 64, 32, CK>(st, in, w, b, out, N, H, W, Ci, Co, relu, f32);
-    else conv_launch<32, 16, 32, CK>(st, in, w, b, out, N, H, W, Ci, Co, relu, f32);
-  } else {
-    if (wide) conv_launch<8, 64, 16, CK>(st, in, w, b, out, N, H, W, Ci, Co, relu, f32);
-    else conv_launch<32, 16, 16, CK>(st, in, w, b, out, N, H, W, Ci, Co, relu, f32);
-  }
+  if (Co % 64 == 0) conv_launch<64, CK>(st, in, w, b, out, N, H, W, Ci, Co, relu, f32);
+  else if (Co % 32 == 0) conv_launch<32, CK>(st, in, w, b, out, N, H, W, Ci, Co, relu, f32);
+  else conv_launch<16, CK>(st, in, w, b, out, N, H, W, Ci, Co, relu, f32);
 }
 
 int conv_fwd(lbtp_nn *nn, const bf16 *in, const bf16 *w, const float *b, void *out, int N, int H, int W, int Ci,
@@ -713,6 +842,51 @@ int forward(lbtp_nn *nn, const float *lnK, const float *S, int N, int H, int W, 
   return LBTP_OK;
 }
 
+template <int TR, int TC, int COT, int CIT>
+int wgrad_launch(lbtp_nn *nn, const bf16 *dy, const bf16 *x, int N, int H, int W, int Ci, int Co, int *slices) {
+  const int ntiles = N * ((H + TR - 1) / TR) * ((W + TC - 1) / TC);
+  const int pairs = (Co / COT) * (Ci / CIT);
+  // about 512 workgroups, each over at least 4 tiles
+  int nchunk = 512 / pairs;
+  if (nchunk > ntiles / 4) nchunk = ntiles / 4;
+  if (nchunk < 1) nchunk = 1;
+  const int tpc = (ntiles + nchunk - 1) / nchunk;
+  nchunk = (ntiles + tpc - 1) / tpc;
+  const int ks = 64 / CIT;
+  *slices = nchunk * ks;
+  const size_t nw = (size_t)Co * 9 * Ci;
+  // weight partials [slices][nw], then bias partials [slices][Co]
+  int rc = ensure((void **)&nn->part, &nn->part_cap, (size_t)*slices * (nw + Co) * sizeof(float));
+  if (rc) return rc;
+  hipLaunchKernelGGL((conv3x3_wgrad_kernel<TR, TC, COT, CIT>), dim3((unsigned)pairs, (unsigned)nchunk), dim3(256), 0,
+                     nn->stream, dy, x, nn->part, nn->part + (size_t)*slices * nw, N, H, W, Ci, Co, tpc);
+  NN_TRY(hipGetLastError());
+  return LBTP_OK;
+}
+
+template <int TR, int TC, int COT>
+int wgrad_ci(lbtp_nn *nn, const bf16 *dy, const bf16 *x, int N, int H, int W, int Ci, int Co, int *slices) {
+  if (Ci % 64 == 0) return wgrad_launch<TR, TC, COT, 64>(nn, dy, x, N, H, W, Ci, Co, slices);
+  if (Ci % 32 == 0) return wgrad_launch<TR, TC, COT, 32>(nn, dy, x, N, H, W, Ci, Co, slices);
+  return wgrad_launch<TR, TC, COT, 16>(nn, dy, x, N, H, W, Ci, Co, slices);
+}
+
+template <int TR, int TC>
+int wgrad_co(lbtp_nn *nn, const bf16 *dy, const bf16 *x, int N, int H, int W, int Ci, int Co, int *slices) {
+  if (Co % 64 == 0) return wgrad_ci<TR, TC, 64>(nn, dy, x, N, H, W, Ci, Co, slices);
+  if (Co % 32 == 0) return wgrad_ci<TR, TC, 32>(nn, dy, x, N, H, W, Ci, Co, slices);
+  return wgrad_ci<TR, TC, 16>(nn, dy, x, N, H, W, Ci, Co, slices);
+}
+
+// Weight- and bias-gradient partials of one convolution into nn->part: *slices
+// weight slices, then *slices bias slices.
+// Tiles of 128 pixels: 2 x 64 on grids at least 64 wide, 8 x 16 on narrower ones.
+int wgrad(lbtp_nn *nn, const bf16 *dy, const bf16 *x, int N, int H, int W, int Ci, int Co, int *slices) {
+  if (Ci <= 0 || Ci % 16 || Co <= 0 || Co % 16) return LBTP_EINVAL;
+  if (W >= 64) return wgrad_co<2, 64>(nn, dy, x, N, H, W, Ci, Co, slices);
+  return wgrad_co<8, 16>(nn, dy, x, N, H, W, Ci, Co, slices);
+}
+
 // Gradient of one convolution: given d(output) after the activation in dy (may
 // be modified), accumulate dw/db and return d(input) in dx (if non-null).
 int conv_bwd(lbtp_nn *nn, int li, const Tape &tp, bf16 *dy, bf16 *dx, int N) {
@@ -723,18 +897,16 @@ int conv_bwd(lbtp_nn *nn, int li, const Tape &tp, bf16 *dy, bf16 *dx, int N) {
     hipLaunchKernelGGL(relu_mask_kernel, GRID1(npix * l.cop), 0, nn->stream, dy, tp.y[li], npix * l.cop);
     NN_TRY(hipGetLastError());
   }
-  // weight gradient, split over pixel chunks
-  const int chunk = 4096;
-  const int nchunk = (int)((npix + chunk - 1) / chunk);
+  // weight and bias gradients: partial sums per (pixel chunk, K slice), added in a fixed order
   const size_t nw = (size_t)l.cop * 9 * l.cip;
-  int rc = ensure((void **)&nn->part, &nn->part_cap, (size_t)nchunk * nw * sizeof(float));
+  int slices = 0;
+  int rc = wgrad(nn, dy, tp.x[li], N, H, W, l.cip, l.cop, &slices);
   if (rc) return rc;
-  hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3((unsigned)((l.cop / 16) * (l.cip / 16) * 9), (unsigned)nchunk),
-                     dim3(64), 0, nn->stream, dy, tp.x[li], nn->part, N, H, W, l.cip, l.cop, chunk);
+  hipLaunchKernelGGL(sum_chunks_kernel, dim3((unsigned)((nw + 63) / 64)), dim3(256), 0, nn->stream, nn->part, l.dw,
+                     (long long)nw, slices);
   NN_TRY(hipGetLastError());
-  hipLaunchKernelGGL(sum_chunks_kernel, GRID1((long long)nw), 0, nn->stream, nn->part, l.dw, (long long)nw, nchunk);
-  NN_TRY(hipGetLastError());
-  hipLaunchKernelGGL(bias_grad_kernel, dim3(l.cop), dim3(256), 0, nn->stream, dy, l.db, npix, l.cop);
+  hipLaunchKernelGGL(sum_chunks_kernel, dim3((unsigned)((l.cop + 63) / 64)), dim3(256), 0, nn->stream,
+                     nn->part + (size_t)slices * nw, l.db, (long long)l.cop, slices);
   NN_TRY(hipGetLastError());
   if (dx) {
     if ((rc = conv_fwd(nn, dy, l.wt, nullptr, dx, N, H, W, l.cop, l.cip, false, false))) return rc;
