@@ -33,7 +33,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from paper_1808_07554_amd.profile_sweep import source_digest, sweep_kernel_name  # noqa: E402
+from paper_1808_07554_amd.profile_sweep import (METHOD_FLOPS_PER_NODE_SWEEP, source_digest,  # noqa: E402
+                                                 sweep_kernel_name)
 
 HBM_PEAK_GBS = 8000.0
 # vector fp32 rate without packed math (off in this build): one fused
@@ -43,13 +44,8 @@ HBM_PEAK_GBS = 8000.0
 # FMA per population; the other operations are single adds or multiplies.
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 # flops the method itself does in one plain pressure sweep per node (eq. 3-1,
-# eq. 3-9a): D2Q5: P = sum of 4 populations / (1 - w0) (3 adds, 1 multiply),
-# w1 P (1 multiply), 4 BGK relaxations f - (f - w P)/tau (sub, mul, add each)
-# = 17.  D2Q9: P (7 adds, 1 multiply), w1 P and w2 P (2 multiplies), 8 BGK
-# relaxations = 34.  The pull corrections of the stored deviations,
-# w (P_b(src) - P_b(node)), are a cost of the storage form, not of the
-# method, and are not counted.
-BLOCK_FLOPS_PER_NODE_SWEEP = {"D2Q5": 17, "D2Q9": 34}
+# eq. 3-9a; the count is itemised where it is defined): D2Q5 17, D2Q9 34
+BLOCK_FLOPS_PER_NODE_SWEEP = METHOD_FLOPS_PER_NODE_SWEEP
 # algorithmic bytes of one plain pressure sweep per node: the Q-1 stored
 # deviations read and written, 1/tau_f and the base pressure P_b read
 POP_BYTES = {"fp32": 4, "fp16": 2, "bf16": 2}

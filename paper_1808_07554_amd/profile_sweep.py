@@ -9,7 +9,11 @@ sweep (lbtp_probe_sweeps, 9 sweeps per launch) on the 4096 x 4096 injection
 problem, on D2Q5 or (--lattice D2Q9) on D2Q9.  Then, on any machine:
     python -m paper_1808_07554_amd.profile_sweep --summarize FETCH.csv WRITE.csv OUT.txt [--storage S] [--lattice L]
 converts the counters of the sweep into HBM bytes per launch with the
-copy's bytes-per-count scale and writes a short text summary.
+copy's bytes-per-count scale and writes a short text summary, and
+    python -m paper_1808_07554_amd.profile_sweep --summarize-trace TRACE.csv OUT.txt --title T --command C [--lattice L]
+turns the kernel trace of a bench run (rocprofv3 --kernel-trace --output-format
+csv) into a per-kernel table with the blocked sweep's achieved rate against the
+vector ALU peak.
 """
 import argparse
 import csv
@@ -22,6 +26,19 @@ COPY_BYTES = 1 << 30
 # the sources the sweep kernels are compiled from
 SWEEP_SOURCES = ("lbtp_kernels.hip", "lbtp_device.h", "lbtp_internal.h", "lbtp_block.hip", "lbtp_block.h")
 SWEEP_SOURCES_Q9 = ("lbtp_d2q9.hip", "lbtp_device.h", "lbtp_internal.h")
+
+
+# flops the method itself does in one plain pressure sweep per node (eq. 3-1,
+# eq. 3-9a): D2Q5: P = sum of 4 populations / (1 - w0) (3 adds, 1 multiply),
+# w1 P (1 multiply), 4 BGK relaxations f - (f - w P)/tau (sub, mul, add each)
+# = 17.  D2Q9: P (7 adds, 1 multiply), w1 P and w2 P (2 multiplies), 8 BGK
+# relaxations = 34.  The pull corrections of the stored deviations,
+# w (P_b(src) - P_b(node)), are a cost of the storage form, not of the
+# method, and are not counted.
+METHOD_FLOPS_PER_NODE_SWEEP = {"D2Q5": 17, "D2Q9": 34}
+# one fp32 fused multiply-add (two flops) per lane per clock, 64 lanes per
+# compute unit, 256 compute units at 2.4 GHz
+ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 
 
 def sweep_sources(lattice="D2Q5"):
@@ -134,6 +151,52 @@ source_sha256: {sha}  (csrc/{", csrc/".join(sweep_sources(lattice))})
     print(text)
 
 
+def _short_name(name):
+    """Kernel name without return type, namespaces and argument list."""
+    name = name.replace("void ", "").replace("lbtp::", "").replace("(anonymous namespace)::", "")
+    depth = 0
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return name[:i]
+    return name
+
+
+def summarize_trace(trace_csv, out_txt, title, command, lattice="D2Q5", n=4096, sweeps_per_launch=9):
+    with open(trace_csv) as f:
+        rows = list(csv.DictReader(f))
+    agg = {}
+    for r in rows:
+        us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        agg.setdefault(_short_name(r["Kernel_Name"]), []).append(us)
+    total = sum(sum(v) for v in agg.values())
+    lines = [title, f"command: {command}", "",
+             f"{'kernel':66s} {'calls':>6s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} {'pct':>6s}"]
+    for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"{k[:66]:66s} {len(v):6d} {sum(v) / len(v):9.2f} {min(v):9.2f} {max(v):9.2f} "
+                     f"{100 * sum(v) / total:6.2f}")
+    kname = sweep_kernel_name("fp32", 2, lattice, sweeps_per_launch)
+    blk = [v for k, v in agg.items() if k.split("<")[0] == kname]
+    if blk:
+        d = blk[0]
+        avg = sum(d) / len(d)
+        fl = METHOD_FLOPS_PER_NODE_SWEEP[lattice] * n * n * sweeps_per_launch
+        lines += ["", f"{kname} runs {sweeps_per_launch} plain pressure sweeps per launch; average launch "
+                  f"{avg:.1f} us = {avg / sweeps_per_launch:.2f} us per sweep;",
+                  f"{METHOD_FLOPS_PER_NODE_SWEEP[lattice]} method flops per node and sweep (eq. 3-1, eq. 3-9a) x "
+                  f"{n * n} nodes x {sweeps_per_launch} = {fl / 1e9:.2f} GFLOP per launch",
+                  f"-> {fl / (avg * 1e-6) / 1e12:.2f} TFLOP/s against {ALU_PEAK_TFLOPS:.2f} TFLOP/s (one fp32 fused "
+                  "multiply-add per lane and clock, 64 lanes per CU, 256 CUs, 2.4 GHz), frac "
+                  f"{fl / (avg * 1e-6) / 1e12 / ALU_PEAK_TFLOPS:.3f}"]
+    text = "\n".join(lines) + "\n"
+    with open(out_txt, "w") as f:
+        f.write(text)
+    print(text)
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--storage", default="fp32")
@@ -141,10 +204,14 @@ if __name__ == "__main__":
     ap.add_argument("--launches", type=int, default=20)
     ap.add_argument("--lattice", default="D2Q5", choices=["D2Q5", "D2Q9"])
     ap.add_argument("--summarize", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_TXT"))
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_CSV", "OUT_TXT"))
+    ap.add_argument("--title", default="")
     ap.add_argument("--command", default=None, help="command line recorded in the summary (default: the one "
                     "that profiles this module with --storage and --n as given)")
     a = ap.parse_args()
-    if a.summarize:
+    if a.summarize_trace:
+        summarize_trace(*a.summarize_trace, a.title, a.command or "", a.lattice, a.n)
+    elif a.summarize:
         args = (f"--storage {a.storage}" + (f" --n {a.n}" if a.n != 4096 else "")
                 + (f" --lattice {a.lattice}" if a.lattice != "D2Q5" else ""))
         command = a.command or (
