@@ -13,7 +13,10 @@ copy's bytes-per-count scale and writes a short text summary, and
     python -m paper_1808_07554_amd.profile_sweep --summarize-trace TRACE.csv OUT.txt --title T --command C [--lattice L]
 turns the kernel trace of a bench run (rocprofv3 --kernel-trace --output-format
 csv) into a per-kernel table with the blocked sweep's achieved rate against the
-vector ALU peak.
+vector ALU peak, and
+    python -m paper_1808_07554_amd.profile_sweep --summarize-counters CSV OUT.txt [--lattice L]
+summarises one instruction-counter run of this workload (SQ_* and GRBM_*
+counters of one rocprofv3 --pmc pass) for the blocked sweep.
 """
 import argparse
 import csv
@@ -197,6 +200,49 @@ def summarize_trace(trace_csv, out_txt, title, command, lattice="D2Q5", n=4096, 
     print(text)
 
 
+def summarize_counters(csv_path, out_txt, command, lattice="D2Q5", n=4096, sweeps_per_launch=9):
+    """Per-dispatch averages of the counters of one --pmc run over the blocked
+    sweep's launches, and the vector issue they imply: a wave64 fp32
+    instruction occupies its SIMD (16 lanes) for 4 cycles, and the chip has
+    1024 SIMDs; the launch time comes from the same dispatches' timestamps."""
+    kname = sweep_kernel_name("fp32", 2, lattice, sweeps_per_launch)
+    with open(csv_path) as f:
+        rows = [r for r in csv.DictReader(f) if _short_name(r["Kernel_Name"]).split("<")[0] == kname]
+    per = {}
+    times = {}
+    for r in rows:
+        per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        times[r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    dur = sum(times.values()) / len(times)
+    avg = {k: sum(v) / len(v) for k, v in per.items()}
+    lines = [f"Instruction counters of {kname} ({sweeps_per_launch} plain pressure sweeps per launch), "
+             f"heterogeneous injection 2-D {n}x{n}, {lattice}, fp32 storage",
+             f"command: {command}", f"dispatches: {len(times)}, mean duration {dur * 1e6:.1f} us", ""]
+    for k in sorted(avg):
+        lines.append(f"{k:24s} {avg[k]:16.6e} per dispatch")
+    if "SQ_INSTS_VALU" in avg:
+        issue = avg["SQ_INSTS_VALU"] * 4 / 1024 / 2.4e9
+        node_sweeps = n * n * sweeps_per_launch
+        lines += ["", f"vector issue: {avg['SQ_INSTS_VALU']:.3e} wave instructions x 4 cycles / 1024 SIMDs = "
+                  f"{issue * 1e6:.1f} us at 2.4 GHz = {issue / dur:.2f} of the launch",
+                  f"per tile node and sweep: {avg['SQ_INSTS_VALU'] * 64 / node_sweeps:.2f} lane instructions "
+                  f"(method flops {METHOD_FLOPS_PER_NODE_SWEEP[lattice]})"]
+    if "GRBM_GUI_ACTIVE" in avg:
+        # the GRBM counters sum over the 8 XCDs
+        clk = avg["GRBM_GUI_ACTIVE"] / 8 / dur
+        lines.append(f"clock held: GRBM_GUI_ACTIVE / 8 XCDs / duration = {clk / 1e9:.2f} GHz; vector issue at that "
+                     f"clock {avg['SQ_INSTS_VALU'] * 4 / 1024 / clk / dur:.2f} of the launch")
+    if "SQ_BUSY_CYCLES" in avg and "GRBM_GUI_ACTIVE" in avg:
+        lines.append(f"SQ_BUSY_CYCLES / GRBM_GUI_ACTIVE = {avg['SQ_BUSY_CYCLES'] / avg['GRBM_GUI_ACTIVE']:.3f}")
+    if "SQ_ACTIVE_INST_VALU" in avg and "SQ_WAVE_CYCLES" in avg:
+        lines.append(f"SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES = {avg['SQ_ACTIVE_INST_VALU'] / avg['SQ_WAVE_CYCLES']:.3f} "
+                     "(share of a wavefront's cycles spent issuing vector instructions)")
+    text = "\n".join(lines) + "\n"
+    with open(out_txt, "w") as f:
+        f.write(text)
+    print(text)
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--storage", default="fp32")
@@ -205,12 +251,15 @@ if __name__ == "__main__":
     ap.add_argument("--lattice", default="D2Q5", choices=["D2Q5", "D2Q9"])
     ap.add_argument("--summarize", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_TXT"))
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_CSV", "OUT_TXT"))
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("CSV", "OUT_TXT"))
     ap.add_argument("--title", default="")
     ap.add_argument("--command", default=None, help="command line recorded in the summary (default: the one "
                     "that profiles this module with --storage and --n as given)")
     a = ap.parse_args()
     if a.summarize_trace:
         summarize_trace(*a.summarize_trace, a.title, a.command or "", a.lattice, a.n)
+    elif a.summarize_counters:
+        summarize_counters(*a.summarize_counters, a.command or "", a.lattice, a.n)
     elif a.summarize:
         args = (f"--storage {a.storage}" + (f" --n {a.n}" if a.n != 4096 else "")
                 + (f" --lattice {a.lattice}" if a.lattice != "D2Q5" else ""))
