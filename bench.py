@@ -44,7 +44,7 @@ HBM_PEAK_GBS = 8000.0
 # FMA per population; the other operations are single adds or multiplies.
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 # flops the method itself does in one plain pressure sweep per node (eq. 3-1,
-# eq. 3-9a; the count is itemised where it is defined): D2Q5 17, D2Q9 34
+# eq. 3-9a; the count is itemised where it is defined): D2Q5 17, D3Q7 25, D2Q9 34
 BLOCK_FLOPS_PER_NODE_SWEEP = METHOD_FLOPS_PER_NODE_SWEEP
 # algorithmic bytes of one plain pressure sweep per node: the Q-1 stored
 # deviations read and written, 1/tau_f and the base pressure P_b read
@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--iters-per-step", type=int, default=64,
                     help="ensemble: pressure iterations per coupled step (fixed, equal work for batched and sequential)")
     ap.add_argument("--max-iters", type=int, default=20_000_000)
+    ap.add_argument("--sweep-block", type=int, default=0,
+                    help="plain sweeps per blocked launch (0: the library default for the lattice)")
     ap.add_argument("--burst", type=int, default=30, help="launches of the dominant kernel timed for the roofline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -231,7 +233,7 @@ def main():
         phi = torch.from_numpy(inputs.f32(fl["phi"]).ravel()).to(dev)
         P0 = torch.from_numpy(inputs.f32(fl["P0"]).ravel()).to(dev)
         S0 = torch.from_numpy(inputs.f32(fl["S0"]).ravel()).to(dev)
-        solver = lbtp.from_problem(params, m=a.m, storage=storage)
+        solver = lbtp.from_problem(params, m=a.m, storage=storage, sweep_block=a.sweep_block)
         solver.set_fields(K, phi)
         solver.set_state(P0, S0)
         del K, phi, P0, S0

@@ -130,11 +130,12 @@ typedef struct lbtp_params {
                                   cap_B K lambda_n f_w to Ds (eq. 2-16), so D_s and tau_g
                                   vary with S and K from node to node; 0 = constant Ds. */
   int sweep_block;             /* plain pressure sweeps fused into one launch inside the
-                                  captured chunks of m sweeps (temporal blocking with the
-                                  region in registers; D2Q5 and D2Q9, float32 results
-                                  bitwise unchanged; 16-bit storage rounds once per launch):
-                                  0 = library default (9 on D2Q5 and D2Q9, none on D3Q7),
-                                  1 = one sweep per launch, or an odd number 3..23 */
+                                  captured chunks of m sweeps (temporal blocking: the region
+                                  in registers on D2Q5 and D2Q9, streaming along z on D3Q7;
+                                  float32 results bitwise unchanged; 16-bit storage rounds
+                                  once per launch): 0 = library default (9 on D2Q5 and D2Q9,
+                                  3 on D3Q7), 1 = one sweep per launch, or an odd number
+                                  3..23 (D3Q7: 3); LBTP_EINVAL otherwise */
   int collision;               /* lbtp_collision of the pressure lattice */
   double mrt_rates[3];         /* MRT: s0, s_q, s_p (unused for BGK) */
 } lbtp_params;

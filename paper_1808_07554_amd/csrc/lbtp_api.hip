@@ -105,8 +105,8 @@ int validate(const lbtp_params *p) {
   if (p->coef_model != LBTP_COEF_QUADRATIC_KR && p->coef_model != LBTP_COEF_RATIONAL) return LBTP_EINVAL;
   if (!(p->cap_B >= 0.0) || !isfinite(p->cap_B)) return LBTP_EINVAL;
   if (p->coef_model == LBTP_COEF_QUADRATIC_KR && (!(p->mu_w > 0) || !(p->mu_n > 0))) return LBTP_EINVAL;
-  if (p->sweep_block < 0 || (p->sweep_block > 1 && (p->sweep_block % 2 == 0 || p->lattice == LBTP_D3Q7)))
-    return LBTP_EINVAL;
+  if (p->sweep_block < 0 || (p->sweep_block > 1 && p->sweep_block % 2 == 0)) return LBTP_EINVAL;
+  if (p->lattice == LBTP_D3Q7 && p->sweep_block > 1 && !block_sweeps_supported_3d(p->sweep_block)) return LBTP_EINVAL;
   if (p->collision != LBTP_COLLISION_BGK && p->collision != LBTP_COLLISION_MRT) return LBTP_EINVAL;
   if (p->collision == LBTP_COLLISION_MRT) {
     if (p->lattice != LBTP_D2Q9) return LBTP_EINVAL;
@@ -340,7 +340,7 @@ int lbtp_init(const lbtp_params *p, lbtp_ctx **out) {
   c->nblk = nblocks(c->ncell);
   fill_kc(c);
   {
-    const int H = p->sweep_block == 0 ? (p->lattice == LBTP_D3Q7 ? 1 : 9) : p->sweep_block;
+    const int H = p->sweep_block == 0 ? (p->lattice == LBTP_D3Q7 ? 3 : 9) : p->sweep_block;
     if (H > 1) {
       if (!block_sweeps_supported(c->lk, c->kc, H)) {
         delete c;

@@ -37,12 +37,14 @@ void block_launch(const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, const fl
 
 int block_sweeps_supported(int dim, const KC &kc, int H) {
   if (dim == kD2Q9) return block_sweeps_supported_q9(H);
+  if (dim == 3) return block_sweeps_supported_3d(H);
   return dim == 2 && kc.nz == 1 && H >= 3 && H % 2 == 1 && kBX - 2 * H >= 16 && kUseW * kUseRW - 2 * H >= 16;
 }
 
 hipError_t launch_f_block(int dim, int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb,
                           const float *itau, const float *Fp, const Ctl *ctl, long long k, int H, hipStream_t s) {
   if (dim == kD2Q9) return launch_f_block_q9(storage, kc, fin, fout, Pb, itau, Fp, ctl, k, H, s);
+  if (dim == 3) return launch_f_block_3d(storage, kc, fin, fout, Pb, itau, Fp, ctl, k, H, s);
   switch (storage) {
     case LBTP_FP16_DEV: block_launch<_Float16, kUseW, kUseRW>(kc, fin, fout, Pb, itau, Fp, ctl, k, H, s); break;
     case LBTP_BF16_DEV: block_launch<bf16_t, kUseW, kUseRW>(kc, fin, fout, Pb, itau, Fp, ctl, k, H, s); break;

@@ -104,13 +104,17 @@ hipError_t launch_f_sweep(int dim, int storage, const KC &kc, FPtrs fin, FPtrs f
                           float *Pb_out, const float *itau, const float *Fp, double *partials, const Ctl *ctl,
                           long long k, int local, int mode, hipStream_t s);
 // H consecutive plain pressure sweeps (no re-basing, no stopping-rule terms)
-// in one launch, sweeps k .. k + H - 1 (temporal blocking, the region in
-// registers; D2Q5 and D2Q9, H odd); fin holds the state before sweep k, fout
-// receives it after.  dim is the lattice kind (2, 3 or kD2Q9).
+// in one launch, sweeps k .. k + H - 1 (temporal blocking: the region in
+// registers on D2Q5 and D2Q9, streaming along z on D3Q7; H odd); fin holds
+// the state before sweep k, fout receives it after.  dim is the lattice kind
+// (2, 3 or kD2Q9).
 int block_sweeps_supported(int dim, const KC &kc, int H);
 hipError_t launch_f_block(int dim, int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb,
                           const float *itau, const float *Fp, const Ctl *ctl, long long k, int H, hipStream_t s);
 int block_sweeps_supported_q9(int H);
+int block_sweeps_supported_3d(int H);
+hipError_t launch_f_block_3d(int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, const float *itau,
+                             const float *Fp, const Ctl *ctl, long long k, int H, hipStream_t s);
 hipError_t launch_f_block_q9(int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, const float *itau,
                              const float *Fp, const Ctl *ctl, long long k, int H, hipStream_t s);
 // Check of the stopping rule at iteration ctl->kcheck + m (device-side

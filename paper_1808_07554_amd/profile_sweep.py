@@ -34,11 +34,12 @@ SWEEP_SOURCES_Q9 = ("lbtp_d2q9.hip", "lbtp_device.h", "lbtp_internal.h")
 # flops the method itself does in one plain pressure sweep per node (eq. 3-1,
 # eq. 3-9a): D2Q5: P = sum of 4 populations / (1 - w0) (3 adds, 1 multiply),
 # w1 P (1 multiply), 4 BGK relaxations f - (f - w P)/tau (sub, mul, add each)
-# = 17.  D2Q9: P (7 adds, 1 multiply), w1 P and w2 P (2 multiplies), 8 BGK
-# relaxations = 34.  The pull corrections of the stored deviations,
+# = 17.  D3Q7: P (5 adds, 1 multiply), w1 P, 6 BGK relaxations = 25.  D2Q9:
+# P (7 adds, 1 multiply), w1 P and w2 P (2 multiplies), 8 BGK relaxations
+# = 34.  The pull corrections of the stored deviations,
 # w (P_b(src) - P_b(node)), are a cost of the storage form, not of the
 # method, and are not counted.
-METHOD_FLOPS_PER_NODE_SWEEP = {"D2Q5": 17, "D2Q9": 34}
+METHOD_FLOPS_PER_NODE_SWEEP = {"D2Q5": 17, "D3Q7": 25, "D2Q9": 34}
 # one fp32 fused multiply-add (two flops) per lane per clock, 64 lanes per
 # compute unit, 256 compute units at 2.4 GHz
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
@@ -60,10 +61,13 @@ def source_digest(lattice="D2Q5"):
 
 def sweep_kernel_name(storage, dim=2, lattice=None, sweeps_per_launch=9):
     """The kernel that runs the plain pull-form pressure sweeps of a full
-    chunk with nx % 4 == 0: the blocked kernels on D2Q5 and D2Q9 (several
-    sweeps per launch), else the 4-nodes-per-thread sweep."""
+    chunk with nx % 4 == 0: the blocked kernels (several sweeps per launch:
+    the region kernels on D2Q5 and D2Q9, the z-streaming one on D3Q7), else
+    the 4-nodes-per-thread sweep."""
     if lattice == "D2Q9":
         return "q9_f_block_kernel" if sweeps_per_launch > 1 else "q9_f_sweep_vec_kernel"
+    if dim == 3 and sweeps_per_launch > 1:
+        return "f_zstream_kernel"
     if dim == 2 and sweeps_per_launch > 1:
         return "f_block_kernel"
     return "f_sweep_vec_kernel"

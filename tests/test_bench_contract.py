@@ -29,7 +29,8 @@ def test_algorithmic_bytes_per_node():
 def test_method_flops_per_node_sweep():
     # D2Q5: P (3 adds, 1 mul), w1 P (1 mul), 4 x BGK (sub, mul, add);
     # D2Q9: P (7 adds, 1 mul), w1 P, w2 P, 8 x BGK
-    assert bench.BLOCK_FLOPS_PER_NODE_SWEEP == {"D2Q5": 3 + 1 + 1 + 4 * 3, "D2Q9": 7 + 1 + 2 + 8 * 3}
+    assert bench.BLOCK_FLOPS_PER_NODE_SWEEP == {"D2Q5": 3 + 1 + 1 + 4 * 3, "D3Q7": 5 + 1 + 1 + 6 * 3,
+                                                "D2Q9": 7 + 1 + 2 + 8 * 3}
 
 
 def test_alu_peak_from_unit_counts():

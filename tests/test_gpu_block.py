@@ -1,6 +1,6 @@
 """Temporal blocking of the plain pressure sweeps (several sweeps per launch,
-the region held in registers; D2Q5 and D2Q9) against one sweep per launch,
-through the C ABI.
+the region held in registers on D2Q5 and D2Q9, streaming along z on D3Q7)
+against one sweep per launch, through the C ABI.
 
 With float32 storage the blocked launches perform the same arithmetic in the
 same order, so populations, pressure and saturation must agree bitwise: on
@@ -187,3 +187,82 @@ def test_q9_blocked_16bit_within_format_bound(storage):
         err = float(np.abs(ref[k] - got[k]).max())
         print("D2Q9", storage, k, f"{err:.2e}")
         assert err <= 16 * ur, (storage, k, err)
+
+
+# ----------------------------------------------------------------- D3Q7
+# The z-streaming kernel (H = 3): columns of 64 x 16 nodes walking segments of
+# z, walls applied in place on every face.
+def _run3(shape, bcs, sweep_block, storage="fp32", Fp=False, wall_face=None, iters=(130, 67)):
+    nx, ny, nz = shape
+    params, _ = inputs.injection_problem(shape, 1.0, 4.0, 11, 12)
+    params = dict(params, bc_f=bcs[0], bc_g=bcs[1])
+    fshape = (nz, ny, nx)
+    K = f32(np.exp(inputs.gaussian_random_field(fshape, 3.0, nx + ny + nz)) * params["mu_n"] / 8)
+    phi = f32(inputs.uniform_field(fshape, 0.15, 0.3, 7))
+    P0, S0 = (f32(a) for a in smooth_state(fshape, 5))
+    fp = f32(mean_free(np.sin(np.arange(nx * ny * nz) * 0.37)) * 1e-3).reshape(fshape) if Fp else None
+    g = gpu_solver(params, m=64, storage=storage, sweep_block=sweep_block)
+    g.set_fields(K, phi, Fp=fp)
+    g.set_state(P0, S0)
+    if wall_face is not None:
+        n_face = nx * ny * nz // shape[wall_face // 2]
+        g.set_wall_values(wall_face, P=f32(1.0 + 0.1 * np.cos(np.arange(n_face) * 0.2)))
+    for n, k in enumerate(iters):
+        g.update_coefficients()
+        assert g.pressure_solve(-1.0, k)[0] == k
+        if n + 1 < len(iters):
+            g.saturation_step()
+    f, gg = g.populations()
+    out = dict(f=f.cpu().numpy(), g=gg.cpu().numpy(), P=g.pressure().cpu().numpy(), S=g.saturation().cpu().numpy())
+    g.close()
+    return out
+
+
+WALLS3 = ([("abb", 1.0), ("abb", 0.0)] + [("bb",)] * 4, [("abb", 1.0), ("outflow",)] + [("bb",)] * 4)
+PERIODIC3 = ([("periodic",)] * 6, [("periodic",)] * 6)
+MIXED3 = ([("periodic",), ("periodic",), ("abb", 0.7), ("abb", 0.2), ("bb",), ("abb", 0.5)],
+          [("periodic",), ("periodic",), ("abb", 0.9), ("bb",), ("bb",), ("bb",)])
+ZPER3 = ([("abb", 1.0), ("bb",), ("bb",), ("abb", 0.3), ("periodic",), ("periodic",)],
+         [("abb", 1.0), ("outflow",), ("bb",), ("bb",), ("periodic",), ("periodic",)])
+
+Q7_CASES = [
+    ((40, 30, 20), WALLS3, {}),
+    ((70, 23, 18), PERIODIC3, dict(Fp=True)),      # two columns in x, two in y
+    ((20, 12, 9), PERIODIC3, dict(Fp=True)),       # narrower than the halo: columns wrap
+    ((130, 25, 33), MIXED3, {}),                   # three columns in x, three segments in z
+    ((33, 40, 70), ZPER3, {}),                     # a periodic z walked in five segments
+    ((45, 28, 19), WALLS3, dict(wall_face=0)),     # per-link data on an x face
+    ((45, 28, 19), MIXED3, dict(wall_face=5)),     # ... on a z face
+    ((38, 21, 17), ZPER3, dict(wall_face=3)),      # ... on a y face beside a periodic z
+    ((50, 30, 24), WALLS3, dict(Fp=True)),
+    ((3, 3, 3), WALLS3, dict(wall_face=1)),
+    ((1, 5, 33), MIXED3, {}),
+    ((2, 2, 2), PERIODIC3, dict(Fp=True)),
+]
+
+
+@pytest.mark.parametrize("shape,bcs,kw", Q7_CASES)
+def test_q7_blocked_sweeps_bitwise_equal_single_sweeps(shape, bcs, kw):
+    ref = _run3(shape, bcs, 1, **kw)
+    got = _run3(shape, bcs, 3, **kw)
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), (shape, k, float(np.abs(ref[k] - got[k]).max()))
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_q7_blocked_16bit_within_format_bound(storage):
+    ref = _run3((40, 30, 20), WALLS3, 1, storage=storage)
+    got = _run3((40, 30, 20), WALLS3, 3, storage=storage)
+    ur = UNIT_ROUNDOFF[storage]
+    for k in ("P", "S"):
+        err = float(np.abs(ref[k] - got[k]).max())
+        print("D3Q7", storage, k, f"{err:.2e}")
+        assert err <= 16 * ur, (storage, k, err)
+
+
+def test_q7_block_lengths_other_than_3_rejected():
+    from paper_1808_07554_amd import lbtp
+    params, _ = inputs.injection_problem((16, 16, 16), 1.0, 4.0, 1, 2)
+    for H in (5, 9):
+        with pytest.raises(lbtp.LbtpError):
+            gpu_solver(params, m=64, sweep_block=H)
