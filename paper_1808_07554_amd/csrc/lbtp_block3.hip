@@ -15,7 +15,8 @@
 // plane the level sweeps next, the +z population of the plane below it and
 // the plane above it; the per-plane constants (the base differences
 // w (P_b(src) - P_b(node)) along -x, +-y and -z, 1/tau_f, P_b) sit in rings
-// of 2H planes, and the step loop is unrolled by 2H so that every
+// of 2H planes (the y-neighbours' bases come through LDS with the populations),
+// and the step loop is unrolled by 2H so that every
 // ring slot is named at compile time.  Only the nodes at least H links from
 // the column's cut x and y edges, in the planes of the workgroup's own
 // segment, are written; the neighbouring columns and segments recompute the
@@ -71,6 +72,7 @@ __global__ __launch_bounds__(kZBX * kZW) void f_zstream_kernel(KC kc, FPtrs fin_
   if (ctl->done || k > ctl->kmax) return;   // uniform over the grid
   __shared__ float xup[2][H][kZW][kZBX];    // +y population of each row, per level (step parity)
   __shared__ float xdn[2][H][kZW][kZBX];    // -y population
+  __shared__ float xpb[2][kZW][kZBX];       // P_b of the plane just taken
   const FP<T> fin = typed<T>(fin_), fout = typed<T>(fout_);
   const float is = kc.inv_dev_scale;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -85,8 +87,6 @@ __global__ __launch_bounds__(kZBX * kZW) void f_zstream_kernel(KC kc, FPtrs fin_
   const int uy = ty * (kZW - 2 * H) - H + wv;      // this wavefront's row (unwrapped)
   const int gx = perx ? z_wrap(ux, nx) : z_clamp(ux, nx);
   const int gy = pery ? z_wrap(uy, ny) : z_clamp(uy, ny);
-  const int gym = pery ? z_wrap(uy - 1, ny) : z_clamp(uy - 1, ny);
-  const int gyp = pery ? z_wrap(uy + 1, ny) : z_clamp(uy + 1, ny);
   const int zs = seg * g.seg, ze = min(zs + g.seg, nz);
   const int z0 = zs - H;                                   // plane taken at step 0 (unwrapped)
   const int nsteps = (ze - zs + 3 * H - 1 + M - 1) / M * M;
@@ -102,14 +102,12 @@ __global__ __launch_bounds__(kZBX * kZW) void f_zstream_kernel(KC kc, FPtrs fin_
   // one plane of the state before the launch at this lane's (x, y): every
   // load is issued (clamped to the box where the lane, row or plane lies
   // outside a walled axis; such values never reach a node of the box)
-  auto load_plane = [&](int uz, float (&d)[6], float &pb, float &pbm, float &pbp, float &it) {
+  auto load_plane = [&](int uz, float (&d)[6], float &pb, float &it) {
     const int gz = perz ? z_wrap(uz, nz) : z_clamp(uz, nz);
     const int c = gz * plane + gy * nx + gx;
 #pragma unroll
     for (int j = 0; j < 6; ++j) d[j] = Storage<T>::load(fin.p[j], c, is);
     pb = Pb[c];
-    pbm = Pb[gz * plane + gym * nx + gx];
-    pbp = Pb[gz * plane + gyp * nx + gx];
     it = itau[c];
   };
 
@@ -119,7 +117,7 @@ __global__ __launch_bounds__(kZBX * kZW) void f_zstream_kernel(KC kc, FPtrs fin_
   // per-plane constants: w (P_b(x-1) - P_b), w (P_b(y-1) - P_b), w (P_b(y+1) - P_b),
   // w (P_b(z-1) - P_b), 1/tau_f, P_b (the source, if any, is read where it is added)
   float apx[M], apym[M], apyp[M], apz[M], itr[M], pbr[M];
-  float pfd[PF][6], pfpb[PF], pfm[PF], pfp[PF], pfit[PF];
+  float pfd[PF][6], pfpb[PF], pfit[PF];
 #pragma unroll
   for (int s = 0; s <= H; ++s) {
     up[s] = 0.0f;
@@ -131,7 +129,7 @@ __global__ __launch_bounds__(kZBX * kZW) void f_zstream_kernel(KC kc, FPtrs fin_
     apx[j] = apym[j] = apyp[j] = apz[j] = itr[j] = pbr[j] = 0.0f;
   }
 #pragma unroll
-  for (int q = 0; q < PF; ++q) load_plane(z0 + q, pfd[q], pfpb[q], pfm[q], pfp[q], pfit[q]);
+  for (int q = 0; q < PF; ++q) load_plane(z0 + q, pfd[q], pfpb[q], pfit[q]);
   float pbprev = 0.0f;
 
   for (int base = 0; base < nsteps; base += M) {
@@ -142,23 +140,27 @@ __global__ __launch_bounds__(kZBX * kZW) void f_zstream_kernel(KC kc, FPtrs fin_
       float fresh[6];
 #pragma unroll
       for (int jj = 0; jj < 6; ++jj) fresh[jj] = pfd[q][jj];
-      const float pbv = pfpb[q], pbm = pfm[q], pbpv = pfp[q], itv = pfit[q];
-      load_plane(uz + PF, pfd[q], pfpb[q], pfm[q], pfp[q], pfit[q]);
+      const float pbv = pfpb[q], itv = pfit[q];
+      load_plane(uz + PF, pfd[q], pfpb[q], pfit[q]);
       apx[j] = kc.w1 * (lane_from_left(pbv) - pbv);
-      apym[j] = kc.w1 * (pbm - pbv);
-      apyp[j] = kc.w1 * (pbpv - pbv);
       apz[j] = kc.w1 * (pbprev - pbv);
       itr[j] = itv;
       pbr[j] = pbv;
       pbprev = pbv;
-      // the y-moving populations of every level's plane, for the rows above
-      // and below (two copies by step parity: one barrier per step)
+      // the y-moving populations of every level's plane and the new plane's
+      // base, for the rows above and below (two copies by step parity: one
+      // barrier per step)
 #pragma unroll
       for (int s = 1; s <= H; ++s) {
         xup[par][s - 1][wv][lane] = cur[s][1];
         xdn[par][s - 1][wv][lane] = cur[s][3];
       }
+      xpb[par][wv][lane] = pbv;
       __syncthreads();
+      // w (P_b(y -+ 1) - P_b(y)) of the new plane (first used at the next
+      // step); the outer rows of the column get 0, which reaches no kept node
+      apym[j] = wv > 0 ? kc.w1 * (xpb[par][wv - 1][lane] - pbv) : 0.0f;
+      apyp[j] = wv < kZW - 1 ? kc.w1 * (xpb[par][wv + 1][lane] - pbv) : 0.0f;
       // levels from H down to 1: level s reads fr[s] before level s - 1 replaces it
 #pragma unroll
       for (int s = H; s >= 1; --s) {
@@ -219,17 +221,44 @@ __global__ __launch_bounds__(kZBX * kZW) void f_zstream_kernel(KC kc, FPtrs fin_
   }
 }
 
+// Compute units of the current device (one workgroup of 16 wavefronts fits
+// a compute unit at a time).
+int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cus[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cus[dev] = n;
+  }
+  return cus[dev];
+}
+
+// Columns of 64 - 2H x 16 - 2H output nodes; the number of z segments is the
+// one that minimises rounds of resident workgroups x planes walked per
+// workgroup (its segment plus the 3H - 1 planes of pipeline fill), over
+// segments of at least 16 planes.
 ZGeom zgeom(const KC &kc, int H) {
   ZGeom g;
   g.tiles_x = (kc.nx + kZBX - 2 * H - 1) / (kZBX - 2 * H);
   g.tiles_y = (kc.ny + kZW - 2 * H - 1) / (kZW - 2 * H);
-  // about 2048 workgroups (8 per compute unit), segments of at least 16 planes
-  const int cols = g.tiles_x * g.tiles_y;
-  int segs = (2048 + cols - 1) / cols;
-  const int most = (kc.nz + 15) / 16;
-  if (segs > most) segs = most;
-  if (segs < 1) segs = 1;
-  g.seg = (kc.nz + segs - 1) / segs;
+  const long long cols = (long long)g.tiles_x * g.tiles_y;
+  const int cus = device_cus();
+  int most = (kc.nz + 15) / 16;
+  if (most < 1) most = 1;
+  long long best = -1;
+  g.segs = 1;
+  for (int segs = 1; segs <= most; ++segs) {
+    const int seg = (kc.nz + segs - 1) / segs;
+    const long long rounds = (cols * segs + cus - 1) / cus;
+    const long long cost = rounds * (seg + 3 * H - 1);
+    if (best < 0 || cost < best) {
+      best = cost;
+      g.segs = segs;
+    }
+  }
+  g.seg = (kc.nz + g.segs - 1) / g.segs;
   g.segs = (kc.nz + g.seg - 1) / g.seg;
   return g;
 }

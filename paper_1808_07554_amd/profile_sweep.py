@@ -5,8 +5,9 @@ Run under rocprofv3 (one counter per run):
     rocprofv3 --pmc WRITE_SIZE -d DIR -o run -- python -m paper_1808_07554_amd.profile_sweep
 The workload is a 1 GiB plain copy (lbtp_copy_probe, the known-size
 reference) followed by a burst of launches of the blocked plain pressure
-sweep (lbtp_probe_sweeps, 9 sweeps per launch) on the 4096 x 4096 injection
-problem, on D2Q5 or (--lattice D2Q9) on D2Q9.  Then, on any machine:
+sweep (lbtp_probe_sweeps) on the 4096 x 4096 injection problem, on D2Q5 or
+(--lattice D2Q9) on D2Q9, 9 sweeps per launch, or (--lattice D3Q7) on the
+512^3 injection problem, 3 sweeps per launch.  Then, on any machine:
     python -m paper_1808_07554_amd.profile_sweep --summarize FETCH.csv WRITE.csv OUT.txt [--storage S] [--lattice L]
 converts the counters of the sweep into HBM bytes per launch with the
 copy's bytes-per-count scale and writes a short text summary, and
@@ -29,6 +30,23 @@ COPY_BYTES = 1 << 30
 # the sources the sweep kernels are compiled from
 SWEEP_SOURCES = ("lbtp_kernels.hip", "lbtp_device.h", "lbtp_internal.h", "lbtp_block.hip", "lbtp_block.h")
 SWEEP_SOURCES_Q9 = ("lbtp_d2q9.hip", "lbtp_device.h", "lbtp_internal.h")
+SWEEP_SOURCES_Q7 = ("lbtp_block3.hip", "lbtp_device.h", "lbtp_internal.h")
+# plain sweeps per blocked launch (the library default) and populations
+# moved per node (the rest population is not stored)
+SWEEPS_PER_LAUNCH = {"D2Q5": 9, "D2Q9": 9, "D3Q7": 3}
+MOVING = {"D2Q5": 4, "D2Q9": 8, "D3Q7": 6}
+
+
+def default_n(lattice):
+    return 512 if lattice == "D3Q7" else 4096
+
+
+def cells_of(lattice, n):
+    return n ** 3 if lattice == "D3Q7" else n * n
+
+
+def grid_name(lattice, n):
+    return f"3-D {n}^3" if lattice == "D3Q7" else f"2-D {n}x{n}"
 
 
 # flops the method itself does in one plain pressure sweep per node (eq. 3-1,
@@ -46,7 +64,7 @@ ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 
 
 def sweep_sources(lattice="D2Q5"):
-    return SWEEP_SOURCES_Q9 if lattice == "D2Q9" else SWEEP_SOURCES
+    return {"D2Q9": SWEEP_SOURCES_Q9, "D3Q7": SWEEP_SOURCES_Q7}.get(lattice, SWEEP_SOURCES)
 
 
 def source_digest(lattice="D2Q5"):
@@ -90,7 +108,7 @@ def run(storage, n, launches, lattice="D2Q5"):
         assert rc == 0, rc
     torch.cuda.synchronize()
     del a, b
-    params, fl = inputs.injection_2d(n)
+    params, fl = inputs.injection_3d(n) if lattice == "D3Q7" else inputs.injection_2d(n)
     if lattice == "D2Q9":
         # the equilibrium of eq. 3-4 needs max(phi)/2 <= beta <= 2 min(phi)
         params = dict(params, lattice="D2Q9", beta=0.2)
@@ -103,7 +121,8 @@ def run(storage, n, launches, lattice="D2Q5"):
     s.pressure_solve(-1.0, 20)
     H = s.probe_sweeps(launches)
     torch.cuda.synchronize()
-    print(f"profile workload done: copy {COPY_BYTES} B x3, {launches} launches of {H} plain sweeps at {n}^2 "
+    print(f"profile workload done: copy {COPY_BYTES} B x3, {launches} launches of {H} plain sweeps at "
+          f"{grid_name(lattice, n)} "
           f"({lattice}, {storage})", flush=True)
 
 
@@ -132,18 +151,19 @@ def summarize(fetch_csv, write_csv, out_txt, storage, n, command, lattice="D2Q5"
     copy_f, ncf = _per_dispatch(f_rows, "copy_probe")
     copy_w, ncw = _per_dispatch(w_rows, "copy_probe")
     # launches of the blocked plain sweep (each moves the state in and out once)
-    kname = sweep_kernel_name(storage, 2, lattice)
+    kname = sweep_kernel_name(storage, 3 if lattice == "D3Q7" else 2, lattice, SWEEPS_PER_LAUNCH[lattice])
     sw_f, nsf = _per_dispatch(f_rows, kname)
     sw_w, nsw = _per_dispatch(w_rows, kname)
     scale_f = COPY_BYTES / copy_f
     scale_w = COPY_BYTES / copy_w
     fetch_b = sw_f * scale_f
     write_b = sw_w * scale_w
-    q1, pop = (8 if lattice == "D2Q9" else 4), (4 if storage == "fp32" else 2)
-    alg_read = n * n * (q1 * pop + 8)
-    alg_write = n * n * q1 * pop
+    q1, pop = MOVING[lattice], (4 if storage == "fp32" else 2)
+    cells = cells_of(lattice, n)
+    alg_read = cells * (q1 * pop + 8)
+    alg_write = cells * q1 * pop
     sha = source_digest(lattice)
-    text = f"""Blocked pressure sweep HBM traffic per launch (9 plain sweeps), heterogeneous injection 2-D {n}x{n}, {lattice}, {storage} storage
+    text = f"""Blocked pressure sweep HBM traffic per launch ({SWEEPS_PER_LAUNCH[lattice]} plain sweeps), heterogeneous injection {grid_name(lattice, n)}, {lattice}, {storage} storage
 command: {command}
 counters: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each from its own rocprofv3 --pmc run
 calibration: lbtp_copy_probe of {COPY_BYTES} B: FETCH_SIZE {copy_f:.1f} ({ncf} dispatches), WRITE_SIZE {copy_w:.1f} ({ncw}) -> {scale_f:.2f} / {scale_w:.2f} B per count
@@ -172,7 +192,8 @@ def _short_name(name):
     return name
 
 
-def summarize_trace(trace_csv, out_txt, title, command, lattice="D2Q5", n=4096, sweeps_per_launch=9):
+def summarize_trace(trace_csv, out_txt, title, command, lattice="D2Q5", n=4096, sweeps_per_launch=None):
+    sweeps_per_launch = sweeps_per_launch or SWEEPS_PER_LAUNCH[lattice]
     with open(trace_csv) as f:
         rows = list(csv.DictReader(f))
     agg = {}
@@ -185,16 +206,16 @@ def summarize_trace(trace_csv, out_txt, title, command, lattice="D2Q5", n=4096, 
     for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
         lines.append(f"{k[:66]:66s} {len(v):6d} {sum(v) / len(v):9.2f} {min(v):9.2f} {max(v):9.2f} "
                      f"{100 * sum(v) / total:6.2f}")
-    kname = sweep_kernel_name("fp32", 2, lattice, sweeps_per_launch)
+    kname = sweep_kernel_name("fp32", 3 if lattice == "D3Q7" else 2, lattice, sweeps_per_launch)
     blk = [v for k, v in agg.items() if k.split("<")[0] == kname]
     if blk:
         d = blk[0]
         avg = sum(d) / len(d)
-        fl = METHOD_FLOPS_PER_NODE_SWEEP[lattice] * n * n * sweeps_per_launch
+        fl = METHOD_FLOPS_PER_NODE_SWEEP[lattice] * cells_of(lattice, n) * sweeps_per_launch
         lines += ["", f"{kname} runs {sweeps_per_launch} plain pressure sweeps per launch; average launch "
                   f"{avg:.1f} us = {avg / sweeps_per_launch:.2f} us per sweep;",
                   f"{METHOD_FLOPS_PER_NODE_SWEEP[lattice]} method flops per node and sweep (eq. 3-1, eq. 3-9a) x "
-                  f"{n * n} nodes x {sweeps_per_launch} = {fl / 1e9:.2f} GFLOP per launch",
+                  f"{cells_of(lattice, n)} nodes x {sweeps_per_launch} = {fl / 1e9:.2f} GFLOP per launch",
                   f"-> {fl / (avg * 1e-6) / 1e12:.2f} TFLOP/s against {ALU_PEAK_TFLOPS:.2f} TFLOP/s (one fp32 fused "
                   "multiply-add per lane and clock, 64 lanes per CU, 256 CUs, 2.4 GHz), frac "
                   f"{fl / (avg * 1e-6) / 1e12 / ALU_PEAK_TFLOPS:.3f}"]
@@ -204,12 +225,13 @@ def summarize_trace(trace_csv, out_txt, title, command, lattice="D2Q5", n=4096, 
     print(text)
 
 
-def summarize_counters(csv_path, out_txt, command, lattice="D2Q5", n=4096, sweeps_per_launch=9):
+def summarize_counters(csv_path, out_txt, command, lattice="D2Q5", n=4096, sweeps_per_launch=None):
     """Per-dispatch averages of the counters of one --pmc run over the blocked
     sweep's launches, and the vector issue they imply: a wave64 fp32
     instruction occupies its SIMD (16 lanes) for 4 cycles, and the chip has
     1024 SIMDs; the launch time comes from the same dispatches' timestamps."""
-    kname = sweep_kernel_name("fp32", 2, lattice, sweeps_per_launch)
+    sweeps_per_launch = sweeps_per_launch or SWEEPS_PER_LAUNCH[lattice]
+    kname = sweep_kernel_name("fp32", 3 if lattice == "D3Q7" else 2, lattice, sweeps_per_launch)
     with open(csv_path) as f:
         rows = [r for r in csv.DictReader(f) if _short_name(r["Kernel_Name"]).split("<")[0] == kname]
     per = {}
@@ -220,13 +242,13 @@ def summarize_counters(csv_path, out_txt, command, lattice="D2Q5", n=4096, sweep
     dur = sum(times.values()) / len(times)
     avg = {k: sum(v) / len(v) for k, v in per.items()}
     lines = [f"Instruction counters of {kname} ({sweeps_per_launch} plain pressure sweeps per launch), "
-             f"heterogeneous injection 2-D {n}x{n}, {lattice}, fp32 storage",
+             f"heterogeneous injection {grid_name(lattice, n)}, {lattice}, fp32 storage",
              f"command: {command}", f"dispatches: {len(times)}, mean duration {dur * 1e6:.1f} us", ""]
     for k in sorted(avg):
         lines.append(f"{k:24s} {avg[k]:16.6e} per dispatch")
     if "SQ_INSTS_VALU" in avg:
         issue = avg["SQ_INSTS_VALU"] * 4 / 1024 / 2.4e9
-        node_sweeps = n * n * sweeps_per_launch
+        node_sweeps = cells_of(lattice, n) * sweeps_per_launch
         lines += ["", f"vector issue: {avg['SQ_INSTS_VALU']:.3e} wave instructions x 4 cycles / 1024 SIMDs = "
                   f"{issue * 1e6:.1f} us at 2.4 GHz = {issue / dur:.2f} of the launch",
                   f"per tile node and sweep: {avg['SQ_INSTS_VALU'] * 64 / node_sweeps:.2f} lane instructions "
@@ -250,9 +272,9 @@ def summarize_counters(csv_path, out_txt, command, lattice="D2Q5", n=4096, sweep
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--storage", default="fp32")
-    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--n", type=int, default=None, help="grid size (default 4096, 512 on D3Q7)")
     ap.add_argument("--launches", type=int, default=20)
-    ap.add_argument("--lattice", default="D2Q5", choices=["D2Q5", "D2Q9"])
+    ap.add_argument("--lattice", default="D2Q5", choices=["D2Q5", "D2Q9", "D3Q7"])
     ap.add_argument("--summarize", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_TXT"))
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_CSV", "OUT_TXT"))
     ap.add_argument("--summarize-counters", nargs=2, metavar=("CSV", "OUT_TXT"))
@@ -260,12 +282,14 @@ if __name__ == "__main__":
     ap.add_argument("--command", default=None, help="command line recorded in the summary (default: the one "
                     "that profiles this module with --storage and --n as given)")
     a = ap.parse_args()
+    if a.n is None:
+        a.n = default_n(a.lattice)
     if a.summarize_trace:
         summarize_trace(*a.summarize_trace, a.title, a.command or "", a.lattice, a.n)
     elif a.summarize_counters:
         summarize_counters(*a.summarize_counters, a.command or "", a.lattice, a.n)
     elif a.summarize:
-        args = (f"--storage {a.storage}" + (f" --n {a.n}" if a.n != 4096 else "")
+        args = (f"--storage {a.storage}" + (f" --n {a.n}" if a.n != default_n(a.lattice) else "")
                 + (f" --lattice {a.lattice}" if a.lattice != "D2Q5" else ""))
         command = a.command or (
             "cd /tmp && export TMPDIR=/tmp; rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR -o run -- "
