@@ -73,7 +73,7 @@ __device__ inline uint32_t pack_bf16x2(float lo, float hi) {
   return (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
 }
 
-// Tile of P = 256 (TN = 64) or 512 (TN <= 32) pixels, TR x TC with TC = 2^tcs
+// Tile of P = 256 pixels, TR x TC with TC = 2^tcs
 // of 8, 16, 32 or 64 columns: the images of the batch are taken as one stack
 // of N*H rows, so a tile may span images; a lane masks the rows above and
 // below its output pixel where they belong to another image (the column halo
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256, 2) void conv3x3_kernel(const bf16 *__restrict_
                                                          const float *__restrict__ bias, void *__restrict__ out,
                                                          int NH, int H, int W, int Ci, int Co, int tcs, int relu,
                                                          int out_f32) {
-  constexpr int P = TN == 64 ? 256 : 512;  // pixels per tile
+  constexpr int P = 256;                   // pixels per tile
   constexpr int CKP = CK + 8;              // LDS pitch (bf16) of one pixel and of one weight row
   constexpr int SPW = P / 64;              // 16-pixel runs per wave
   constexpr int NB = TN / 16;              // 16-channel output blocks
@@ -127,21 +127,58 @@ __global__ __launch_bounds__(256, 2) void conv3x3_kernel(const bf16 *__restrict_
   for (int i = 0; i < SPW; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  for (int c0 = 0; c0 < Ci; c0 += CK) {
-    __syncthreads();  // the previous chunk's fragments have been read
-    for (int idx = tid; idx < HR * HC * Q; idx += 256) {
+  // The next chunk's input (and, below 64 output channels, its weights) is
+  // loaded into registers while the current one is swept, and written to LDS
+  // between two barriers; at 64 channels the weights, which every workgroup
+  // reads and so come from L2, are loaded there (registers for both would
+  // spill).
+  constexpr bool PREW = TN < 64;
+  constexpr int NXI = (conv_halo_max(P) * Q + 255) / 256, NWI = (TN * 9 * Q + 255) / 256;
+  uint4 px[NXI], pw[PREW ? NWI : 1];
+  const int nhalo = HR * HC * Q;
+  auto fetch = [&](int c0) {
+#pragma unroll
+    for (int k = 0; k < NXI; ++k) {
+      const int idx = tid + 256 * k;
       const int q = idx % Q, p = idx / Q;
       const int r = (int)__umulhi((uint32_t)p, hc_magic);
       const int ys = ty0 + r - 1, gx = tx0 + (p - r * HC) - 1;
-      uint4 v = z4;
-      if (ys >= 0 && ys < NH && gx >= 0 && gx < W) v = *(const uint4 *)(in + ((size_t)ys * W + gx) * Ci + c0 + 8 * q);
-      *(uint4 *)(sx + p * CKP + 8 * q) = v;
+      px[k] = make_uint4(0u, 0u, 0u, 0u);
+      if (idx < nhalo && ys >= 0 && ys < NH && gx >= 0 && gx < W)
+        px[k] = *(const uint4 *)(in + ((size_t)ys * W + gx) * Ci + c0 + 8 * q);
     }
-    for (int idx = tid; idx < TN * 9 * Q; idx += 256) {
-      const int q = idx % Q, row = idx / Q;  // row = local output channel * 9 + tap
-      *(uint4 *)(sw + row * CKP + 8 * q) = *(const uint4 *)(w + ((size_t)co0 * 9 + row) * Ci + c0 + 8 * q);
+    if constexpr (PREW) {
+#pragma unroll
+      for (int k = 0; k < NWI; ++k) {
+        const int idx = tid + 256 * k;
+        const int q = idx % Q, row = idx / Q;  // row = local output channel * 9 + tap
+        pw[k] = make_uint4(0u, 0u, 0u, 0u);
+        if (idx < TN * 9 * Q) pw[k] = *(const uint4 *)(w + ((size_t)co0 * 9 + row) * Ci + c0 + 8 * q);
+      }
+    }
+  };
+  fetch(0);
+  for (int c0 = 0; c0 < Ci; c0 += CK) {
+    __syncthreads();  // the previous chunk's fragments have been read
+#pragma unroll
+    for (int k = 0; k < NXI; ++k) {
+      const int idx = tid + 256 * k;
+      if (idx < nhalo) *(uint4 *)(sx + (idx / Q) * CKP + 8 * (idx % Q)) = px[k];
+    }
+    if constexpr (PREW) {
+#pragma unroll
+      for (int k = 0; k < NWI; ++k) {
+        const int idx = tid + 256 * k;
+        if (idx < TN * 9 * Q) *(uint4 *)(sw + (idx / Q) * CKP + 8 * (idx % Q)) = pw[k];
+      }
+    } else {
+      for (int idx = tid; idx < TN * 9 * Q; idx += 256) {
+        const int q = idx % Q, row = idx / Q;
+        *(uint4 *)(sw + row * CKP + 8 * q) = *(const uint4 *)(w + ((size_t)co0 * 9 + row) * Ci + c0 + 8 * q);
+      }
     }
     __syncthreads();
+    if (c0 + CK < Ci) fetch(c0 + CK);
 #pragma unroll
     for (int s = 0; s < KSTEPS; ++s) {
       const int tap = CK == 32 ? s : 2 * s + (g >> 1);
@@ -718,7 +755,7 @@ void conv_launch(hipStream_t st, const bf16 *in, const bf16 *w, const float *b, 
       tcs = t;
     }
   }
-  const int P = TN == 64 ? 256 : 512;
+  const int P = 256;
   const int ntx = (W + (1 << tcs) - 1) >> tcs, nty = (N * H + (P >> tcs) - 1) / (P >> tcs);
   const dim3 g((unsigned)(ntx * nty), (unsigned)(Co / TN));
   hipLaunchKernelGGL((conv3x3_kernel<TN, CK>), g, dim3(256), 0, st, in, w, b, out, N * H, H, W, Ci, Co, tcs,
