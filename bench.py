@@ -56,6 +56,7 @@ def f_sweep_bytes(lattice, storage):
     return 2 * q1 * POP_BYTES[storage] + 4 + 4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "f_block_traffic_injection2d_4096_{}.txt")
 TRAFFIC_FILE_Q9 = os.path.join(ROOT, "profiles", "f_block_traffic_injection2d_4096_d2q9_{}.txt")
+TRAFFIC_FILE_Q7 = os.path.join(ROOT, "profiles", "f_block_traffic_injection3d_512_{}.txt")
 
 
 def parse():
@@ -92,7 +93,7 @@ def measured_traffic(storage, lattice="D2Q5"):
     """HBM bytes per f-sweep launch from the committed rocprofv3 counter summary
     for this lattice and storage format, if it was taken on the current kernel
     sources (else None)."""
-    path = (TRAFFIC_FILE_Q9 if lattice == "D2Q9" else TRAFFIC_FILE).format(storage)
+    path = {"D2Q9": TRAFFIC_FILE_Q9, "D3Q7": TRAFFIC_FILE_Q7}.get(lattice, TRAFFIC_FILE).format(storage)
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -348,8 +349,8 @@ def main():
         torch.cuda.synchronize()
         gstep_s += e0.elapsed_time(e1) / 1e3 / nsat
     alg_bytes = f_sweep_bytes(params["lattice"], a.storage) * ncell
-    traffic = (measured_traffic(a.storage, a.lattice)
-               if (a.workload == "injection2d" and a.n == 4096 and H > 1) else None)
+    traffic = (measured_traffic(a.storage, params["lattice"])
+               if (a.workload in ("injection2d", "injection3d") and a.n == 4096 and H > 1) else None)
     kname = sweep_kernel_name(a.storage, 3 if a.workload == "injection3d" else 2, params["lattice"], H)
     if H > 1:
         flops = BLOCK_FLOPS_PER_NODE_SWEEP[params["lattice"]] * ncell * H

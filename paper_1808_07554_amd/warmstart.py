@@ -153,10 +153,11 @@ def solve(lnK, S, phi, P0=None, tol=1e-8, m=64, max_iters=None, storage="fp32"):
     return P, its[0], dt
 
 
-def solve_chunked(lnK, S, phi, chunk=1024, **kw):
+def solve_chunked(lnK, S, phi, chunk=1024, P0=None, **kw):
     out, its, t = [], [], 0.0
     for a in range(0, lnK.shape[0], chunk):
-        P, k, dt = solve(lnK[a:a + chunk], S[a:a + chunk], phi[a:a + chunk], **kw)
+        P, k, dt = solve(lnK[a:a + chunk], S[a:a + chunk], phi[a:a + chunk],
+                         None if P0 is None else P0[a:a + chunk], **kw)
         out.append(P)
         its.append(k)
         t += dt
@@ -214,7 +215,8 @@ def _refine_deviation(Pc, f):
     return (1.0 - (np.arange(w * f) + 0.5) / (w * f)) + R
 
 
-def evaluate(net, lnK, S, phi, factor=1, tol=1e-8, m=64, starts=("linear", "zero", "network", "coarse_solve")):
+def evaluate(net, lnK, S, phi, factor=1, tol=1e-8, m=64, starts=("linear", "zero", "network", "coarse_solve"),
+             chunk=32):
     """Solve the same fields to the same tolerance from several initial
     pressures and report iterations and wall time for each:
       linear        the linear profile between the Dirichlet walls (cold start)
@@ -226,7 +228,8 @@ def evaluate(net, lnK, S, phi, factor=1, tol=1e-8, m=64, starts=("linear", "zero
       ceiling       the block average of the converged pressure (from the
                     linear start), refined the same way: what a perfect
                     coarse-grid predictor would give
-    Times include preparing the start (inference, the coarse solve)."""
+    Times include preparing the start (inference, the coarse solve).  Every
+    start solves the fields in the same batches of `chunk` fields."""
     import torch
     count, n, _ = lnK.shape
     out = dict(fields=int(count), size=int(n), factor=int(factor))
@@ -254,7 +257,7 @@ def evaluate(net, lnK, S, phi, factor=1, tol=1e-8, m=64, starts=("linear", "zero
             raise ValueError(st)
         torch.cuda.synchronize()
         t_prep = time.perf_counter() - t0
-        Pk, its, t = solve(lnK, S, phi, P0, tol, m)
+        Pk, its, t = solve_chunked(lnK, S, phi, chunk, P0=P0, tol=tol, m=m)
         if st == "linear":
             P_conv = Pk
         res[st] = dict(iterations_mean=float(its.mean()), iterations_median=float(np.median(its)),
