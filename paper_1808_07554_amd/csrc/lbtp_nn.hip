@@ -136,22 +136,35 @@ __global__ __launch_bounds__(256, 2) void conv3x3_kernel(const bf16 *__restrict_
   constexpr int NXI = (conv_halo_max(P) * Q + 255) / 256, NWI = (TN * 9 * Q + 255) / 256;
   uint4 px[NXI], pw[PREW ? NWI : 1];
   const int nhalo = HR * HC * Q;
+  // staging piece idx -> (row, piece), rows being pixels or weight rows:
+  // with 4 pieces per row the 16 lanes of a group take rows a, a+4, a+8,
+  // a+12 of a run of 16, which (80 bytes apart) start 16 banks apart, so the
+  // group's writes fill the 64 banks once (weight rows come in multiples of
+  // 16); with 2 pieces per row the plain order does
+  auto stage_pixel = [&](int idx) {
+    if constexpr (Q == 4) {
+      const int u = (idx >> 2) & 15;
+      return (idx >> 6) * 16 + ((u & 3) << 2) + (u >> 2);
+    } else {
+      return idx / Q;
+    }
+  };
   auto fetch = [&](int c0) {
 #pragma unroll
     for (int k = 0; k < NXI; ++k) {
       const int idx = tid + 256 * k;
-      const int q = idx % Q, p = idx / Q;
+      const int q = idx % Q, p = stage_pixel(idx);
       const int r = (int)__umulhi((uint32_t)p, hc_magic);
       const int ys = ty0 + r - 1, gx = tx0 + (p - r * HC) - 1;
       px[k] = make_uint4(0u, 0u, 0u, 0u);
-      if (idx < nhalo && ys >= 0 && ys < NH && gx >= 0 && gx < W)
+      if (p < nhalo / Q && ys >= 0 && ys < NH && gx >= 0 && gx < W)
         px[k] = *(const uint4 *)(in + ((size_t)ys * W + gx) * Ci + c0 + 8 * q);
     }
     if constexpr (PREW) {
 #pragma unroll
       for (int k = 0; k < NWI; ++k) {
         const int idx = tid + 256 * k;
-        const int q = idx % Q, row = idx / Q;  // row = local output channel * 9 + tap
+        const int q = idx % Q, row = stage_pixel(idx);  // row = local output channel * 9 + tap
         pw[k] = make_uint4(0u, 0u, 0u, 0u);
         if (idx < TN * 9 * Q) pw[k] = *(const uint4 *)(w + ((size_t)co0 * 9 + row) * Ci + c0 + 8 * q);
       }
@@ -163,17 +176,18 @@ __global__ __launch_bounds__(256, 2) void conv3x3_kernel(const bf16 *__restrict_
 #pragma unroll
     for (int k = 0; k < NXI; ++k) {
       const int idx = tid + 256 * k;
-      if (idx < nhalo) *(uint4 *)(sx + (idx / Q) * CKP + 8 * (idx % Q)) = px[k];
+      const int p = stage_pixel(idx);
+      if (p < nhalo / Q) *(uint4 *)(sx + p * CKP + 8 * (idx % Q)) = px[k];
     }
     if constexpr (PREW) {
 #pragma unroll
       for (int k = 0; k < NWI; ++k) {
         const int idx = tid + 256 * k;
-        if (idx < TN * 9 * Q) *(uint4 *)(sw + (idx / Q) * CKP + 8 * (idx % Q)) = pw[k];
+        if (idx < TN * 9 * Q) *(uint4 *)(sw + stage_pixel(idx) * CKP + 8 * (idx % Q)) = pw[k];
       }
     } else {
       for (int idx = tid; idx < TN * 9 * Q; idx += 256) {
-        const int q = idx % Q, row = idx / Q;
+        const int q = idx % Q, row = stage_pixel(idx);
         *(uint4 *)(sw + row * CKP + 8 * q) = *(const uint4 *)(w + ((size_t)co0 * 9 + row) * Ci + c0 + 8 * q);
       }
     }
