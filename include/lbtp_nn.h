@@ -3,7 +3,7 @@
  * matrix cores).  Not part of the paper's method: the network only supplies
  * the initial pressure P0 handed to lbtp_set_state / lbtp_batch_set_state;
  * the lattice Boltzmann pressure iteration (eq. 3-1) then runs to the same
- * stopping tolerance as from any other start, so it remains the judge.
+ * stopping tolerance as from any other start, so it still decides the result.
  *
  * Network: convolutional encoder-decoder on an N x H x W batch of fields.
  * Inputs per node: lnK (log absolute permeability), S (saturation) and the
