@@ -34,6 +34,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "lbtp_device.h"
 
 namespace lbtp {
@@ -224,15 +226,15 @@ __global__ __launch_bounds__(kZBX * kZW) void f_zstream_kernel(KC kc, FPtrs fin_
 // Compute units of the current device (one workgroup of 16 wavefronts fits
 // a compute unit at a time).
 int device_cus() {
-  static int cus[64] = {0};
+  static std::atomic<int> cus[64];   // 0 = not queried yet (a repeated query writes the same value)
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (!cus[dev]) {
-    int n = 0;
+  int n = cus[dev].load(std::memory_order_relaxed);
+  if (!n) {
     if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
-    cus[dev] = n;
+    cus[dev].store(n, std::memory_order_relaxed);
   }
-  return cus[dev];
+  return n;
 }
 
 // Columns of 64 - 2H x 16 - 2H output nodes; the number of z segments is the
