@@ -684,9 +684,11 @@ int lbtp_pressure_solve(lbtp_ctx *c, double tol, long long max_iters, long long 
     HIP_TRY(sweep(0));
     k = 1;
   }
-  int slot = 0;
+  int slot = 0, last_copy = -1;   // ring slot of the control block copied after the last enqueued work
   bool pending[2] = {false, false};
+  bool stop = false;
   for (long long j = 1; k <= last; ++j) {
+    last_copy = -1;
     const long long kend = (j * m < last) ? j * m : last;
     if (graphs && kend == j * m && k == (j - 1) * m + 1) {
       hipGraphExec_t g = nullptr;
@@ -701,11 +703,11 @@ int lbtp_pressure_solve(lbtp_ctx *c, double tol, long long max_iters, long long 
     HIP_TRY(hipMemcpyAsync(&c->ctl_ring[slot], c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipEventRecord(c->ev[slot], c->stream));
     pending[slot] = true;
+    last_copy = slot;
     const int prev = slot ^ 1;
     int wait = -1;
     if (j == 1) wait = slot;
     else if (pending[prev]) wait = prev;
-    bool stop = false;
     if (wait >= 0) {
       HIP_TRY(hipEventSynchronize(c->ev[wait]));
       pending[wait] = false;
@@ -714,8 +716,16 @@ int lbtp_pressure_solve(lbtp_ctx *c, double tol, long long max_iters, long long 
     slot = prev;
     if (stop) break;
   }
-  int rc = read_ctl(c);
-  if (rc) return rc;
+  if (stop && last_copy >= 0) {
+    // the copy behind the last enqueued work is the final control block (work
+    // queued after a stop only exits early and leaves it as it is)
+    if (pending[last_copy]) HIP_TRY(hipEventSynchronize(c->ev[last_copy]));
+    pending[last_copy] = false;
+    *c->ctl_host = c->ctl_ring[last_copy];
+  } else {
+    const int rc = read_ctl(c);
+    if (rc) return rc;
+  }
   const Ctl &h = *c->ctl_host;
   long long K;
   int status;
