@@ -85,7 +85,7 @@ def parse():
     ap.add_argument("--no-tail", action="store_true",
                     help="2-D injection: skip running the rest of the 5000 configured coupled steps")
     ap.add_argument("--no-legs", action="store_true",
-                    help="2-D injection: skip the fp16 / bf16 storage legs")
+                    help="2-D injection: skip the fp16 / bf16 storage legs and the ensemble and warm-start legs")
     return ap.parse_args()
 
 
@@ -199,6 +199,80 @@ def ensemble_bench(a):
         "sequential_mlups": round(mlups_seq, 1), "batched_over_sequential": round(t_seq / t_batch, 3),
     }
     print(json.dumps(out), flush=True)
+
+
+def ensemble_leg(storage, m, tol, n_members=32, steps=4, sizes=(128, 256)):
+    """Batching against plain FP32 at the same residual: n_members 2-D
+    injection realisations (sides from `sizes`, sigma_lnK in [0.5, 2]) for
+    `steps` coupled steps to r <= tol (the first solve cold), advanced together
+    (lbtp_batch, per-member stopping) and one after another through single
+    contexts.  The iteration counts of the two runs must agree."""
+    import torch
+    from paper_1808_07554_amd import inputs, lbtp
+    dev = torch.device("cuda", 0)
+    members = inputs.ensemble(n_members, sizes=sizes)
+    dfields = [{k: torch.from_numpy(inputs.f32(fl[k]).ravel()).to(dev) for k in ("K", "phi", "P0", "S0")}
+               for _, fl in members]
+    cells = np.array([p["shape"][0] * p["shape"][1] for p, _ in members], dtype=np.float64)
+    b = lbtp.Batch([p for p, _ in members], m=m, storage=storage)
+    for i, d in enumerate(dfields):
+        b.set_fields(i, d["K"], d["phi"])
+        b.set_state(i, d["P0"], d["S0"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its_b, _ = b.step(steps, tol, 10_000_000)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    b.close()
+    t_seq, its_s = 0.0, []
+    for i, (p, _) in enumerate(members):
+        s = lbtp.from_problem(p, m=m, storage=storage)
+        d = dfields[i]
+        s.set_fields(d["K"], d["phi"])
+        s.set_state(d["P0"], d["S0"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, _ = s.step(steps, tol, 10_000_000)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        its_s.append(list(its))
+        s.close()
+    its_s = np.array(its_s, dtype=np.int64).T   # [steps, members]
+    updates = float(np.sum(cells * (its_b.sum(axis=0) + steps)))
+    return {"members": n_members, "sides": list(sizes), "coupled_steps": steps, "tol": tol,
+            "batched_mlups": round(updates / t_batch / 1e6, 1),
+            "sequential_mlups": round(updates / t_seq / 1e6, 1),
+            "batched_over_sequential": round(t_seq / t_batch, 3),
+            "iterations_equal": bool(np.array_equal(its_b, its_s)),
+            "iterations_total": int(its_b.sum())}
+
+
+def warmstart_leg(train_pairs=2048, train_size=64, train_steps=1000, eval_fields=32, eval_size=256):
+    """The learned start against the plain linear start at the same residual:
+    a network trained briefly on the GPU (its own kernels) on solver-generated
+    pairs, then held-out fields solved to r <= 1e-8 from both starts (wall
+    time of the network start includes inference)."""
+    from paper_1808_07554_amd import lbtp, warmstart as ws
+    t0 = time.perf_counter()
+    lnK, S, P, _ = ws.training_set(train_pairs, train_size, 1_000_000, factors=(1, 2, 4), log=False)
+    t_data = time.perf_counter() - t0
+    net = lbtp.WarmStartNet(32, 4, 3.2)
+    net.set_params(ws.init_params(32, 4, seed=0))
+    t0 = time.perf_counter()
+    ws.train(net, lnK, S, P, train_steps, 32, 1e-3, log_every=0, weight=ws.relative_weights(P))
+    t_train = time.perf_counter() - t0
+    eK, eS, ephi = ws.fields(eval_fields, eval_size, 6_500_000)
+    r = ws.evaluate(net, eK, eS, ephi, eval_size // train_size, starts=("linear", "network"))
+    net.close()
+    cold, warm = r["starts"]["linear"], r["starts"]["network"]
+    return {"train_pairs": train_pairs, "train_size": train_size, "train_steps": train_steps,
+            "data_s": round(t_data, 1), "train_s": round(t_train, 1),
+            "eval_fields": eval_fields, "eval_size": eval_size, "tol": 1e-8,
+            "linear_iterations_mean": round(cold["iterations_mean"], 1),
+            "network_iterations_mean": round(warm["iterations_mean"], 1),
+            "iteration_ratio": round(warm["iteration_ratio"], 3),
+            "wall_ratio_with_inference": round(warm["wall_ratio"], 3),
+            "fields_improved": round(warm["fewer_iterations_fraction"], 3)}
 
 
 def main():
@@ -434,6 +508,15 @@ def main():
                         "step_time_fp32_over_this": round(t_run / leg["t_run"], 3),
                         "cold_solve_fp32_over_this": round(t_cold / leg["t_cold"], 3) if t_cold else None}
         out["storage_legs"] = legs
+        # batching and the learned start against plain FP32 at the same residual
+        t0 = time.perf_counter()
+        out["ensemble_leg"] = ensemble_leg("fp32", a.m, a.tol)
+        print(f"ensemble leg: {out['ensemble_leg']['batched_over_sequential']}x batched over sequential, "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        out["warmstart_leg"] = warmstart_leg()
+        print(f"warm-start leg: {out['warmstart_leg']['iteration_ratio']}x fewer iterations, "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     if not a.no_cpu and a.workload == "injection2d":
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
     print(json.dumps(out), flush=True)
