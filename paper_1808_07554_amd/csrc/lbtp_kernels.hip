@@ -83,7 +83,22 @@ __global__ __launch_bounds__(1024) void finish_residual_kernel(const double *__r
                                                                int nblk, Ctl *ctl, int m) {
   __shared__ double sa[1024], sb[1024];
   double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += 1024) {
+  int i = threadIdx.x;
+  // eight partials in flight, added in the same order as one at a time
+  for (; i + 7 * 1024 < nblk; i += 8 * 1024) {
+    double va[8], vb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      va[u] = partials[2 * (i + 1024 * u)];
+      vb[u] = partials[2 * (i + 1024 * u) + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a += va[u];
+      b += vb[u];
+    }
+  }
+  for (; i < nblk; i += 1024) {
     a += partials[2 * i];
     b += partials[2 * i + 1];
   }
@@ -134,7 +149,16 @@ __global__ __launch_bounds__(1024) void finish_sum_kernel(const double *__restri
                                                           double *dst, int accumulate, double *copy_to) {
   __shared__ double sa[1024];
   double a = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += 1024) a += partials[i];
+  int i = threadIdx.x;
+  // eight partials in flight, added in the same order as one at a time
+  for (; i + 7 * 1024 < nblk; i += 8 * 1024) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = partials[i + 1024 * u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a += v[u];
+  }
+  for (; i < nblk; i += 1024) a += partials[i];
   sa[threadIdx.x] = a;
   __syncthreads();
   for (int w = 512; w > 0; w >>= 1) {
