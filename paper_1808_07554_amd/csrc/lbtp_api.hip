@@ -52,8 +52,8 @@ struct lbtp_ctx {
   // captured chunks of m sweeps (+ the check), by (buffer parity, base
   // buffer, checks, F_p); kc_ver counts changes of the launch constants
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t chunk[16] = {};
-  int chunk_ver[16] = {};
+  hipGraphExec_t chunk[64] = {};
+  int chunk_ver[64] = {};
   int kc_ver = 1;
   int sweep_block = 0;      // plain sweeps per launch inside chunks (0 or 1: one)
 };
@@ -572,12 +572,78 @@ int lbtp_update_coefficients(lbtp_ctx *c) {
 }
 
 namespace {
-// Launches of one full chunk: sweeps k0+1 .. k0+m of a solve (pull form), the
-// last one re-basing (and, with checks, evaluating the stopping rule).  With
-// m even the buffer parities of a chunk depend only on fs; the base buffer
-// alternates from chunk to chunk.
-hipError_t enqueue_chunk(lbtp_ctx *c, long long k0, int pb, bool checks, hipStream_t s) {
+// Launch lengths covering n consecutive sweeps with blocked launches only
+// (D2Q5): odd lengths (a launch must end in the buffer n single sweeps
+// would), as few launches as the supported lengths allow near the configured
+// length H, the longer ones first.  Returns the number of launches, or 0
+// where chunks keep their one-sweep launches.
+int fused_plan(const lbtp_ctx *c, int n, int *len, int cap) {
+  const int H = c->sweep_block;
+  if (H < 3 || n < 3 || !block_first_supported(c->lk, c->kc, 3)) return 0;
+  int hmax = 0;
+  for (int h = 3; h <= 63; h += 2)
+    if (block_first_supported(c->lk, c->kc, h)) hmax = h;
+  int b = n / H;
+  if (b < 1) b = 1;
+  if ((b & 1) != (n & 1)) b = b > 1 ? b - 1 : b + 1;
+  while (b <= cap && n > b * hmax) b += 2;
+  if (b > cap) return 0;
+  int q = n / b;
+  if (!(q & 1)) --q;
+  if (q < 3) return 0;
+  int d = n - b * q;     // even: n and b * q have b's parity
+  for (int i = 0; i < b; ++i) len[i] = q;
+  for (int i = 0; d > 0; i = (i + 1) % b, d -= 2) len[i] += 2;
+  for (int i = 0; i < b; ++i)
+    if (len[i] > hmax) return 0;
+  return b;
+}
+
+constexpr int kMaxLaunches = 64;
+
+// The launches of one chunk: m sweeps with one re-basing sweep and, with
+// checks, one evaluation of the stopping rule.  kChunkOneSweep: sweeps
+// k0+1 .. k0+m, blocked where the lattice allows and one per launch
+// otherwise, sweep k0+m re-basing and checking in a launch of its own.
+// kChunkFused (D2Q5, blocked launches only): sweeps k0 .. k0+m-1, the first
+// launch performing the re-basing sweep k0 as its first sweep; with checks a
+// probe of sweep k0+m (a one-sweep launch that only forms P and the
+// stopping-rule sums) follows.  The re-basing sweep k0+m opens the next
+// chunk, so the state a check passes on (the one sweep k0+m reads) is the
+// one in memory.  kChunkFusedAfterLocal: the same for chunk 1 after a
+// one-sweep local sweep 0, sweeps 1 .. m-1 and the probe of m.  With m even
+// the buffer parities of a chunk depend only on fs.
+enum ChunkKind { kChunkOneSweep = 0, kChunkFused = 1, kChunkFusedAfterLocal = 2 };
+
+hipError_t enqueue_chunk(lbtp_ctx *c, long long k0, int pb, bool checks, int kind, hipStream_t s) {
   const int m = c->p.residual_stride;
+  if (kind != kChunkOneSweep) {
+    const bool first = kind == kChunkFused;
+    int len[kMaxLaunches];
+    const int nb = fused_plan(c, first ? m : m - 1, len, kMaxLaunches);
+    if (nb <= 0) return hipErrorInvalidValue;   // callers ask for it only where the plan exists
+    long long k = first ? k0 : k0 + 1;
+    int cur = pb;
+    for (int b = 0; b < nb; ++b) {
+      const int parity = (int)((c->fs + k) & 1);
+      const hipError_t e =
+          (first && b == 0)
+              ? launch_f_block_first(c->p.storage, c->kc, fptrs(c, c->fbuf[parity]), fptrs(c, c->fbuf[parity ^ 1]),
+                                     c->Pb[cur], c->Pb[cur ^ 1], c->itau, Fp_or_null(c), c->ctl, k, len[b], s)
+              : launch_f_block(c->lk, c->p.storage, c->kc, fptrs(c, c->fbuf[parity]), fptrs(c, c->fbuf[parity ^ 1]),
+                               c->Pb[cur], c->itau, Fp_or_null(c), c->ctl, k, len[b], s);
+      if (e != hipSuccess) return e;
+      if (first && b == 0) cur ^= 1;
+      k += len[b];
+    }
+    if (!checks) return hipSuccess;
+    const int parity = (int)((c->fs + k) & 1);
+    hipError_t e = launch_f_sweep(c->lk, c->p.storage, c->kc, fptrs(c, c->fbuf[parity]),
+                                  fptrs(c, c->fbuf[parity ^ 1]), c->Pb[cur], c->Pb[cur ^ 1], c->itau, Fp_or_null(c),
+                                  c->partials, c->ctl, k, 0, 3, s);
+    if (e == hipSuccess) e = launch_finish_residual(c->partials, sweep_blocks(c->kc, 0), c->ctl, m, s);
+    return e;
+  }
   int i = 1;
   // plain sweeps in blocks of H (H odd: a block ends in the buffer where H
   // single sweeps would), the rest one by one
@@ -610,8 +676,8 @@ hipError_t enqueue_chunk(lbtp_ctx *c, long long k0, int pb, bool checks, hipStre
 // iteration arguments are those of the first chunk; they only guard against
 // sweeps beyond the iteration limit, which a full chunk never reaches, and
 // the check counts iterations on the device.
-hipError_t chunk_graph(lbtp_ctx *c, int pb, bool checks, hipGraphExec_t *out) {
-  const int key = (c->fs & 1) | (pb << 1) | ((checks ? 1 : 0) << 2) | ((c->has_Fp ? 1 : 0) << 3);
+hipError_t chunk_graph(lbtp_ctx *c, int pb, bool checks, int kind, hipGraphExec_t *out) {
+  const int key = (c->fs & 1) | (pb << 1) | ((checks ? 1 : 0) << 2) | ((c->has_Fp ? 1 : 0) << 3) | (kind << 4);
   if (c->chunk[key] && c->chunk_ver[key] == c->kc_ver) {
     *out = c->chunk[key];
     return hipSuccess;
@@ -626,7 +692,7 @@ hipError_t chunk_graph(lbtp_ctx *c, int pb, bool checks, hipGraphExec_t *out) {
   e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
   // the fs of the first chunk of a solve: sweeps 1..m read (fs + k) & 1
-  const hipError_t el = enqueue_chunk(c, 0, pb, checks, c->cap_stream);
+  const hipError_t el = enqueue_chunk(c, 0, pb, checks, kind, c->cap_stream);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(c->cap_stream, &g);
   if (el != hipSuccess || e != hipSuccess) {
@@ -661,9 +727,10 @@ int lbtp_pressure_solve(lbtp_ctx *c, double tol, long long max_iters, long long 
   // the base to the current P (writing the other base buffer); with checks on,
   // those with k > 0 also evaluate the stopping rule.
   int pb = c->pbs;
+  long long probed = -1;     // a sweep whose check a fused chunk's probe has made
   auto sweep = [&](long long k) -> hipError_t {
     const int parity = (int)((c->fs + k) & 1);
-    const int mode = (k % m != 0) ? 0 : ((k == 0 || !checks) ? 1 : 2);
+    const int mode = (k % m != 0) ? 0 : ((k == 0 || !checks || k == probed) ? 1 : 2);
     const int local = (k == 0) && c->f_local;
     hipError_t e = launch_f_sweep(c->lk, c->p.storage, c->kc, fptrs(c, c->fbuf[parity]),
                                   fptrs(c, c->fbuf[parity ^ 1]), c->Pb[pb], c->Pb[pb ^ 1], c->itau,
@@ -675,12 +742,18 @@ int lbtp_pressure_solve(lbtp_ctx *c, double tol, long long max_iters, long long 
   };
   // full chunks run as captured graphs (m even: the parities repeat)
   const bool graphs = m % 2 == 0 && m > 1;
-  // Chunk 0 is sweep 0 (snapshot of P^0); chunk j >= 1 is sweeps
-  // (j-1)m+1 .. jm and ends with the check at jm.  The first check is waited
-  // for at once (warm steps usually stop there); later ones are read one
-  // chunk behind so the GPU never idles while the host decides.
+  // fused chunks (enqueue_chunk): chunk j is sweeps (j-1)m .. jm-1 and the
+  // probe of jm; after a local sweep 0, chunk 1 is sweeps 1 .. m-1 and the
+  // probe of m
+  int plan[kMaxLaunches];
+  const bool fused = graphs && fused_plan(c, m, plan, kMaxLaunches) > 0 &&
+                     (!c->f_local || fused_plan(c, m - 1, plan, kMaxLaunches) > 0);
+  // Chunk 0 is sweep 0 (snapshot of P^0) where it runs alone; chunk j >= 1
+  // ends with the check at jm.  The first check is waited for at once (warm
+  // steps usually stop there); later ones are read one chunk behind so the
+  // GPU never idles while the host decides.
   long long k = 0;
-  if (last >= 0) {
+  if (last >= 0 && (!fused || c->f_local)) {
     HIP_TRY(sweep(0));
     k = 1;
   }
@@ -690,9 +763,20 @@ int lbtp_pressure_solve(lbtp_ctx *c, double tol, long long max_iters, long long 
   for (long long j = 1; k <= last; ++j) {
     last_copy = -1;
     const long long kend = (j * m < last) ? j * m : last;
-    if (graphs && kend == j * m && k == (j - 1) * m + 1) {
+    const bool full = graphs && kend == j * m;
+    if (full && fused && (k == (j - 1) * m || (j == 1 && k == 1))) {
+      const bool first = k == (j - 1) * m;     // the chunk performs the re-basing sweep (j-1)m
       hipGraphExec_t g = nullptr;
-      HIP_TRY(chunk_graph(c, pb, checks, &g));
+      HIP_TRY(chunk_graph(c, pb, checks, first ? kChunkFused : kChunkFusedAfterLocal, &g));
+      HIP_TRY(hipGraphLaunch(g, c->stream));
+      if (first) pb ^= 1;
+      // sweep jm, re-basing, opens the next chunk; its output is needed only
+      // below max_iters (with checks on, its check is made)
+      k = j * m < max_iters ? j * m : last + 1;
+      if (checks) probed = j * m;
+    } else if (full && !fused && k == (j - 1) * m + 1) {
+      hipGraphExec_t g = nullptr;
+      HIP_TRY(chunk_graph(c, pb, checks, kChunkOneSweep, &g));
       HIP_TRY(hipGraphLaunch(g, c->stream));
       pb ^= 1;
       k = kend + 1;

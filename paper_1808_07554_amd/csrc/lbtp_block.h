@@ -2,19 +2,21 @@
 // work of one workgroup, shared by the single-context kernel
 // (lbtp_block.hip) and the ensemble kernel (lbtp_batch.hip).
 //
-// A workgroup of W wavefronts runs H consecutive plain sweeps (eq. 3-1, no
-// re-basing, no stopping-rule terms) over a region of 64 columns x (W * RW)
-// rows held in registers: each lane of a wavefront owns one column, each
+// A workgroup of W wavefronts runs H consecutive sweeps (eq. 3-1) over a
+// region of 64 columns x (W * RW) rows held in registers: each lane of a wavefront owns one column, each
 // wavefront RW consecutive rows.  The x-streamed populations move between
 // adjacent lanes (lane shuffles), the y-streamed ones between the rows of a
 // lane's registers, and across wavefronts through a small LDS exchange (one
 // barrier per sweep).  Only the tile, the nodes at least H links from any cut
 // edge of the region, is written back; the halo around it is recomputed by
 // the neighbouring workgroups.  Walls and periodic faces are handled where the
-// region meets them, with the same rules as the one-sweep kernels.
+// region meets them, with the same rules as the one-sweep kernels.  The
+// sweeps are plain, except that single contexts may make the first one
+// re-base (a chunk's first sweep), so that the re-basing sweep needs no
+// launch of its own.
 //
-// Arithmetic and its order are those of sweep_cell (lbtp_device.h) for a
-// plain sweep, so float32 storage gives bitwise the same populations as H
+// Arithmetic and its order are those of sweep_cell (lbtp_device.h) for each
+// mode, so float32 storage gives bitwise the same populations and bases as H
 // single sweeps.  16-bit storage rounds to the storage format only when the
 // tile is written back (once per launch instead of once per sweep).
 //
@@ -61,77 +63,129 @@ struct BlkRows {
   float fp[HAS_FP ? RW : 1];   // dt wbar F_p
 };
 
-// H sweeps of the region.  walls: the region holds wall nodes (uniform over
-// the workgroup, so regions inside the domain skip every wall test).  Rows
-// are updated in place from the bottom up; the old +y population of the row
-// below, which the next row still pulls, is kept aside.
-template <int W, int RW, bool HAS_FP>
-__device__ inline void blk_sweep_rows(const KC &kc, BlkRows<RW, HAS_FP> &r, float (*xup)[kBWmax][kBX],
-                                  float (*xdn)[kBWmax][kBX], int H, int lane, int wv, int ux, int gx, int uy0,
-                                  bool perx, bool pery, bool walls) {
-  const bool wall_l = !perx && ux == 0, wall_r = !perx && ux == kc.nx - 1;
-  for (int s = 1; s <= H; ++s) {
-    const int rd = (s - 1) & 1;
-    // the neighbouring wavefronts' rows (garbage at the region's outer rows,
-    // which are cut edges or walls)
-    float prev1 = wv > 0 ? xup[rd][wv - 1][lane] : 0.0f;
-    const float above = wv < W - 1 ? xdn[rd][wv + 1][lane] : 0.0f;
+// One sweep of the lane's rows.  PASS 0: plain (eq. 3-1); 1: also re-base
+// every node to its new P and keep the new bases in place of the old ones
+// (the pass reads the old ones throughout).  Rows are updated in place from
+// the bottom up; the old +y population of the row below, which the next row
+// still pulls, is kept aside.
+template <int W, int RW, bool HAS_FP, int PASS>
+__device__ inline void blk_pass(const KC &kc, BlkRows<RW, HAS_FP> &r, float prev1, float above, int gx, int uy0,
+                                bool wall_l, bool wall_r, bool pery, bool walls) {
+  float pn[PASS == 1 ? RW : 1];
 #pragma unroll
-    for (int t = 0; t < RW; ++t) {
-      const float p = r.pb[t + 1];
-      const float v0 = lane_from_left(r.d[t][0]);
-      const float v2 = lane_from_right(r.d[t][2]);
-      const float v3 = t < RW - 1 ? r.d[t + 1][3] : above;
-      float e[4];
-      e[0] = v0 + kc.w1 * (r.pbl[t] - p);
-      e[1] = prev1 + kc.w1 * (r.pb[t] - p);
-      e[2] = v2 + kc.w1 * (r.pbr[t] - p);
-      // w (P_b(y+1) - P_b(y)) is minus the term row t + 1 adds to its e[1]
-      // (exactly: negation commutes with the subtraction and the product),
-      // so inner rows reuse that value instead of holding one of their own
-      e[3] = t < RW - 1 ? v3 - kc.w1 * (r.pb[t + 1] - r.pb[t + 2]) : v3 + kc.w1 * (r.pb[t + 2] - p);
-      if (walls) {
-        const int uy = uy0 + t;
-        const int wy = pery ? blk_wrap(uy, kc.ny) : uy;
-        if (wall_l) e[0] = blk_wall_rule(kc, 0, 0, wy, p, r.d[t][2]);
-        if (wall_r) e[2] = blk_wall_rule(kc, 1, kc.nx - 1, wy, p, r.d[t][0]);
-        if (!pery && uy == 0) e[1] = blk_wall_rule(kc, 2, gx, 0, p, r.d[t][3]);
-        if (!pery && uy == kc.ny - 1) e[3] = blk_wall_rule(kc, 3, gx, kc.ny - 1, p, r.d[t][1]);
-      }
-      const float wdP = dsum<2>(e) * kc.w1_1mw0;
-      // with a source, keep = 1 - 1/tau_f is formed again every sweep: held
-      // for all rows it would cost 8 registers and one wavefront per SIMD
-      float it = r.it[t];
-      if (HAS_FP) asm volatile("" : "+v"(it));
-      const float keep = 1.0f - it, gain = wdP * it;
-      prev1 = r.d[t][1];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        float o = bgk_relax(e[j], keep, gain);
-        if (HAS_FP) o += r.fp[t];
-        r.d[t][j] = o;
-      }
+  for (int t = 0; t < RW; ++t) {
+    const float p = r.pb[t + 1];
+    const float v0 = lane_from_left(r.d[t][0]);
+    const float v2 = lane_from_right(r.d[t][2]);
+    const float v3 = t < RW - 1 ? r.d[t + 1][3] : above;
+    float e[4];
+    e[0] = v0 + kc.w1 * (r.pbl[t] - p);
+    e[1] = prev1 + kc.w1 * (r.pb[t] - p);
+    e[2] = v2 + kc.w1 * (r.pbr[t] - p);
+    // w (P_b(y+1) - P_b(y)) is minus the term row t + 1 adds to its e[1]
+    // (exactly: negation commutes with the subtraction and the product),
+    // so inner rows reuse that value instead of holding one of their own
+    e[3] = t < RW - 1 ? v3 - kc.w1 * (r.pb[t + 1] - r.pb[t + 2]) : v3 + kc.w1 * (r.pb[t + 2] - p);
+    if (walls) {
+      const int uy = uy0 + t;
+      const int wy = pery ? blk_wrap(uy, kc.ny) : uy;
+      if (wall_l) e[0] = blk_wall_rule(kc, 0, 0, wy, p, r.d[t][2]);
+      if (wall_r) e[2] = blk_wall_rule(kc, 1, kc.nx - 1, wy, p, r.d[t][0]);
+      if (!pery && uy == 0) e[1] = blk_wall_rule(kc, 2, gx, 0, p, r.d[t][3]);
+      if (!pery && uy == kc.ny - 1) e[3] = blk_wall_rule(kc, 3, gx, kc.ny - 1, p, r.d[t][1]);
     }
-    if (s == H) break;
+    const float sum = dsum<2>(e);
+    const float wdP = sum * kc.w1_1mw0;
+    // with a source, keep = 1 - 1/tau_f is formed again every sweep: held
+    // for all rows it would cost 8 registers and one wavefront per SIMD
+    float it = r.it[t];
+    if (HAS_FP) asm volatile("" : "+v"(it));
+    const float keep = 1.0f - it, gain = wdP * it;
+    // the terms added after the relaxation, formed as the one-sweep kernels
+    // form them (source first, then the re-basing shift)
+    float add = HAS_FP ? r.fp[t] : 0.0f;
+    if (PASS == 1) {
+      const float dP = sum * kc.inv_1mw0;
+      const float P = p + dP;
+      add += kc.w1 * (p - P);
+      pn[t] = P;
+    }
+    prev1 = r.d[t][1];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float o = bgk_relax(e[j], keep, gain);
+      if (HAS_FP || PASS == 1) o += add;
+      r.d[t][j] = o;
+    }
+  }
+  if (PASS == 1) {
+#pragma unroll
+    for (int t = 0; t < RW; ++t) r.pb[t + 1] = pn[t];
+  }
+}
+
+// H sweeps of the region.  walls: the region holds wall nodes (uniform over
+// the workgroup, so regions inside the domain skip every wall test).  FIRST:
+// the first sweep re-bases (pass 1); after it the new bases of the rows next
+// to a wavefront's own come through the LDS and those of the neighbouring
+// columns by lane shuffles.  The region's outermost rows and columns keep
+// their old bases, which only nodes outside the tile's dependence cone read.
+template <int W, int RW, bool HAS_FP, int FIRST>
+__device__ inline void blk_sweep_rows(const KC &kc, BlkRows<RW, HAS_FP> &r, float (*xup)[kBWmax][kBX],
+                                      float (*xdn)[kBWmax][kBX], float (*pbx)[kBWmax][kBX], int H, int lane,
+                                      int wv, int ux, int gx, int uy0, bool perx, bool pery, bool walls) {
+  const bool wall_l = !perx && ux == 0, wall_r = !perx && ux == kc.nx - 1;
+  // the neighbouring wavefronts' rows (garbage at the region's outer rows,
+  // which are cut edges or walls)
+  auto from_below = [&](int rd) { return wv > 0 ? xup[rd][wv - 1][lane] : 0.0f; };
+  auto from_above = [&](int rd) { return wv < W - 1 ? xdn[rd][wv + 1][lane] : 0.0f; };
+  // the +y population of the last row and the -y one of the first row for
+  // the neighbouring wavefronts' next sweep
+  auto exchange = [&](int s) {
     xup[s & 1][wv][lane] = r.d[RW - 1][1];
     xdn[s & 1][wv][lane] = r.d[0][3];
+  };
+  int s = 1;
+  if (FIRST) {
+    blk_pass<W, RW, HAS_FP, 1>(kc, r, from_below(0), from_above(0), gx, uy0, wall_l, wall_r, pery, walls);
+    exchange(1);
+    pbx[0][wv][lane] = r.pb[1];
+    pbx[1][wv][lane] = r.pb[RW];
+    __syncthreads();
+    if (wv > 0) r.pb[0] = pbx[1][wv - 1][lane];
+    if (wv < W - 1) r.pb[RW + 1] = pbx[0][wv + 1][lane];
+#pragma unroll
+    for (int t = 0; t < RW; ++t) {
+      r.pbl[t] = __shfl_up(r.pb[t + 1], 1, 64);
+      r.pbr[t] = __shfl_down(r.pb[t + 1], 1, 64);
+    }
+    s = 2;
+  }
+  for (; s <= H; ++s) {
+    const int rd = (s - 1) & 1;
+    blk_pass<W, RW, HAS_FP, 0>(kc, r, from_below(rd), from_above(rd), gx, uy0, wall_l, wall_r, pery, walls);
+    if (s == H) break;
+    exchange(s);
     __syncthreads();
   }
 }
 
-// The work of one workgroup (kBX * W threads): H plain sweeps of the region
-// of tile (tile_x, tile_y) of a context, reading fin and writing the tile to
-// fout.
-template <typename T, bool HAS_FP, int W, int RW>
+// The work of one workgroup (kBX * W threads): H sweeps of the region of
+// tile (tile_x, tile_y) of a context, reading fin and writing the tile to
+// fout; plain sweeps unless FIRST makes the first one re-base (reading the
+// bases Pb and writing the tile's new ones to Pb_out).
+template <typename T, bool HAS_FP, int W, int RW, int FIRST = 0>
 __device__ inline void block_region(const KC &kc, const FP<T> &fin, const FP<T> &fout, const float *__restrict__ Pb,
                                     const float *__restrict__ itau, const float *__restrict__ Fp, int H, int tile_x,
-                                    int tile_y) {
+                                    int tile_y, float *__restrict__ Pb_out = nullptr) {
   constexpr int kBY = W * RW;     // region rows
   // boundary rows exchanged between wavefronts, two copies (sweep s reads
   // copy (s - 1) & 1): the +y population of each wavefront's last row and
   // the -y population of its first row
   __shared__ float xup[2][kBWmax][kBX];
   __shared__ float xdn[2][kBWmax][kBX];
+  // after a re-basing first sweep: each wavefront's new first- and last-row bases
+  __shared__ float pbx[FIRST ? 2 : 1][kBWmax][kBX];
   const float is = kc.inv_dev_scale;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int tcols = kBX - 2 * H, trows = kBY - 2 * H;
@@ -176,17 +230,22 @@ __device__ inline void block_region(const KC &kc, const FP<T> &fin, const FP<T> 
 
   // wall nodes in the region: x = 0 or nx - 1 on a walled x axis, likewise y
   const bool walls = (!perx && (gx0 <= 0 || gx0 + kBX > kc.nx - 1)) || (!pery && (gy0 <= 0 || gy0 + kBY > kc.ny - 1));
-  blk_sweep_rows<W, RW, HAS_FP>(kc, r, xup, xdn, H, lane, wv, ux, gx, uy0, perx, pery, walls);
+  blk_sweep_rows<W, RW, HAS_FP, FIRST>(kc, r, xup, xdn, pbx, H, lane, wv, ux, gx, uy0, perx, pery, walls);
 
   // the tile: columns and rows [H, extent - H) of the region inside the domain
-  if (lane < H || lane >= kBX - H || ux >= kc.nx) return;
+  const bool tcol = lane >= H && lane < kBX - H && ux < kc.nx;
+  auto trow = [&](int t) {
+    const int ry = wv * RW + t;
+    return ry >= H && ry < kBY - H && uy0 + t < kc.ny;
+  };
+  if (!tcol) return;
 #pragma unroll
   for (int t = 0; t < RW; ++t) {
-    const int ry = wv * RW + t, uy = uy0 + t;
-    if (ry < H || ry >= kBY - H || uy >= kc.ny) continue;
-    const int c = uy * kc.nx + ux;
+    if (!trow(t)) continue;
+    const int c = (uy0 + t) * kc.nx + ux;
 #pragma unroll
     for (int j = 0; j < 4; ++j) Storage<T>::store(fout.p[j], c, r.d[t][j], kc.dev_scale);
+    if (FIRST) Pb_out[c] = r.pb[t + 1];
   }
 }
 

@@ -19,18 +19,52 @@ __global__ __launch_bounds__(kBX * W) void f_block_kernel(
   block_region<T, HAS_FP, W, RW>(kc, typed<T>(fin_), typed<T>(fout_), Pb, itau, Fp, H, t % tiles_x, t / tiles_x);
 }
 
-template <typename T, int W, int RW>
-void block_launch(const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, const float *itau, const float *Fp,
-                  const Ctl *ctl, long long k, int H, hipStream_t s) {
-  static_assert(W == kUseW && RW == kUseRW, "the tile counts assume the launch shape in use");
+// The same with a re-basing first sweep (a chunk's first), which reads the
+// bases Pb and writes the tile's new ones to Pb_out.
+template <typename T, bool HAS_FP, int W, int RW>
+__global__ __launch_bounds__(kBX * W) void f_block_first_kernel(
+    KC kc, FPtrs fin_, FPtrs fout_, const float *__restrict__ Pb, const float *__restrict__ itau,
+    const float *__restrict__ Fp, const Ctl *__restrict__ ctl, long long k, int H, int tiles_x,
+    float *__restrict__ Pb_out) {
+  if (ctl->done || k > ctl->kmax) return;
+  const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  block_region<T, HAS_FP, W, RW, 1>(kc, typed<T>(fin_), typed<T>(fout_), Pb, itau, Fp, H, t % tiles_x, t / tiles_x,
+                                    Pb_out);
+}
+
+template <typename T>
+void block_launch(const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, float *Pb_out, const float *itau,
+                  const float *Fp, const Ctl *ctl, long long k, int H, hipStream_t s) {
+  constexpr int W = kUseW, RW = kUseRW;
   int tx, ty;
   block_tile_counts(kc, H, &tx, &ty);
-  if (Fp)
-    hipLaunchKernelGGL((f_block_kernel<T, true, W, RW>), dim3(tx * ty), dim3(kBX * W), 0, s, kc, fin, fout, Pb,
-                       itau, Fp, ctl, k, H, tx);
-  else
-    hipLaunchKernelGGL((f_block_kernel<T, false, W, RW>), dim3(tx * ty), dim3(kBX * W), 0, s, kc, fin, fout, Pb,
-                       itau, Fp, ctl, k, H, tx);
+  const dim3 grid(tx * ty), block(kBX * W);
+  if (Pb_out) {
+    if (Fp)
+      hipLaunchKernelGGL((f_block_first_kernel<T, true, W, RW>), grid, block, 0, s, kc, fin, fout, Pb, itau, Fp,
+                         ctl, k, H, tx, Pb_out);
+    else
+      hipLaunchKernelGGL((f_block_first_kernel<T, false, W, RW>), grid, block, 0, s, kc, fin, fout, Pb, itau, Fp,
+                         ctl, k, H, tx, Pb_out);
+  } else {
+    if (Fp)
+      hipLaunchKernelGGL((f_block_kernel<T, true, W, RW>), grid, block, 0, s, kc, fin, fout, Pb, itau, Fp, ctl, k,
+                         H, tx);
+    else
+      hipLaunchKernelGGL((f_block_kernel<T, false, W, RW>), grid, block, 0, s, kc, fin, fout, Pb, itau, Fp, ctl, k,
+                         H, tx);
+  }
+}
+
+hipError_t block_launch_storage(int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, float *Pb_out,
+                                const float *itau, const float *Fp, const Ctl *ctl, long long k, int H,
+                                hipStream_t s) {
+  switch (storage) {
+    case LBTP_FP16_DEV: block_launch<_Float16>(kc, fin, fout, Pb, Pb_out, itau, Fp, ctl, k, H, s); break;
+    case LBTP_BF16_DEV: block_launch<bf16_t>(kc, fin, fout, Pb, Pb_out, itau, Fp, ctl, k, H, s); break;
+    default: block_launch<float>(kc, fin, fout, Pb, Pb_out, itau, Fp, ctl, k, H, s); break;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -45,12 +79,18 @@ hipError_t launch_f_block(int dim, int storage, const KC &kc, FPtrs fin, FPtrs f
                           const float *itau, const float *Fp, const Ctl *ctl, long long k, int H, hipStream_t s) {
   if (dim == kD2Q9) return launch_f_block_q9(storage, kc, fin, fout, Pb, itau, Fp, ctl, k, H, s);
   if (dim == 3) return launch_f_block_3d(storage, kc, fin, fout, Pb, itau, Fp, ctl, k, H, s);
-  switch (storage) {
-    case LBTP_FP16_DEV: block_launch<_Float16, kUseW, kUseRW>(kc, fin, fout, Pb, itau, Fp, ctl, k, H, s); break;
-    case LBTP_BF16_DEV: block_launch<bf16_t, kUseW, kUseRW>(kc, fin, fout, Pb, itau, Fp, ctl, k, H, s); break;
-    default: block_launch<float, kUseW, kUseRW>(kc, fin, fout, Pb, itau, Fp, ctl, k, H, s); break;
-  }
-  return hipGetLastError();
+  return block_launch_storage(storage, kc, fin, fout, Pb, nullptr, itau, Fp, ctl, k, H, s);
+}
+
+int block_first_supported(int dim, const KC &kc, int H) {
+  return dim == 2 && kc.nz == 1 && block_sweeps_supported(dim, kc, H);
+}
+
+hipError_t launch_f_block_first(int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, float *Pb_out,
+                                const float *itau, const float *Fp, const Ctl *ctl, long long k, int H,
+                                hipStream_t s) {
+  if (!Pb_out || Pb_out == Pb) return hipErrorInvalidValue;
+  return block_launch_storage(storage, kc, fin, fout, Pb, Pb_out, itau, Fp, ctl, k, H, s);
 }
 
 }  // namespace lbtp

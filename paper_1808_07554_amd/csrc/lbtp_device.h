@@ -308,6 +308,12 @@ __device__ inline void sweep_cell(const KC &kc, const FP<T> &fin, const FP<T> &f
   load_e<DIM, T, LOCAL>(fin, Pb_in, q, kc, pb, e);
   const float sum = dsum<DIM>(e);
   const float dP = sum * kc.inv_1mw0, wdP = sum * kc.w1_1mw0;
+  if (MODE == 3) {        // probe: the stopping-rule terms only
+    const float P = pb + dP;
+    acc[0] += (double)dP * (double)dP;
+    acc[1] += (double)P * (double)P;
+    return;
+  }
   const float it = itau[c];
   const float keep = 1.0f - it, gain = wdP * it;
   float add = HAS_FP ? kc.dt * kc.wbar * Fp[c] : 0.0f;
@@ -586,6 +592,21 @@ __device__ inline void sweep_quad(const KC &kc, const FP<T> &fin, const FP<T> &f
     load_pb_axis(kc, Pb_in, c, a, coordv, n, st, pbm, pbp);
     pull_axis_quad<T>(kc, fin, c, a, coordv, n, st, x0, (a == 1) ? z : y, pb, pbm, pbp, e[a == 1 ? 1 : 4],
                       e[a == 1 ? 3 : 5]);
+  }
+  if (MODE == 3) {        // probe: the stopping-rule terms only, as collide_quad forms them
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float ev[2 * DIM];
+#pragma unroll
+        for (int j = 0; j < 2 * DIM; ++j) ev[j] = f4get(e[j], i);
+        const float dP = dsum<DIM>(ev) * kc.inv_1mw0;
+        const float P = f4get(pb, i) + dP;
+        acc[0] += (double)dP * (double)dP;
+        acc[1] += (double)P * (double)P;
+      }
+    }
+    return;
   }
   const float4 it = *(const float4 *)(itau + c);
   float4 fp = make_float4(0.f, 0.f, 0.f, 0.f);

@@ -100,6 +100,8 @@ struct GPtrs {
 // dimension of those), kD2Q9 = D2Q9.
 constexpr int kD2Q9 = 9;
 
+// One pressure sweep per launch; mode as f_sweep_kernel's (3, the probe
+// that only evaluates the stopping-rule sums, on D2Q5 and D3Q7).
 hipError_t launch_f_sweep(int dim, int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb_in,
                           float *Pb_out, const float *itau, const float *Fp, double *partials, const Ctl *ctl,
                           long long k, int local, int mode, hipStream_t s);
@@ -111,6 +113,13 @@ hipError_t launch_f_sweep(int dim, int storage, const KC &kc, FPtrs fin, FPtrs f
 int block_sweeps_supported(int dim, const KC &kc, int H);
 hipError_t launch_f_block(int dim, int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb,
                           const float *itau, const float *Fp, const Ctl *ctl, long long k, int H, hipStream_t s);
+// The same on D2Q5 with the first sweep, k, re-basing (as f_sweep_kernel's
+// mode 1: a chunk's first sweep): the launch reads bases Pb and writes the
+// new ones to Pb_out (another buffer).
+int block_first_supported(int dim, const KC &kc, int H);
+hipError_t launch_f_block_first(int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, float *Pb_out,
+                                const float *itau, const float *Fp, const Ctl *ctl, long long k, int H,
+                                hipStream_t s);
 int block_sweeps_supported_q9(int H);
 int block_sweeps_supported_3d(int H);
 hipError_t launch_f_block_3d(int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, const float *itau,

@@ -45,7 +45,8 @@ namespace {
 // One iteration of eq. 3-1: stream, P (eq. 3-9a), BGK collision with the local
 // 1/tau_f (eq. 2-1b a) and the source dt wbar_i F_p, store at node y.
 // MODE 0: plain; 1: also reset the base to P (first sweep of a solve);
-// 2: reset the base and accumulate sum (P - P_b)^2 and sum P^2 (stopping rule).
+// 2: reset the base and accumulate sum (P - P_b)^2 and sum P^2 (stopping rule);
+// 3: a probe, which only accumulates those sums and writes nothing else.
 template <int DIM, typename T, bool LOCAL, int MODE, bool HAS_FP>
 __global__ __launch_bounds__(kThreads) void f_sweep_kernel(KC kc, FPtrs fin_, FPtrs fout_,
                                                            const float *__restrict__ Pb_in,
@@ -60,7 +61,7 @@ __global__ __launch_bounds__(kThreads) void f_sweep_kernel(KC kc, FPtrs fin_, FP
   double acc[2] = {0.0, 0.0};
   if (c < kc.ncell)
     sweep_cell<DIM, T, LOCAL, MODE, HAS_FP>(kc, typed<T>(fin_), typed<T>(fout_), Pb_in, Pb_out, itau, Fp, c, acc);
-  if (MODE == 2) block_sum<2>(acc, partials);
+  if (MODE >= 2) block_sum<2>(acc, partials);
 }
 
 template <int DIM, typename T, int MODE, bool HAS_FP>
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(kThreads) void f_sweep_vec_kernel(KC kc, FPtrs fin_
   double acc[2] = {0.0, 0.0};
   sweep_quad<DIM, T, MODE, HAS_FP>(kc, typed<T>(fin_), typed<T>(fout_), Pb_in, Pb_out, itau, Fp,
                                    blockIdx.x * kThreads + threadIdx.x, acc);
-  if (MODE == 2) block_sum<2>(acc, partials);
+  if (MODE >= 2) block_sum<2>(acc, partials);
 }
 
 // Stopping rule r = ||P^k - P^{k-m}|| / (m ||P^k||) from the block partials.
@@ -370,7 +371,9 @@ struct SweepLaunch {
       hipLaunchKernelGGL((f_sweep_kernel<DIM, T, LOCAL, M, HF>), LBTP_GRID(kc), kc, fin, fout, Pb_in, Pb_out,  \
                          itau, Fp, partials, ctl, k);                                                         \
   } while (0)
-    if (Fp) {
+    if (mode == 3) {
+      LBTP_SWEEP(3, false);   // P does not depend on the source
+    } else if (Fp) {
       if (mode == 0) LBTP_SWEEP(0, true);
       else if (mode == 1) LBTP_SWEEP(1, true);
       else LBTP_SWEEP(2, true);

@@ -89,6 +89,61 @@ def test_every_block_length_bitwise(H):
         assert np.array_equal(ref[k], got[k]), (H, k)
 
 
+def _run_checked(shape, bcs, sweep_block, m=64, Fp=False, tol=1e-7, steps=3):
+    """Solves with the stopping rule on: the first from the initial state
+    (local form: sweep 0 in a launch of its own), the later ones warm (pull
+    form: every chunk's re-basing sweep inside its first blocked launch)."""
+    nx, ny = shape
+    params, _ = inputs.injection_problem(shape, 1.0, 4.0, 11, 12)
+    params = dict(params, bc_f=bcs[0], bc_g=bcs[1])
+    fshape = (1, ny, nx)
+    K = f32(np.exp(inputs.gaussian_random_field((ny, nx), 4.0, nx + ny)).reshape(fshape) * params["mu_n"] / 6)
+    phi = f32(inputs.uniform_field(fshape, 0.15, 0.3, 7))
+    P0, S0 = (f32(a) for a in smooth_state(fshape, 5))
+    fp = f32(mean_free(np.sin(np.arange(nx * ny) * 0.37)) * 1e-3).reshape(fshape) if Fp else None
+    g = gpu_solver(params, m=m, sweep_block=sweep_block)
+    g.set_fields(K, phi, Fp=fp)
+    g.set_state(P0, S0)
+    solves = []
+    for n in range(steps):
+        g.update_coefficients()
+        solves.append(g.pressure_solve(tol, 10_000_000))
+        if n + 1 < steps:
+            g.saturation_step()
+    f, gg = g.populations()
+    out = dict(f=f.cpu().numpy(), g=gg.cpu().numpy(), P=g.pressure().cpu().numpy(), S=g.saturation().cpu().numpy())
+    g.close()
+    return solves, out
+
+
+CHECKED = [
+    ((200, 150), WALLS, 9, 64, {}),
+    ((130, 70), MIXED, 9, 64, dict(Fp=True)),
+    ((64, 64), PERIODIC, 9, 64, dict(Fp=True, tol=1e-9)),
+    ((150, 110), WALLS, 23, 64, {}),     # chunks of 17 + 17 + 15 + 15 sweeps (21 + 21 + 21 after sweep 0)
+    ((150, 110), WALLS, 3, 64, {}),
+    ((96, 47), WALLS, 9, 8, {}),         # short chunks: 5 + 3 sweeps (one launch of 7 after sweep 0)
+    ((20, 12), PERIODIC, 9, 6, dict(Fp=True)),   # 3 + 3 sweeps, narrower than the halo
+]
+
+
+@pytest.mark.parametrize("shape,bcs,H,m,kw", CHECKED)
+def test_checked_solves_blocked_equal_single_sweeps(shape, bcs, H, m, kw):
+    """The re-basing sweep of a chunk runs inside its first blocked launch
+    and the stopping rule is evaluated by a probe at the end of its last one:
+    same stopping iterations, bitwise the same state, and the residual up to
+    the order of its float64 sums."""
+    ref_solves, ref = _run_checked(shape, bcs, 1, m=m, **kw)
+    got_solves, got = _run_checked(shape, bcs, H, m=m, **kw)
+    print(shape, H, m, [(k, f"{r:.3e}") for k, r, _ in got_solves])
+    for (k0, r0, st0), (k1, r1, st1) in zip(ref_solves, got_solves):
+        assert (k0, st0) == (k1, st1), (ref_solves, got_solves)
+        assert abs(r1 - r0) <= 1e-12 * abs(r0), (r0, r1)
+    assert len(ref_solves[0]) and ref_solves[0][0] > m     # the cold solve runs several chunks
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), (shape, k, float(np.abs(ref[k] - got[k]).max()))
+
+
 @pytest.mark.parametrize("storage", ["fp16", "bf16"])
 def test_blocked_16bit_within_format_bound(storage):
     ref = _run((200, 150), WALLS, 1, storage=storage)
