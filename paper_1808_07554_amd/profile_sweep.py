@@ -192,6 +192,17 @@ def _short_name(name):
     return name
 
 
+def d2q5_block_length(grid_x, n):
+    """Sweeps per launch of a D2Q5 blocked launch (64 x 64 regions of 512
+    threads, tiles of 64 - 2H nodes a side) on an n x n grid, from its grid
+    size; None if no block length gives it."""
+    for h in range(3, 25, 2):
+        t = -(-n // (64 - 2 * h))
+        if t * t * 512 == grid_x:
+            return h
+    return None
+
+
 def summarize_trace(trace_csv, out_txt, title, command, lattice="D2Q5", n=4096, sweeps_per_launch=None):
     sweeps_per_launch = sweeps_per_launch or SWEEPS_PER_LAUNCH[lattice]
     with open(trace_csv) as f:
@@ -199,7 +210,13 @@ def summarize_trace(trace_csv, out_txt, title, command, lattice="D2Q5", n=4096, 
     agg = {}
     for r in rows:
         us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
-        agg.setdefault(_short_name(r["Kernel_Name"]), []).append(us)
+        name = _short_name(r["Kernel_Name"])
+        # D2Q5 chunks mix block lengths: one row per length
+        if lattice == "D2Q5" and name.split("<")[0] in ("f_block_kernel", "f_block_first_kernel"):
+            h = d2q5_block_length(int(r["Grid_Size_X"]), n)
+            if h is not None:
+                name = f"{name} H={h}"
+        agg.setdefault(name, []).append(us)
     total = sum(sum(v) for v in agg.values())
     lines = [title, f"command: {command}", "",
              f"{'kernel':66s} {'calls':>6s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} {'pct':>6s}"]
@@ -207,7 +224,8 @@ def summarize_trace(trace_csv, out_txt, title, command, lattice="D2Q5", n=4096, 
         lines.append(f"{k[:66]:66s} {len(v):6d} {sum(v) / len(v):9.2f} {min(v):9.2f} {max(v):9.2f} "
                      f"{100 * sum(v) / total:6.2f}")
     kname = sweep_kernel_name("fp32", 3 if lattice == "D3Q7" else 2, lattice, sweeps_per_launch)
-    blk = [v for k, v in agg.items() if k.split("<")[0] == kname]
+    blk = [v for k, v in agg.items() if k.split("<")[0] == kname and
+           (lattice != "D2Q5" or k.endswith(f" H={sweeps_per_launch}"))]
     if blk:
         d = blk[0]
         avg = sum(d) / len(d)
