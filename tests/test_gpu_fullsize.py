@@ -18,18 +18,21 @@ from tests.test_gpu_parity import UNIT_ROUNDOFF
 
 pytestmark = pytest.mark.gpu
 
-# pressure iterations before and after the saturation step.  65 runs sweep 0
-# and then one full chunk of m = 64 (sweeps 1 .. 63 in blocked launches of 9
-# on D2Q5 and D2Q9, sweep 64 alone), the configuration of the benchmark's
-# warm steps; D3Q7 has no blocked sweeps and runs 20.
-K1_2D, K1_3D, K2 = 65, 20, 6
+# pressure iterations before and after the saturation step.  From the
+# initial state 65 runs the local sweep 0 alone and then a chunk of blocked
+# launches (sweeps 1 .. 63, 9 per launch on D2Q5 and D2Q9) and sweep 64
+# alone.  After the saturation step the state is in pull form, and on D2Q5
+# the second solve of 65 (K2_2D) is a warm benchmark step's: the re-basing
+# sweep 0 inside the first of six blocked launches (11, 11, 11, 11, 11, 9
+# sweeps), then sweep 64 alone.  D3Q7 runs 20 and 6.
+K1_2D, K1_3D, K2, K2_2D = 65, 20, 6, 65
 
 
 def reach(k1, k2=K2):
     return 1 + k1 + 1 + 1 + k2 + 1 + 2
 
 
-def _run(solver, k1, k2=K2):
+def _run(solver, k1, k2):
     solver.update_coefficients()
     solver.pressure_solve(-1.0, k1)
     solver.saturation_step()
@@ -53,15 +56,15 @@ def _crop_params(params, lo, hi, full):
     return p
 
 
-def _check_samples(params, fl, samples, storage, k1):
+def _check_samples(params, fl, samples, storage, k1, k2=K2):
     full = params["shape"][:3] if params["lattice"] == "D3Q7" else params["shape"][:2]
-    R = reach(k1)
+    R = reach(k1, k2)
     dim = len(full)
     K, phi, P0, S0 = (inputs.f32(fl[k]) for k in ("K", "phi", "P0", "S0"))
     g = gpu_solver(params, m=64, storage=storage)
     g.set_fields(K.ravel(), phi.ravel())
     g.set_state(P0.ravel(), S0.ravel())
-    _run(g, k1)
+    _run(g, k1, k2)
     P = g.pressure().cpu().numpy()
     u = g.velocity().cpu().numpy()
     S = g.saturation().cpu().numpy()
@@ -78,7 +81,7 @@ def _check_samples(params, fl, samples, storage, k1):
         o = oracle_solver(cp, m=64)
         o.set_fields(f32(K[sl]), f32(phi[sl]))
         o.set_state(f32(P0[sl]), f32(S0[sl]))
-        _run(o, k1)
+        _run(o, k1, k2)
         loc = tuple(pt[a] - lo[a] for a in reversed(range(dim)))
         if dim == 2:
             loc = (0,) + loc
@@ -112,7 +115,7 @@ def _samples(full, rng, n_interior, R):
 def test_injection_2d_4096_sampled_parity(storage):
     params, fl = inputs.injection_2d(4096)
     rng = np.random.default_rng(17)
-    worst = _check_samples(params, fl, _samples((4096, 4096), rng, 4, reach(K1_2D)), storage, K1_2D)
+    worst = _check_samples(params, fl, _samples((4096, 4096), rng, 4, reach(K1_2D, K2_2D)), storage, K1_2D, K2_2D)
     tol = 1e-5 if storage == "fp32" else 16 * UNIT_ROUNDOFF[storage]
     for k, v in worst.items():
         assert v <= tol, (k, v, tol)
