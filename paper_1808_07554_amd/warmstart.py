@@ -290,11 +290,14 @@ def main():
     ap.add_argument("--no-weights", action="store_true", help="plain (unweighted) mean squared error")
     ap.add_argument("--load", default=None, help="start from these weights (.npy) instead of training from scratch")
     ap.add_argument("--out", default=None, help="write the report (JSON) and weights (.npy) with this prefix")
+    ap.add_argument("--eval-seed", type=int, default=6_000_000,
+                    help="seed of the first held-out field (item j of --eval starts 100 000 j later)")
     a = ap.parse_args()
     rep = {}
     net = lbtp.WarmStartNet(32, 4, a.scale)
     if a.load:
-        net.set_params(np.load(a.load).astype(np.float32))
+        with open(a.load, "rb") as f:        # a .npy file under any name
+            net.set_params(np.load(f).astype(np.float32))
     else:
         t0 = time.perf_counter()
         lnK, S, P, fac = training_set(a.train_fields, a.train_size, 1_000_000)
@@ -314,7 +317,7 @@ def main():
     rep["eval"] = []
     for j, item in enumerate(a.eval.split(",")):
         size, count = (int(v) for v in item.split(":"))
-        eK, eS, ephi = fields(count, size, 6_000_000 + 100_000 * j)
+        eK, eS, ephi = fields(count, size, a.eval_seed + 100_000 * j)
         r = evaluate(net, eK, eS, ephi, max(1, size // a.train_size), starts=a.starts.split(","))
         rep["eval"].append(r)
         print(json.dumps(r), file=sys.stderr, flush=True)
