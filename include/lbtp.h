@@ -62,12 +62,15 @@ typedef struct lbtp_ctx lbtp_ctx;
 /* D2Q9 plain pressure sweeps run blocked (several per launch) or four nodes per thread. */
 enum lbtp_lattice { LBTP_D2Q5 = 0, LBTP_D3Q7 = 1, LBTP_D2Q9 = 2 };
 
-/* Storage of the pressure-lattice populations.  Every form stores the
- * deviation of f_i from a per-node base equilibrium, f_i - w_i P_b, where P_b
- * is the pressure at the start of the solve or at the last residual check;
- * FP32 stores it as float, FP16_DEV as (power-of-two scaled) fp16, BF16_DEV
- * as bf16.  Collision arithmetic is float32 in every form, the saturation
- * lattice is float32, and the residual / mass reductions are float64. */
+/* Storage of the populations of both lattices.  The pressure lattice stores
+ * the deviation of f_i from a per-node base equilibrium, f_i - w_i P_b, where
+ * P_b is the pressure at the start of the solve or at the last residual
+ * check: FP32 as float, FP16_DEV as (power-of-two scaled) fp16, BF16_DEV as
+ * bf16.  The saturation lattice stores g_i itself as float under FP32, and
+ * under FP16_DEV / BF16_DEV the deviation g_i - g_i^eq(S_b) (eq. 3-4b) from
+ * the equilibrium of a per-node base saturation S_b, the saturation of the
+ * step that wrote it, in the same 16-bit format.  Collision arithmetic is
+ * float32 in every form, and the residual / mass reductions are float64. */
 enum lbtp_storage { LBTP_FP32 = 0, LBTP_FP16_DEV = 1, LBTP_BF16_DEV = 2 };
 
 /* Boundary condition of one face (faces ordered -x, +x, -y, +y, -z, +z).
