@@ -29,12 +29,32 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def build(verbose=False):
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(HERE, "..", "include"), "-o", tmp] + sources()
+def _compile(src, obj, verbose):
+    cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + ["-I", os.path.join(HERE, "..", "include"), "-c", "-o",
+                                                             obj, src]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
+    return obj
+
+
+def build(verbose=False, jobs=None):
+    """Compile every source to an object in a temporary folder (in parallel),
+    then link the shared library and move it into place."""
+    import concurrent.futures
+    import tempfile
+
+    srcs = sources()
+    jobs = jobs or min(len(srcs), os.cpu_count() or 1, 16)
+    with tempfile.TemporaryDirectory(prefix="lbtp_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.basename(f)[:-4] + ".o") for f in srcs]
+        with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
+            list(ex.map(lambda a: _compile(a[0], a[1], verbose), zip(srcs, objs)))
+        tmp = LIB + ".tmp"
+        cmd = [HIPCC] + FLAGS + ["-o", tmp] + objs
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
 
