@@ -53,6 +53,17 @@ __device__ inline float blk_wall_rule(const KC &kc, int face, int x, int y, floa
   return kc.bc_f[face] == LBTP_BC_DIRICHLET ? 2.0f * kc.w1 * (wall_P(kc, face, x, y, 0, 1, 0) - pb) - o : o;
 }
 
+// Element i of an array, addressed by a 32-bit byte offset from its base
+// (a context holds fewer than 2^31 populations, so no array reaches 4 GiB).
+template <typename T>
+__device__ inline T *blk_at(T *p, uint32_t i) {
+  return (T *)((char *)p + i * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ inline const T *blk_at(const T *p, uint32_t i) {
+  return (const T *)((const char *)p + i * (uint32_t)sizeof(T));
+}
+
 // State of one lane: RW rows of its column.
 template <int RW, bool HAS_FP>
 struct BlkRows {
@@ -156,8 +167,8 @@ __device__ inline void blk_sweep_rows(const KC &kc, BlkRows<RW, HAS_FP> &r, floa
     if (wv < W - 1) r.pb[RW + 1] = pbx[0][wv + 1][lane];
 #pragma unroll
     for (int t = 0; t < RW; ++t) {
-      r.pbl[t] = __shfl_up(r.pb[t + 1], 1, 64);
-      r.pbr[t] = __shfl_down(r.pb[t + 1], 1, 64);
+      r.pbl[t] = lane_from_left(r.pb[t + 1]);
+      r.pbr[t] = lane_from_right(r.pb[t + 1]);
     }
     s = 2;
   }
@@ -200,29 +211,53 @@ __device__ inline void block_region(const KC &kc, const FP<T> &fin, const FP<T> 
   auto row_in = [&](int uy) { return pery || (uy >= 0 && uy < kc.ny); };
   auto gidx = [&](int uy) { return (pery ? blk_wrap(uy, kc.ny) : uy) * kc.nx + gx; };
 
+  // a region one node or more inside the domain on every side (most of a
+  // large grid) wraps no index, holds no wall node and needs no row or column
+  // test; its loads take 32-bit offsets from the arrays' uniform base
+  // addresses, one offset per row shared by every array
+  const bool interior = gx0 >= 1 && gx0 + kBX <= kc.nx - 1 && gy0 >= 1 && gy0 + kBY <= kc.ny - 1;
   BlkRows<RW, HAS_FP> r;
+  if (interior) {
+    const uint32_t rs = (uint32_t)kc.nx, n0 = (uint32_t)uy0 * rs + (uint32_t)ux;
 #pragma unroll
-  for (int t = 0; t < RW + 2; ++t) {
-    const int uy = uy0 + t - 1;
-    r.pb[t] = (colin && row_in(uy)) ? Pb[gidx(uy)] : 0.0f;
+    for (int t = 0; t < RW + 2; ++t) r.pb[t] = *blk_at(Pb, n0 + (uint32_t)t * rs - rs);
+#pragma unroll
+    for (int t = 0; t < RW; ++t) {
+      const uint32_t c = n0 + (uint32_t)t * rs;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) r.d[t][j] = Storage<T>::load(blk_at(fin.p[j], c), 0, is);
+      r.it[t] = *blk_at(itau, c);
+      if (HAS_FP) r.fp[t] = kc.dt * kc.wbar * *blk_at(Fp, c);
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < RW + 2; ++t) {
+      const int uy = uy0 + t - 1;
+      r.pb[t] = (colin && row_in(uy)) ? Pb[gidx(uy)] : 0.0f;
+    }
+#pragma unroll
+    for (int t = 0; t < RW; ++t) {
+      const int uy = uy0 + t;
+      const bool in = colin && row_in(uy);
+      const int c = in ? gidx(uy) : 0;
+      // every load is issued (from node 0 outside the domain) and the value
+      // selected afterwards: a load made conditional on the row would make
+      // the compiler wait for each one before issuing the next
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float v = Storage<T>::load(fin.p[j], c, is);
+        r.d[t][j] = in ? v : 0.0f;
+      }
+      r.it[t] = in ? itau[c] : 0.0f;
+      if (HAS_FP) r.fp[t] = in ? kc.dt * kc.wbar * Fp[c] : 0.0f;
+    }
   }
+  // the x-neighbours' bases by lane shifts (the outermost lanes get 0: they
+  // are columns outside the tile's dependence cone, or beyond a wall)
 #pragma unroll
   for (int t = 0; t < RW; ++t) {
-    const int uy = uy0 + t;
-    const bool in = colin && row_in(uy);
-    const int c = in ? gidx(uy) : 0;
-    // every load is issued (from node 0 outside the domain) and the value
-    // selected afterwards: a load made conditional on the row would make the
-    // compiler wait for each one before issuing the next
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const float v = Storage<T>::load(fin.p[j], c, is);
-      r.d[t][j] = in ? v : 0.0f;
-    }
-    r.it[t] = in ? itau[c] : 0.0f;
-    if (HAS_FP) r.fp[t] = in ? kc.dt * kc.wbar * Fp[c] : 0.0f;
-    r.pbl[t] = __shfl_up(r.pb[t + 1], 1, 64);
-    r.pbr[t] = __shfl_down(r.pb[t + 1], 1, 64);
+    r.pbl[t] = lane_from_left(r.pb[t + 1]);
+    r.pbr[t] = lane_from_right(r.pb[t + 1]);
   }
   xup[0][wv][lane] = r.d[RW - 1][1];
   xdn[0][wv][lane] = r.d[0][3];
@@ -242,10 +277,10 @@ __device__ inline void block_region(const KC &kc, const FP<T> &fin, const FP<T> 
 #pragma unroll
   for (int t = 0; t < RW; ++t) {
     if (!trow(t)) continue;
-    const int c = (uy0 + t) * kc.nx + ux;
+    const uint32_t c = (uint32_t)(uy0 + t) * (uint32_t)kc.nx + (uint32_t)ux;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) Storage<T>::store(fout.p[j], c, r.d[t][j], kc.dev_scale);
-    if (FIRST) Pb_out[c] = r.pb[t + 1];
+    for (int j = 0; j < 4; ++j) Storage<T>::store(blk_at(fout.p[j], c), 0, r.d[t][j], kc.dev_scale);
+    if (FIRST) *blk_at(Pb_out, c) = r.pb[t + 1];
   }
 }
 
