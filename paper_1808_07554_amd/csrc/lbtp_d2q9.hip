@@ -80,6 +80,12 @@ __device__ inline int q9_wrap_any(int v, int n) {
   return r < 0 ? r + n : r;
 }
 
+// Element i of an array, addressed by a 32-bit byte offset from its base.
+template <typename T>
+__device__ inline T *q9_at(T *p, uint32_t i) {
+  return (T *)((char *)p + i * (uint32_t)sizeof(T));
+}
+
 // BGK_ONLY: the collision is BGK, so the sweep loop carries no MRT code (4 %
 // of its time); otherwise kc.mrt chooses at run time (a fixed MRT would
 // need more than 128 registers).
@@ -116,25 +122,49 @@ __global__ __launch_bounds__(kQ9BX * kQ9W) void q9_f_block_kernel(KC kc, FPtrs f
   float d[RW][8], it[RW];
   float fpv[HAS_FP ? RW : 1];
   float pb[RW + 2], pbl[RW + 2], pbr[RW + 2];   // base of rows -1 .. RW at x, x - 1, x + 1
+  // a region one node or more inside the domain on every side wraps no
+  // index, holds no wall node and needs no row or column test; its loads take
+  // 32-bit offsets from the arrays' uniform base addresses (a context holds
+  // fewer than 2^31 populations, so no array reaches 4 GiB)
+  const bool interior = gx0 >= 1 && gx0 + kQ9BX <= kc.nx - 1 && gy0 >= 1 && gy0 + BY <= kc.ny - 1;
+  if (interior) {
+    const uint32_t rs = (uint32_t)kc.nx, n0 = (uint32_t)uy0 * rs + (uint32_t)ux;
+#pragma unroll
+    for (int t = 0; t < RW + 2; ++t) pb[t] = *q9_at(Pb, n0 + (uint32_t)t * rs - rs);
+#pragma unroll
+    for (int t = 0; t < RW; ++t) {
+      const uint32_t c = n0 + (uint32_t)t * rs;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) d[t][j] = Storage<T>::load(q9_at(fin.p[j], c), 0, is);
+      it[t] = *q9_at(itau, c);
+      if (HAS_FP) fpv[t] = kc.dt * kc.wbar * *q9_at(Fp, c);
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < RW + 2; ++t) {
+      const int uy = uy0 + t - 1;
+      pb[t] = (colin && row_in(uy)) ? Pb[gidx(uy)] : 0.0f;
+    }
+#pragma unroll
+    for (int t = 0; t < RW; ++t) {
+      const int uy = uy0 + t;
+      const bool in = colin && row_in(uy);
+      const int c = in ? gidx(uy) : 0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {   // unconditional loads, selected afterwards (as in block_region)
+        const float v = Storage<T>::load(fin.p[j], c, is);
+        d[t][j] = in ? v : 0.0f;
+      }
+      it[t] = in ? itau[c] : 0.0f;
+      if (HAS_FP) fpv[t] = in ? kc.dt * kc.wbar * Fp[c] : 0.0f;
+    }
+  }
+  // the x-neighbours' bases by lane shifts (the outermost lanes get 0: they
+  // are columns outside the tile's dependence cone, or beyond a wall)
 #pragma unroll
   for (int t = 0; t < RW + 2; ++t) {
-    const int uy = uy0 + t - 1;
-    pb[t] = (colin && row_in(uy)) ? Pb[gidx(uy)] : 0.0f;
-    pbl[t] = __shfl_up(pb[t], 1, 64);
-    pbr[t] = __shfl_down(pb[t], 1, 64);
-  }
-#pragma unroll
-  for (int t = 0; t < RW; ++t) {
-    const int uy = uy0 + t;
-    const bool in = colin && row_in(uy);
-    const int c = in ? gidx(uy) : 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {   // unconditional loads, selected afterwards (as in block_region)
-      const float v = Storage<T>::load(fin.p[j], c, is);
-      d[t][j] = in ? v : 0.0f;
-    }
-    it[t] = in ? itau[c] : 0.0f;
-    if (HAS_FP) fpv[t] = in ? kc.dt * kc.wbar * Fp[c] : 0.0f;
+    pbl[t] = lane_from_left(pb[t]);
+    pbr[t] = lane_from_right(pb[t]);
   }
   xup[0][0][wv][lane] = d[RW - 1][1];
   xup[0][1][wv][lane] = d[RW - 1][4];
@@ -261,9 +291,9 @@ __global__ __launch_bounds__(kQ9BX * kQ9W) void q9_f_block_kernel(KC kc, FPtrs f
   for (int t = 0; t < RW; ++t) {
     const int ry = wv * RW + t, uy = uy0 + t;
     if (ry < H || ry >= BY - H || uy >= kc.ny) continue;
-    const int c = uy * kc.nx + ux;
+    const uint32_t c = (uint32_t)uy * (uint32_t)kc.nx + (uint32_t)ux;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) Storage<T>::store(fout.p[j], c, d[t][j], kc.dev_scale);
+    for (int j = 0; j < 8; ++j) Storage<T>::store(q9_at(fout.p[j], c), 0, d[t][j], kc.dev_scale);
   }
 }
 
