@@ -178,8 +178,53 @@ source_sha256: {sha}  (csrc/{", csrc/".join(sweep_sources(lattice))})
     print(text)
 
 
+def _demangle_lbtp(name):
+    """Readable form of a mangled kernel name of this library that the
+    profiler left mangled (it does so where a template argument is
+    _Float16): name<args> for the argument kinds the kernels use (types,
+    bools, ints); None for anything else."""
+    import re
+    m = re.match(r"_ZN4lbtp12_GLOBAL__N_1(\d+)", name)
+    if not m:
+        return None
+    k = m.end()
+    ident = name[k:k + int(m.group(1))]
+    k += int(m.group(1))
+    if k >= len(name) or name[k] != "I":
+        return ident
+    k += 1
+    args = []
+    simple = {"f": "float", "d": "double", "i": "int", "b": "bool"}
+    while k < len(name) and name[k] != "E":
+        if name.startswith("DF16_", k):
+            args.append("_Float16")
+            k += 5
+        elif name[k] in simple:
+            args.append(simple[name[k]])
+            k += 1
+        elif name[k] == "L":
+            lit = re.match(r"L([bi])(n?\d+)E", name[k:])
+            if not lit:
+                return None
+            v = lit.group(2).replace("n", "-")
+            args.append(("true" if v == "1" else "false") if lit.group(1) == "b" else v)
+            k += lit.end()
+        elif name[k] == "N":
+            nested = re.match(r"NS\d*_(\d+)", name[k:])
+            if not nested:
+                return None
+            j = k + nested.end()
+            args.append(name[j:j + int(nested.group(1))])
+            k = j + int(nested.group(1)) + 1   # the closing E
+        else:
+            return None
+    return f"{ident}<{', '.join(args)}>"
+
+
 def _short_name(name):
     """Kernel name without return type, namespaces and argument list."""
+    if name.startswith("_Z"):
+        name = _demangle_lbtp(name) or name
     name = name.replace("void ", "").replace("lbtp::", "").replace("(anonymous namespace)::", "")
     depth = 0
     for i, ch in enumerate(name):
