@@ -98,7 +98,12 @@ __device__ inline void blk_pass(const KC &kc, BlkRows<RW, HAS_FP> &r, float prev
     // so inner rows reuse that value instead of holding one of their own
     e[3] = t < RW - 1 ? v3 - kc.w1 * (r.pb[t + 1] - r.pb[t + 2]) : v3 + kc.w1 * (r.pb[t + 2] - p);
     if (walls) {
-      const int uy = uy0 + t;
+      // the row index is made opaque here so that the compiler forms the
+      // wall rows' coordinates (a modulo on a periodic axis) inside this
+      // branch, in the regions that hold wall nodes, instead of hoisting
+      // them for every region and row out of the sweep loop
+      int uy = uy0 + t;
+      asm volatile("" : "+v"(uy));
       const int wy = pery ? blk_wrap(uy, kc.ny) : uy;
       if (wall_l) e[0] = blk_wall_rule(kc, 0, 0, wy, p, r.d[t][2]);
       if (wall_r) e[2] = blk_wall_rule(kc, 1, kc.nx - 1, wy, p, r.d[t][0]);
