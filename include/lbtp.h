@@ -321,8 +321,8 @@ LBTP_API int lbtp_batch_mass(lbtp_batch *b, int member, double *mass, double *le
  * sweeps of the whole ensemble for each width (leaving the state unchanged)
  * and keeps the fastest; *threads receives it.  With blocked plain sweeps
  * (D2Q5, sweep_block > 1) it then tunes, for each size class of members (one
- * grid size), the region shape of the blocked kernel (8 x 8, 8 x 6, 16 x 4 or
- * 4 x 8 wavefronts x rows) and the sweeps per launch (an odd divisor >= 3 of
+ * grid size), the region shape of the blocked kernel (8 x 8, 8 x 6, 16 x 4,
+ * 4 x 8 or 8 x 9 wavefronts x rows) and the sweeps per launch (an odd divisor >= 3 of
  * the m - 1 plain sweeps of a chunk), timing `sweeps` chunks' worth of
  * blocked launches per candidate, and keeps the fastest per class; the
  * choice is remembered for the process (by grid size, storage and m) and

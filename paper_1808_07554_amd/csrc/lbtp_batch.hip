@@ -122,8 +122,10 @@ void batch_block_launch_shape(bool has_fp, int nblk, const Member *mem, const BC
 template <typename T>
 void batch_block_launch(int shape, bool has_fp, int nblk, const Member *mem, const BCtl *ctl, const int *tm,
                         const int *ti, int j, int H, hipStream_t s) {
-  static_assert(batch_shape_rows(0) == kUseW * kUseRW, "shape 0 is the single-context launch shape");
+  static_assert(batch_shape_rows(0) == kUseW * kUseRW && batch_shape_rows(4) == kUseW * kUseRWPlain,
+                "shapes 0 and 4 are the single-context launch shapes");
   switch (shape) {
+    case 4: batch_block_launch_shape<T, batch_shape_w(4), batch_shape_rw(4)>(has_fp, nblk, mem, ctl, tm, ti, j, H, s); break;
     case 1: batch_block_launch_shape<T, batch_shape_w(1), batch_shape_rw(1)>(has_fp, nblk, mem, ctl, tm, ti, j, H, s); break;
     case 2: batch_block_launch_shape<T, batch_shape_w(2), batch_shape_rw(2)>(has_fp, nblk, mem, ctl, tm, ti, j, H, s); break;
     case 3: batch_block_launch_shape<T, batch_shape_w(3), batch_shape_rw(3)>(has_fp, nblk, mem, ctl, tm, ti, j, H, s); break;

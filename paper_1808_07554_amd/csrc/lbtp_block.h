@@ -31,11 +31,13 @@ namespace lbtp {
 
 constexpr int kBX = 64;        // region columns: one per lane
 constexpr int kBWmax = 16;     // most wavefronts per workgroup
-// The launch shape in use: 8 wavefronts of 8 rows (a 64 x 64 region), so
-// that two workgroups fit a compute unit and one loads while the other
-// sweeps (measured on the 4096^2 injection problem against 16 x 6, 16 x 8,
-// 8 x 6 and 8 x 10).
-constexpr int kUseW = 8, kUseRW = 8;
+// The launch shapes in use: 8 wavefronts of 9 rows (a 64 x 72 region)
+// without a pressure source and of 8 rows (64 x 64) with one, so that two
+// workgroups fit a compute unit (at most 128 registers a lane) and one loads
+// while the other sweeps (measured on the 4096^2 injection problem against
+// 16 x 6, 16 x 8, 8 x 6, 8 x 8 and 8 x 10; 9 rows and a source need 130
+// registers).
+constexpr int kUseW = 8, kUseRW = 8, kUseRWPlain = 9;
 
 __device__ inline int blk_wrap(int v, int n) {
   const int r = v % n;
@@ -296,18 +298,19 @@ __host__ __device__ inline void block_tile_counts_rows(const KC &kc, int H, int 
   *ty = (kc.ny + trows - 1) / trows;
 }
 
-// The same for the launch shape of single contexts.
-__host__ __device__ inline void block_tile_counts(const KC &kc, int H, int *tx, int *ty) {
-  block_tile_counts_rows(kc, H, kUseW * kUseRW, tx, ty);
+// The same for the launch shape of single contexts (with or without a
+// pressure source).
+__host__ __device__ inline void block_tile_counts(const KC &kc, int H, bool has_fp, int *tx, int *ty) {
+  block_tile_counts_rows(kc, H, kUseW * (has_fp ? kUseRW : kUseRWPlain), tx, ty);
 }
 
 // Region shapes the ensemble autotuner chooses from: W wavefronts of RW rows.
 // Every one keeps the region in registers; they differ in region height
 // (the halo share and the ragged last tile of a small member) and in the
 // number of workgroups a compute unit holds.
-constexpr int kBatchShapes = 4;
-__host__ __device__ constexpr int batch_shape_w(int s) { return s == 0 ? 8 : s == 1 ? 8 : s == 2 ? 16 : 4; }
-__host__ __device__ constexpr int batch_shape_rw(int s) { return s == 0 ? 8 : s == 1 ? 6 : s == 2 ? 4 : 8; }
+constexpr int kBatchShapes = 5;
+__host__ __device__ constexpr int batch_shape_w(int s) { return s == 0 ? 8 : s == 1 ? 8 : s == 2 ? 16 : s == 3 ? 4 : 8; }
+__host__ __device__ constexpr int batch_shape_rw(int s) { return s == 0 ? 8 : s == 1 ? 6 : s == 2 ? 4 : s == 3 ? 8 : 9; }
 __host__ __device__ constexpr int batch_shape_rows(int s) { return batch_shape_w(s) * batch_shape_rw(s); }
 
 }  // namespace lbtp

@@ -35,20 +35,20 @@ __global__ __launch_bounds__(kBX * W) void f_block_first_kernel(
 template <typename T>
 void block_launch(const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, float *Pb_out, const float *itau,
                   const float *Fp, const Ctl *ctl, long long k, int H, hipStream_t s) {
-  constexpr int W = kUseW, RW = kUseRW;
+  constexpr int W = kUseW, RWF = kUseRW, RW = kUseRWPlain;
   int tx, ty;
-  block_tile_counts(kc, H, &tx, &ty);
+  block_tile_counts(kc, H, Fp != nullptr, &tx, &ty);
   const dim3 grid(tx * ty), block(kBX * W);
   if (Pb_out) {
     if (Fp)
-      hipLaunchKernelGGL((f_block_first_kernel<T, true, W, RW>), grid, block, 0, s, kc, fin, fout, Pb, itau, Fp,
+      hipLaunchKernelGGL((f_block_first_kernel<T, true, W, RWF>), grid, block, 0, s, kc, fin, fout, Pb, itau, Fp,
                          ctl, k, H, tx, Pb_out);
     else
       hipLaunchKernelGGL((f_block_first_kernel<T, false, W, RW>), grid, block, 0, s, kc, fin, fout, Pb, itau, Fp,
                          ctl, k, H, tx, Pb_out);
   } else {
     if (Fp)
-      hipLaunchKernelGGL((f_block_kernel<T, true, W, RW>), grid, block, 0, s, kc, fin, fout, Pb, itau, Fp, ctl, k,
+      hipLaunchKernelGGL((f_block_kernel<T, true, W, RWF>), grid, block, 0, s, kc, fin, fout, Pb, itau, Fp, ctl, k,
                          H, tx);
     else
       hipLaunchKernelGGL((f_block_kernel<T, false, W, RW>), grid, block, 0, s, kc, fin, fout, Pb, itau, Fp, ctl, k,

@@ -237,13 +237,15 @@ def _short_name(name):
     return name
 
 
-def d2q5_block_length(grid_x, n):
-    """Sweeps per launch of a D2Q5 blocked launch (64 x 64 regions of 512
-    threads, tiles of 64 - 2H nodes a side) on an n x n grid, from its grid
-    size; None if no block length gives it."""
+def d2q5_block_length(grid_x, n, rows=72):
+    """Sweeps per launch of a D2Q5 blocked launch (regions of 64 columns x
+    `rows` rows, 512 threads, tiles of (64 - 2H) x (rows - 2H) nodes; 72 rows
+    without a pressure source) on an n x n grid, from its grid size; None if
+    no block length gives it."""
     for h in range(3, 25, 2):
-        t = -(-n // (64 - 2 * h))
-        if t * t * 512 == grid_x:
+        tx = -(-n // (64 - 2 * h))
+        ty = -(-n // (rows - 2 * h))
+        if tx * ty * 512 == grid_x:
             return h
     return None
 
