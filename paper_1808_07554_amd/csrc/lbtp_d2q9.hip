@@ -63,7 +63,8 @@ __global__ __launch_bounds__(kThreads) void q9_f_sweep_vec_kernel(KC kc, FPtrs f
 // ------------------------------------------------ blocked plain sweeps
 // H plain sweeps per launch with the region held in registers, as the D2Q5
 // blocked kernel (lbtp_block.h) does: each lane owns one column of a
-// 64-column region, each of the kQ9W wavefronts kQ9RW consecutive rows.
+// 64-column region, each of the kQ9W wavefronts RW consecutive rows (5 for
+// the BGK kernel without a source, 126 registers; kQ9RW = 4 otherwise).
 // Populations moving along x or diagonally come from the adjacent lanes
 // (shuffles), those moving along y from the lane's own rows or, across
 // wavefronts, through an LDS exchange of the three populations that leave a
@@ -89,7 +90,7 @@ __device__ inline T *q9_at(T *p, uint32_t i) {
 // BGK_ONLY: the collision is BGK, so the sweep loop carries no MRT code (4 %
 // of its time); otherwise kc.mrt chooses at run time (a fixed MRT would
 // need more than 128 registers).
-template <typename T, bool HAS_FP, bool BGK_ONLY>
+template <typename T, bool HAS_FP, bool BGK_ONLY, int RW>
 __global__ __launch_bounds__(kQ9BX * kQ9W) void q9_f_block_kernel(KC kc, FPtrs fin_, FPtrs fout_,
                                                                   const float *__restrict__ Pb,
                                                                   const float *__restrict__ itau,
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(kQ9BX * kQ9W) void q9_f_block_kernel(KC kc, FPtrs f
                                                                   const Ctl *__restrict__ ctl, long long k, int H,
                                                                   int tiles_x) {
   if (ctl->done || k > ctl->kmax) return;
-  constexpr int W = kQ9W, RW = kQ9RW, BY = W * RW;
+  constexpr int W = kQ9W, BY = W * RW;
   // two copies (sweep s reads copy (s - 1) & 1): the upward populations of
   // each wavefront's last row, the downward ones of its first row
   __shared__ float xup[2][3][W][kQ9BX];
@@ -505,7 +506,10 @@ int block_sweeps_supported_q9(int H) { return H >= 3 && H % 2 == 1 && kQ9BX - 2 
 
 hipError_t launch_f_block_q9(int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, const float *itau,
                              const float *Fp, const Ctl *ctl, long long k, int H, hipStream_t s) {
-  const int tcols = kQ9BX - 2 * H, trows = kQ9W * kQ9RW - 2 * H;
+  // 5 rows per wavefront (an 80-row region) for the BGK kernel without a
+  // source, 4 (64 rows) where a source or MRT leaves too few registers
+  const int rw = (!Fp && !kc.mrt) ? 5 : kQ9RW;
+  const int tcols = kQ9BX - 2 * H, trows = kQ9W * rw - 2 * H;
   const int tx = (kc.nx + tcols - 1) / tcols, ty = (kc.ny + trows - 1) / trows;
   q9_dispatch(storage, 0, [&](auto t, auto) {
     using T = std::remove_pointer_t<decltype(t)>;
@@ -513,11 +517,11 @@ hipError_t launch_f_block_q9(int storage, const KC &kc, FPtrs fin, FPtrs fout, c
       hipLaunchKernelGGL(kernel, dim3(tx * ty), dim3(kQ9BX * kQ9W), 0, s, kc, fin, fout, Pb, itau, Fp, ctl, k, H, tx);
     };
     if (Fp) {
-      if (kc.mrt) go(q9_f_block_kernel<T, true, false>);
-      else go(q9_f_block_kernel<T, true, true>);
+      if (kc.mrt) go(q9_f_block_kernel<T, true, false, 4>);
+      else go(q9_f_block_kernel<T, true, true, 5>);
     } else {
-      if (kc.mrt) go(q9_f_block_kernel<T, false, false>);
-      else go(q9_f_block_kernel<T, false, true>);
+      if (kc.mrt) go(q9_f_block_kernel<T, false, false, 4>);
+      else go(q9_f_block_kernel<T, false, true, 5>);
     }
   });
   return hipGetLastError();
