@@ -31,12 +31,13 @@ namespace lbtp {
 
 constexpr int kBX = 64;        // region columns: one per lane
 constexpr int kBWmax = 16;     // most wavefronts per workgroup
-// The launch shapes in use: 8 wavefronts of 9 rows (a 64 x 72 region)
-// without a pressure source and of 8 rows (64 x 64) with one, so that two
-// workgroups fit a compute unit (at most 128 registers a lane) and one loads
-// while the other sweeps (measured on the 4096^2 injection problem against
-// 16 x 6, 16 x 8, 8 x 6, 8 x 8 and 8 x 10; 9 rows and a source need 130
-// registers).
+// The launch shapes of single contexts: 8 wavefronts of 9 rows (a 64 x 72
+// region) without a pressure source (grids of few tiles may take 8 rows, see
+// block_rows_per_wave in lbtp_block.hip) and of 8 rows (64 x 64) with one, so
+// that two workgroups fit a compute unit (at most 128 registers a lane) and
+// one loads while the other sweeps (measured on the 4096^2 injection problem
+// against 16 x 6, 16 x 8, 8 x 6, 8 x 8 and 8 x 10; 9 rows and a source need
+// 130 registers, 10 rows 134).
 constexpr int kUseW = 8, kUseRW = 8, kUseRWPlain = 9;
 
 __device__ inline int blk_wrap(int v, int n) {
@@ -296,12 +297,6 @@ __host__ __device__ inline void block_tile_counts_rows(const KC &kc, int H, int 
   const int tcols = kBX - 2 * H, trows = rows - 2 * H;
   *tx = (kc.nx + tcols - 1) / tcols;
   *ty = (kc.ny + trows - 1) / trows;
-}
-
-// The same for the launch shape of single contexts (with or without a
-// pressure source).
-__host__ __device__ inline void block_tile_counts(const KC &kc, int H, bool has_fp, int *tx, int *ty) {
-  block_tile_counts_rows(kc, H, kUseW * (has_fp ? kUseRW : kUseRWPlain), tx, ty);
 }
 
 // Region shapes the ensemble autotuner chooses from: W wavefronts of RW rows.

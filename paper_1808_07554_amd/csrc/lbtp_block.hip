@@ -32,28 +32,56 @@ __global__ __launch_bounds__(kBX * W) void f_block_first_kernel(
                                     Pb_out);
 }
 
-template <typename T>
-void block_launch(const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, float *Pb_out, const float *itau,
-                  const float *Fp, const Ctl *ctl, long long k, int H, hipStream_t s) {
-  constexpr int W = kUseW, RWF = kUseRW, RW = kUseRWPlain;
+// Rows per wavefront of a launch: 9 (a 64 x 72 region, less halo per node)
+// without a pressure source, 8 with one.  On a grid of few tiles (fewer
+// than two rounds of resident workgroups, two per compute unit, at 8 rows)
+// 9 rows are taken only if they need no more rounds x rows than 8: there
+// more and shorter workgroups finish sooner.
+inline int block_rows_per_wave(const KC &kc, int H, bool has_fp) {
+  if (has_fp) return kUseRW;
+  const long long slots = 2LL * device_cus();
+  long long tiles[2];
+  const int rws[2] = {kUseRW, kUseRWPlain};
+  for (int i = 0; i < 2; ++i) {
+    int tx, ty;
+    block_tile_counts_rows(kc, H, kUseW * rws[i], &tx, &ty);
+    tiles[i] = (long long)tx * ty;
+  }
+  if (tiles[0] >= 2 * slots) return kUseRWPlain;
+  return (tiles[1] + slots - 1) / slots * rws[1] <= (tiles[0] + slots - 1) / slots * rws[0] ? kUseRWPlain : kUseRW;
+}
+
+template <typename T, int RW>
+void block_launch_rw(const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, float *Pb_out, const float *itau,
+                     const float *Fp, const Ctl *ctl, long long k, int H, hipStream_t s) {
+  constexpr int W = kUseW;
   int tx, ty;
-  block_tile_counts(kc, H, Fp != nullptr, &tx, &ty);
+  block_tile_counts_rows(kc, H, W * RW, &tx, &ty);
   const dim3 grid(tx * ty), block(kBX * W);
   if (Pb_out) {
     if (Fp)
-      hipLaunchKernelGGL((f_block_first_kernel<T, true, W, RWF>), grid, block, 0, s, kc, fin, fout, Pb, itau, Fp,
+      hipLaunchKernelGGL((f_block_first_kernel<T, true, W, RW>), grid, block, 0, s, kc, fin, fout, Pb, itau, Fp,
                          ctl, k, H, tx, Pb_out);
     else
       hipLaunchKernelGGL((f_block_first_kernel<T, false, W, RW>), grid, block, 0, s, kc, fin, fout, Pb, itau, Fp,
                          ctl, k, H, tx, Pb_out);
   } else {
     if (Fp)
-      hipLaunchKernelGGL((f_block_kernel<T, true, W, RWF>), grid, block, 0, s, kc, fin, fout, Pb, itau, Fp, ctl, k,
+      hipLaunchKernelGGL((f_block_kernel<T, true, W, RW>), grid, block, 0, s, kc, fin, fout, Pb, itau, Fp, ctl, k,
                          H, tx);
     else
       hipLaunchKernelGGL((f_block_kernel<T, false, W, RW>), grid, block, 0, s, kc, fin, fout, Pb, itau, Fp, ctl, k,
                          H, tx);
   }
+}
+
+template <typename T>
+void block_launch(const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, float *Pb_out, const float *itau,
+                  const float *Fp, const Ctl *ctl, long long k, int H, hipStream_t s) {
+  if (Fp || block_rows_per_wave(kc, H, false) == kUseRW)
+    block_launch_rw<T, kUseRW>(kc, fin, fout, Pb, Pb_out, itau, Fp, ctl, k, H, s);
+  else
+    block_launch_rw<T, kUseRWPlain>(kc, fin, fout, Pb, Pb_out, itau, Fp, ctl, k, H, s);
 }
 
 hipError_t block_launch_storage(int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, float *Pb_out,

@@ -223,8 +223,9 @@ __global__ __launch_bounds__(kZBX * kZW) void f_zstream_kernel(KC kc, FPtrs fin_
   }
 }
 
-// Compute units of the current device (one workgroup of 16 wavefronts fits
-// a compute unit at a time).
+}  // namespace
+
+// Compute units of the current device (queried once per device).
 int device_cus() {
   static std::atomic<int> cus[64];   // 0 = not queried yet (a repeated query writes the same value)
   int dev = 0;
@@ -236,6 +237,9 @@ int device_cus() {
   }
   return n;
 }
+
+namespace {
+
 
 // Columns of 64 - 2H x 16 - 2H output nodes; the number of z segments is the
 // one that minimises rounds of resident workgroups x planes walked per

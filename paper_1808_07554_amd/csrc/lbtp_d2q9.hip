@@ -64,7 +64,8 @@ __global__ __launch_bounds__(kThreads) void q9_f_sweep_vec_kernel(KC kc, FPtrs f
 // H plain sweeps per launch with the region held in registers, as the D2Q5
 // blocked kernel (lbtp_block.h) does: each lane owns one column of a
 // 64-column region, each of the kQ9W wavefronts RW consecutive rows (5 for
-// the BGK kernel without a source, 126 registers; kQ9RW = 4 otherwise).
+// the BGK kernel without a source on grids of many tiles, 126 registers;
+// kQ9RW = 4 otherwise).
 // Populations moving along x or diagonally come from the adjacent lanes
 // (shuffles), those moving along y from the lane's own rows or, across
 // wavefronts, through an LDS exchange of the three populations that leave a
@@ -507,10 +508,15 @@ int block_sweeps_supported_q9(int H) { return H >= 3 && H % 2 == 1 && kQ9BX - 2 
 hipError_t launch_f_block_q9(int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, const float *itau,
                              const float *Fp, const Ctl *ctl, long long k, int H, hipStream_t s) {
   // 5 rows per wavefront (an 80-row region) for the BGK kernel without a
-  // source, 4 (64 rows) where a source or MRT leaves too few registers
-  const int rw = (!Fp && !kc.mrt) ? 5 : kQ9RW;
-  const int tcols = kQ9BX - 2 * H, trows = kQ9W * rw - 2 * H;
-  const int tx = (kc.nx + tcols - 1) / tcols, ty = (kc.ny + trows - 1) / trows;
+  // source, 4 (64 rows) where a source or MRT leaves too few registers; on a
+  // grid of few tiles (fewer than two rounds of resident workgroups, one per
+  // compute unit, at 4 rows) 5 only if it needs no more rounds x rows
+  const int tcols = kQ9BX - 2 * H, tx = (kc.nx + tcols - 1) / tcols;
+  auto tiles = [&](int rw) { return (long long)tx * ((kc.ny + kQ9W * rw - 2 * H - 1) / (kQ9W * rw - 2 * H)); };
+  const long long cus = device_cus();
+  const bool rows5 = !Fp && !kc.mrt &&
+                     (tiles(4) >= 2 * cus || (tiles(5) + cus - 1) / cus * 5 <= (tiles(4) + cus - 1) / cus * 4);
+  const int ty = (int)(tiles(rows5 ? 5 : kQ9RW) / tx);
   q9_dispatch(storage, 0, [&](auto t, auto) {
     using T = std::remove_pointer_t<decltype(t)>;
     auto go = [&](auto kernel) {
@@ -518,10 +524,11 @@ hipError_t launch_f_block_q9(int storage, const KC &kc, FPtrs fin, FPtrs fout, c
     };
     if (Fp) {
       if (kc.mrt) go(q9_f_block_kernel<T, true, false, 4>);
-      else go(q9_f_block_kernel<T, true, true, 5>);
+      else go(q9_f_block_kernel<T, true, true, 4>);
     } else {
       if (kc.mrt) go(q9_f_block_kernel<T, false, false, 4>);
-      else go(q9_f_block_kernel<T, false, true, 5>);
+      else if (rows5) go(q9_f_block_kernel<T, false, true, 5>);
+      else go(q9_f_block_kernel<T, false, true, 4>);
     }
   });
   return hipGetLastError();

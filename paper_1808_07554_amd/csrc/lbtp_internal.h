@@ -120,6 +120,8 @@ int block_first_supported(int dim, const KC &kc, int H);
 hipError_t launch_f_block_first(int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, float *Pb_out,
                                 const float *itau, const float *Fp, const Ctl *ctl, long long k, int H,
                                 hipStream_t s);
+// Compute units of the current device (queried once per device).
+int device_cus();
 int block_sweeps_supported_q9(int H);
 int block_sweeps_supported_3d(int H);
 hipError_t launch_f_block_3d(int storage, const KC &kc, FPtrs fin, FPtrs fout, const float *Pb, const float *itau,

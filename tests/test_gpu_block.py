@@ -70,6 +70,9 @@ CASES = [
     ((3, 41), WALLS, dict(wall_face=0)),
     ((1, 33), MIXED, {}),
     ((2, 2), PERIODIC, dict(Fp=True)),
+    # grids of many tiles, where launches without a source take regions of 9 rows per wavefront
+    ((1024, 1024), WALLS, {}),
+    ((1100, 1050), MIXED, dict(wall_face=2)),
 ]
 
 
@@ -124,6 +127,7 @@ CHECKED = [
     ((150, 110), WALLS, 3, 64, {}),
     ((96, 47), WALLS, 9, 8, {}),         # short chunks: 5 + 3 sweeps (one launch of 7 after sweep 0)
     ((20, 12), PERIODIC, 9, 6, dict(Fp=True)),   # 3 + 3 sweeps, narrower than the halo
+    ((1024, 1024), WALLS, 9, 64, dict(steps=2)),  # regions of 9 rows per wavefront
 ]
 
 
@@ -205,6 +209,8 @@ Q9_CASES = [
     ((3, 3), Q9_WALLS, dict(wall_face=1)),
     ((1, 29), MIXED, {}),
     ((2, 2), PERIODIC, dict(Fp=True)),
+    ((1024, 1024), Q9_WALLS, {}),                                 # regions of 5 rows per wavefront
+    ((1030, 1000), MIXED, dict(wall_face=3)),
 ]
 
 
