@@ -763,7 +763,9 @@ int lbtp_pressure_solve(lbtp_ctx *c, double tol, long long max_iters, long long 
   for (long long j = 1; k <= last; ++j) {
     last_copy = -1;
     const long long kend = (j * m < last) ? j * m : last;
-    const bool full = graphs && kend == j * m;
+    // a fused chunk ends at sweep jm - 1 (the probe of jm only with checks
+    // on), so without checks it also serves a solve that stops there
+    const bool full = graphs && (kend == j * m || (fused && !checks && kend == j * m - 1));
     if (full && fused && (k == (j - 1) * m || (j == 1 && k == 1))) {
       const bool first = k == (j - 1) * m;     // the chunk performs the re-basing sweep (j-1)m
       hipGraphExec_t g = nullptr;

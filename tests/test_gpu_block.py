@@ -84,6 +84,15 @@ def test_blocked_sweeps_bitwise_equal_single_sweeps(shape, bcs, kw):
         assert np.array_equal(ref[k], got[k]), (shape, k, float(np.abs(ref[k] - got[k]).max()))
 
 
+def test_fixed_count_solves_ending_on_a_chunk_bitwise():
+    """Solves of a whole number of chunks without the stopping rule: the
+    last chunk runs as blocked launches too (it ends at sweep jm - 1)."""
+    ref = _run((200, 150), WALLS, 1, iters=(640, 128))
+    got = _run((200, 150), WALLS, 9, iters=(640, 128))
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), k
+
+
 @pytest.mark.parametrize("H", [3, 5, 7, 21, 23])
 def test_every_block_length_bitwise(H):
     ref = _run((150, 110), WALLS, 1)
