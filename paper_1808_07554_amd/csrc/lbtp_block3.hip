@@ -54,6 +54,16 @@ __device__ inline int z_wrap(int v, int n) {
   return r < 0 ? r + n : r;
 }
 __device__ inline int z_clamp(int v, int n) { return v < 0 ? 0 : (v > n - 1 ? n - 1 : v); }
+// Element i of an array, addressed by a 32-bit byte offset from its base (a
+// context holds fewer than 2^31 populations, so no array reaches 4 GiB).
+template <typename T>
+__device__ inline T *z_at(T *p, uint32_t i) {
+  return (T *)((char *)p + i * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ inline const T *z_at(const T *p, uint32_t i) {
+  return (const T *)((const char *)p + i * (uint32_t)sizeof(T));
+}
 
 // Anti-bounce-back / bounce-back value of the population arriving through
 // wall face `face` at the node whose opposite population is o (load_e).
@@ -104,13 +114,21 @@ __global__ __launch_bounds__(kZBX * kZW) void f_zstream_kernel(KC kc, FPtrs fin_
   // one plane of the state before the launch at this lane's (x, y): every
   // load is issued (clamped to the box where the lane, row or plane lies
   // outside a walled axis; such values never reach a node of the box)
+  // plane index of unwrapped plane uz on a periodic z axis; the value is made
+  // opaque so that the modulo is formed only where it is used (periodic z,
+  // wall planes), not for every plane and level
+  auto zwrap = [&](int uz) {
+    asm volatile("" : "+s"(uz));
+    return z_wrap(uz, nz);
+  };
+  const uint32_t col = (uint32_t)(gy * nx + gx);
   auto load_plane = [&](int uz, float (&d)[6], float &pb, float &it) {
-    const int gz = perz ? z_wrap(uz, nz) : z_clamp(uz, nz);
-    const int c = gz * plane + gy * nx + gx;
+    const int gz = perz ? zwrap(uz) : z_clamp(uz, nz);
+    const uint32_t c = (uint32_t)gz * (uint32_t)plane + col;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) d[j] = Storage<T>::load(fin.p[j], c, is);
-    pb = Pb[c];
-    it = itau[c];
+    for (int j = 0; j < 6; ++j) d[j] = Storage<T>::load(z_at(fin.p[j], c), 0, is);
+    pb = *z_at(Pb, c);
+    it = *z_at(itau, c);
   };
 
   float cur[H + 1][6];   // level s: plane p_s of level s - 1 (p_s = the plane level s sweeps next)
@@ -185,12 +203,12 @@ __global__ __launch_bounds__(kZBX * kZW) void f_zstream_kernel(KC kc, FPtrs fin_
         // likewise w (P_b(z + 1) - P_b(z)) is minus the term of plane p + 1
         e[5] = in[5] - apz[rs1];
         if (xwalls) {
-          const int wz = perz ? z_wrap(pz, nz) : z_clamp(pz, nz);
+          const int wz = perz ? zwrap(pz) : z_clamp(pz, nz);
           if (wall_l) e[0] = z_wall_rule(kc, 0, 0, gy, wz, pbr[rs], cur[s][2]);
           if (wall_r) e[2] = z_wall_rule(kc, 1, nx - 1, gy, wz, pbr[rs], cur[s][0]);
         }
         if (wall_b || wall_t) {
-          const int wz = perz ? z_wrap(pz, nz) : z_clamp(pz, nz);
+          const int wz = perz ? zwrap(pz) : z_clamp(pz, nz);
           if (wall_b) e[1] = z_wall_rule(kc, 2, gx, 0, wz, pbr[rs], cur[s][3]);
           if (wall_t) e[3] = z_wall_rule(kc, 3, gx, ny - 1, wz, pbr[rs], cur[s][1]);
         }
@@ -214,9 +232,9 @@ __global__ __launch_bounds__(kZBX * kZW) void f_zstream_kernel(KC kc, FPtrs fin_
           for (int jj = 0; jj < 6; ++jj) fr[s + 1][jj] = o[jj];
         } else if (keep_node && pz >= zs && pz < ze) {
           // plane uz - (2H - 1) after H sweeps
-          const int c = pz * plane + uy * nx + ux;
+          const uint32_t c = (uint32_t)pz * (uint32_t)plane + (uint32_t)(uy * nx + ux);
 #pragma unroll
-          for (int jj = 0; jj < 6; ++jj) Storage<T>::store(fout.p[jj], c, o[jj], kc.dev_scale);
+          for (int jj = 0; jj < 6; ++jj) Storage<T>::store(z_at(fout.p[jj], c), 0, o[jj], kc.dev_scale);
         }
       }
     }
