@@ -91,7 +91,7 @@ def sweep_kernel_name(storage, dim=2, lattice=None, sweeps_per_launch=9):
     return "f_sweep_vec_kernel"
 
 
-def run(storage, n, launches, lattice="D2Q5"):
+def run(storage, n, launches, lattice="D2Q5", coupled_steps=0):
     import ctypes
 
     import torch
@@ -120,10 +120,62 @@ def run(storage, n, launches, lattice="D2Q5"):
     s.update_coefficients()
     s.pressure_solve(-1.0, 20)
     H = s.probe_sweeps(launches)
+    # coupled steps (coefficients, one chunk of the pressure solve, the
+    # saturation step): the other kernels of a warm step, for their counters
+    for _ in range(coupled_steps):
+        s.update_coefficients()
+        s.pressure_solve(-1.0, 64)
+        s.saturation_step()
     torch.cuda.synchronize()
     print(f"profile workload done: copy {COPY_BYTES} B x3, {launches} launches of {H} plain sweeps at "
           f"{grid_name(lattice, n)} "
-          f"({lattice}, {storage})", flush=True)
+          f"({lattice}, {storage}), {coupled_steps} coupled steps", flush=True)
+
+
+# Algorithmic bytes per node of the once-per-step kernels on D2Q5 (read,
+# written): the saturation step reads g (5 populations), the pressure
+# deviations (4) and their base, 1/tau_f, K and phi, and writes g; with 16-bit
+# storage it also reads the input's base saturation and S^n and writes the
+# output's base.  The moments read g (and its base), K and phi and write S and
+# 1/tau_f.
+STEP_BYTES = {
+    ("g_sweep_kernel", "fp32"): (5 * 4 + 4 * 4 + 4 + 12, 5 * 4),
+    ("g_sweep_kernel", "16"): (5 * 2 + 4 * 2 + 4 + 12 + 4 + 4, 5 * 2 + 4),
+    ("moments_kernel", "fp32"): (5 * 4 + 8, 8),
+    ("moments_kernel", "16"): (5 * 2 + 4 + 8, 8),
+}
+
+
+def summarize_step(fetch_csv, write_csv, out_txt, storage, n, command):
+    """HBM traffic of the saturation step and the moments (D2Q5) from one
+    FETCH_SIZE and one WRITE_SIZE run of the workload with coupled steps,
+    scaled by the plain copy's bytes per count, against their algorithmic
+    bytes."""
+    f_rows = _counter_rows(fetch_csv)
+    w_rows = _counter_rows(write_csv)
+    copy_f, _ = _per_dispatch(f_rows, "copy_probe")
+    copy_w, _ = _per_dispatch(w_rows, "copy_probe")
+    scale_f, scale_w = COPY_BYTES / copy_f, COPY_BYTES / copy_w
+    cells = n * n
+    lines = [f"HBM traffic of the once-per-step kernels, heterogeneous injection {grid_name('D2Q5', n)}, "
+             f"D2Q5, {storage} storage",
+             f"command: {command}",
+             "counters: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each from its own rocprofv3 --pmc run; "
+             f"scaled by the plain copy's {scale_f:.2f} / {scale_w:.2f} B per count"]
+    for k in ("g_sweep_kernel", "moments_kernel"):
+        fv, nf = _per_dispatch(f_rows, k)
+        wv, _ = _per_dispatch(w_rows, k)
+        if fv is None or wv is None:
+            continue
+        ar, aw = STEP_BYTES[(k, "fp32" if storage == "fp32" else "16")]
+        fb, wb = fv * scale_f, wv * scale_w
+        lines.append(f"{k} ({nf} dispatches): {fb / 1e6:.1f} MB read (algorithmic {ar} B/node = "
+                     f"{ar * cells / 1e6:.1f} MB, ratio {fb / (ar * cells):.3f}), {wb / 1e6:.1f} MB written "
+                     f"(algorithmic {aw} B/node = {aw * cells / 1e6:.1f} MB, ratio {wb / (aw * cells):.3f})")
+    text = "\n".join(lines) + "\n"
+    with open(out_txt, "w") as f:
+        f.write(text)
+    print(text)
 
 
 def _counter_rows(path):
@@ -343,6 +395,9 @@ if __name__ == "__main__":
     ap.add_argument("--summarize", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_TXT"))
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_CSV", "OUT_TXT"))
     ap.add_argument("--summarize-counters", nargs=2, metavar=("CSV", "OUT_TXT"))
+    ap.add_argument("--coupled-steps", type=int, default=0,
+                    help="coupled steps after the sweep burst (their kernels' counters; D2Q5)")
+    ap.add_argument("--summarize-step", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_TXT"))
     ap.add_argument("--title", default="")
     ap.add_argument("--command", default=None, help="command line recorded in the summary (default: the one "
                     "that profiles this module with --storage and --n as given)")
@@ -353,6 +408,14 @@ if __name__ == "__main__":
         summarize_trace(*a.summarize_trace, a.title, a.command or "", a.lattice, a.n)
     elif a.summarize_counters:
         summarize_counters(*a.summarize_counters, a.command or "", a.lattice, a.n)
+    elif a.summarize_step:
+        args = f"--storage {a.storage} --coupled-steps 10"
+        command = a.command or (
+            "cd /tmp && export TMPDIR=/tmp; rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR -o run -- "
+            f"python -u -m paper_1808_07554_amd.profile_sweep {args}  (then the same with --pmc WRITE_SIZE); "
+            "summary: python -m paper_1808_07554_amd.profile_sweep --summarize-step FETCH.csv WRITE.csv OUT.txt "
+            f"--storage {a.storage}")
+        summarize_step(*a.summarize_step, a.storage, a.n, command)
     elif a.summarize:
         args = (f"--storage {a.storage}" + (f" --n {a.n}" if a.n != default_n(a.lattice) else "")
                 + (f" --lattice {a.lattice}" if a.lattice != "D2Q5" else ""))
@@ -362,5 +425,5 @@ if __name__ == "__main__":
             f"summary: python -m paper_1808_07554_amd.profile_sweep --summarize FETCH.csv WRITE.csv OUT.txt {args}")
         summarize(*a.summarize, a.storage, a.n, command, a.lattice)
     else:
-        run(a.storage, a.n, a.launches, a.lattice)
+        run(a.storage, a.n, a.launches, a.lattice, a.coupled_steps)
         sys.exit(0)
