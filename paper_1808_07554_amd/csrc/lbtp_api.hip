@@ -863,7 +863,8 @@ int lbtp_saturation_step(lbtp_ctx *c) {
   HIP_TRY(launch_g_sweep(c->lk, c->p.storage, c->kc, gptrs(c, c->gs), gptrs(c, c->gs ^ 1),
                          fptrs(c, c->fbuf[c->fs]), c->f_local, c->Pb[c->pbs], c->itau, c->K, c->phi, Fs_or_null(c),
                          c->S, c->partials, c->stream));
-  HIP_TRY(launch_finish_sum(c->partials, c->nblk, &c->ctl->ledger, 1, &c->ctl->last_flux, c->stream));
+  HIP_TRY(launch_finish_sum(c->partials, g_sweep_blocks(c->lk, c->kc, c->f_local), &c->ctl->ledger, 1,
+                            &c->ctl->last_flux, c->stream));
   c->gs ^= 1;
   c->step += 1;
   c->have_coef = 0;

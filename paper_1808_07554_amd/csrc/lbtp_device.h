@@ -641,6 +641,39 @@ __device__ inline double moments_cell(const KC &kc, const GPtrs &g_, const float
   return dm;
 }
 
+// Push of the post-collision moving population j of node q (value o) to
+// x + c_j, or its reflection at a wall (Section 4: bounce-back, anti-bounce-back
+// with S_wb, or the zero-gradient outlet with S_wb = Sv, the node's S);
+// periodic faces wrap.  16-bit storage writes the deviation from g^eq of the
+// node written, from S^n (Sn; Snc at q).  Returns the reflected link's flux.
+template <typename T>
+__device__ inline double g_push(const KC &kc, const GP<T> &gout, const float *__restrict__ Sn, const Cell &q, int j,
+                                float o, float Sv, float Snc) {
+  const int a = dir_axis(j), s = dir_sign(j);
+  const int c = q.c;
+  const int x = coord(q, a), n = extent(kc, a), st = stride_of(kc, a);
+  const bool out = (s > 0) ? (x == n - 1) : (x == 0);
+  if (!out) {
+    const int d = c + s * st;
+    gstore(gout.p[j + 1], d, o, gdev<T>() ? kc.w1beta * Sn[d] : 0.0f, kc);
+    return 0.0;
+  }
+  const int face = 2 * a + (s > 0 ? 1 : 0);
+  const int bc = kc.bc_g[face];
+  if (bc == LBTP_BC_PERIODIC) {
+    const int d = c + s * st - s * n * st;
+    gstore(gout.p[j + 1], d, o, gdev<T>() ? kc.w1beta * Sn[d] : 0.0f, kc);
+    return 0.0;
+  }
+  float r;
+  if (bc == LBTP_BC_NOFLUX) r = o;
+  else if (bc == LBTP_BC_DIRICHLET)
+    r = (kc.wS[face] ? 2.0f * kc.w1beta * wall_S(kc, face, q.x, q.y, q.z, 1, 0) : kc.abbS[face]) - o;
+  else r = 2.0f * kc.w1beta * Sv - o;    // outflow: S_wb = S of this node
+  gstore(gout.p[dir_opp(j) + 1], c, r, gdev<T>() ? kc.w1beta * Snc : 0.0f, kc);
+  return (double)r - (double)o;
+}
+
 // One node of the saturation step (eq. 3-2 with g^eq of eq. 3-4b, the local
 // grad P of eq. 3-10a read from the pressure lattice as in the pressure sweep,
 // gamma = -lambda_w K / (c_s^2 dt), eq. 3-8): collide and push to x + c_i, or
@@ -691,27 +724,111 @@ __device__ inline double g_sweep_cell(const KC &kc, const GPtrs &gin_, const GPt
     float o = gv[j + 1] + (geq - gv[j + 1]) * itg;
     if (HAS_FS) o += kc.w1 * srcw;
     o += conv * (float)s * m1[a];
-    const int x = coord(q, a), n = extent(kc, a), st = stride_of(kc, a);
-    const bool out = (s > 0) ? (x == n - 1) : (x == 0);
-    if (!out) {
-      const int d = c + s * st;
-      gstore(gout.p[j + 1], d, o, gdev<T>() ? kc.w1beta * Sn[d] : 0.0f, kc);
-    } else {
-      const int face = 2 * a + (s > 0 ? 1 : 0);
-      const int bc = kc.bc_g[face];
-      if (bc == LBTP_BC_PERIODIC) {
-        const int d = c + s * st - s * n * st;
-        gstore(gout.p[j + 1], d, o, gdev<T>() ? kc.w1beta * Sn[d] : 0.0f, kc);
+    flux += g_push<T>(kc, gout, Sn, q, j, o, Sv, Snc);
+  }
+  return flux;
+}
+
+// The saturation step of the four nodes x0 .. x0 + 3 of a row (D2Q5, the
+// pressure lattice in pull form, nx % 4 == 0; thread qi): per node the
+// arithmetic of g_sweep_cell, with the pressure deviations pulled by the quad
+// functions of the pressure sweep (the same values as load_e), the node data
+// read and the rest and y-moving populations written as 4-wide vectors; the
+// x-moving populations, and the y-moving ones of a row at a y face, go
+// through g_push.  Every lane of the wavefront must call it (the pulls
+// shuffle between lanes).
+template <typename T, bool HAS_FS>
+__device__ inline double g_sweep_quad(const KC &kc, const GPtrs &gin_, const GPtrs &gout_, const FP<T> &f,
+                                      const float *__restrict__ Pb, const float *__restrict__ itau,
+                                      const float *__restrict__ K, const float *__restrict__ phi,
+                                      const float *__restrict__ Fs, const float *__restrict__ Sn, int qi) {
+  const int n4 = kc.ncell >> 2;
+  const bool active = qi < n4;
+  const int c = (active ? qi : n4 - 1) << 2;     // first of the four nodes
+  const int y = c / kc.nx;
+  const int x0 = c - y * kc.nx;
+  const float4 pb = *(const float4 *)(Pb + c);
+  float4 e4[4];
+  pull_x_quad<T>(kc, f, Pb, c, x0, y, 0, pb, e4[0], e4[2]);
+  {
+    float4 pbm = pb, pbp = pb;
+    load_pb_axis(kc, Pb, c, 1, y, kc.ny, kc.nx, pbm, pbp);
+    pull_axis_quad<T>(kc, f, c, 1, y, kc.ny, kc.nx, x0, 0, pb, pbm, pbp, e4[1], e4[3]);
+  }
+  if (!active) return 0.0;
+  const GP<T> gin = gtyped<T>(gin_), gout = gtyped<T>(gout_);
+  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 ph4 = *(const float4 *)(phi + c);
+  const float4 B4 = gdev<T>() ? *(const float4 *)(gin.B + c) : zero;
+  float4 g4[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) g4[i] = Vec4<T>::load(gin.p[i], c, kc.inv_g_scale);
+  const float4 fs4 = HAS_FS ? *(const float4 *)(Fs + c) : zero;
+  const float4 Sn4 = gdev<T>() ? *(const float4 *)(Sn + c) : zero;
+  if (gdev<T>()) *(float4 *)(gout.B + c) = Sn4;
+  const float4 it4 = *(const float4 *)(itau + c);
+  const float4 K4 = *(const float4 *)(K + c);
+  const float4 itg4 = kc.itg ? *(const float4 *)(kc.itg + c) : zero;
+  // both y pushes land on rows of the domain (else g_push applies the y faces)
+  const bool yin = y > 0 && y < kc.ny - 1;
+  float4 Snm = zero, Snp = zero;
+  if (gdev<T>() && yin) {
+    Snm = *(const float4 *)(Sn + c - kc.nx);
+    Snp = *(const float4 *)(Sn + c + kc.nx);
+  }
+  float4 out0 = zero, outp = zero, outm = zero;   // rest, +y, -y: what the vectors store
+  double flux = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float ph = f4get(ph4, k), Bc = f4get(B4, k);
+    float gv[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      const float v = f4get(g4[i], k);
+      gv[i] = gdev<T>() ? v + geq_odd(kc, i, Bc, ph) : v;
+    }
+    const float fs = HAS_FS ? f4get(fs4, k) : 0.0f;
+    const float Snc = gdev<T>() ? f4get(Sn4, k) : 0.0f;
+    const float Sv = saturation_of(sum_g<2>(gv), fs, ph, kc);
+    const float e[4] = {f4get(e4[0], k), f4get(e4[1], k), f4get(e4[2], k), f4get(e4[3], k)};
+    float m1[3];
+    moment_c<2>(e, kc, m1);
+    const float gscale = -f4get(it4, k) * kc.inv_cs2dt;
+    const float gamma = -lwk_of(Sv, f4get(K4, k), kc) * kc.inv_cs2dt;
+    const float itg = kc.itg ? f4get(itg4, k) : kc.inv_tau_g;
+    const float srcg = kc.itg ? kc.dt * (1.0f - 0.5f * itg) : kc.src_g;
+    const float conv = gamma * kc.dt * kc.w1 * itg * kc.c * gscale;
+    const float srcw = srcg * fs;
+    {
+      const float geq = (kc.geq0_phi + ph) * Sv;
+      float o = gv[0] + (geq - gv[0]) * itg;
+      if (HAS_FS) o += kc.w0 * srcw;
+      f4set(out0, k, gdev<T>() ? o - geq_odd(kc, 0, Snc, ph) : o);
+    }
+    const float geq = kc.w1beta * Sv;
+    Cell q;
+    q.c = c + k;
+    q.x = x0 + k;
+    q.y = y;
+    q.z = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int a = dir_axis(j), s = dir_sign(j);
+      float o = gv[j + 1] + (geq - gv[j + 1]) * itg;
+      if (HAS_FS) o += kc.w1 * srcw;
+      o += conv * (float)s * m1[a];
+      if (a == 1 && yin) {
+        if (s > 0) f4set(outp, k, gdev<T>() ? o - kc.w1beta * f4get(Snp, k) : o);
+        else f4set(outm, k, gdev<T>() ? o - kc.w1beta * f4get(Snm, k) : o);
       } else {
-        float r;
-        if (bc == LBTP_BC_NOFLUX) r = o;
-        else if (bc == LBTP_BC_DIRICHLET)
-          r = (kc.wS[face] ? 2.0f * kc.w1beta * wall_S(kc, face, q.x, q.y, q.z, 1, 0) : kc.abbS[face]) - o;
-        else r = 2.0f * kc.w1beta * Sv - o;    // outflow: S_wb = S of this node
-        gstore(gout.p[dir_opp(j) + 1], c, r, gdev<T>() ? kc.w1beta * Snc : 0.0f, kc);
-        flux += (double)r - (double)o;
+        flux += g_push<T>(kc, gout, Sn, q, j, o, Sv, Snc);
       }
     }
+  }
+  Vec4<T>::store(gout.p[0], c, out0, kc.g_scale);
+  if (yin) {
+    Vec4<T>::store(gout.p[2], c + kc.nx, outp, kc.g_scale);   // +y (j = 1)
+    Vec4<T>::store(gout.p[4], c - kc.nx, outm, kc.g_scale);   // -y (j = 3)
   }
   return flux;
 }

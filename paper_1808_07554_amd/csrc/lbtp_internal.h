@@ -238,5 +238,11 @@ inline int sweep_blocks(const KC &kc, int local) {
 }
 
 inline int nblocks(long long n) { return (int)((n + kThreads - 1) / kThreads); }
+// Whether the saturation step of a context runs four nodes per thread (D2Q5,
+// the pressure lattice in pull form, nx % 4 == 0), and its blocks (partials).
+inline bool g_sweep_quads(int lk, const KC &kc, int local) { return lk == 2 && !local && kc.nx % 4 == 0 && kc.nz == 1; }
+inline int g_sweep_blocks(int lk, const KC &kc, int local) {
+  return g_sweep_quads(lk, kc, local) ? nblocks(kc.ncell / 4) : nblocks(kc.ncell);
+}
 
 }  // namespace lbtp

@@ -209,6 +209,21 @@ __global__ __launch_bounds__(kThreads) void g_sweep_kernel(KC kc, GPtrs gin, GPt
   block_sum<1>(acc, partials);
 }
 
+// The D2Q5 saturation step four nodes per thread (pull form, nx % 4 == 0).
+template <typename T, bool HAS_FS>
+__global__ __launch_bounds__(kThreads) void g_sweep_quad_kernel(KC kc, GPtrs gin, GPtrs gout, FPtrs f_,
+                                                                const float *__restrict__ Pb,
+                                                                const float *__restrict__ itau,
+                                                                const float *__restrict__ K,
+                                                                const float *__restrict__ phi,
+                                                                const float *__restrict__ Fs,
+                                                                const float *__restrict__ Sn,
+                                                                double *__restrict__ partials) {
+  double acc[1] = {g_sweep_quad<T, HAS_FS>(kc, gin, gout, typed<T>(f_), Pb, itau, K, phi, Fs, Sn,
+                                           blockIdx.x * kThreads + threadIdx.x)};
+  block_sum<1>(acc, partials);
+}
+
 template <int DIM, typename T>
 __global__ __launch_bounds__(kThreads) void init_kernel(KC kc, const float *__restrict__ P0,
                                                         const float *__restrict__ S0,
@@ -435,6 +450,16 @@ template <int DIM, typename T, bool LOCAL>
 struct GSweepLaunch {
   static void run(const KC &kc, GPtrs gin, GPtrs gout, FPtrs f, const float *Pb, const float *itau, const float *K,
                   const float *phi, const float *Fs, const float *Sn, double *partials, hipStream_t s) {
+    if (g_sweep_quads(DIM, kc, LOCAL)) {
+      const dim3 grid(nblocks(kc.ncell / 4)), block(kThreads);
+      if (Fs)
+        hipLaunchKernelGGL((g_sweep_quad_kernel<T, true>), grid, block, 0, s, kc, gin, gout, f, Pb, itau, K, phi,
+                           Fs, Sn, partials);
+      else
+        hipLaunchKernelGGL((g_sweep_quad_kernel<T, false>), grid, block, 0, s, kc, gin, gout, f, Pb, itau, K, phi,
+                           Fs, Sn, partials);
+      return;
+    }
     if (Fs)
       hipLaunchKernelGGL((g_sweep_kernel<DIM, T, LOCAL, true>), LBTP_GRID(kc), kc, gin, gout, f, Pb, itau, K, phi,
                          Fs, Sn, partials);
