@@ -139,8 +139,8 @@ def run(storage, n, launches, lattice="D2Q5", coupled_steps=0):
 # output's base.  The moments read g (and its base), K and phi and write S and
 # 1/tau_f.
 STEP_BYTES = {
-    ("g_sweep_kernel", "fp32"): (5 * 4 + 4 * 4 + 4 + 12, 5 * 4),
-    ("g_sweep_kernel", "16"): (5 * 2 + 4 * 2 + 4 + 12 + 4 + 4, 5 * 2 + 4),
+    ("g_sweep", "fp32"): (5 * 4 + 4 * 4 + 4 + 12, 5 * 4),
+    ("g_sweep", "16"): (5 * 2 + 4 * 2 + 4 + 12 + 4 + 4, 5 * 2 + 4),
     ("moments_kernel", "fp32"): (5 * 4 + 8, 8),
     ("moments_kernel", "16"): (5 * 2 + 4 + 8, 8),
 }
@@ -162,14 +162,16 @@ def summarize_step(fetch_csv, write_csv, out_txt, storage, n, command):
              f"command: {command}",
              "counters: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each from its own rocprofv3 --pmc run; "
              f"scaled by the plain copy's {scale_f:.2f} / {scale_w:.2f} B per count"]
-    for k in ("g_sweep_kernel", "moments_kernel"):
+    for k in ("g_sweep", "moments_kernel"):
         fv, nf = _per_dispatch(f_rows, k)
         wv, _ = _per_dispatch(w_rows, k)
         if fv is None or wv is None:
             continue
+        # the kernel's own name (the saturation step runs one or four nodes per thread)
+        name = next(_short_name(n).split("<")[0] for n, _, _ in f_rows if k in n)
         ar, aw = STEP_BYTES[(k, "fp32" if storage == "fp32" else "16")]
         fb, wb = fv * scale_f, wv * scale_w
-        lines.append(f"{k} ({nf} dispatches): {fb / 1e6:.1f} MB read (algorithmic {ar} B/node = "
+        lines.append(f"{name} ({nf} dispatches): {fb / 1e6:.1f} MB read (algorithmic {ar} B/node = "
                      f"{ar * cells / 1e6:.1f} MB, ratio {fb / (ar * cells):.3f}), {wb / 1e6:.1f} MB written "
                      f"(algorithmic {aw} B/node = {aw * cells / 1e6:.1f} MB, ratio {wb / (aw * cells):.3f})")
     text = "\n".join(lines) + "\n"
