@@ -152,6 +152,18 @@ def test_example2_saturation_fixed_c_error_is_the_modified_equation_term():
     assert E10c < 0.45 * E10, (E10, E10c)
 
 
+def test_example2_saturation_second_order_when_c_is_large():
+    """The part of the fixed-c error that does not fall with dx shrinks like
+    1/c^2, so at a large lattice speed the grid error shows: at c = 80 the
+    saturation error of Example 2 falls at second order or better from 48^2
+    to 96^2 (measured 4.98e-4 -> 9.0e-5, order 2.47), while at c = 10 it
+    does not fall at all (2.27e-3 -> 2.44e-3)."""
+    from tests.paper_examples import example2_saturation
+    E48, E96 = example2_saturation(48, c=80.0), example2_saturation(96, c=80.0)
+    assert _order(E48, E96) > 2.0, (E48, E96)
+    assert E96 < 0.05 * example2_saturation(96, c=10.0), E96
+
+
 @pytest.mark.parametrize("N", [32, 64])
 def test_example2_saturation_error_falls_with_beta(N):
     """Fig. 11 (phi = 0.5, beta = 0.25, 0.5, 0.75, 1): the saturation error
