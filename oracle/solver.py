@@ -444,11 +444,15 @@ class Solver:
 
     # --------------------------------------------------------- initialisation
     def _cdiff(self, u):
-        """Second-order central differences (one-sided second order at walls)."""
+        """Second-order central differences (one-sided second order at walls;
+        the three-point one-sided formula needs three nodes along a walled
+        axis, and a shorter one is refused)."""
         g = np.zeros((3,) + self.fshape)
         axes = (2, 1, 0)
         for a in range(self.lat.dim):
             ax = axes[a]
+            if self.bc_f[2 * a][0] != "periodic" and u.shape[ax] < 3:
+                raise ValueError("a walled axis needs at least three nodes (one-sided differences)")
             if self.bc_f[2 * a][0] == "periodic":
                 g[a] = (np.roll(u, -1, ax) - np.roll(u, 1, ax)) / (2 * self.dx)
             else:
