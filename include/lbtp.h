@@ -149,6 +149,8 @@ typedef struct lbtp_params {
 LBTP_API void lbtp_default_params(lbtp_params *p);
 
 /* Validate *p (tau_g > 1/2, beta >= 0, periodicity consistent, sizes > 0,
+ * at least three nodes along every walled axis -- the one-sided differences
+ * of the initial gradients need them; a periodic axis may have any length --
  * storage/lattice known) and allocate all device buffers of a context.
  * Returns LBTP_EINVAL, LBTP_ENOMEM or LBTP_EHIP on failure (*out = NULL). */
 LBTP_API int lbtp_init(const lbtp_params *p, lbtp_ctx **out);
