@@ -1115,7 +1115,7 @@ void free_tmp(lbtp_nn *nn, std::vector<void *> &tmp) {
 // address hipGetSymbolAddress returns for the current device, never the
 // array's name.
 constexpr size_t kNNScratchBytes = (size_t)LBTP_NN_SCRATCH_BYTES;
-__device__ __align__(256) unsigned char nn_scratch[kNNScratchBytes];
+static __device__ __align__(256) unsigned char nn_scratch[kNNScratchBytes];
 
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
